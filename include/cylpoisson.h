@@ -1,0 +1,168 @@
+/*
+ * cylpoisson -- full-spectrum cylindrical Poisson solve on one AMD Instinct
+ * MI355X (gfx950): azimuthal DFT, batched matrix-free geometric multigrid on
+ * every Fourier plane, inverse DFT.
+ *
+ * The equation is the cylindrical Poisson equation of Sec. 3.1,
+ *     -[ (1/r) d/dr (r dphi/dr) + (1/r^2) d2phi/dtheta^2 + d2phi/dz^2 ] = rho/eps0,
+ * discretised by the finite-volume cell balance of App. A on a vertex-centred
+ * annular grid, with the periodic three-point azimuthal difference of
+ * Sec. 3.1.  The solve follows Sec. 3: the azimuthal DFT (Eq. azimuthal_dft)
+ * splits the 3-D system into independent 2-D systems A_m = A_0 + lambda_m M
+ * (Eq. shifted_operator_family) with the exact discrete eigenvalue
+ * lambda_m = (4/dtheta^2) sin^2(pi m / Ntheta) (Eq. discrete_azimuthal_eigenvalue),
+ * right-hand side s_q rho^_m + b^D delta_{m0} (Eq. mode_rhs); every mode is
+ * solved by V-cycles over one shared hierarchy, and the inverse DFT returns phi.
+ *
+ * Conventions
+ * -----------
+ * Grid.  Nr radial nodes r_i = r_in + i (r_out - r_in)/(Nr - 1) and Nz axial
+ *   nodes z_k = k dz, both counts including the two Dirichlet faces; Ntheta
+ *   periodic nodes theta_j = 2 pi j / Ntheta over the full annulus.
+ * Arrays.  Node arrays are C-contiguous double[Ntheta][Nz][Nr] (r fastest) in
+ *   device memory of the plan's device.  rho in C/m^3, phi in volts,
+ *   eps0 = 8.8541878128e-12 F/m.
+ * Planes.  The N = Ntheta real planes of a node array x are
+ *     plane m          (m = 0 .. floor(N/2))      : Re x^_m
+ *     plane floor(N/2)+m (m = 1 .. ceil(N/2) - 1) : Im x^_m
+ *   with x^_m = (1/N) sum_j x_j exp(-2 pi i m j / N) (Eq. azimuthal_dft).
+ *   Plane arrays have the node-array shape; plane p replaces azimuthal index p.
+ * Ownership.  All pointers passed in are owned by the caller; the plan owns
+ *   its device workspace from create to destroy.
+ * Streams.  `stream` is a hipStream_t (NULL = default stream) of the plan's
+ *   device.  Every kernel is enqueued on it.  Calls that need a convergence
+ *   decision synchronise that stream.  A plan runs one call at a time; calls
+ *   on different plans may run concurrently.
+ * Errors.  Functions return a status (below); on failure a thread-local
+ *   message is available from cylpoisson_last_error().  Arguments are
+ *   validated before any device work is enqueued.
+ */
+#ifndef CYLPOISSON_H
+#define CYLPOISSON_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define CYLPOISSON_OK 0
+#define CYLPOISSON_NOT_CONVERGED 1 /* tolerance not reached; phi holds the last iterate */
+#define CYLPOISSON_EINVAL (-1)     /* invalid argument */
+#define CYLPOISSON_ENOMEM (-2)     /* device or host allocation failed */
+#define CYLPOISSON_EHIP (-3)       /* a HIP runtime call failed */
+#define CYLPOISSON_ENONFINITE (-4) /* rho (or a plane right-hand side) holds NaN or Inf */
+#define CYLPOISSON_EDEVICE (-5)    /* a pointer is not device memory of the plan's device */
+
+#define CYLPOISSON_MAX_HISTORY 64
+#define CYLPOISSON_MAX_LEVELS 24
+
+typedef struct cylpoisson_plan cylpoisson_plan; /* opaque */
+
+/* Dirichlet values (volts) on the four faces, invariant in theta, so that only
+ * the m = 0 mode carries a boundary term (Eq. mode_rhs).  The axial faces win
+ * at the (r, z) corners. */
+typedef struct {
+    double phi_r_in, phi_r_out, phi_z0, phi_zL;
+} cylpoisson_bc;
+
+typedef struct {
+    int status;          /* status returned by the last solve */
+    int cycles;          /* V-cycles performed by the last solve */
+    int checks;          /* host convergence checks (stream synchronisations) */
+    int n_history;       /* entries of rel_residual_history that are set */
+    double rel_residual; /* final relative residual (definition below) */
+    double initial_residual_norm; /* ||b|| in finite-volume scaling */
+    /* relative residual after cycle c (index c - 1); NaN where not evaluated.
+     * Relative residual = sqrt(sum_p w_p ||r_p||^2 / sum_p w_p ||b_p||^2) over
+     * interior nodes, with the Parseval weights w_p = 1 for m = 0 and m = N/2,
+     * 2 otherwise, i.e. the 2-norm of the 3-D residual relative to that of the
+     * 3-D right-hand side s rho + b^D. */
+    double rel_residual_history[CYLPOISSON_MAX_HISTORY];
+} cylpoisson_stats;
+
+typedef struct {
+    int nr, ntheta, nz;
+    int levels;                             /* multigrid levels (1 = direct only) */
+    int level_nr[CYLPOISSON_MAX_LEVELS];    /* nodes per level, incl. the ring */
+    int level_nz[CYLPOISSON_MAX_LEVELS];
+    int coarse_unknowns;                    /* interior nodes of the coarsest plane */
+    long long workspace_bytes;              /* device memory owned by the plan */
+    int device;                             /* HIP device ordinal */
+} cylpoisson_info;
+
+/* Create a plan for an Nr x Ntheta x Nz grid.  Requires Nr >= 3, Nz >= 3,
+ * Ntheta >= 1, 0 < r_in < r_out, dz > 0 and finite boundary values.  Builds
+ * the multigrid hierarchy and its coefficient tables on the host, allocates
+ * the device workspace on the current HIP device and uploads the tables.
+ * Returns NULL on error (see cylpoisson_last_error; EINVAL or ENOMEM). */
+cylpoisson_plan* cylpoisson_plan_create(int Nr, int Ntheta, int Nz, double r_in, double r_out,
+                                        double dz, const cylpoisson_bc* bc);
+
+/* Release the plan and its device memory.  NULL-safe.  The plan must be idle. */
+void cylpoisson_plan_destroy(cylpoisson_plan* plan);
+
+/* Set a solver option.  Keys (value ranges):
+ *   "nu1", "nu2"     pre-/post-smoothing sweeps (1 .. 8; default 2, 2)
+ *   "omega"          red-black over-relaxation factor (0 < omega < 2; default 1.15)
+ *   "max_cycles"     V-cycle limit per solve (1 .. CYLPOISSON_MAX_HISTORY; default 40)
+ *   "check_every"    cycles between host convergence checks once the predicted
+ *                    cycle count is reached (1 .. 64; default 1)
+ *   "fused"          1 = fused streaming kernels on large levels, 0 = one kernel
+ *                    per sweep everywhere (default 1)
+ * Returns CYLPOISSON_OK or CYLPOISSON_EINVAL. */
+int cylpoisson_plan_set_option(cylpoisson_plan* plan, const char* key, double value);
+
+/* Solve for phi given rho (both device node arrays).  Zero initial guess,
+ * V-cycles until the relative residual (cylpoisson_stats) is <= tol or
+ * max_cycles is reached.  rho is read only at interior nodes; every node of
+ * phi is written, boundary nodes with the Dirichlet values.  tol > 0.
+ * Returns OK, NOT_CONVERGED (phi holds the last iterate), ENONFINITE (phi not
+ * written), EINVAL, EDEVICE or EHIP.  Blocks until the result is decided;
+ * phi is complete once the stream reaches the end of the enqueued work. */
+int cylpoisson_solve(cylpoisson_plan* plan, const double* rho, double* phi, double tol,
+                     void* stream);
+
+/* Statistics of the last solve (or plane solve).  Returns OK or EINVAL. */
+int cylpoisson_get_stats(const cylpoisson_plan* plan, cylpoisson_stats* out);
+
+/* Plan geometry and hierarchy.  Returns OK or EINVAL. */
+int cylpoisson_get_info(const cylpoisson_plan* plan, cylpoisson_info* out);
+
+/* Apply the discrete 3-D operator through the mode path:
+ *     rho_out = (A_full phi) / s_q   at interior nodes,  0 at boundary nodes,
+ * where A_full is the seven-point cell balance of App. A plus the azimuthal
+ * three-point term (the left-hand side of Eq. full_finite_volume_row with the
+ * boundary nodes of phi as neighbours) and s_q = r_i dr dz / eps0.  So
+ * solving with rho_out returns phi.  Computed as DFT, per-plane
+ * A_0 + lambda_m M (Eq. shifted_operator_family), inverse DFT.  Enqueues on
+ * stream without synchronising.  Returns OK, EINVAL, EDEVICE or EHIP. */
+int cylpoisson_apply(cylpoisson_plan* plan, const double* phi, double* rho_out, void* stream);
+
+/* Forward azimuthal DFT of a node array into planes (convention above).
+ * Enqueues without synchronising.  x and planes must not overlap. */
+int cylpoisson_dft_forward(cylpoisson_plan* plan, const double* x, double* planes, void* stream);
+
+/* Inverse of cylpoisson_dft_forward: x_j = sum_m x^_m exp(2 pi i m j / N)
+ * over all N modes, using conjugate symmetry.  planes and x must not overlap. */
+int cylpoisson_dft_inverse(cylpoisson_plan* plan, const double* planes, double* x, void* stream);
+
+/* Solve the per-plane 2-D systems (A_0 + lambda_p M) u_p = b_p of
+ * Eq. shifted_operator_family directly, without the DFTs.  b holds the
+ * finite-volume right-hand side of every plane at interior nodes (ring
+ * entries ignored).  On entry the boundary ring of each plane of u holds
+ * that plane's Dirichlet data (interior entries ignored; zero initial
+ * guess); on exit the interior holds the solution and the ring is unchanged.
+ * Same convergence rule and return values as cylpoisson_solve. */
+int cylpoisson_solve_planes(cylpoisson_plan* plan, const double* b, double* u, double tol,
+                            void* stream);
+
+/* Thread-local message describing the last failure in this thread ("" if none). */
+const char* cylpoisson_last_error(void);
+
+/* Static description of a status code. */
+const char* cylpoisson_status_string(int status);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CYLPOISSON_H */
