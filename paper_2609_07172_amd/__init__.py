@@ -1,0 +1,244 @@
+"""Python binding of the cylpoisson C ABI (``include/cylpoisson.h``).
+
+Argument marshalling only: every step of the solve runs in the HIP library
+``libcylpoisson.so`` built from ``csrc/``.  There is no fallback; if the
+library is missing, every call raises.  PyTorch provides device memory and
+streams (tensors are passed by ``data_ptr()``, streams by handle).
+
+The functions carry the C names without the ``cylpoisson_`` prefix; ``Plan``
+wraps a plan handle.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+
+import torch  # imported first: the library then binds to the HIP runtime torch loaded
+
+__all__ = [
+    "OK", "NOT_CONVERGED", "EINVAL", "ENOMEM", "EHIP", "ENONFINITE", "EDEVICE",
+    "CylPoissonError", "library", "library_path", "plan_create", "plan_destroy",
+    "plan_set_option", "solve", "solve_planes", "apply", "dft_forward", "dft_inverse",
+    "get_stats", "get_info", "last_error", "status_string", "Plan", "EXPORTED_SYMBOLS",
+]
+
+OK, NOT_CONVERGED = 0, 1
+EINVAL, ENOMEM, EHIP, ENONFINITE, EDEVICE = -1, -2, -3, -4, -5
+MAX_HISTORY = 64
+MAX_LEVELS = 24
+
+EXPORTED_SYMBOLS = (
+    "cylpoisson_plan_create", "cylpoisson_plan_destroy", "cylpoisson_plan_set_option",
+    "cylpoisson_solve", "cylpoisson_get_stats", "cylpoisson_get_info", "cylpoisson_apply",
+    "cylpoisson_dft_forward", "cylpoisson_dft_inverse", "cylpoisson_solve_planes",
+    "cylpoisson_last_error", "cylpoisson_status_string",
+)
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+library_path = os.path.join(_HERE, "libcylpoisson.so")
+
+
+class BC(ctypes.Structure):
+    _fields_ = [("phi_r_in", ctypes.c_double), ("phi_r_out", ctypes.c_double),
+                ("phi_z0", ctypes.c_double), ("phi_zL", ctypes.c_double)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int), ("cycles", ctypes.c_int), ("checks", ctypes.c_int),
+                ("n_history", ctypes.c_int), ("rel_residual", ctypes.c_double),
+                ("initial_residual_norm", ctypes.c_double),
+                ("rel_residual_history", ctypes.c_double * MAX_HISTORY)]
+
+    def as_dict(self) -> dict:
+        hist = [self.rel_residual_history[i] for i in range(min(self.n_history, MAX_HISTORY))]
+        return {"status": self.status, "cycles": self.cycles, "checks": self.checks,
+                "rel_residual": self.rel_residual,
+                "initial_residual_norm": self.initial_residual_norm,
+                "history": [None if math.isnan(h) else h for h in hist]}
+
+
+class Info(ctypes.Structure):
+    _fields_ = [("nr", ctypes.c_int), ("ntheta", ctypes.c_int), ("nz", ctypes.c_int),
+                ("levels", ctypes.c_int), ("level_nr", ctypes.c_int * MAX_LEVELS),
+                ("level_nz", ctypes.c_int * MAX_LEVELS), ("coarse_unknowns", ctypes.c_int),
+                ("workspace_bytes", ctypes.c_longlong), ("device", ctypes.c_int)]
+
+    def as_dict(self) -> dict:
+        return {"nr": self.nr, "ntheta": self.ntheta, "nz": self.nz, "levels": self.levels,
+                "level_shapes": [(self.level_nr[i], self.level_nz[i]) for i in range(self.levels)],
+                "coarse_unknowns": self.coarse_unknowns,
+                "workspace_bytes": self.workspace_bytes, "device": self.device}
+
+
+class CylPoissonError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{status_string(status)} ({status}): {message}")
+        self.status = status
+
+
+_lib = None
+
+
+def library() -> ctypes.CDLL:
+    """Load ``libcylpoisson.so`` (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(library_path):
+        raise RuntimeError(f"HIP library not built: {library_path} is missing "
+                           "(run __graft_entry__.build())")
+    L = ctypes.CDLL(library_path)
+    vp, dp, i, d = ctypes.c_void_p, ctypes.c_double, ctypes.c_int, ctypes.c_double
+    L.cylpoisson_plan_create.restype = vp
+    L.cylpoisson_plan_create.argtypes = [i, i, i, d, d, d, ctypes.POINTER(BC)]
+    L.cylpoisson_plan_destroy.restype = None
+    L.cylpoisson_plan_destroy.argtypes = [vp]
+    L.cylpoisson_plan_set_option.restype = i
+    L.cylpoisson_plan_set_option.argtypes = [vp, ctypes.c_char_p, d]
+    for name in ("cylpoisson_solve", "cylpoisson_solve_planes"):
+        getattr(L, name).restype = i
+        getattr(L, name).argtypes = [vp, vp, vp, d, vp]
+    for name in ("cylpoisson_apply", "cylpoisson_dft_forward", "cylpoisson_dft_inverse"):
+        getattr(L, name).restype = i
+        getattr(L, name).argtypes = [vp, vp, vp, vp]
+    L.cylpoisson_get_stats.restype = i
+    L.cylpoisson_get_stats.argtypes = [vp, ctypes.POINTER(Stats)]
+    L.cylpoisson_get_info.restype = i
+    L.cylpoisson_get_info.argtypes = [vp, ctypes.POINTER(Info)]
+    L.cylpoisson_last_error.restype = ctypes.c_char_p
+    L.cylpoisson_last_error.argtypes = []
+    L.cylpoisson_status_string.restype = ctypes.c_char_p
+    L.cylpoisson_status_string.argtypes = [i]
+    _lib = L
+    return L
+
+
+def last_error() -> str:
+    return library().cylpoisson_last_error().decode()
+
+
+def status_string(status: int) -> str:
+    return library().cylpoisson_status_string(int(status)).decode()
+
+
+def _ptr(t) -> int:
+    if isinstance(t, torch.Tensor):
+        if t.dtype != torch.float64:
+            raise TypeError("tensors must be torch.float64")
+        if not t.is_contiguous():
+            raise ValueError("tensors must be contiguous")
+        return t.data_ptr()
+    return int(t)
+
+
+def _stream(stream) -> int:
+    if stream is None:
+        return torch.cuda.current_stream().cuda_stream if torch.cuda.is_available() else 0
+    if isinstance(stream, torch.cuda.Stream):
+        return stream.cuda_stream
+    return int(stream)
+
+
+def _check(status: int, allow=(OK,)) -> int:
+    if status not in allow:
+        raise CylPoissonError(status, last_error())
+    return status
+
+
+def plan_create(nr, ntheta, nz, r_in, r_out, dz, bc=(0.0, 0.0, 0.0, 0.0)) -> int:
+    """``cylpoisson_plan_create``; returns the plan handle (int) or raises."""
+    b = BC(*[float(x) for x in bc])
+    h = library().cylpoisson_plan_create(int(nr), int(ntheta), int(nz), float(r_in),
+                                         float(r_out), float(dz), ctypes.byref(b))
+    if not h:
+        raise CylPoissonError(EINVAL, last_error())
+    return h
+
+
+def plan_destroy(plan) -> None:
+    library().cylpoisson_plan_destroy(plan)
+
+
+def plan_set_option(plan, key: str, value: float) -> None:
+    _check(library().cylpoisson_plan_set_option(plan, key.encode(), float(value)))
+
+
+def solve(plan, rho, phi, tol=1e-12, stream=None, allow=(OK,)) -> int:
+    return _check(library().cylpoisson_solve(plan, _ptr(rho), _ptr(phi), float(tol),
+                                             _stream(stream)), allow)
+
+
+def solve_planes(plan, b, u, tol=1e-12, stream=None, allow=(OK,)) -> int:
+    return _check(library().cylpoisson_solve_planes(plan, _ptr(b), _ptr(u), float(tol),
+                                                    _stream(stream)), allow)
+
+
+def apply(plan, phi, rho_out, stream=None) -> None:
+    _check(library().cylpoisson_apply(plan, _ptr(phi), _ptr(rho_out), _stream(stream)))
+
+
+def dft_forward(plan, x, planes, stream=None) -> None:
+    _check(library().cylpoisson_dft_forward(plan, _ptr(x), _ptr(planes), _stream(stream)))
+
+
+def dft_inverse(plan, planes, x, stream=None) -> None:
+    _check(library().cylpoisson_dft_inverse(plan, _ptr(planes), _ptr(x), _stream(stream)))
+
+
+def get_stats(plan) -> dict:
+    s = Stats()
+    _check(library().cylpoisson_get_stats(plan, ctypes.byref(s)))
+    return s.as_dict()
+
+
+def get_info(plan) -> dict:
+    s = Info()
+    _check(library().cylpoisson_get_info(plan, ctypes.byref(s)))
+    return s.as_dict()
+
+
+class Plan:
+    """A solver plan for one annular grid (see ``cylpoisson_plan_create``)."""
+
+    def __init__(self, nr, ntheta, nz, r_in, r_out, dz, bc=(0.0, 0.0, 0.0, 0.0), **options):
+        self.shape = (int(ntheta), int(nz), int(nr))
+        self.handle = plan_create(nr, ntheta, nz, r_in, r_out, dz, bc)
+        for k, v in options.items():
+            plan_set_option(self.handle, k, v)
+
+    @classmethod
+    def for_problem(cls, p, **options) -> "Plan":
+        return cls(p.nr, p.ntheta, p.nz, p.r_in, p.r_out, p.dz, p.bc, **options)
+
+    def set_option(self, key, value):
+        plan_set_option(self.handle, key, value)
+
+    def _check_shape(self, *tensors):
+        for t in tensors:
+            if tuple(t.shape) != self.shape:
+                raise ValueError(f"expected a tensor of shape {self.shape}, got {tuple(t.shape)}")
+
+    def solve(self, rho, tol=1e-12, phi=None, stream=None, allow=(OK,)):
+        self._check_shape(rho, *(() if phi is None else (phi,)))
+        if phi is None:
+            phi = torch.empty_like(rho)
+        solve(self.handle, rho, phi, tol, stream, allow)
+        return phi, get_stats(self.handle)
+
+    def info(self) -> dict:
+        return get_info(self.handle)
+
+    def stats(self) -> dict:
+        return get_stats(self.handle)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,146 @@
+// Internal types shared by the host driver and the HIP kernels of the
+// cylindrical Poisson library.  Not part of the public C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "cylpoisson.h"
+
+namespace cp {
+
+// Vacuum permittivity, CODATA 2018 (F/m).
+constexpr double kEps0 = 8.8541878128e-12;
+
+// One multigrid level as seen by a kernel.  Plane arrays are
+// [Ntheta][nz][pitch] doubles, node (k, i) of plane p at p*pstride + k*pitch + i;
+// nodes include the Dirichlet ring (i = 0, nr-1; k = 0, nz-1).
+//
+// Finite-volume coefficients (App. A, vertex-centred, separable in r and z):
+//   G_W(i,k) = rw[i] * zc[k]   G_E(i,k) = re[i] * zc[k]
+//   G_S(i,k) = rb[i] * zs[k]   G_N(i,k) = rb[i] * zn[k]
+//   mu(i,k)  = rm[i] * zc[k]
+// with rw = r_{i-1/2}/h_w, re = r_{i+1/2}/h_e, rb = r_i dr_i, rm = dr_i/r_i,
+// zc = dz_k, zs = 1/h_s, zn = 1/h_n (h = centre-to-centre distances).
+struct LevelView {
+    int nr, nz, pitch;
+    int pad_;
+    long long pstride;
+    const double* rw;
+    const double* re;
+    const double* rb;
+    const double* rm;
+    const double* zc;
+    const double* zs;
+    const double* zn;
+};
+
+// Grid transfer between a fine level and the next coarser one, one direction.
+// Prolongation (coarse -> fine), for fine node i:
+//   e_f(i) = pwl[i] * e_c(pidx[i]) + pwr[i] * e_c(pidx[i] + 1)
+// (pwr = 0 where the fine node coincides with a coarse node).
+// Restriction R = P^T, for coarse node I (its coincident fine node cidx[I]):
+//   r_c(I) = rwm[I] * r_f(cidx[I]-1) + r_f(cidx[I]) + rwp[I] * r_f(cidx[I]+1)
+struct Transfer1D {
+    const int* pidx;
+    const double* pwl;
+    const double* pwr;
+    const int* cidx;
+    const double* rwm;
+    const double* rwp;
+};
+
+struct DeviceLevel {
+    LevelView v;
+    Transfer1D tr, tz;  // to the next coarser level (unused on the coarsest)
+    double* u = nullptr;
+    double* f = nullptr;
+    double* r = nullptr;  // residual scratch (ring kept at zero)
+    double* u2 = nullptr; // second iterate buffer for the fused kernels
+};
+
+struct HostLevel {
+    int nr = 0, nz = 0, pitch = 0;
+    std::vector<double> r, z;                 // node coordinates
+    std::vector<double> rw, re, rb, rm;       // radial tables (size nr)
+    std::vector<double> zc, zs, zn;           // axial tables (size nz)
+    // transfer to the next coarser level
+    std::vector<int> pidx_r, cidx_r, pidx_z, cidx_z;
+    std::vector<double> pwl_r, pwr_r, rwm_r, rwp_r, pwl_z, pwr_z, rwm_z, rwp_z;
+};
+
+struct Options {
+    int nu1 = 2, nu2 = 2;
+    double omega = 1.15;
+    int max_cycles = 40;
+    int check_every = 1;
+    int fused = 1;
+};
+
+}  // namespace cp
+
+struct cylpoisson_plan {
+    int device = 0;
+    int nr = 0, nt = 0, nz = 0;
+    double r_in = 0, r_out = 0, dz = 0, dr = 0, dtheta = 0;
+    cylpoisson_bc bc{};
+    cp::Options opt;
+
+    std::vector<cp::HostLevel> hl;
+    std::vector<cp::DeviceLevel> dl;
+    std::vector<double> lam;  // per plane
+    int coarse_n = 0;         // interior unknowns of the coarsest plane
+
+    // device buffers
+    double* d_lam = nullptr;
+    double* d_F = nullptr;       // forward DFT matrix [N][N]
+    double* d_G = nullptr;       // inverse DFT matrix [N][N]
+    double* d_s = nullptr;       // s_i = r_i dr dz / eps0, per radial node (fine level)
+    double* d_inv_s = nullptr;   // 1 / s_i (0 on the ring)
+    double* d_cinv = nullptr;    // coarsest-level inverse per plane [N][n][n]
+    double* d_partial = nullptr; // per-plane partial sums [N][kMaxPartial]
+    double* d_norms = nullptr;   // per-plane squared norms [slots][N]
+    double* h_norms = nullptr;   // pinned host copy
+    double* d_tmp = nullptr;     // node-array scratch (apply, plane solves)
+    std::vector<void*> allocations;
+    long long workspace_bytes = 0;
+
+    cylpoisson_stats stats{};
+};
+
+namespace cp {
+
+constexpr int kMaxPartial = 256;
+constexpr int kNormSlots = CYLPOISSON_MAX_HISTORY + 2;
+
+// Error reporting (thread-local message).
+void set_error(const char* fmt, ...);
+
+// ---- kernel launchers (kernels.hip) ----
+hipError_t launch_dft(const double* M, const double* X, double* Y, int n, long long ncols,
+                      const double* colscale, int nr, hipStream_t s);
+hipError_t launch_init_fine_u(const DeviceLevel& L, int nt, const cylpoisson_bc& bc, hipStream_t s);
+hipError_t launch_zero_interior(const DeviceLevel& L, int nt, double* u, hipStream_t s);
+hipError_t launch_zero(double* p, long long n, hipStream_t s);
+hipError_t launch_copy_interior(const DeviceLevel& L, int nt, const double* src, double* dst,
+                                hipStream_t s);
+hipError_t launch_rb_sweep(const DeviceLevel& L, int nt, const double* lam, double* u,
+                           const double* f, int color, double omega, hipStream_t s);
+hipError_t launch_residual(const DeviceLevel& L, int nt, const double* lam, const double* u,
+                           const double* f, double* r, hipStream_t s);
+hipError_t launch_restrict(const DeviceLevel& F, const DeviceLevel& C, int nt, const double* r,
+                           double* fc, hipStream_t s);
+hipError_t launch_prolong(const DeviceLevel& F, const DeviceLevel& C, int nt, const double* uc,
+                          double* u, hipStream_t s);
+hipError_t launch_coarse_solve(const DeviceLevel& L, int nt, const double* lam, const double* cinv,
+                               int n, const double* f, double* u, hipStream_t s);
+hipError_t launch_plane_norms(const DeviceLevel& L, int nt, const double* r, double* partial,
+                              double* norms_out, hipStream_t s);
+hipError_t launch_apply(const DeviceLevel& L, int nt, const double* lam, const double* u,
+                        const double* inv_s, double* out, hipStream_t s);
+hipError_t launch_scan_nonfinite(const double* x, long long n, double* flag, hipStream_t s);
+
+}  // namespace cp

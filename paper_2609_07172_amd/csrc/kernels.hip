@@ -1,0 +1,327 @@
+// Reference HIP kernels for gfx950: one kernel per elementary multigrid step.
+// They are the correctness baseline and serve the small levels; the fused
+// streaming kernels (fused.hip) take over the large levels.
+#include "cp_internal.h"
+#include "stencil.h"
+
+namespace cp {
+
+namespace {
+
+constexpr int kTx = 64, kTy = 4;
+
+// ---------------------------------------------------------------- DFT (FMA)
+// Y[p][c] = cs(c) * sum_j M[p][j] X[j][c] for c in [0, ncols), p in [0, n).
+// Each thread owns one column c and kDftRows consecutive output rows; the
+// matrix row index is uniform across the wavefront, so M is read through the
+// scalar unit.
+constexpr int kDftRows = 16;
+
+__global__ void __launch_bounds__(256) k_dft(const double* __restrict__ M,
+                                             const double* __restrict__ X,
+                                             double* __restrict__ Y, int n, long long ncols,
+                                             const double* __restrict__ cs, int nr) {
+    const long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const int p0 = blockIdx.y * kDftRows;
+    if (c >= ncols) return;
+    double acc[kDftRows];
+#pragma unroll
+    for (int q = 0; q < kDftRows; ++q) acc[q] = 0.0;
+    const int rows = min(kDftRows, n - p0);
+    for (int j = 0; j < n; ++j) {
+        const double x = X[(long long)j * ncols + c];
+        const double* m = M + (long long)p0 * n + j;
+#pragma unroll
+        for (int q = 0; q < kDftRows; ++q)
+            if (q < rows) acc[q] = fma(m[(long long)q * n], x, acc[q]);
+    }
+    const double scale = cs ? cs[c % nr] : 1.0;
+#pragma unroll
+    for (int q = 0; q < kDftRows; ++q)
+        if (q < rows) Y[(long long)(p0 + q) * ncols + c] = acc[q] * scale;
+}
+
+// ------------------------------------------------------------ initialisation
+// Fine-level iterate: zero interior; ring of plane 0 holds the Dirichlet data
+// (axial faces win at corners), rings of the other planes are zero because a
+// theta-invariant boundary has only an m = 0 component (Eq. mode_rhs).
+__global__ void k_init_fine_u(LevelView v, double* u, double prz, double prout, double pz0,
+                              double pzl) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int k = blockIdx.y * blockDim.y + threadIdx.y;
+    const int p = blockIdx.z;
+    if (i >= v.nr || k >= v.nz) return;
+    double val = 0.0;
+    if (p == 0) {
+        if (i == 0) val = prz;
+        if (i == v.nr - 1) val = prout;
+        if (k == 0) val = pz0;
+        if (k == v.nz - 1) val = pzl;
+    }
+    u[(long long)p * v.pstride + (long long)k * v.pitch + i] = val;
+}
+
+__global__ void k_zero_interior(LevelView v, double* u) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x + 1;
+    const int k = blockIdx.y * blockDim.y + threadIdx.y + 1;
+    const int p = blockIdx.z;
+    if (i > v.nr - 2 || k > v.nz - 2) return;
+    u[(long long)p * v.pstride + (long long)k * v.pitch + i] = 0.0;
+}
+
+__global__ void k_zero(double* p, long long n) {
+    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < n) p[t] = 0.0;
+}
+
+__global__ void k_copy_interior(LevelView v, const double* __restrict__ src, double* __restrict__ dst) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x + 1;
+    const int k = blockIdx.y * blockDim.y + threadIdx.y + 1;
+    const int p = blockIdx.z;
+    if (i > v.nr - 2 || k > v.nz - 2) return;
+    const long long o = (long long)p * v.pstride + (long long)k * v.pitch + i;
+    dst[o] = src[o];
+}
+
+// --------------------------------------------------------- red-black sweep
+// One colour of red-black over-relaxed Gauss-Seidel on A_p = A_0 + lambda_p M
+// (Eq. matrix_free_mode_operator).  Colour = (i + k) & 1.  In place.
+__global__ void __launch_bounds__(256) k_rb(LevelView v, const double* __restrict__ lam,
+                                            double* __restrict__ u,
+                                            const double* __restrict__ f, int color,
+                                            double omega) {
+    const int k = blockIdx.y * blockDim.y + threadIdx.y + 1;
+    const int i = 2 - (color ^ (k & 1)) + 2 * (blockIdx.x * blockDim.x + threadIdx.x);
+    const int p = blockIdx.z;
+    if (i > v.nr - 2 || k > v.nz - 2) return;
+    const long long o = (long long)p * v.pstride + (long long)k * v.pitch + i;
+    const Coef c = coef_at(v, i, k, lam[p]);
+    u[o] = relax(u[o], f[o], u[o - 1], u[o + 1], u[o - v.pitch], u[o + v.pitch], c, omega);
+}
+
+// ---------------------------------------------------------------- residual
+__global__ void __launch_bounds__(256) k_residual(LevelView v, const double* __restrict__ lam,
+                                                  const double* __restrict__ u,
+                                                  const double* __restrict__ f,
+                                                  double* __restrict__ r) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x + 1;
+    const int k = blockIdx.y * blockDim.y + threadIdx.y + 1;
+    const int p = blockIdx.z;
+    if (i > v.nr - 2 || k > v.nz - 2) return;
+    const long long o = (long long)p * v.pstride + (long long)k * v.pitch + i;
+    const Coef c = coef_at(v, i, k, lam[p]);
+    r[o] = residual(u[o], f[o], u[o - 1], u[o + 1], u[o - v.pitch], u[o + v.pitch], c);
+}
+
+// ------------------------------------------------------------- restriction
+// f_c = P^T r (full weighting on the distance-weighted bilinear P).
+__global__ void __launch_bounds__(256) k_restrict(LevelView vf, LevelView vc, Transfer1D tr,
+                                                  Transfer1D tz, const double* __restrict__ r,
+                                                  double* __restrict__ fc) {
+    const int I = blockIdx.x * blockDim.x + threadIdx.x + 1;
+    const int K = blockIdx.y * blockDim.y + threadIdx.y + 1;
+    const int p = blockIdx.z;
+    if (I > vc.nr - 2 || K > vc.nz - 2) return;
+    const int fi = tr.cidx[I], fk = tz.cidx[K];
+    const double wr[3] = {tr.rwm[I], 1.0, tr.rwp[I]};
+    const double wz[3] = {tz.rwm[K], 1.0, tz.rwp[K]};
+    const double* rp = r + (long long)p * vf.pstride;
+    double s = 0.0;
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+        const double* row = rp + (long long)(fk + b - 1) * vf.pitch + fi;
+        const double t = wr[0] * row[-1] + row[0] + wr[2] * row[1];
+        s = fma(wz[b], t, s);
+    }
+    fc[(long long)p * vc.pstride + (long long)K * vc.pitch + I] = s;
+}
+
+// ------------------------------------------------------------ prolongation
+// u_f += P e_c (the coarse ring is zero).
+__global__ void __launch_bounds__(256) k_prolong(LevelView vf, LevelView vc, Transfer1D tr,
+                                                 Transfer1D tz, const double* __restrict__ uc,
+                                                 double* __restrict__ u) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x + 1;
+    const int k = blockIdx.y * blockDim.y + threadIdx.y + 1;
+    const int p = blockIdx.z;
+    if (i > vf.nr - 2 || k > vf.nz - 2) return;
+    const int I = tr.pidx[i], K = tz.pidx[k];
+    const double* c0 = uc + (long long)p * vc.pstride + (long long)K * vc.pitch + I;
+    const double e = prolong_value(c0, vc.pitch, tr.pwl[i], tr.pwr[i], tz.pwl[k], tz.pwr[k]);
+    u[(long long)p * vf.pstride + (long long)k * vf.pitch + i] += e;
+}
+
+// -------------------------------------------------------- coarsest solve
+// u += A_p^{-1} (f - A_p u) with the inverse precomputed on the host per plane;
+// one block per plane.  Interior unknown q = (k-1)*(nr-2) + (i-1).
+__global__ void __launch_bounds__(256) k_coarse_solve(LevelView v, const double* __restrict__ lam,
+                                                      const double* __restrict__ cinv, int n,
+                                                      const double* __restrict__ f,
+                                                      double* __restrict__ u) {
+    extern __shared__ double sres[];
+    const int p = blockIdx.x;
+    const int ni = v.nr - 2;
+    double* up = u + (long long)p * v.pstride;
+    const double* fp = f + (long long)p * v.pstride;
+    for (int q = threadIdx.x; q < n; q += blockDim.x) {
+        const int i = q % ni + 1, k = q / ni + 1;
+        const long long o = (long long)k * v.pitch + i;
+        const Coef c = coef_at(v, i, k, lam[p]);
+        sres[q] = residual(up[o], fp[o], up[o - 1], up[o + 1], up[o - v.pitch], up[o + v.pitch], c);
+    }
+    __syncthreads();
+    const double* Ci = cinv + (long long)p * n * n;
+    double* scor = sres + n;
+    for (int q = threadIdx.x; q < n; q += blockDim.x) {
+        double s = 0.0;
+        for (int t = 0; t < n; ++t) s = fma(Ci[(long long)q * n + t], sres[t], s);
+        scor[q] = s;
+    }
+    __syncthreads();
+    for (int q = threadIdx.x; q < n; q += blockDim.x) {
+        const int i = q % ni + 1, k = q / ni + 1;
+        up[(long long)k * v.pitch + i] += scor[q];
+    }
+}
+
+// ------------------------------------------------------------ plane norms
+// partial[p][b] = sum over block b's share of plane p's interior of r^2.
+__global__ void __launch_bounds__(256) k_norm_partial(LevelView v, const double* __restrict__ r,
+                                                      double* __restrict__ partial) {
+    __shared__ double red[256];
+    const int p = blockIdx.y;
+    const int ni = v.nr - 2, nk = v.nz - 2;
+    const long long total = (long long)ni * nk;
+    const double* rp = r + (long long)p * v.pstride;
+    double s = 0.0;
+    for (long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x; q < total;
+         q += (long long)gridDim.x * blockDim.x) {
+        const int i = (int)(q % ni) + 1, k = (int)(q / ni) + 1;
+        const double x = rp[(long long)k * v.pitch + i];
+        s = fma(x, x, s);
+    }
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) partial[(long long)p * kMaxPartial + blockIdx.x] = red[0];
+}
+
+__global__ void k_norm_final(const double* __restrict__ partial, int nb, int nt,
+                             double* __restrict__ out) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= nt) return;
+    double s = 0.0;
+    for (int b = 0; b < nb; ++b) s += partial[(long long)p * kMaxPartial + b];
+    out[p] = s;
+}
+
+// ------------------------------------------------------------------ apply
+// out = (A_p u) / s at interior nodes, 0 on the ring.
+__global__ void __launch_bounds__(256) k_apply(LevelView v, const double* __restrict__ lam,
+                                               const double* __restrict__ u,
+                                               const double* __restrict__ inv_s,
+                                               double* __restrict__ out) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int k = blockIdx.y * blockDim.y + threadIdx.y;
+    const int p = blockIdx.z;
+    if (i >= v.nr || k >= v.nz) return;
+    const long long o = (long long)p * v.pstride + (long long)k * v.pitch + i;
+    if (i == 0 || k == 0 || i == v.nr - 1 || k == v.nz - 1) {
+        out[o] = 0.0;
+        return;
+    }
+    const Coef c = coef_at(v, i, k, lam[p]);
+    out[o] = apply_row(u[o], u[o - 1], u[o + 1], u[o - v.pitch], u[o + v.pitch], c) * inv_s[i];
+}
+
+dim3 grid_interior(const LevelView& v, int nt, int xdiv = 1) {
+    const int ni = (v.nr - 2 + xdiv - 1) / xdiv, nk = v.nz - 2;
+    return dim3((ni + kTx - 1) / kTx, (nk + kTy - 1) / kTy, nt);
+}
+
+}  // namespace
+
+hipError_t launch_dft(const double* M, const double* X, double* Y, int n, long long ncols,
+                      const double* colscale, int nr, hipStream_t s) {
+    dim3 grid((unsigned)((ncols + 255) / 256), (n + kDftRows - 1) / kDftRows);
+    k_dft<<<grid, 256, 0, s>>>(M, X, Y, n, ncols, colscale, nr);
+    return hipGetLastError();
+}
+
+hipError_t launch_init_fine_u(const DeviceLevel& L, int nt, const cylpoisson_bc& bc, hipStream_t s) {
+    dim3 grid((L.v.nr + kTx - 1) / kTx, (L.v.nz + kTy - 1) / kTy, nt);
+    k_init_fine_u<<<grid, dim3(kTx, kTy), 0, s>>>(L.v, L.u, bc.phi_r_in, bc.phi_r_out, bc.phi_z0,
+                                                   bc.phi_zL);
+    return hipGetLastError();
+}
+
+hipError_t launch_zero_interior(const DeviceLevel& L, int nt, double* u, hipStream_t s) {
+    k_zero_interior<<<grid_interior(L.v, nt), dim3(kTx, kTy), 0, s>>>(L.v, u);
+    return hipGetLastError();
+}
+
+hipError_t launch_zero(double* p, long long n, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    k_zero<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(p, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_copy_interior(const DeviceLevel& L, int nt, const double* src, double* dst,
+                                hipStream_t s) {
+    k_copy_interior<<<grid_interior(L.v, nt), dim3(kTx, kTy), 0, s>>>(L.v, src, dst);
+    return hipGetLastError();
+}
+
+hipError_t launch_rb_sweep(const DeviceLevel& L, int nt, const double* lam, double* u,
+                           const double* f, int color, double omega, hipStream_t s) {
+    k_rb<<<grid_interior(L.v, nt, 2), dim3(kTx, kTy), 0, s>>>(L.v, lam, u, f, color, omega);
+    return hipGetLastError();
+}
+
+hipError_t launch_residual(const DeviceLevel& L, int nt, const double* lam, const double* u,
+                           const double* f, double* r, hipStream_t s) {
+    k_residual<<<grid_interior(L.v, nt), dim3(kTx, kTy), 0, s>>>(L.v, lam, u, f, r);
+    return hipGetLastError();
+}
+
+hipError_t launch_restrict(const DeviceLevel& F, const DeviceLevel& C, int nt, const double* r,
+                           double* fc, hipStream_t s) {
+    k_restrict<<<grid_interior(C.v, nt), dim3(kTx, kTy), 0, s>>>(F.v, C.v, F.tr, F.tz, r, fc);
+    return hipGetLastError();
+}
+
+hipError_t launch_prolong(const DeviceLevel& F, const DeviceLevel& C, int nt, const double* uc,
+                          double* u, hipStream_t s) {
+    k_prolong<<<grid_interior(F.v, nt), dim3(kTx, kTy), 0, s>>>(F.v, C.v, F.tr, F.tz, uc, u);
+    return hipGetLastError();
+}
+
+hipError_t launch_coarse_solve(const DeviceLevel& L, int nt, const double* lam, const double* cinv,
+                               int n, const double* f, double* u, hipStream_t s) {
+    k_coarse_solve<<<nt, 256, 2 * n * sizeof(double), s>>>(L.v, lam, cinv, n, f, u);
+    return hipGetLastError();
+}
+
+hipError_t launch_plane_norms(const DeviceLevel& L, int nt, const double* r, double* partial,
+                              double* norms_out, hipStream_t s) {
+    const long long total = (long long)(L.v.nr - 2) * (L.v.nz - 2);
+    int nb = (int)std::min<long long>(kMaxPartial, (total + 255) / 256);
+    if (nb < 1) nb = 1;
+    k_norm_partial<<<dim3(nb, nt), 256, 0, s>>>(L.v, r, partial);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    k_norm_final<<<(nt + 63) / 64, 64, 0, s>>>(partial, nb, nt, norms_out);
+    return hipGetLastError();
+}
+
+hipError_t launch_apply(const DeviceLevel& L, int nt, const double* lam, const double* u,
+                        const double* inv_s, double* out, hipStream_t s) {
+    dim3 grid((L.v.nr + kTx - 1) / kTx, (L.v.nz + kTy - 1) / kTy, nt);
+    k_apply<<<grid, dim3(kTx, kTy), 0, s>>>(L.v, lam, u, inv_s, out);
+    return hipGetLastError();
+}
+
+}  // namespace cp

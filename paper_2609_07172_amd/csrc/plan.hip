@@ -1,0 +1,528 @@
+// Plan construction: validation, multigrid hierarchy, coefficient and
+// transfer tables, DFT matrices, coarsest-level inverses, device workspace.
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+
+#include "cp_internal.h"
+
+namespace cp {
+
+namespace {
+thread_local char g_err[512] = "";
+constexpr int kCoarseMax = 64;  // stop coarsening once a plane has this few unknowns
+}  // namespace
+
+void set_error(const char* fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof g_err, fmt, ap);
+    va_end(ap);
+}
+
+const char* last_error() { return g_err; }
+
+namespace {
+
+// Keep every other node counted from the first one and always keep the last
+// one, so an odd number of intervals leaves one short last interval.
+std::vector<int> coarsen_positions(const std::vector<int>& pos) {
+    std::vector<int> out;
+    const int n = (int)pos.size();
+    for (int i = 0; i < n; i += 2) out.push_back(pos[i]);
+    if (out.back() != pos[n - 1]) out.push_back(pos[n - 1]);
+    return out;
+}
+
+// Finite-volume tables of one direction from integer node positions (in units
+// of the fine spacing h).  Vertex-centred control volume of node i: faces
+// half-way to the neighbours (App. A, Eq. cell_geometry_appendix with the
+// node as centre).
+struct Axis {
+    std::vector<double> x;         // coordinates
+    std::vector<double> hm, hp;    // distances to the lower / upper neighbour
+    std::vector<double> width;     // control-volume width
+};
+
+Axis axis_geometry(const std::vector<int>& pos, double origin, double h) {
+    const int n = (int)pos.size();
+    Axis a;
+    a.x.resize(n);
+    a.hm.assign(n, 0.0);
+    a.hp.assign(n, 0.0);
+    a.width.assign(n, 0.0);
+    for (int i = 0; i < n; ++i) a.x[i] = origin + pos[i] * h;
+    for (int i = 1; i + 1 < n; ++i) {
+        a.hm[i] = (pos[i] - pos[i - 1]) * h;
+        a.hp[i] = (pos[i + 1] - pos[i]) * h;
+        a.width[i] = 0.5 * (a.hm[i] + a.hp[i]);
+    }
+    return a;
+}
+
+// 1-D linear interpolation between node sets pf (fine) and pc (coarse), and
+// its transpose, as described by Transfer1D.
+void transfer_tables(const std::vector<int>& pf, const std::vector<int>& pc, std::vector<int>& pidx,
+                     std::vector<double>& pwl, std::vector<double>& pwr, std::vector<int>& cidx,
+                     std::vector<double>& rwm, std::vector<double>& rwp) {
+    const int nf = (int)pf.size(), nc = (int)pc.size();
+    pidx.assign(nf, 0);
+    pwl.assign(nf, 0.0);
+    pwr.assign(nf, 0.0);
+    int I = 0;
+    for (int i = 0; i < nf; ++i) {
+        while (I + 1 < nc && pc[I + 1] <= pf[i]) ++I;
+        if (pc[I] == pf[i]) {
+            pidx[i] = I;
+            pwl[i] = 1.0;
+            pwr[i] = 0.0;
+        } else {
+            const double span = (double)(pc[I + 1] - pc[I]);
+            pidx[i] = I;
+            pwl[i] = (double)(pc[I + 1] - pf[i]) / span;
+            pwr[i] = (double)(pf[i] - pc[I]) / span;
+        }
+    }
+    cidx.assign(nc, 0);
+    rwm.assign(nc, 0.0);
+    rwp.assign(nc, 0.0);
+    int i = 0;
+    for (int J = 0; J < nc; ++J) {
+        while (pf[i] != pc[J]) ++i;
+        cidx[J] = i;
+        if (i > 0 && pidx[i - 1] == J - 1 && pwr[i - 1] != 0.0) rwm[J] = pwr[i - 1];
+        if (i + 1 < nf && pidx[i + 1] == J && pwr[i + 1] != 0.0) rwp[J] = pwl[i + 1];
+    }
+}
+
+// Dense inverse by Gauss-Jordan elimination with partial pivoting.
+bool invert(std::vector<double>& a, int n, std::vector<double>& inv) {
+    inv.assign((size_t)n * n, 0.0);
+    for (int i = 0; i < n; ++i) inv[(size_t)i * n + i] = 1.0;
+    for (int c = 0; c < n; ++c) {
+        int piv = c;
+        for (int r = c + 1; r < n; ++r)
+            if (std::fabs(a[(size_t)r * n + c]) > std::fabs(a[(size_t)piv * n + c])) piv = r;
+        if (a[(size_t)piv * n + c] == 0.0) return false;
+        if (piv != c)
+            for (int t = 0; t < n; ++t) {
+                std::swap(a[(size_t)c * n + t], a[(size_t)piv * n + t]);
+                std::swap(inv[(size_t)c * n + t], inv[(size_t)piv * n + t]);
+            }
+        const double d = 1.0 / a[(size_t)c * n + c];
+        for (int t = 0; t < n; ++t) {
+            a[(size_t)c * n + t] *= d;
+            inv[(size_t)c * n + t] *= d;
+        }
+        for (int r = 0; r < n; ++r) {
+            if (r == c) continue;
+            const double m = a[(size_t)r * n + c];
+            if (m == 0.0) continue;
+            for (int t = 0; t < n; ++t) {
+                a[(size_t)r * n + t] -= m * a[(size_t)c * n + t];
+                inv[(size_t)r * n + t] -= m * inv[(size_t)c * n + t];
+            }
+        }
+    }
+    return true;
+}
+
+template <typename T>
+hipError_t dev_alloc(cylpoisson_plan* p, T** out, size_t count) {
+    void* ptr = nullptr;
+    const size_t bytes = std::max<size_t>(count, 1) * sizeof(T);
+    hipError_t e = hipMalloc(&ptr, bytes);
+    if (e != hipSuccess) return e;
+    p->allocations.push_back(ptr);
+    p->workspace_bytes += (long long)bytes;
+    *out = static_cast<T*>(ptr);
+    return hipSuccess;
+}
+
+template <typename T>
+hipError_t upload(cylpoisson_plan* p, T** out, const std::vector<T>& host) {
+    hipError_t e = dev_alloc(p, out, host.size());
+    if (e != hipSuccess) return e;
+    if (host.empty()) return hipSuccess;
+    return hipMemcpy(*out, host.data(), host.size() * sizeof(T), hipMemcpyHostToDevice);
+}
+
+void free_plan(cylpoisson_plan* p) {
+    for (void* ptr : p->allocations) (void)hipFree(ptr);
+    p->allocations.clear();
+    if (p->h_norms) (void)hipHostFree(p->h_norms);
+    p->h_norms = nullptr;
+}
+
+// Build the level hierarchy on the host.
+void build_levels(cylpoisson_plan* p) {
+    std::vector<int> pr(p->nr), pz(p->nz);
+    for (int i = 0; i < p->nr; ++i) pr[i] = i;
+    for (int k = 0; k < p->nz; ++k) pz[k] = k;
+    std::vector<std::vector<int>> lr{pr}, lz{pz};
+    while ((int)lr.size() < CYLPOISSON_MAX_LEVELS) {
+        const auto& r = lr.back();
+        const auto& z = lz.back();
+        const long long interior = (long long)(r.size() - 2) * (long long)(z.size() - 2);
+        const bool cr = r.size() >= 4, cz = z.size() >= 4;
+        if (interior <= kCoarseMax || (!cr && !cz)) break;
+        lr.push_back(cr ? coarsen_positions(r) : r);
+        lz.push_back(cz ? coarsen_positions(z) : z);
+    }
+    const int nl = (int)lr.size();
+    p->hl.assign(nl, HostLevel{});
+    for (int l = 0; l < nl; ++l) {
+        HostLevel& H = p->hl[l];
+        H.nr = (int)lr[l].size();
+        H.nz = (int)lz[l].size();
+        H.pitch = H.nr;
+        const Axis ar = axis_geometry(lr[l], p->r_in, p->dr);
+        const Axis az = axis_geometry(lz[l], 0.0, p->dz);
+        H.r = ar.x;
+        H.z = az.x;
+        H.rw.assign(H.nr, 0.0);
+        H.re.assign(H.nr, 0.0);
+        H.rb.assign(H.nr, 0.0);
+        H.rm.assign(H.nr, 0.0);
+        for (int i = 1; i + 1 < H.nr; ++i) {
+            const double rc = ar.x[i];
+            const double rlo = rc - 0.5 * ar.hm[i];
+            const double rhi = rc + 0.5 * ar.hp[i];
+            H.rw[i] = rlo / ar.hm[i];
+            H.re[i] = rhi / ar.hp[i];
+            H.rb[i] = rc * ar.width[i];
+            H.rm[i] = ar.width[i] / rc;
+        }
+        H.zc.assign(H.nz, 0.0);
+        H.zs.assign(H.nz, 0.0);
+        H.zn.assign(H.nz, 0.0);
+        for (int k = 1; k + 1 < H.nz; ++k) {
+            H.zc[k] = az.width[k];
+            H.zs[k] = 1.0 / az.hm[k];
+            H.zn[k] = 1.0 / az.hp[k];
+        }
+        if (l + 1 < nl) {
+            transfer_tables(lr[l], lr[l + 1], H.pidx_r, H.pwl_r, H.pwr_r, H.cidx_r, H.rwm_r, H.rwp_r);
+            transfer_tables(lz[l], lz[l + 1], H.pidx_z, H.pwl_z, H.pwr_z, H.cidx_z, H.rwm_z, H.rwp_z);
+        }
+    }
+}
+
+// Coarsest-level dense inverse of A_p for every plane.
+bool coarse_inverses(cylpoisson_plan* p, std::vector<double>& out) {
+    const HostLevel& H = p->hl.back();
+    const int ni = H.nr - 2, nk = H.nz - 2, n = ni * nk;
+    p->coarse_n = n;
+    out.assign((size_t)p->nt * n * n, 0.0);
+    std::vector<double> a, inv;
+    for (int q = 0; q < p->nt; ++q) {
+        // cos and sin planes of one mode share lambda: reuse the previous inverse
+        int same = -1;
+        for (int t = 0; t < q; ++t)
+            if (p->lam[t] == p->lam[q]) {
+                same = t;
+                break;
+            }
+        if (same >= 0) {
+            std::copy(out.begin() + (size_t)same * n * n, out.begin() + (size_t)(same + 1) * n * n,
+                      out.begin() + (size_t)q * n * n);
+            continue;
+        }
+        a.assign((size_t)n * n, 0.0);
+        for (int k = 1; k <= nk; ++k)
+            for (int i = 1; i <= ni; ++i) {
+                const int row = (k - 1) * ni + (i - 1);
+                const double zc = H.zc[k];
+                const double gw = H.rw[i] * zc, ge = H.re[i] * zc;
+                const double gs = H.rb[i] * H.zs[k], gn = H.rb[i] * H.zn[k];
+                a[(size_t)row * n + row] = (gw + ge) + (gs + gn) + p->lam[q] * (H.rm[i] * zc);
+                if (i > 1) a[(size_t)row * n + row - 1] = -gw;
+                if (i < ni) a[(size_t)row * n + row + 1] = -ge;
+                if (k > 1) a[(size_t)row * n + row - ni] = -gs;
+                if (k < nk) a[(size_t)row * n + row + ni] = -gn;
+            }
+        if (!invert(a, n, inv)) return false;
+        std::copy(inv.begin(), inv.end(), out.begin() + (size_t)q * n * n);
+    }
+    return true;
+}
+
+// Forward / inverse DFT matrices in the plane convention of cylpoisson.h.
+void dft_matrices(int N, std::vector<double>& F, std::vector<double>& G) {
+    F.assign((size_t)N * N, 0.0);
+    G.assign((size_t)N * N, 0.0);
+    const int nc = N / 2 + 1;
+    const double two_pi = 6.283185307179586476925286766559;
+    for (int p = 0; p < N; ++p) {
+        const bool sine = p >= nc;
+        const int m = sine ? p - nc + 1 : p;
+        const bool single = (m == 0) || (2 * m == N);
+        for (int j = 0; j < N; ++j) {
+            const double ang = two_pi * (double)(((long long)m * j) % N) / (double)N;
+            const double c = std::cos(ang), s = std::sin(ang);
+            F[(size_t)p * N + j] = (sine ? -s : c) / (double)N;
+            const double w = single ? 1.0 : 2.0;
+            G[(size_t)j * N + p] = sine ? -w * s : w * c;
+        }
+    }
+    for (int j = 0; j < N; ++j) G[(size_t)j * N + 0] = 1.0;
+}
+
+}  // namespace
+
+}  // namespace cp
+
+using namespace cp;
+
+extern "C" {
+
+const char* cylpoisson_last_error(void) { return cp::last_error(); }
+
+const char* cylpoisson_status_string(int status) {
+    switch (status) {
+        case CYLPOISSON_OK: return "ok";
+        case CYLPOISSON_NOT_CONVERGED: return "not converged";
+        case CYLPOISSON_EINVAL: return "invalid argument";
+        case CYLPOISSON_ENOMEM: return "out of memory";
+        case CYLPOISSON_EHIP: return "HIP runtime error";
+        case CYLPOISSON_ENONFINITE: return "non-finite input";
+        case CYLPOISSON_EDEVICE: return "pointer is not device memory of the plan's device";
+        default: return "unknown status";
+    }
+}
+
+cylpoisson_plan* cylpoisson_plan_create(int Nr, int Ntheta, int Nz, double r_in, double r_out,
+                                        double dz, const cylpoisson_bc* bc) {
+    set_error("%s", "");
+    if (Nr < 3 || Nz < 3 || Ntheta < 1) {
+        set_error("need Nr >= 3, Nz >= 3 and Ntheta >= 1 (got %d, %d, %d)", Nr, Nz, Ntheta);
+        return nullptr;
+    }
+    if (!(std::isfinite(r_in) && std::isfinite(r_out) && std::isfinite(dz)) || !(r_in > 0.0) ||
+        !(r_out > r_in) || !(dz > 0.0)) {
+        set_error("need finite 0 < r_in < r_out and dz > 0");
+        return nullptr;
+    }
+    if (!bc) {
+        set_error("bc must not be NULL");
+        return nullptr;
+    }
+    if (!(std::isfinite(bc->phi_r_in) && std::isfinite(bc->phi_r_out) && std::isfinite(bc->phi_z0) &&
+          std::isfinite(bc->phi_zL))) {
+        set_error("boundary values must be finite");
+        return nullptr;
+    }
+    const long long nodes = (long long)Nr * Ntheta * Nz;
+    if (nodes > (1LL << 40) || Ntheta > 65536) {
+        set_error("grid too large (%lld nodes)", nodes);
+        return nullptr;
+    }
+    cylpoisson_plan* p = new (std::nothrow) cylpoisson_plan();
+    if (!p) {
+        set_error("host allocation failed");
+        return nullptr;
+    }
+    p->nr = Nr;
+    p->nt = Ntheta;
+    p->nz = Nz;
+    p->r_in = r_in;
+    p->r_out = r_out;
+    p->dz = dz;
+    p->dr = (r_out - r_in) / (Nr - 1);
+    p->dtheta = 6.283185307179586476925286766559 / Ntheta;
+    p->bc = *bc;
+    if (hipGetDevice(&p->device) != hipSuccess) {
+        set_error("no HIP device available");
+        delete p;
+        return nullptr;
+    }
+    // exact discrete eigenvalue per plane, Eq. (discrete_azimuthal_eigenvalue)
+    const int nc = Ntheta / 2 + 1;
+    p->lam.resize(Ntheta);
+    for (int q = 0; q < Ntheta; ++q) {
+        const int m = q >= nc ? q - nc + 1 : q;
+        const double s = std::sin(3.14159265358979323846264338328 * (double)m / Ntheta);
+        p->lam[q] = 4.0 / (p->dtheta * p->dtheta) * s * s;
+    }
+    build_levels(p);
+    {
+        const HostLevel& Hc = p->hl.back();
+        const long long nc = (long long)(Hc.nr - 2) * (Hc.nz - 2);
+        if (nc > 4096) {  // the coarsest-level kernel keeps 2 n doubles in LDS
+            set_error("coarsest level too large (%lld unknowns)", nc);
+            delete p;
+            return nullptr;
+        }
+    }
+    std::vector<double> cinv;
+    if (!coarse_inverses(p, cinv)) {
+        set_error("coarsest operator is singular");
+        delete p;
+        return nullptr;
+    }
+
+    hipError_t e = hipSuccess;
+#define CP_TRY(x)                  \
+    do {                           \
+        e = (x);                   \
+        if (e != hipSuccess) goto fail; \
+    } while (0)
+    {
+        const int nl = (int)p->hl.size();
+        p->dl.assign(nl, DeviceLevel{});
+        for (int l = 0; l < nl; ++l) {
+            HostLevel& H = p->hl[l];
+            DeviceLevel& D = p->dl[l];
+            const long long pstride = (long long)H.nz * H.pitch;
+            const long long n = pstride * Ntheta;
+            D.v.nr = H.nr;
+            D.v.nz = H.nz;
+            D.v.pitch = H.pitch;
+            D.v.pad_ = 0;
+            D.v.pstride = pstride;
+            CP_TRY(dev_alloc(p, &D.u, n));
+            CP_TRY(dev_alloc(p, &D.f, n));
+            CP_TRY(dev_alloc(p, &D.r, n));
+            CP_TRY(hipMemset(D.u, 0, n * sizeof(double)));
+            CP_TRY(hipMemset(D.f, 0, n * sizeof(double)));
+            CP_TRY(hipMemset(D.r, 0, n * sizeof(double)));
+            double *rw, *re, *rb, *rm, *zc, *zs, *zn;
+            CP_TRY(upload(p, &rw, H.rw));
+            CP_TRY(upload(p, &re, H.re));
+            CP_TRY(upload(p, &rb, H.rb));
+            CP_TRY(upload(p, &rm, H.rm));
+            CP_TRY(upload(p, &zc, H.zc));
+            CP_TRY(upload(p, &zs, H.zs));
+            CP_TRY(upload(p, &zn, H.zn));
+            D.v.rw = rw;
+            D.v.re = re;
+            D.v.rb = rb;
+            D.v.rm = rm;
+            D.v.zc = zc;
+            D.v.zs = zs;
+            D.v.zn = zn;
+            if (l + 1 < nl) {
+                int *a, *b, *c, *d;
+                double *w1, *w2, *w3, *w4, *w5, *w6, *w7, *w8;
+                CP_TRY(upload(p, &a, H.pidx_r));
+                CP_TRY(upload(p, &b, H.cidx_r));
+                CP_TRY(upload(p, &c, H.pidx_z));
+                CP_TRY(upload(p, &d, H.cidx_z));
+                CP_TRY(upload(p, &w1, H.pwl_r));
+                CP_TRY(upload(p, &w2, H.pwr_r));
+                CP_TRY(upload(p, &w3, H.rwm_r));
+                CP_TRY(upload(p, &w4, H.rwp_r));
+                CP_TRY(upload(p, &w5, H.pwl_z));
+                CP_TRY(upload(p, &w6, H.pwr_z));
+                CP_TRY(upload(p, &w7, H.rwm_z));
+                CP_TRY(upload(p, &w8, H.rwp_z));
+                D.tr = Transfer1D{a, w1, w2, b, w3, w4};
+                D.tz = Transfer1D{c, w5, w6, d, w7, w8};
+            }
+        }
+        std::vector<double> F, G;
+        dft_matrices(Ntheta, F, G);
+        CP_TRY(upload(p, &p->d_F, F));
+        CP_TRY(upload(p, &p->d_G, G));
+        CP_TRY(upload(p, &p->d_lam, p->lam));
+        std::vector<double> s(Nr, 0.0), inv_s(Nr, 0.0);
+        const HostLevel& H0 = p->hl[0];
+        for (int i = 1; i + 1 < Nr; ++i) {
+            // s_q = r_i dr_i dz_k / eps0 (Eq. mode_rhs), uniform fine spacing
+            s[i] = H0.r[i] * p->dr * p->dz / kEps0;
+            inv_s[i] = 1.0 / s[i];
+        }
+        CP_TRY(upload(p, &p->d_s, s));
+        CP_TRY(upload(p, &p->d_inv_s, inv_s));
+        CP_TRY(upload(p, &p->d_cinv, cinv));
+        CP_TRY(dev_alloc(p, &p->d_partial, (size_t)Ntheta * kMaxPartial));
+        CP_TRY(dev_alloc(p, &p->d_norms, (size_t)kNormSlots * Ntheta));
+        CP_TRY(dev_alloc(p, &p->d_tmp, (size_t)nodes));
+        CP_TRY(hipHostMalloc((void**)&p->h_norms, (size_t)kNormSlots * Ntheta * sizeof(double),
+                             hipHostMallocDefault));
+        CP_TRY(hipDeviceSynchronize());
+    }
+#undef CP_TRY
+    p->stats.status = CYLPOISSON_OK;
+    return p;
+fail:
+    set_error("device allocation or upload failed: %s", hipGetErrorString(e));
+    free_plan(p);
+    delete p;
+    (void)hipGetLastError();
+    return nullptr;
+}
+
+void cylpoisson_plan_destroy(cylpoisson_plan* plan) {
+    if (!plan) return;
+    int prev = 0;
+    (void)hipGetDevice(&prev);
+    (void)hipSetDevice(plan->device);
+    free_plan(plan);
+    (void)hipSetDevice(prev);
+    delete plan;
+}
+
+int cylpoisson_plan_set_option(cylpoisson_plan* plan, const char* key, double value) {
+    if (!plan || !key) {
+        set_error("plan and key must not be NULL");
+        return CYLPOISSON_EINVAL;
+    }
+    auto int_in = [&](int lo, int hi, int* dst) {
+        if (!(value >= lo && value <= hi) || value != std::floor(value)) {
+            set_error("option %s must be an integer in [%d, %d]", key, lo, hi);
+            return CYLPOISSON_EINVAL;
+        }
+        *dst = (int)value;
+        return CYLPOISSON_OK;
+    };
+    if (!std::strcmp(key, "nu1")) return int_in(1, 8, &plan->opt.nu1);
+    if (!std::strcmp(key, "nu2")) return int_in(1, 8, &plan->opt.nu2);
+    if (!std::strcmp(key, "max_cycles")) return int_in(1, CYLPOISSON_MAX_HISTORY, &plan->opt.max_cycles);
+    if (!std::strcmp(key, "check_every")) return int_in(1, 64, &plan->opt.check_every);
+    if (!std::strcmp(key, "fused")) return int_in(0, 1, &plan->opt.fused);
+    if (!std::strcmp(key, "omega")) {
+        if (!(value > 0.0 && value < 2.0)) {
+            set_error("omega must lie in (0, 2)");
+            return CYLPOISSON_EINVAL;
+        }
+        plan->opt.omega = value;
+        return CYLPOISSON_OK;
+    }
+    set_error("unknown option '%s'", key);
+    return CYLPOISSON_EINVAL;
+}
+
+int cylpoisson_get_stats(const cylpoisson_plan* plan, cylpoisson_stats* out) {
+    if (!plan || !out) {
+        set_error("plan and out must not be NULL");
+        return CYLPOISSON_EINVAL;
+    }
+    *out = plan->stats;
+    return CYLPOISSON_OK;
+}
+
+int cylpoisson_get_info(const cylpoisson_plan* plan, cylpoisson_info* out) {
+    if (!plan || !out) {
+        set_error("plan and out must not be NULL");
+        return CYLPOISSON_EINVAL;
+    }
+    std::memset(out, 0, sizeof *out);
+    out->nr = plan->nr;
+    out->ntheta = plan->nt;
+    out->nz = plan->nz;
+    out->levels = (int)plan->hl.size();
+    for (int l = 0; l < out->levels; ++l) {
+        out->level_nr[l] = plan->hl[l].nr;
+        out->level_nz[l] = plan->hl[l].nz;
+    }
+    out->coarse_unknowns = plan->coarse_n;
+    out->workspace_bytes = plan->workspace_bytes;
+    out->device = plan->device;
+    return CYLPOISSON_OK;
+}
+
+}  // extern "C"

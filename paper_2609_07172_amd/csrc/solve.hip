@@ -1,0 +1,338 @@
+// Solve driver: forward DFT, V-cycles on every plane with host convergence
+// checks, inverse DFT; and the other entry points of the C ABI.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+
+#include "cp_internal.h"
+
+namespace cp {
+
+// fused.hip
+hipError_t vcycle_fused_top(cylpoisson_plan* p, int level, hipStream_t s, bool* handled);
+
+namespace {
+
+struct DeviceGuard {
+    int prev = -1;
+    explicit DeviceGuard(int dev) {
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        (void)hipSetDevice(dev);
+    }
+    ~DeviceGuard() {
+        if (prev >= 0) (void)hipSetDevice(prev);
+    }
+};
+
+#define CP_HIP(x)                                                                  \
+    do {                                                                           \
+        hipError_t e_ = (x);                                                       \
+        if (e_ != hipSuccess) {                                                    \
+            set_error("%s failed: %s", #x, hipGetErrorString(e_));                 \
+            (void)hipGetLastError();                                               \
+            return CYLPOISSON_EHIP;                                                \
+        }                                                                          \
+    } while (0)
+
+// Check that [ptr, ptr + bytes) lies inside one device allocation of the plan's device.
+int check_device_range(const cylpoisson_plan* p, const void* ptr, size_t bytes, const char* name) {
+    if (!ptr) {
+        set_error("%s must not be NULL", name);
+        return CYLPOISSON_EINVAL;
+    }
+    hipPointerAttribute_t attr;
+    std::memset(&attr, 0, sizeof attr);
+    if (hipPointerGetAttributes(&attr, ptr) != hipSuccess) {
+        (void)hipGetLastError();
+        set_error("%s is not memory known to HIP", name);
+        return CYLPOISSON_EDEVICE;
+    }
+    const bool device_mem = attr.type == hipMemoryTypeDevice || attr.isManaged;
+    if (!device_mem || attr.device != p->device) {
+        set_error("%s is not device memory of device %d", name, p->device);
+        return CYLPOISSON_EDEVICE;
+    }
+    void* base = nullptr;
+    size_t size = 0;
+    if (hipMemGetAddressRange(&base, &size, const_cast<void*>(ptr)) != hipSuccess) {
+        (void)hipGetLastError();
+        set_error("%s: cannot query its allocation", name);
+        return CYLPOISSON_EDEVICE;
+    }
+    const char* b = static_cast<const char*>(base);
+    const char* q = static_cast<const char*>(ptr);
+    if (q < b || (size_t)(q - b) + bytes > size) {
+        set_error("%s: allocation holds %zu bytes from its base, need %zu from offset %zu", name,
+                  size, bytes, (size_t)(q - b));
+        return CYLPOISSON_EINVAL;
+    }
+    return CYLPOISSON_OK;
+}
+
+size_t node_bytes(const cylpoisson_plan* p) {
+    return (size_t)p->nr * p->nz * p->nt * sizeof(double);
+}
+
+// Parseval weights of the planes: 1 for m = 0 and m = N/2, else 2.
+double plane_weight(int nt, int q) {
+    const int nc = nt / 2 + 1;
+    const int m = q >= nc ? q - nc + 1 : q;
+    return (m == 0 || 2 * m == nt) ? 1.0 : 2.0;
+}
+
+double weighted(const cylpoisson_plan* p, const double* norms) {
+    double s = 0.0;
+    for (int q = 0; q < p->nt; ++q) s += plane_weight(p->nt, q) * norms[q];
+    return s;
+}
+
+hipError_t residual_norms(cylpoisson_plan* p, int slot, hipStream_t s) {
+    DeviceLevel& L = p->dl[0];
+    hipError_t e = launch_residual(L, p->nt, p->d_lam, L.u, L.f, L.r, s);
+    if (e != hipSuccess) return e;
+    return launch_plane_norms(L, p->nt, L.r, p->d_partial, p->d_norms + (size_t)slot * p->nt, s);
+}
+
+hipError_t smooth(cylpoisson_plan* p, DeviceLevel& L, int sweeps, hipStream_t s) {
+    for (int it = 0; it < sweeps; ++it)
+        for (int color = 0; color < 2; ++color) {
+            hipError_t e = launch_rb_sweep(L, p->nt, p->d_lam, L.u, L.f, color, p->opt.omega, s);
+            if (e != hipSuccess) return e;
+        }
+    return hipSuccess;
+}
+
+hipError_t vcycle(cylpoisson_plan* p, int l, hipStream_t s) {
+    const int nl = (int)p->dl.size();
+    DeviceLevel& L = p->dl[l];
+    if (l == nl - 1)
+        return launch_coarse_solve(L, p->nt, p->d_lam, p->d_cinv, p->coarse_n, L.f, L.u, s);
+    if (p->opt.fused) {
+        bool handled = false;
+        hipError_t e = vcycle_fused_top(p, l, s, &handled);
+        if (handled || e != hipSuccess) return e;
+    }
+    DeviceLevel& C = p->dl[l + 1];
+    hipError_t e = smooth(p, L, p->opt.nu1, s);
+    if (e == hipSuccess) e = launch_residual(L, p->nt, p->d_lam, L.u, L.f, L.r, s);
+    if (e == hipSuccess) e = launch_restrict(L, C, p->nt, L.r, C.f, s);
+    if (e == hipSuccess) e = launch_zero_interior(C, p->nt, C.u, s);
+    if (e == hipSuccess) e = vcycle(p, l + 1, s);
+    if (e == hipSuccess) e = launch_prolong(L, C, p->nt, C.u, L.u, s);
+    if (e == hipSuccess) e = smooth(p, L, p->opt.nu2, s);
+    return e;
+}
+
+// V-cycles on the level-0 planes (f and u with its Dirichlet ring already set).
+int run_cycles(cylpoisson_plan* p, double tol, hipStream_t s) {
+    cylpoisson_stats& st = p->stats;
+    std::memset(&st, 0, sizeof st);
+    for (double& h : st.rel_residual_history) h = NAN;
+    const int nt = p->nt;
+
+    CP_HIP(residual_norms(p, 0, s));
+    CP_HIP(hipMemcpyAsync(p->h_norms, p->d_norms, nt * sizeof(double), hipMemcpyDeviceToHost, s));
+    CP_HIP(hipStreamSynchronize(s));
+    st.checks = 1;
+    const double b2 = weighted(p, p->h_norms);
+    if (!std::isfinite(b2)) {
+        set_error("right-hand side holds NaN or Inf");
+        st.status = CYLPOISSON_ENONFINITE;
+        return st.status;
+    }
+    st.initial_residual_norm = std::sqrt(b2);
+    if (b2 == 0.0) {
+        st.rel_residual = 0.0;
+        st.status = CYLPOISSON_OK;
+        return st.status;
+    }
+
+    const int maxc = p->opt.max_cycles;
+    int next_check = std::min(2, maxc);
+    int last_read = 0;
+    double prev_rel = 1.0;
+    int status = CYLPOISSON_NOT_CONVERGED;
+    int stagnant = 0;
+    for (int c = 1; c <= maxc; ++c) {
+        CP_HIP(vcycle(p, 0, s));
+        CP_HIP(residual_norms(p, c, s));
+        st.cycles = c;
+        if (c != next_check && c != maxc) continue;
+        const int first = last_read + 1;
+        CP_HIP(hipMemcpyAsync(p->h_norms + (size_t)first * nt, p->d_norms + (size_t)first * nt,
+                              (size_t)(c - first + 1) * nt * sizeof(double),
+                              hipMemcpyDeviceToHost, s));
+        CP_HIP(hipStreamSynchronize(s));
+        ++st.checks;
+        for (int t = first; t <= c; ++t) {
+            const double rel = std::sqrt(weighted(p, p->h_norms + (size_t)t * nt) / b2);
+            if (t - 1 < CYLPOISSON_MAX_HISTORY) st.rel_residual_history[t - 1] = rel;
+            st.n_history = t;
+        }
+        last_read = c;
+        const double rel = st.rel_residual_history[c - 1];
+        st.rel_residual = rel;
+        if (!std::isfinite(rel)) {
+            set_error("iteration produced NaN or Inf");
+            status = CYLPOISSON_ENONFINITE;
+            break;
+        }
+        if (rel <= tol) {
+            status = CYLPOISSON_OK;
+            break;
+        }
+        // predict the cycle count from the last contraction factor
+        const double prev = c >= 2 ? st.rel_residual_history[c - 2] : prev_rel;
+        const double rate = std::isfinite(prev) && prev > 0.0 ? rel / prev : 1.0;
+        stagnant = rate > 0.6 ? stagnant + 1 : 0;
+        if (stagnant >= 3) {
+            set_error("residual stagnated at %.3e (tolerance %.3e)", rel, tol);
+            break;
+        }
+        int step = p->opt.check_every;
+        if (rate > 0.0 && rate < 0.9) {
+            const double need = std::ceil(std::log(tol / rel) / std::log(rate) - 1e-9);
+            step = std::max(1, std::min((int)need, 64));
+        } else {
+            step = 1;
+        }
+        next_check = std::min(maxc, c + step);
+        prev_rel = rel;
+    }
+    st.status = status;
+    if (status == CYLPOISSON_NOT_CONVERGED && st.cycles >= maxc)
+        set_error("tolerance %.3e not reached in %d cycles (relative residual %.3e)", tol, maxc,
+                  st.rel_residual);
+    return status;
+}
+
+}  // namespace
+
+}  // namespace cp
+
+using namespace cp;
+
+extern "C" {
+
+int cylpoisson_solve(cylpoisson_plan* p, const double* rho, double* phi, double tol, void* stream) {
+    if (!p) {
+        set_error("plan must not be NULL");
+        return CYLPOISSON_EINVAL;
+    }
+    if (!(tol > 0.0) || !std::isfinite(tol)) {
+        set_error("tol must be a positive finite number");
+        return CYLPOISSON_EINVAL;
+    }
+    DeviceGuard g(p->device);
+    const size_t bytes = node_bytes(p);
+    int st = check_device_range(p, rho, bytes, "rho");
+    if (st == CYLPOISSON_OK) st = check_device_range(p, phi, bytes, "phi");
+    if (st != CYLPOISSON_OK) return p->stats.status = st;
+    const char* a = (const char*)rho;
+    const char* b = (const char*)phi;
+    if (a < b + bytes && b < a + bytes) {
+        set_error("rho and phi overlap");
+        return p->stats.status = CYLPOISSON_EINVAL;
+    }
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    DeviceLevel& L = p->dl[0];
+    const long long ncols = (long long)p->nz * p->nr;
+    // f_p = s_i * (F rho)_p  (Eqs. azimuthal_dft, mode_rhs); the Dirichlet data
+    // enter through the ring of plane 0 of u.
+    CP_HIP(launch_dft(p->d_F, rho, L.f, p->nt, ncols, p->d_s, p->nr, s));
+    CP_HIP(launch_init_fine_u(L, p->nt, p->bc, s));
+    const int status = run_cycles(p, tol, s);
+    if (status == CYLPOISSON_OK || status == CYLPOISSON_NOT_CONVERGED)
+        CP_HIP(launch_dft(p->d_G, L.u, phi, p->nt, ncols, nullptr, p->nr, s));
+    return status;
+}
+
+int cylpoisson_solve_planes(cylpoisson_plan* p, const double* b, double* u, double tol, void* stream) {
+    if (!p) {
+        set_error("plan must not be NULL");
+        return CYLPOISSON_EINVAL;
+    }
+    if (!(tol > 0.0) || !std::isfinite(tol)) {
+        set_error("tol must be a positive finite number");
+        return CYLPOISSON_EINVAL;
+    }
+    DeviceGuard g(p->device);
+    const size_t bytes = node_bytes(p);
+    int st = check_device_range(p, b, bytes, "b");
+    if (st == CYLPOISSON_OK) st = check_device_range(p, u, bytes, "u");
+    if (st != CYLPOISSON_OK) return p->stats.status = st;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    DeviceLevel& L = p->dl[0];
+    CP_HIP(hipMemcpyAsync(L.f, b, bytes, hipMemcpyDeviceToDevice, s));
+    CP_HIP(hipMemcpyAsync(L.u, u, bytes, hipMemcpyDeviceToDevice, s));
+    CP_HIP(launch_zero_interior(L, p->nt, L.u, s));
+    const int status = run_cycles(p, tol, s);
+    if (status == CYLPOISSON_OK || status == CYLPOISSON_NOT_CONVERGED)
+        CP_HIP(launch_copy_interior(L, p->nt, L.u, u, s));
+    return status;
+}
+
+int cylpoisson_apply(cylpoisson_plan* p, const double* phi, double* rho_out, void* stream) {
+    if (!p) {
+        set_error("plan must not be NULL");
+        return CYLPOISSON_EINVAL;
+    }
+    DeviceGuard g(p->device);
+    const size_t bytes = node_bytes(p);
+    int st = check_device_range(p, phi, bytes, "phi");
+    if (st == CYLPOISSON_OK) st = check_device_range(p, rho_out, bytes, "rho_out");
+    if (st != CYLPOISSON_OK) return st;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    DeviceLevel& L = p->dl[0];
+    const long long ncols = (long long)p->nz * p->nr;
+    CP_HIP(launch_dft(p->d_F, phi, L.r, p->nt, ncols, nullptr, p->nr, s));
+    CP_HIP(launch_apply(L, p->nt, p->d_lam, L.r, p->d_inv_s, p->d_tmp, s));
+    CP_HIP(launch_dft(p->d_G, p->d_tmp, rho_out, p->nt, ncols, nullptr, p->nr, s));
+    // the residual scratch must keep a zero ring for the solver
+    CP_HIP(launch_zero(L.r, (long long)p->nt * L.v.pstride, s));
+    return CYLPOISSON_OK;
+}
+
+int cylpoisson_dft_forward(cylpoisson_plan* p, const double* x, double* planes, void* stream) {
+    if (!p) {
+        set_error("plan must not be NULL");
+        return CYLPOISSON_EINVAL;
+    }
+    DeviceGuard g(p->device);
+    const size_t bytes = node_bytes(p);
+    int st = check_device_range(p, x, bytes, "x");
+    if (st == CYLPOISSON_OK) st = check_device_range(p, planes, bytes, "planes");
+    if (st != CYLPOISSON_OK) return st;
+    const char* a = (const char*)x;
+    const char* b = (const char*)planes;
+    if (a < b + bytes && b < a + bytes) {
+        set_error("x and planes overlap");
+        return CYLPOISSON_EINVAL;
+    }
+    CP_HIP(launch_dft(p->d_F, x, planes, p->nt, (long long)p->nz * p->nr, nullptr, p->nr,
+                      static_cast<hipStream_t>(stream)));
+    return CYLPOISSON_OK;
+}
+
+int cylpoisson_dft_inverse(cylpoisson_plan* p, const double* planes, double* x, void* stream) {
+    if (!p) {
+        set_error("plan must not be NULL");
+        return CYLPOISSON_EINVAL;
+    }
+    DeviceGuard g(p->device);
+    const size_t bytes = node_bytes(p);
+    int st = check_device_range(p, planes, bytes, "planes");
+    if (st == CYLPOISSON_OK) st = check_device_range(p, x, bytes, "x");
+    if (st != CYLPOISSON_OK) return st;
+    const char* a = (const char*)x;
+    const char* b = (const char*)planes;
+    if (a < b + bytes && b < a + bytes) {
+        set_error("planes and x overlap");
+        return CYLPOISSON_EINVAL;
+    }
+    CP_HIP(launch_dft(p->d_G, planes, x, p->nt, (long long)p->nz * p->nr, nullptr, p->nr,
+                      static_cast<hipStream_t>(stream)));
+    return CYLPOISSON_OK;
+}
+
+}  // extern "C"

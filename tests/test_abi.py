@@ -1,0 +1,62 @@
+"""The C-ABI library loads, exports every declared symbol, and validates its
+arguments before touching a device (runs without a GPU)."""
+import os
+import re
+
+import pytest
+
+import paper_2609_07172_amd as P
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_symbols():
+    text = open(os.path.join(ROOT, "include", "cylpoisson.h")).read()
+    return sorted(set(re.findall(r"\b(cylpoisson_[a-z_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = P.library()
+    names = declared_symbols()
+    assert len(names) >= 12
+    for name in names:
+        assert hasattr(lib, name), name
+    assert sorted(P.EXPORTED_SYMBOLS) == names
+
+
+@pytest.mark.parametrize("args", [
+    (2, 4, 5, 0.02, 0.05, 0.01),        # Nr < 3
+    (5, 4, 2, 0.02, 0.05, 0.01),        # Nz < 3
+    (5, 0, 5, 0.02, 0.05, 0.01),        # Ntheta < 1
+    (5, 4, 5, 0.0, 0.05, 0.01),         # r_in not positive
+    (5, 4, 5, 0.05, 0.02, 0.01),        # r_out <= r_in
+    (5, 4, 5, 0.02, 0.05, 0.0),         # dz not positive
+    (5, 4, 5, 0.02, float("nan"), 0.01),
+])
+def test_plan_create_rejects_bad_geometry(args):
+    with pytest.raises(P.CylPoissonError) as e:
+        P.plan_create(*args)
+    assert e.value.status == P.EINVAL
+    assert P.last_error()
+
+
+def test_plan_create_rejects_non_finite_bc():
+    with pytest.raises(P.CylPoissonError):
+        P.plan_create(5, 4, 5, 0.02, 0.05, 0.01, bc=(0.0, float("inf"), 0.0, 0.0))
+    assert "finite" in P.last_error()
+
+
+def test_null_plan_and_status_strings():
+    lib = P.library()
+    lib.cylpoisson_plan_destroy(None)  # NULL-safe
+    assert lib.cylpoisson_solve(None, None, None, 1e-12, None) == P.EINVAL
+    assert lib.cylpoisson_apply(None, None, None, None) == P.EINVAL
+    assert lib.cylpoisson_dft_forward(None, None, None, None) == P.EINVAL
+    assert lib.cylpoisson_dft_inverse(None, None, None, None) == P.EINVAL
+    assert lib.cylpoisson_solve_planes(None, None, None, 1e-12, None) == P.EINVAL
+    assert lib.cylpoisson_get_stats(None, None) == P.EINVAL
+    assert lib.cylpoisson_get_info(None, None) == P.EINVAL
+    assert lib.cylpoisson_plan_set_option(None, b"nu1", 2.0) == P.EINVAL
+    for code in (P.OK, P.NOT_CONVERGED, P.EINVAL, P.ENOMEM, P.EHIP, P.ENONFINITE, P.EDEVICE):
+        assert P.status_string(code) != "unknown status"
+    assert P.status_string(42) == "unknown status"

@@ -1,0 +1,252 @@
+"""Parity of the HIP path (through the C ABI) with the CPU oracle.
+
+Tolerances:
+* DFT: each plane value is a sum of N terms of size |x_j|/N; two FP64
+  evaluations differ by at most a few eps * sum_j |x_j| (per column).
+* apply: the operator cancels large neighbour terms, so the bound is taken
+  relative to the absolute-valued operator |A| |phi| / s at the node
+  (times the column mixing of the two transforms).
+* solve: relative L2 over interior nodes <= 1e-12 against the oracle's direct
+  solution (the stated target); boundary nodes must equal the Dirichlet data.
+"""
+import numpy as np
+import pytest
+import torch
+
+import workloads as W
+from oracle import fv, solvers, spectral
+
+from gpu_util import INTERIOR, dev, host, rel_l2, say
+
+pytestmark = pytest.mark.gpu
+
+EPS = np.finfo(np.float64).eps
+
+
+@pytest.fixture(scope="module")
+def P():
+    import paper_2609_07172_amd as P
+    P.library()
+    assert torch.cuda.is_available()
+    return P
+
+
+def manufactured(p, seed=12345):
+    """phi_true and rho = A phi_true / s formed in extended precision, rounded once."""
+    phit = W.manufactured_potential(p, seed, np.longdouble)
+    rho = fv.charge_from_potential(fv.Grid.of(p, np.longdouble), phit).astype(np.float64)
+    return phit.astype(np.float64), rho
+
+
+def check_boundary(phi, p):
+    np.testing.assert_array_equal(phi[:, 0, :], p.phi_z0)
+    np.testing.assert_array_equal(phi[:, -1, :], p.phi_zL)
+    np.testing.assert_array_equal(phi[:, 1:-1, 0], p.phi_r_in)
+    np.testing.assert_array_equal(phi[:, 1:-1, -1], p.phi_r_out)
+
+
+# ------------------------------------------------------------------ DFT
+@pytest.mark.parametrize("shape", [(5, 16, 7), (9, 7, 4), (6, 1, 5), (4, 2, 6), (33, 128, 9)])
+def test_dft_matches_oracle(P, shape):
+    nr, nt, nz = shape
+    say("dft", shape)
+    plan = P.Plan(nr, nt, nz, 0.02, 0.05, 0.01)
+    x = np.random.default_rng(nr + nt).standard_normal((nt, nz, nr))
+    xd = dev(x)
+    planes = torch.empty_like(xd)
+    P.dft_forward(plan.handle, xd, planes)
+    ref = spectral.forward(x)
+    bound = 4 * EPS * np.abs(x).sum(axis=0)[None] + 1e-300
+    err = np.abs(host(planes) - ref)
+    assert (err <= bound).all(), float((err / bound).max())
+    back = torch.empty_like(xd)
+    P.dft_inverse(plan.handle, planes, back)
+    ref_back = spectral.inverse(host(planes))
+    bound = 8 * nt * EPS * np.abs(host(planes)).sum(axis=0)[None] + 1e-300
+    assert (np.abs(host(back) - ref_back) <= bound).all()
+    np.testing.assert_allclose(host(back), x, atol=64 * nt * EPS * np.abs(x).max())
+
+
+# ---------------------------------------------------------------- apply
+def abs_operator_scale(p, phi):
+    """(|A| |phi| + |b^D|(|phi|)) / s at interior nodes: the size of the terms that cancel."""
+    g = fv.Grid.of(p)
+    a = abs(fv.assemble(g))
+    ab = np.abs(phi)
+    s = a @ ab[INTERIOR].ravel() + fv.rhs(g, np.zeros(g.shape), ab).ravel()
+    return s.reshape(g.interior_shape) * fv.EPS0 / g.s_eps0
+
+
+@pytest.mark.parametrize("prob", [W.SMALL, W.HIGH_SHIFT.with_sizes(17, 12, 13), W.SMALL.with_sizes(6, 5, 4)])
+def test_apply_matches_oracle(P, prob):
+    say("apply", prob.name, prob.shape)
+    phi = W.manufactured_potential(prob, 3)
+    plan = P.Plan.for_problem(prob)
+    out = torch.empty_like(dev(phi))
+    P.apply(plan.handle, dev(phi), out)
+    got = host(out)
+    ref = fv.charge_from_potential(fv.Grid.of(prob, np.longdouble), phi.astype(np.longdouble))
+    ref = ref.astype(np.float64)
+    scale = abs_operator_scale(prob, phi)
+    col = scale.max(axis=0)[None] * prob.ntheta
+    err = np.abs(got[INTERIOR] - ref[INTERIOR])
+    assert (err <= 64 * EPS * col).all(), float((err / col).max() / EPS)
+    assert (got[:, 0, :] == 0).all() and (got[:, -1, :] == 0).all()
+    assert (got[:, :, 0] == 0).all() and (got[:, :, -1] == 0).all()
+
+
+# ---------------------------------------------------------------- solve
+def test_solve_small_matches_sparse_direct(P):
+    """Small workload: 33 x 16 x 33, manufactured rho, against SuperLU of the 3-D system."""
+    p = W.SMALL
+    phit, rho = manufactured(p)
+    ref = solvers.solve_sparse(fv.Grid.of(p), rho, p.bc)
+    say("solve", p.name)
+    plan = P.Plan.for_problem(p)
+    phi, st = plan.solve(dev(rho), tol=1e-14)
+    got = host(phi)
+    assert st["status"] == P.OK and st["rel_residual"] <= 1e-14
+    assert rel_l2(got, ref) <= 1e-12, rel_l2(got, ref)
+    assert rel_l2(got, phit) <= 1e-12
+    check_boundary(got, p)
+
+
+@pytest.mark.parametrize("shape", [(3, 4, 3), (3, 5, 9), (9, 1, 3), (7, 2, 6), (10, 3, 11), (12, 5, 7),
+                                   (18, 6, 20), (35, 9, 34)])
+def test_solve_edge_shapes_match_dense(P, shape):
+    """Single-level grids (Nr or Nz = 3), Ntheta in {1, 2}, odd Ntheta, odd interval counts
+    (non-uniform coarse grids), against brute-force or sparse direct solves."""
+    nr, nt, nz = shape
+    p = W.HIGH_SHIFT.with_sizes(nr, nt, nz)
+    rho = W.blob_charge(p, seed=nr * 7 + nt)
+    g = fv.Grid.of(p)
+    ref = solvers.solve_dense(g, rho, p.bc) if g.n_unknowns <= 3000 else solvers.solve_sparse(g, rho, p.bc)
+    say("solve-edge", shape)
+    plan = P.Plan.for_problem(p)
+    phi, st = plan.solve(dev(rho), tol=1e-14)
+    got = host(phi)
+    assert st["status"] == P.OK, st
+    assert rel_l2(got, ref) <= 1e-12, rel_l2(got, ref)
+    check_boundary(got, p)
+
+
+@pytest.mark.parametrize("prob", [W.BATCHED, W.HIGH_SHIFT])
+def test_solve_matches_separable(P, prob):
+    rho = W.blob_charge(prob, seed=24680)
+    ref = solvers.solve_separable(fv.Grid.of(prob), rho, prob.bc)
+    say("solve", prob.name)
+    plan = P.Plan.for_problem(prob)
+    phi, st = plan.solve(dev(rho), tol=1e-14)
+    got = host(phi)
+    assert st["status"] == P.OK, st
+    assert rel_l2(got, ref) <= 1e-12, rel_l2(got, ref)
+    check_boundary(got, prob)
+
+
+def test_solve_planes_matches_mode_systems(P):
+    """Each plane solves (A_0 + lambda_m M) u = b (Eq. shifted_operator_family), with its own
+    Dirichlet ring, against the oracle's sparse solve of that 2-D system."""
+    p = W.HIGH_SHIFT.with_sizes(19, 6, 14)
+    g = fv.Grid.of(p)
+    rng = np.random.default_rng(5)
+    b = rng.standard_normal(p.shape)
+    ring = np.zeros(p.shape)
+    ring[:, 0, :] = rng.standard_normal((p.ntheta, p.nr))
+    ring[:, :, 0] = rng.standard_normal((p.ntheta, p.nz))
+    lam = spectral.plane_eigenvalues(p.ntheta, float(g.dtheta))
+    ref = np.empty(g.interior_shape)
+    for q in range(p.ntheta):
+        rhs_q = b[q][1:-1, 1:-1] + fv.rhs(g, np.zeros(g.shape), ring)[q]
+        ref[q] = solvers.solve_mode(g, lam[q], rhs_q)
+    say("solve_planes")
+    plan = P.Plan.for_problem(p)
+    u = dev(ring)
+    P.solve_planes(plan.handle, dev(b), u, 1e-14)
+    got = host(u)
+    assert rel_l2(got[INTERIOR], ref, where=Ellipsis) <= 1e-12
+    np.testing.assert_array_equal(got[:, 0, :], ring[:, 0, :])
+    np.testing.assert_array_equal(got[:, :, 0], ring[:, :, 0])
+
+
+def test_boundary_data_only_enters_plane_zero(P):
+    """rho = 0: only m = 0 carries a boundary term (Eq. mode_rhs), so every other plane stays
+    exactly zero and phi is exactly theta-invariant."""
+    p = W.SMALL.with_sizes(21, 8, 17)
+    say("rho=0")
+    plan = P.Plan.for_problem(p)
+    phi, st = plan.solve(torch.zeros(p.shape, dtype=torch.float64, device="cuda:0"), tol=1e-14)
+    got = host(phi)
+    assert (got == got[:1]).all()
+    ref = solvers.solve_sparse(fv.Grid.of(p), np.zeros(p.shape), p.bc)
+    assert rel_l2(got, ref) <= 1e-12
+    assert got[INTERIOR].min() > 0 and got[INTERIOR].max() < 300
+
+
+def test_theta_reflection(P):
+    """theta -> -theta maps cos planes to themselves and negates sin planes; the solution reflects."""
+    p = W.SMALL.with_sizes(17, 12, 17)
+    rho = W.blob_charge(p, 9)
+    refl = np.ascontiguousarray(rho[(-np.arange(p.ntheta)) % p.ntheta])
+    say("reflection")
+    plan = P.Plan.for_problem(p)
+    a, _ = plan.solve(dev(rho), tol=1e-14)
+    b, _ = plan.solve(dev(refl), tol=1e-14)
+    a, b = host(a), host(b)
+    assert rel_l2(b, a[(-np.arange(p.ntheta)) % p.ntheta]) <= 1e-13
+
+
+# ------------------------------------------------------------- failures
+def test_non_finite_rho_is_reported(P):
+    p = W.SMALL.with_sizes(9, 4, 9)
+    rho = W.blob_charge(p, 1)
+    rho[2, 3, 4] = np.nan
+    say("nan rho")
+    plan = P.Plan.for_problem(p)
+    phi = torch.full(p.shape, 7.0, dtype=torch.float64, device="cuda:0")
+    with pytest.raises(P.CylPoissonError) as e:
+        plan.solve(dev(rho), phi=phi)
+    assert e.value.status == P.ENONFINITE
+    assert (host(phi) == 7.0).all()
+
+
+def test_not_converged_returns_last_iterate(P):
+    p = W.SMALL
+    rho = W.blob_charge(p, 2)
+    say("max_cycles=1")
+    plan = P.Plan.for_problem(p, max_cycles=1)
+    phi, st = plan.solve(dev(rho), tol=1e-14, allow=(P.OK, P.NOT_CONVERGED))
+    assert st["status"] == P.NOT_CONVERGED and st["cycles"] == 1
+    assert 1e-14 < st["rel_residual"] < 0.2
+    check_boundary(host(phi), p)
+
+
+def test_host_pointer_is_rejected(P):
+    p = W.SMALL.with_sizes(5, 2, 5)
+    plan = P.Plan.for_problem(p)
+    cpu = torch.zeros(p.shape, dtype=torch.float64)
+    gpu = torch.zeros(p.shape, dtype=torch.float64, device="cuda:0")
+    with pytest.raises(P.CylPoissonError) as e:
+        P.solve(plan.handle, cpu, gpu)
+    assert e.value.status == P.EDEVICE
+    # the binding checks tensor shapes (the C ABI can only check allocation bounds)
+    with pytest.raises(ValueError):
+        plan.solve(torch.zeros(3, dtype=torch.float64, device="cuda:0"))
+
+
+# ------------------------------------------------------------ full size
+@pytest.mark.slow
+def test_paper_scale_matches_separable_oracle(P):
+    """400 x 128 x 512 (65 modes), manufactured rho: against the exact separable solver and phi_true."""
+    p = W.PAPER_SCALE
+    phit = W.manufactured_potential(p, 12345)
+    say("paper-scale: forming rho on the CPU")
+    phit_ld, rho = manufactured(p)
+    ref = solvers.solve_separable(fv.Grid.of(p), rho, p.bc, workers=16)
+    say("paper-scale solve")
+    plan = P.Plan.for_problem(p)
+    phi, st = plan.solve(dev(rho), tol=1e-14)
+    got = host(phi)
+    assert st["status"] == P.OK, st
+    assert rel_l2(got, ref) <= 1e-12, rel_l2(got, ref)
+    assert rel_l2(got, phit) <= 1e-12
+    check_boundary(got, p)
