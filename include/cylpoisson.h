@@ -54,6 +54,7 @@ extern "C" {
 
 #define CYLPOISSON_MAX_HISTORY 64
 #define CYLPOISSON_MAX_LEVELS 24
+#define CYLPOISSON_KERNEL_CLASSES 6
 
 typedef struct cylpoisson_plan cylpoisson_plan; /* opaque */
 
@@ -77,6 +78,14 @@ typedef struct {
      * 2 otherwise, i.e. the 2-norm of the 3-D residual relative to that of the
      * 3-D right-hand side s rho + b^D. */
     double rel_residual_history[CYLPOISSON_MAX_HISTORY];
+    /* Device time per kernel class in the last solve, from HIP events recorded
+     * around each launch on the solve's stream when the option "timing" is 1
+     * (all zero otherwise).  Classes: 0 forward DFT, 1 inverse DFT, 2 finest-level
+     * down pass (smoothing, residual, restriction), 3 finest-level up pass
+     * (prolongation, smoothing, residual norm), 4 all coarser levels (one
+     * interval per cycle), 5 other work (initialisation, norm reductions). */
+    int kernel_launches[CYLPOISSON_KERNEL_CLASSES];
+    double kernel_ms[CYLPOISSON_KERNEL_CLASSES];
 } cylpoisson_stats;
 
 typedef struct {
@@ -106,8 +115,12 @@ void cylpoisson_plan_destroy(cylpoisson_plan* plan);
  *   "max_cycles"     V-cycle limit per solve (1 .. CYLPOISSON_MAX_HISTORY; default 40)
  *   "check_every"    cycles between host convergence checks once the predicted
  *                    cycle count is reached (1 .. 64; default 1)
- *   "fused"          1 = fused streaming kernels on large levels, 0 = one kernel
- *                    per sweep everywhere (default 1)
+ *   "fused"          1 = fused streaming passes (all sweeps, residual and grid
+ *                    transfer of a level in one kernel), 0 = one kernel per
+ *                    sweep everywhere (default 1)
+ *   "chunk_rows"     axial rows per workgroup of the fused passes (0 = automatic)
+ *   "prefetch"       rows the fused passes load ahead of the one they consume (1 .. 4; default 3)
+ *   "timing"         1 = record per-kernel-class device times (cylpoisson_stats)
  * Returns CYLPOISSON_OK or CYLPOISSON_EINVAL. */
 int cylpoisson_plan_set_option(cylpoisson_plan* plan, const char* key, double value);
 

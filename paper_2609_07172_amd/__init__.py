@@ -27,6 +27,7 @@ OK, NOT_CONVERGED = 0, 1
 EINVAL, ENOMEM, EHIP, ENONFINITE, EDEVICE = -1, -2, -3, -4, -5
 MAX_HISTORY = 64
 MAX_LEVELS = 24
+KERNEL_CLASSES = ("dft_forward", "dft_inverse", "fine_down", "fine_up", "coarse_levels", "other")
 
 EXPORTED_SYMBOLS = (
     "cylpoisson_plan_create", "cylpoisson_plan_destroy", "cylpoisson_plan_set_option",
@@ -48,14 +49,18 @@ class Stats(ctypes.Structure):
     _fields_ = [("status", ctypes.c_int), ("cycles", ctypes.c_int), ("checks", ctypes.c_int),
                 ("n_history", ctypes.c_int), ("rel_residual", ctypes.c_double),
                 ("initial_residual_norm", ctypes.c_double),
-                ("rel_residual_history", ctypes.c_double * MAX_HISTORY)]
+                ("rel_residual_history", ctypes.c_double * MAX_HISTORY),
+                ("kernel_launches", ctypes.c_int * len(KERNEL_CLASSES)),
+                ("kernel_ms", ctypes.c_double * len(KERNEL_CLASSES))]
 
     def as_dict(self) -> dict:
         hist = [self.rel_residual_history[i] for i in range(min(self.n_history, MAX_HISTORY))]
         return {"status": self.status, "cycles": self.cycles, "checks": self.checks,
                 "rel_residual": self.rel_residual,
                 "initial_residual_norm": self.initial_residual_norm,
-                "history": [None if math.isnan(h) else h for h in hist]}
+                "history": [None if math.isnan(h) else h for h in hist],
+                "kernel_launches": dict(zip(KERNEL_CLASSES, list(self.kernel_launches))),
+                "kernel_ms": dict(zip(KERNEL_CLASSES, list(self.kernel_ms)))}
 
 
 class Info(ctypes.Structure):

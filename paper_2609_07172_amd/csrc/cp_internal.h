@@ -60,6 +60,11 @@ struct DeviceLevel {
     double* f = nullptr;
     double* r = nullptr;  // residual scratch (ring kept at zero)
     double* u2 = nullptr; // second iterate buffer for the fused kernels
+    // fused-pass tables (towards the next coarser level)
+    const int* colc = nullptr;             // fine column -> coincident coarse interior column or -1
+    const int* rowc = nullptr;             // fine row -> coincident coarse interior row or -1
+    int spec_lo = 0;  // rows >= spec_lo have axial coefficients other than (zc0, zs0, zn0)
+    double zc0 = 0, zs0 = 0, zn0 = 0;
 };
 
 struct HostLevel {
@@ -78,6 +83,9 @@ struct Options {
     int max_cycles = 40;
     int check_every = 1;
     int fused = 1;
+    int chunk_rows = 0;  // rows per workgroup in the fused passes (0 = automatic)
+    int prefetch = 3;    // rows the fused passes load ahead of the row they consume
+    int timing = 0;      // record per-kernel-class device times with HIP events
 };
 
 }  // namespace cp
@@ -109,6 +117,11 @@ struct cylpoisson_plan {
     long long workspace_bytes = 0;
 
     cylpoisson_stats stats{};
+
+    // timing events: pairs (start, stop) and the kernel class of each pair
+    std::vector<hipEvent_t> events;
+    std::vector<int> event_class;
+    int events_used = 0;
 };
 
 namespace cp {
@@ -141,6 +154,13 @@ hipError_t launch_plane_norms(const DeviceLevel& L, int nt, const double* r, dou
                               double* norms_out, hipStream_t s);
 hipError_t launch_apply(const DeviceLevel& L, int nt, const double* lam, const double* u,
                         const double* inv_s, double* out, hipStream_t s);
-hipError_t launch_scan_nonfinite(const double* x, long long n, double* flag, hipStream_t s);
+hipError_t launch_norm_final(const double* partial, int nb, int nt, double* out, hipStream_t s);
+hipError_t launch_copy_ring(const DeviceLevel& L, int nt, const double* src, double* dst,
+                            hipStream_t s);
+
+// ---- fused passes (fused.hip) ----
+bool fused_supported(const cylpoisson_plan* p, int l);
+hipError_t fused_down(cylpoisson_plan* p, int l, bool zero_u, hipStream_t s);
+hipError_t fused_up(cylpoisson_plan* p, int l, double* partial, int* nchunks, hipStream_t s);
 
 }  // namespace cp

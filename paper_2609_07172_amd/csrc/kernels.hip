@@ -123,17 +123,14 @@ __global__ void __launch_bounds__(256) k_restrict(LevelView vf, LevelView vc, Tr
     const int p = blockIdx.z;
     if (I > vc.nr - 2 || K > vc.nz - 2) return;
     const int fi = tr.cidx[I], fk = tz.cidx[K];
-    const double wr[3] = {tr.rwm[I], 1.0, tr.rwp[I]};
-    const double wz[3] = {tz.rwm[K], 1.0, tz.rwp[K]};
-    const double* rp = r + (long long)p * vf.pstride;
-    double s = 0.0;
+    const double* rp = r + (long long)p * vf.pstride + (long long)fk * vf.pitch + fi;
+    const double wzm = tz.rwm[K], wzp = tz.rwp[K];
+    double col[3];
 #pragma unroll
-    for (int b = 0; b < 3; ++b) {
-        const double* row = rp + (long long)(fk + b - 1) * vf.pitch + fi;
-        const double t = wr[0] * row[-1] + row[0] + wr[2] * row[1];
-        s = fma(wz[b], t, s);
-    }
-    fc[(long long)p * vc.pstride + (long long)K * vc.pitch + I] = s;
+    for (int a = 0; a < 3; ++a)
+        col[a] = restrict3(rp[a - 1 - vf.pitch], rp[a - 1], rp[a - 1 + vf.pitch], wzm, wzp);
+    fc[(long long)p * vc.pstride + (long long)K * vc.pitch + I] =
+        restrict3(col[0], col[1], col[2], tr.rwm[I], tr.rwp[I]);
 }
 
 // ------------------------------------------------------------ prolongation
@@ -237,6 +234,25 @@ __global__ void __launch_bounds__(256) k_apply(LevelView v, const double* __rest
     out[o] = apply_row(u[o], u[o - 1], u[o + 1], u[o - v.pitch], u[o + v.pitch], c) * inv_s[i];
 }
 
+// Copy the Dirichlet ring (boundary rows and columns) of every plane.
+__global__ void k_copy_ring(LevelView v, const double* __restrict__ src, double* __restrict__ dst) {
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;  // index along the ring
+    const int p = blockIdx.y;
+    const int n_rows = 2 * v.nr, n_cols = 2 * (v.nz - 2);
+    if (q >= n_rows + n_cols) return;
+    int i, k;
+    if (q < n_rows) {
+        i = q % v.nr;
+        k = q < v.nr ? 0 : v.nz - 1;
+    } else {
+        const int c = q - n_rows;
+        k = 1 + c % (v.nz - 2);
+        i = c < v.nz - 2 ? 0 : v.nr - 1;
+    }
+    const long long o = (long long)p * v.pstride + (long long)k * v.pitch + i;
+    dst[o] = src[o];
+}
+
 dim3 grid_interior(const LevelView& v, int nt, int xdiv = 1) {
     const int ni = (v.nr - 2 + xdiv - 1) / xdiv, nk = v.nz - 2;
     return dim3((ni + kTx - 1) / kTx, (nk + kTy - 1) / kTy, nt);
@@ -314,6 +330,18 @@ hipError_t launch_plane_norms(const DeviceLevel& L, int nt, const double* r, dou
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     k_norm_final<<<(nt + 63) / 64, 64, 0, s>>>(partial, nb, nt, norms_out);
+    return hipGetLastError();
+}
+
+hipError_t launch_norm_final(const double* partial, int nb, int nt, double* out, hipStream_t s) {
+    k_norm_final<<<(nt + 63) / 64, 64, 0, s>>>(partial, nb, nt, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_copy_ring(const DeviceLevel& L, int nt, const double* src, double* dst,
+                            hipStream_t s) {
+    const int n = 2 * L.v.nr + 2 * (L.v.nz - 2);
+    k_copy_ring<<<dim3((n + 255) / 256, nt), 256, 0, s>>>(L.v, src, dst);
     return hipGetLastError();
 }
 

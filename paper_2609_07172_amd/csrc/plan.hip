@@ -151,6 +151,8 @@ hipError_t upload(cylpoisson_plan* p, T** out, const std::vector<T>& host) {
 }
 
 void free_plan(cylpoisson_plan* p) {
+    for (hipEvent_t e : p->events) (void)hipEventDestroy(e);
+    p->events.clear();
     for (void* ptr : p->allocations) (void)hipFree(ptr);
     p->allocations.clear();
     if (p->h_norms) (void)hipHostFree(p->h_norms);
@@ -384,11 +386,30 @@ cylpoisson_plan* cylpoisson_plan_create(int Nr, int Ntheta, int Nz, double r_in,
             D.v.pad_ = 0;
             D.v.pstride = pstride;
             CP_TRY(dev_alloc(p, &D.u, n));
+            CP_TRY(dev_alloc(p, &D.u2, n));
             CP_TRY(dev_alloc(p, &D.f, n));
             CP_TRY(dev_alloc(p, &D.r, n));
             CP_TRY(hipMemset(D.u, 0, n * sizeof(double)));
+            CP_TRY(hipMemset(D.u2, 0, n * sizeof(double)));
             CP_TRY(hipMemset(D.f, 0, n * sizeof(double)));
             CP_TRY(hipMemset(D.r, 0, n * sizeof(double)));
+            {
+                // The fused passes use one set of axial coefficients for every
+                // row below spec_lo (the first row whose coefficients differ from
+                // those of row 1; coarsening only makes the last intervals
+                // irregular) and the exact per-row tables from there on.
+                D.spec_lo = H.nz - 1;
+                if (H.nz >= 3) {
+                    D.zc0 = H.zc[1];
+                    D.zs0 = H.zs[1];
+                    D.zn0 = H.zn[1];
+                    for (int k = 1; k + 1 < H.nz; ++k)
+                        if (!(H.zc[k] == D.zc0 && H.zs[k] == D.zs0 && H.zn[k] == D.zn0)) {
+                            D.spec_lo = k;
+                            break;
+                        }
+                }
+            }
             double *rw, *re, *rb, *rm, *zc, *zs, *zn;
             CP_TRY(upload(p, &rw, H.rw));
             CP_TRY(upload(p, &re, H.re));
@@ -421,6 +442,16 @@ cylpoisson_plan* cylpoisson_plan_create(int Nr, int Ntheta, int Nz, double r_in,
                 CP_TRY(upload(p, &w8, H.rwp_z));
                 D.tr = Transfer1D{a, w1, w2, b, w3, w4};
                 D.tz = Transfer1D{c, w5, w6, d, w7, w8};
+                // fine column / row -> coincident coarse interior index (or -1)
+                const HostLevel& Hc = p->hl[l + 1];
+                std::vector<int> colc(H.nr, -1), rowc(H.nz, -1);
+                for (int I = 1; I + 1 < Hc.nr; ++I) colc[H.cidx_r[I]] = I;
+                for (int K = 1; K + 1 < Hc.nz; ++K) rowc[H.cidx_z[K]] = K;
+                int *cc, *rc;
+                CP_TRY(upload(p, &cc, colc));
+                CP_TRY(upload(p, &rc, rowc));
+                D.colc = cc;
+                D.rowc = rc;
             }
         }
         std::vector<double> F, G;
@@ -484,6 +515,9 @@ int cylpoisson_plan_set_option(cylpoisson_plan* plan, const char* key, double va
     if (!std::strcmp(key, "max_cycles")) return int_in(1, CYLPOISSON_MAX_HISTORY, &plan->opt.max_cycles);
     if (!std::strcmp(key, "check_every")) return int_in(1, 64, &plan->opt.check_every);
     if (!std::strcmp(key, "fused")) return int_in(0, 1, &plan->opt.fused);
+    if (!std::strcmp(key, "chunk_rows")) return int_in(0, 1 << 20, &plan->opt.chunk_rows);
+    if (!std::strcmp(key, "timing")) return int_in(0, 1, &plan->opt.timing);
+    if (!std::strcmp(key, "prefetch")) return int_in(1, 4, &plan->opt.prefetch);
     if (!std::strcmp(key, "omega")) {
         if (!(value > 0.0 && value < 2.0)) {
             set_error("omega must lie in (0, 2)");

@@ -8,9 +8,6 @@
 
 namespace cp {
 
-// fused.hip
-hipError_t vcycle_fused_top(cylpoisson_plan* p, int level, hipStream_t s, bool* handled);
-
 namespace {
 
 struct DeviceGuard {
@@ -86,7 +83,55 @@ double weighted(const cylpoisson_plan* p, const double* norms) {
     return s;
 }
 
+// HIP events around a launch (or a group of launches) of one kernel class,
+// recorded on the solve's stream when the option "timing" is set.
+class Timed {
+  public:
+    Timed(cylpoisson_plan* p, int cls, hipStream_t s) : p_(p), s_(s) {
+        if (!p->opt.timing || cls < 0) return;
+        const int need = 2 * (p->events_used + 1);
+        while ((int)p->events.size() < need) {
+            hipEvent_t e;
+            if (hipEventCreate(&e) != hipSuccess) {
+                (void)hipGetLastError();
+                return;
+            }
+            p->events.push_back(e);
+        }
+        idx_ = p->events_used++;
+        if ((int)p->event_class.size() <= idx_) p->event_class.resize(idx_ + 1);
+        p->event_class[idx_] = cls;
+        (void)hipEventRecord(p->events[2 * idx_], s);
+    }
+    ~Timed() {
+        if (idx_ >= 0) (void)hipEventRecord(p_->events[2 * idx_ + 1], s_);
+    }
+
+  private:
+    cylpoisson_plan* p_;
+    hipStream_t s_;
+    int idx_ = -1;
+};
+
+enum { kDftFwd = 0, kDftInv = 1, kFineDown = 2, kFineUp = 3, kCoarse = 4, kOther = 5 };
+
+// After the stream has drained: fold the recorded event pairs into the stats.
+void collect_timing(cylpoisson_plan* p) {
+    for (int i = 0; i < p->events_used; ++i) {
+        float ms = 0.0f;
+        if (hipEventElapsedTime(&ms, p->events[2 * i], p->events[2 * i + 1]) == hipSuccess) {
+            const int c = p->event_class[i];
+            p->stats.kernel_launches[c] += 1;
+            p->stats.kernel_ms[c] += ms;
+        } else {
+            (void)hipGetLastError();
+        }
+    }
+    p->events_used = 0;
+}
+
 hipError_t residual_norms(cylpoisson_plan* p, int slot, hipStream_t s) {
+    Timed tm(p, kOther, s);
     DeviceLevel& L = p->dl[0];
     hipError_t e = launch_residual(L, p->nt, p->d_lam, L.u, L.f, L.r, s);
     if (e != hipSuccess) return e;
@@ -102,32 +147,73 @@ hipError_t smooth(cylpoisson_plan* p, DeviceLevel& L, int sweeps, hipStream_t s)
     return hipSuccess;
 }
 
-hipError_t vcycle(cylpoisson_plan* p, int l, hipStream_t s) {
+// One V-cycle from level l.  On levels l > 0 the iterate starts at zero; on
+// level 0 `zero_top` says its interior is still zero (first cycle).  If
+// `norms` is given and level 0 runs the fused passes, the up pass also
+// produces the per-plane squared residual norms there (and *norms_done is set).
+hipError_t vcycle(cylpoisson_plan* p, int l, hipStream_t s, bool zero_top, double* norms,
+                  bool* norms_done) {
     const int nl = (int)p->dl.size();
     DeviceLevel& L = p->dl[l];
-    if (l == nl - 1)
-        return launch_coarse_solve(L, p->nt, p->d_lam, p->d_cinv, p->coarse_n, L.f, L.u, s);
-    if (p->opt.fused) {
-        bool handled = false;
-        hipError_t e = vcycle_fused_top(p, l, s, &handled);
-        if (handled || e != hipSuccess) return e;
+    hipError_t e = hipSuccess;
+    if (l == nl - 1) {
+        if (l > 0) e = launch_zero_interior(L, p->nt, L.u, s);
+        if (e == hipSuccess)
+            e = launch_coarse_solve(L, p->nt, p->d_lam, p->d_cinv, p->coarse_n, L.f, L.u, s);
+        return e;
     }
     DeviceLevel& C = p->dl[l + 1];
-    hipError_t e = smooth(p, L, p->opt.nu1, s);
-    if (e == hipSuccess) e = launch_residual(L, p->nt, p->d_lam, L.u, L.f, L.r, s);
-    if (e == hipSuccess) e = launch_restrict(L, C, p->nt, L.r, C.f, s);
-    if (e == hipSuccess) e = launch_zero_interior(C, p->nt, C.u, s);
-    if (e == hipSuccess) e = vcycle(p, l + 1, s);
-    if (e == hipSuccess) e = launch_prolong(L, C, p->nt, C.u, L.u, s);
-    if (e == hipSuccess) e = smooth(p, L, p->opt.nu2, s);
+    if (fused_supported(p, l)) {
+        {
+            Timed tm(p, l == 0 ? kFineDown : -1, s);
+            // coarser levels start from a zero iterate with a zero ring
+            e = fused_down(p, l, l > 0, s);
+        }
+        if (e == hipSuccess) {
+            Timed tm(p, l == 0 ? kCoarse : -1, s);
+            e = vcycle(p, l + 1, s, true, nullptr, nullptr);
+        }
+        const bool want = l == 0 && norms != nullptr;
+        int nch = 0;
+        if (e == hipSuccess) {
+            Timed tm(p, l == 0 ? kFineUp : -1, s);
+            e = fused_up(p, l, want ? p->d_partial : nullptr, &nch, s);
+        }
+        if (e == hipSuccess && want) {
+            Timed tm(p, kOther, s);
+            e = launch_norm_final(p->d_partial, nch, p->nt, norms, s);
+            if (e == hipSuccess) *norms_done = true;
+        }
+        return e;
+    }
+    if (l > 0) e = launch_zero_interior(L, p->nt, L.u, s);
+    {
+        Timed tm(p, l == 0 ? kFineDown : -1, s);
+        if (e == hipSuccess) e = smooth(p, L, p->opt.nu1, s);
+        if (e == hipSuccess) e = launch_residual(L, p->nt, p->d_lam, L.u, L.f, L.r, s);
+        if (e == hipSuccess) e = launch_restrict(L, C, p->nt, L.r, C.f, s);
+    }
+    if (e == hipSuccess) {
+        Timed tm(p, l == 0 ? kCoarse : -1, s);
+        e = vcycle(p, l + 1, s, true, nullptr, nullptr);
+    }
+    {
+        Timed tm(p, l == 0 ? kFineUp : -1, s);
+        if (e == hipSuccess) e = launch_prolong(L, C, p->nt, C.u, L.u, s);
+        if (e == hipSuccess) e = smooth(p, L, p->opt.nu2, s);
+    }
     return e;
+}
+
+void reset_stats(cylpoisson_plan* p) {
+    std::memset(&p->stats, 0, sizeof p->stats);
+    for (double& h : p->stats.rel_residual_history) h = NAN;
+    p->events_used = 0;
 }
 
 // V-cycles on the level-0 planes (f and u with its Dirichlet ring already set).
 int run_cycles(cylpoisson_plan* p, double tol, hipStream_t s) {
     cylpoisson_stats& st = p->stats;
-    std::memset(&st, 0, sizeof st);
-    for (double& h : st.rel_residual_history) h = NAN;
     const int nt = p->nt;
 
     CP_HIP(residual_norms(p, 0, s));
@@ -154,8 +240,9 @@ int run_cycles(cylpoisson_plan* p, double tol, hipStream_t s) {
     int status = CYLPOISSON_NOT_CONVERGED;
     int stagnant = 0;
     for (int c = 1; c <= maxc; ++c) {
-        CP_HIP(vcycle(p, 0, s));
-        CP_HIP(residual_norms(p, c, s));
+        bool norms_done = false;
+        CP_HIP(vcycle(p, 0, s, c == 1, p->d_norms + (size_t)c * nt, &norms_done));
+        if (!norms_done) CP_HIP(residual_norms(p, c, s));
         st.cycles = c;
         if (c != next_check && c != maxc) continue;
         const int first = last_read + 1;
@@ -237,13 +324,27 @@ int cylpoisson_solve(cylpoisson_plan* p, const double* rho, double* phi, double 
     hipStream_t s = static_cast<hipStream_t>(stream);
     DeviceLevel& L = p->dl[0];
     const long long ncols = (long long)p->nz * p->nr;
+    reset_stats(p);
     // f_p = s_i * (F rho)_p  (Eqs. azimuthal_dft, mode_rhs); the Dirichlet data
     // enter through the ring of plane 0 of u.
-    CP_HIP(launch_dft(p->d_F, rho, L.f, p->nt, ncols, p->d_s, p->nr, s));
-    CP_HIP(launch_init_fine_u(L, p->nt, p->bc, s));
+    {
+        Timed tm(p, kDftFwd, s);
+        CP_HIP(launch_dft(p->d_F, rho, L.f, p->nt, ncols, p->d_s, p->nr, s));
+    }
+    {
+        Timed tm(p, kOther, s);
+        CP_HIP(launch_init_fine_u(L, p->nt, p->bc, s));
+        CP_HIP(launch_copy_ring(L, p->nt, L.u, L.u2, s));
+    }
     const int status = run_cycles(p, tol, s);
-    if (status == CYLPOISSON_OK || status == CYLPOISSON_NOT_CONVERGED)
+    if (status == CYLPOISSON_OK || status == CYLPOISSON_NOT_CONVERGED) {
+        Timed tm(p, kDftInv, s);
         CP_HIP(launch_dft(p->d_G, L.u, phi, p->nt, ncols, nullptr, p->nr, s));
+    }
+    if (p->opt.timing) {
+        CP_HIP(hipStreamSynchronize(s));
+        collect_timing(p);
+    }
     return status;
 }
 
@@ -263,10 +364,16 @@ int cylpoisson_solve_planes(cylpoisson_plan* p, const double* b, double* u, doub
     if (st != CYLPOISSON_OK) return p->stats.status = st;
     hipStream_t s = static_cast<hipStream_t>(stream);
     DeviceLevel& L = p->dl[0];
+    reset_stats(p);
     CP_HIP(hipMemcpyAsync(L.f, b, bytes, hipMemcpyDeviceToDevice, s));
     CP_HIP(hipMemcpyAsync(L.u, u, bytes, hipMemcpyDeviceToDevice, s));
     CP_HIP(launch_zero_interior(L, p->nt, L.u, s));
+    CP_HIP(launch_copy_ring(L, p->nt, L.u, L.u2, s));
     const int status = run_cycles(p, tol, s);
+    if (p->opt.timing) {
+        CP_HIP(hipStreamSynchronize(s));
+        collect_timing(p);
+    }
     if (status == CYLPOISSON_OK || status == CYLPOISSON_NOT_CONVERGED)
         CP_HIP(launch_copy_interior(L, p->nt, L.u, u, s));
     return status;

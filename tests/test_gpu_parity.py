@@ -250,3 +250,35 @@ def test_paper_scale_matches_separable_oracle(P):
     assert rel_l2(got, ref) <= 1e-12, rel_l2(got, ref)
     assert rel_l2(got, phit) <= 1e-12
     check_boundary(got, p)
+
+
+# -------------------------------------------------- fused vs per-step path
+@pytest.mark.parametrize("shape", [(33, 16, 33), (40, 8, 37), (129, 8, 129), (26, 3, 71)])
+def test_fused_passes_match_per_step_kernels(P, shape):
+    """The fused streaming passes run the same red-black schedule and point arithmetic as the
+    one-kernel-per-step path, so the two solutions agree (bitwise where every level is fused)."""
+    nr, nt, nz = shape
+    p = W.SMALL.with_sizes(nr, nt, nz)
+    rho = dev(W.blob_charge(p, seed=nr + nz))
+    say("fused-vs-step", shape)
+    a = P.Plan.for_problem(p, fused=1, max_cycles=6)
+    b = P.Plan.for_problem(p, fused=0, max_cycles=6)
+    pa, sa = a.solve(rho, tol=1e-30, allow=(P.OK, P.NOT_CONVERGED))
+    pb, sb = b.solve(rho, tol=1e-30, allow=(P.OK, P.NOT_CONVERGED))
+    ha, hb = host(pa), host(pb)
+    assert sa["cycles"] == sb["cycles"] == 6
+    assert rel_l2(ha, hb) <= 1e-14, rel_l2(ha, hb)
+    np.testing.assert_allclose(sa["history"][:6], sb["history"][:6], rtol=1e-9)
+
+
+@pytest.mark.parametrize("chunk", [1, 5, 16, 1000])
+def test_fused_chunking_is_exact(P, chunk):
+    """Chunk boundaries (axial halos recomputed per workgroup) do not change the result."""
+    p = W.SMALL.with_sizes(45, 8, 61)
+    rho = dev(W.blob_charge(p, seed=4))
+    say("chunk", chunk)
+    ref_plan = P.Plan.for_problem(p, fused=0, max_cycles=3)
+    r, _ = ref_plan.solve(rho, tol=1e-30, allow=(P.OK, P.NOT_CONVERGED))
+    plan = P.Plan.for_problem(p, chunk_rows=chunk, max_cycles=3)
+    x, _ = plan.solve(rho, tol=1e-30, allow=(P.OK, P.NOT_CONVERGED))
+    assert rel_l2(host(x), host(r)) <= 1e-14
