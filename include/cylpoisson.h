@@ -94,6 +94,7 @@ typedef struct {
     int level_nr[CYLPOISSON_MAX_LEVELS];    /* nodes per level, incl. the ring */
     int level_nz[CYLPOISSON_MAX_LEVELS];
     int coarse_unknowns;                    /* interior nodes of the coarsest plane */
+    int bottom_level;                       /* first level run by the LDS bottom kernel, -1 if none */
     long long workspace_bytes;              /* device memory owned by the plan */
     int device;                             /* HIP device ordinal */
 } cylpoisson_info;
@@ -121,6 +122,10 @@ void cylpoisson_plan_destroy(cylpoisson_plan* plan);
  *   "chunk_rows"     axial rows per workgroup of the fused passes (0 = automatic)
  *   "prefetch"       rows the fused passes load ahead of the one they consume (1 .. 4; default 3)
  *   "timing"         1 = record per-kernel-class device times (cylpoisson_stats)
+ *   "bottom"         1 = run the small levels of each plane in one LDS-resident
+ *                    kernel (with "fused" = 1; default 1)
+ *   "fft"            1 = azimuthal transforms as register FFTs when Ntheta is 16,
+ *                    32, 64 or 128; 0 = dense DFT product (default 1)
  * Returns CYLPOISSON_OK or CYLPOISSON_EINVAL. */
 int cylpoisson_plan_set_option(cylpoisson_plan* plan, const char* key, double value);
 

@@ -67,12 +67,13 @@ class Info(ctypes.Structure):
     _fields_ = [("nr", ctypes.c_int), ("ntheta", ctypes.c_int), ("nz", ctypes.c_int),
                 ("levels", ctypes.c_int), ("level_nr", ctypes.c_int * MAX_LEVELS),
                 ("level_nz", ctypes.c_int * MAX_LEVELS), ("coarse_unknowns", ctypes.c_int),
+                ("bottom_level", ctypes.c_int),
                 ("workspace_bytes", ctypes.c_longlong), ("device", ctypes.c_int)]
 
     def as_dict(self) -> dict:
         return {"nr": self.nr, "ntheta": self.ntheta, "nz": self.nz, "levels": self.levels,
                 "level_shapes": [(self.level_nr[i], self.level_nz[i]) for i in range(self.levels)],
-                "coarse_unknowns": self.coarse_unknowns,
+                "coarse_unknowns": self.coarse_unknowns, "bottom_level": self.bottom_level,
                 "workspace_bytes": self.workspace_bytes, "device": self.device}
 
 

@@ -67,6 +67,14 @@ struct DeviceLevel {
     double zc0 = 0, zs0 = 0, zn0 = 0;
 };
 
+// A level handled by the bottom kernel: its global tables and where its
+// iterate and right-hand side live in LDS (full node arrays, pitch nr).
+struct BottomLevel {
+    LevelView v;
+    Transfer1D tr, tz;
+    int off_u, off_f;
+};
+
 struct HostLevel {
     int nr = 0, nz = 0, pitch = 0;
     std::vector<double> r, z;                 // node coordinates
@@ -86,6 +94,8 @@ struct Options {
     int chunk_rows = 0;  // rows per workgroup in the fused passes (0 = automatic)
     int prefetch = 3;    // rows the fused passes load ahead of the row they consume
     int timing = 0;      // record per-kernel-class device times with HIP events
+    int bottom = 1;      // run the small levels in one LDS-resident kernel per plane
+    int fft = 1;         // azimuthal transforms as register FFTs where Ntheta allows
 };
 
 }  // namespace cp
@@ -106,6 +116,7 @@ struct cylpoisson_plan {
     double* d_lam = nullptr;
     double* d_F = nullptr;       // forward DFT matrix [N][N]
     double* d_G = nullptr;       // inverse DFT matrix [N][N]
+    double* d_tw = nullptr;      // (cos, sin)(2 pi k / N), k < N, for the register FFTs
     double* d_s = nullptr;       // s_i = r_i dr dz / eps0, per radial node (fine level)
     double* d_inv_s = nullptr;   // 1 / s_i (0 on the ring)
     double* d_cinv = nullptr;    // coarsest-level inverse per plane [N][n][n]
@@ -113,6 +124,9 @@ struct cylpoisson_plan {
     double* d_norms = nullptr;   // per-plane squared norms [slots][N]
     double* h_norms = nullptr;   // pinned host copy
     double* d_tmp = nullptr;     // node-array scratch (apply, plane solves)
+    int bottom_level = -1;       // first level of the LDS bottom kernel (-1 = none)
+    int bottom_off_r = 0;
+    cp::BottomLevel* d_bottom = nullptr;
     std::vector<void*> allocations;
     long long workspace_bytes = 0;
 
@@ -157,6 +171,16 @@ hipError_t launch_apply(const DeviceLevel& L, int nt, const double* lam, const d
 hipError_t launch_norm_final(const double* partial, int nb, int nt, double* out, hipStream_t s);
 hipError_t launch_copy_ring(const DeviceLevel& L, int nt, const double* src, double* dst,
                             hipStream_t s);
+
+// ---- register FFTs (fft.hip) ----
+bool fft_supported(int n);
+hipError_t launch_fft(bool inverse, int n, const double* in, double* out, long long ncols,
+                      const double* cs, int nr, const double* tw, hipStream_t s);
+
+// ---- bottom of the V-cycle (bottom.hip) ----
+size_t bottom_lds_bytes(const cylpoisson_plan* p, int lb);
+hipError_t bottom_prepare(const cylpoisson_plan* p, int lb);
+hipError_t launch_bottom(cylpoisson_plan* p, hipStream_t s);
 
 // ---- fused passes (fused.hip) ----
 bool fused_supported(const cylpoisson_plan* p, int l);

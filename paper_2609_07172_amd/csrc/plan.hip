@@ -14,6 +14,7 @@ namespace cp {
 namespace {
 thread_local char g_err[512] = "";
 constexpr int kCoarseMax = 64;  // stop coarsening once a plane has this few unknowns
+constexpr size_t kBottomLdsBytes = 150 * 1024;  // LDS budget of the bottom kernel
 }  // namespace
 
 void set_error(const char* fmt, ...) {
@@ -454,10 +455,44 @@ cylpoisson_plan* cylpoisson_plan_create(int Nr, int Ntheta, int Nz, double r_in,
                 D.rowc = rc;
             }
         }
+        // the bottom kernel: the first level from 1 on whose levels all fit in LDS
+        for (int lb = 1; lb < nl; ++lb) {
+            if (bottom_lds_bytes(p, lb) > kBottomLdsBytes) continue;
+            if (bottom_prepare(p, lb) != hipSuccess) {
+                (void)hipGetLastError();
+                continue;
+            }
+            std::vector<BottomLevel> bl;
+            int off = 0;
+            for (int l = lb; l < nl; ++l) {
+                BottomLevel b{};
+                b.v = p->dl[l].v;
+                b.tr = p->dl[l].tr;
+                b.tz = p->dl[l].tz;
+                b.off_u = off;
+                off += p->hl[l].nr * p->hl[l].nz;
+                b.off_f = off;
+                off += p->hl[l].nr * p->hl[l].nz;
+                bl.push_back(b);
+            }
+            p->bottom_off_r = off;
+            CP_TRY(upload(p, &p->d_bottom, bl));
+            p->bottom_level = lb;
+            break;
+        }
         std::vector<double> F, G;
         dft_matrices(Ntheta, F, G);
         CP_TRY(upload(p, &p->d_F, F));
         CP_TRY(upload(p, &p->d_G, G));
+        {
+            std::vector<double> tw(2 * (size_t)Ntheta);
+            for (int k = 0; k < Ntheta; ++k) {
+                const long double a = 2.0L * 3.14159265358979323846264338327950288L * k / Ntheta;
+                tw[2 * k] = (double)cosl(a);
+                tw[2 * k + 1] = (double)sinl(a);
+            }
+            CP_TRY(upload(p, &p->d_tw, tw));
+        }
         CP_TRY(upload(p, &p->d_lam, p->lam));
         std::vector<double> s(Nr, 0.0), inv_s(Nr, 0.0);
         const HostLevel& H0 = p->hl[0];
@@ -518,6 +553,8 @@ int cylpoisson_plan_set_option(cylpoisson_plan* plan, const char* key, double va
     if (!std::strcmp(key, "chunk_rows")) return int_in(0, 1 << 20, &plan->opt.chunk_rows);
     if (!std::strcmp(key, "timing")) return int_in(0, 1, &plan->opt.timing);
     if (!std::strcmp(key, "prefetch")) return int_in(1, 4, &plan->opt.prefetch);
+    if (!std::strcmp(key, "bottom")) return int_in(0, 1, &plan->opt.bottom);
+    if (!std::strcmp(key, "fft")) return int_in(0, 1, &plan->opt.fft);
     if (!std::strcmp(key, "omega")) {
         if (!(value > 0.0 && value < 2.0)) {
             set_error("omega must lie in (0, 2)");
@@ -554,6 +591,7 @@ int cylpoisson_get_info(const cylpoisson_plan* plan, cylpoisson_info* out) {
         out->level_nz[l] = plan->hl[l].nz;
     }
     out->coarse_unknowns = plan->coarse_n;
+    out->bottom_level = plan->bottom_level;
     out->workspace_bytes = plan->workspace_bytes;
     out->device = plan->device;
     return CYLPOISSON_OK;

@@ -162,6 +162,7 @@ hipError_t vcycle(cylpoisson_plan* p, int l, hipStream_t s, bool zero_top, doubl
             e = launch_coarse_solve(L, p->nt, p->d_lam, p->d_cinv, p->coarse_n, L.f, L.u, s);
         return e;
     }
+    if (l > 0 && l == p->bottom_level && p->opt.bottom && p->opt.fused) return launch_bottom(p, s);
     DeviceLevel& C = p->dl[l + 1];
     if (fused_supported(p, l)) {
         {
@@ -203,6 +204,17 @@ hipError_t vcycle(cylpoisson_plan* p, int l, hipStream_t s, bool zero_top, doubl
         if (e == hipSuccess) e = smooth(p, L, p->opt.nu2, s);
     }
     return e;
+}
+
+// Azimuthal transform of node/plane arrays: register FFT where supported,
+// dense DFT product otherwise.  colscale (forward only) multiplies column c by
+// colscale[c % Nr].
+hipError_t transform(cylpoisson_plan* p, bool inverse, const double* in, double* out,
+                     const double* colscale, hipStream_t s) {
+    const long long ncols = (long long)p->nz * p->nr;
+    if (p->opt.fft && fft_supported(p->nt))
+        return launch_fft(inverse, p->nt, in, out, ncols, colscale, p->nr, p->d_tw, s);
+    return launch_dft(inverse ? p->d_G : p->d_F, in, out, p->nt, ncols, colscale, p->nr, s);
 }
 
 void reset_stats(cylpoisson_plan* p) {
@@ -323,13 +335,12 @@ int cylpoisson_solve(cylpoisson_plan* p, const double* rho, double* phi, double 
     }
     hipStream_t s = static_cast<hipStream_t>(stream);
     DeviceLevel& L = p->dl[0];
-    const long long ncols = (long long)p->nz * p->nr;
     reset_stats(p);
     // f_p = s_i * (F rho)_p  (Eqs. azimuthal_dft, mode_rhs); the Dirichlet data
     // enter through the ring of plane 0 of u.
     {
         Timed tm(p, kDftFwd, s);
-        CP_HIP(launch_dft(p->d_F, rho, L.f, p->nt, ncols, p->d_s, p->nr, s));
+        CP_HIP(transform(p, false, rho, L.f, p->d_s, s));
     }
     {
         Timed tm(p, kOther, s);
@@ -339,7 +350,7 @@ int cylpoisson_solve(cylpoisson_plan* p, const double* rho, double* phi, double 
     const int status = run_cycles(p, tol, s);
     if (status == CYLPOISSON_OK || status == CYLPOISSON_NOT_CONVERGED) {
         Timed tm(p, kDftInv, s);
-        CP_HIP(launch_dft(p->d_G, L.u, phi, p->nt, ncols, nullptr, p->nr, s));
+        CP_HIP(transform(p, true, L.u, phi, nullptr, s));
     }
     if (p->opt.timing) {
         CP_HIP(hipStreamSynchronize(s));
@@ -391,10 +402,9 @@ int cylpoisson_apply(cylpoisson_plan* p, const double* phi, double* rho_out, voi
     if (st != CYLPOISSON_OK) return st;
     hipStream_t s = static_cast<hipStream_t>(stream);
     DeviceLevel& L = p->dl[0];
-    const long long ncols = (long long)p->nz * p->nr;
-    CP_HIP(launch_dft(p->d_F, phi, L.r, p->nt, ncols, nullptr, p->nr, s));
+    CP_HIP(transform(p, false, phi, L.r, nullptr, s));
     CP_HIP(launch_apply(L, p->nt, p->d_lam, L.r, p->d_inv_s, p->d_tmp, s));
-    CP_HIP(launch_dft(p->d_G, p->d_tmp, rho_out, p->nt, ncols, nullptr, p->nr, s));
+    CP_HIP(transform(p, true, p->d_tmp, rho_out, nullptr, s));
     // the residual scratch must keep a zero ring for the solver
     CP_HIP(launch_zero(L.r, (long long)p->nt * L.v.pstride, s));
     return CYLPOISSON_OK;
@@ -416,8 +426,7 @@ int cylpoisson_dft_forward(cylpoisson_plan* p, const double* x, double* planes, 
         set_error("x and planes overlap");
         return CYLPOISSON_EINVAL;
     }
-    CP_HIP(launch_dft(p->d_F, x, planes, p->nt, (long long)p->nz * p->nr, nullptr, p->nr,
-                      static_cast<hipStream_t>(stream)));
+    CP_HIP(transform(p, false, x, planes, nullptr, static_cast<hipStream_t>(stream)));
     return CYLPOISSON_OK;
 }
 
@@ -437,8 +446,7 @@ int cylpoisson_dft_inverse(cylpoisson_plan* p, const double* planes, double* x, 
         set_error("planes and x overlap");
         return CYLPOISSON_EINVAL;
     }
-    CP_HIP(launch_dft(p->d_G, planes, x, p->nt, (long long)p->nz * p->nr, nullptr, p->nr,
-                      static_cast<hipStream_t>(stream)));
+    CP_HIP(transform(p, true, planes, x, nullptr, static_cast<hipStream_t>(stream)));
     return CYLPOISSON_OK;
 }
 

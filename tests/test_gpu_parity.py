@@ -282,3 +282,19 @@ def test_fused_chunking_is_exact(P, chunk):
     plan = P.Plan.for_problem(p, chunk_rows=chunk, max_cycles=3)
     x, _ = plan.solve(rho, tol=1e-30, allow=(P.OK, P.NOT_CONVERGED))
     assert rel_l2(host(x), host(r)) <= 1e-14
+
+
+@pytest.mark.parametrize("shape", [(129, 8, 129), (65, 5, 97), (401, 4, 65)])
+def test_bottom_kernel_matches_level_by_level(P, shape):
+    """The LDS bottom kernel (all small levels of a plane in one workgroup) runs the same
+    V-cycle as the level-by-level kernels."""
+    nr, nt, nz = shape
+    p = W.SMALL.with_sizes(nr, nt, nz)
+    rho = dev(W.blob_charge(p, seed=nt))
+    say("bottom", shape)
+    a = P.Plan.for_problem(p, bottom=1, max_cycles=4)
+    b = P.Plan.for_problem(p, bottom=0, max_cycles=4)
+    assert a.info()["bottom_level"] >= 1
+    pa, sa = a.solve(rho, tol=1e-30, allow=(P.OK, P.NOT_CONVERGED))
+    pb, sb = b.solve(rho, tol=1e-30, allow=(P.OK, P.NOT_CONVERGED))
+    assert rel_l2(host(pa), host(pb)) <= 1e-14
