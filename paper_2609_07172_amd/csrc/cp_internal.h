@@ -91,8 +91,9 @@ struct Options {
     int max_cycles = 40;
     int check_every = 1;
     int fused = 1;
-    int chunk_rows = 0;  // rows per workgroup in the fused passes (0 = automatic)
-    int prefetch = 3;    // rows the fused passes load ahead of the row they consume
+    int chunk_rows = 0;  // rows per workgroup in the finest fused passes (0 = automatic)
+    int chunk_rows_coarse = 0;  // the same on the coarser levels
+    int prefetch = 1;    // rows the fused passes load ahead of the row they consume
     int timing = 0;      // record per-kernel-class device times with HIP events
     int bottom = 1;      // run the small levels in one LDS-resident kernel per plane
     int fft = 1;         // azimuthal transforms as register FFTs where Ntheta allows
@@ -121,6 +122,8 @@ struct cylpoisson_plan {
     double* d_inv_s = nullptr;   // 1 / s_i (0 on the ring)
     double* d_cinv = nullptr;    // coarsest-level inverse per plane [N][n][n]
     double* d_partial = nullptr; // per-plane partial sums [N][kMaxPartial]
+    double* d_slot_partial = nullptr;  // finest up-pass partials per cycle [slots][N][kSlotPartial]
+    double* h_slot_partial = nullptr;  // pinned host copy
     double* d_norms = nullptr;   // per-plane squared norms [slots][N]
     double* h_norms = nullptr;   // pinned host copy
     double* d_tmp = nullptr;     // node-array scratch (apply, plane solves)
@@ -141,6 +144,7 @@ struct cylpoisson_plan {
 namespace cp {
 
 constexpr int kMaxPartial = 256;
+constexpr int kSlotPartial = 64;  // per-slot partial sums kept for the host (chunks per plane)
 constexpr int kNormSlots = CYLPOISSON_MAX_HISTORY + 2;
 
 // Error reporting (thread-local message).
@@ -169,6 +173,9 @@ hipError_t launch_plane_norms(const DeviceLevel& L, int nt, const double* r, dou
 hipError_t launch_apply(const DeviceLevel& L, int nt, const double* lam, const double* u,
                         const double* inv_s, double* out, hipStream_t s);
 hipError_t launch_norm_final(const double* partial, int nb, int nt, double* out, hipStream_t s);
+hipError_t launch_init_ring(const DeviceLevel& L, int nt, const cylpoisson_bc& bc, hipStream_t s);
+hipError_t launch_rhs_norms(const DeviceLevel& L, int nt, const double* lam, const double* u,
+                            const double* f, double* partial, double* norms_out, hipStream_t s);
 hipError_t launch_copy_ring(const DeviceLevel& L, int nt, const double* src, double* dst,
                             hipStream_t s);
 
@@ -184,7 +191,9 @@ hipError_t launch_bottom(cylpoisson_plan* p, hipStream_t s);
 
 // ---- fused passes (fused.hip) ----
 bool fused_supported(const cylpoisson_plan* p, int l);
-hipError_t fused_down(cylpoisson_plan* p, int l, bool zero_u, hipStream_t s);
-hipError_t fused_up(cylpoisson_plan* p, int l, double* partial, int* nchunks, hipStream_t s);
+hipError_t fused_down(cylpoisson_plan* p, int l, bool zero_u, bool zero_interior, hipStream_t s);
+hipError_t fused_up(cylpoisson_plan* p, int l, double* partial, int partial_ld, int* nchunks,
+                    hipStream_t s);
+int fused_chunks(const cylpoisson_plan* p, int l, int nu);
 
 }  // namespace cp

@@ -43,35 +43,46 @@ struct PassArgs {
     const int* rowc;     // fine row -> coarse interior row it coincides with, else -1
     int spec_lo;         // rows >= spec_lo have axial coefficients other than (zc0, zs0, zn0)
     double* partial;     // up: per (plane, chunk) sum of squared residuals, or nullptr
+    int partial_ld;      // stride between planes in `partial`
     double omega, zc0, zs0, zn0;
+    int zero_interior;   // down: treat the interior of the input iterate as zero (ring is read)
     int chunk, nchunks, nt, tn;  // rows per chunk, chunks per plane, planes, columns pairs
     int xcd_major;       // map consecutive chunks of a plane to one XCD
 };
 
 template <int NU, int PD, bool DOWN, bool ZERO_U>
 struct Pass {
-    static constexpr int Q = 2 * NU + 3 + PD;  // register rows: x+PD (prefetch) .. x-2NU-2
-    static constexpr int WL = (2 * NU + 2 <= 8) ? 8 : 16;
+    // Register history: rows x+PD (prefetch) down to x-2NU-2.  Q is even and
+    // the first row s is even, so slot J holds rows of one parity and the
+    // colour of each column in every half-sweep is known at compile time.
+    static constexpr int Q0 = 2 * NU + 3 + PD;
+    static constexpr int Q = (Q0 & 1) ? Q0 + 1 : Q0;
+    static constexpr int QS = Q + 1;  // LDS doubles per column history (odd stride)
 
     const PassArgs& a;
-    double* lds;      // WL rows of S doubles, 2 restriction rows, then per-row data
-    int S, t, c1, c2;
-    bool ex1, ex2, act1, act2;
-    int p, chunk, za, zb, s, lend;
+    double* lds;
+    // LDS layout (doubles): column histories A[tn + 1][QS] (column 2t+1 of thread t)
+    // and B[tn + 1][QS] (column 2j; j = 0 is the radial ring column, j = t + 1 is
+    // column 2t+2 of thread t); restriction rows V[2][2][tn + 1]; per-row tables.
+    double* At;  // own column c1
+    double* Bt;  // own column c2
+    double* Bl;  // column 2t (west of c1)
+    double* Ar;  // column 2t+3 (east of c2)
+    int t, c1, c2, k1, k2;
+    bool act1, act2;
+    int p, chunk, za, zb, s, lend, rows;
     double lam;
     Coef cu1, cu2;
     double rw1, re1, rb1, rm1, rw2, re2, rb2, rm2;  // radial tables of the two columns
-    const double* ubase;
-    const double* fbase;
+    const double* urow;  // row s + ... of the input iterate (advanced per issued row)
+    const double* frow;
     double* obase;
     double uu[Q][2], ff[Q][2];
     double r_m2[2], r_m1[2], r_0[2];
-    // down: coarse columns and their radial restriction weights
-    int I1, I2;
+    int I1, I2;  // down: coincident coarse columns (or -1)
     double wm1, wp1, wm2, wp2;
     int pendK;
-    // up: prolongation columns and weights; coarse row in flight
-    int P1, P2;
+    int P1, P2;  // up: prolongation columns and weights
     double pl1, pr1, pl2, pr2;
     int cK, cnext;
     double cval;
@@ -79,36 +90,39 @@ struct Pass {
 
     __device__ __forceinline__ Pass(const PassArgs& args, double* smem) : a(args), lds(smem) {}
 
-    __device__ __forceinline__ double& A(int slot, int i) { return lds[slot * S + i]; }
-    __device__ __forceinline__ double& B(int slot, int j) { return lds[slot * S + a.tn + 1 + j]; }
-    __device__ __forceinline__ double& V(int buf, int i) { return lds[(WL + buf) * S + i]; }
-    __device__ __forceinline__ double& VB(int buf, int j) { return lds[(WL + buf) * S + a.tn + 1 + j]; }
-    // Per loaded row x (index x - s): radial ring value u(x, 0), then two
-    // weights and an index of the axial transfer (down: coincident coarse row
-    // and its restriction weights; up: left coarse row and prolongation weights).
-    __device__ __forceinline__ double* col0() { return lds + (WL + 2) * S; }
-    __device__ __forceinline__ double* roww0() { return col0() + a.chunk + 4 * NU + 4; }
-    __device__ __forceinline__ double* roww1() { return roww0() + a.chunk + 4 * NU + 4; }
-    __device__ __forceinline__ int* rowk() { return (int*)(roww1() + a.chunk + 4 * NU + 4); }
-    // axial coefficient tables of the loaded rows (for rows >= spec_lo)
-    __device__ __forceinline__ double* rowzc() { return roww1() + 2 * (a.chunk + 4 * NU + 4); }
-    __device__ __forceinline__ double* rowzs() { return rowzc() + a.chunk + 4 * NU + 4; }
-    __device__ __forceinline__ double* rowzn() { return rowzs() + a.chunk + 4 * NU + 4; }
-    // Up pass: ring of kCRing coarse-correction rows (row K in slot K % kCRing).
-    static constexpr int kCRing = 8;
-    __device__ __forceinline__ double* cring() { return rowzn() + a.chunk + 4 * NU + 4; }
+    __device__ __forceinline__ double* Vrow(int buf, int half) {
+        return lds + 2 * (a.tn + 1) * QS + (2 * buf + half) * (a.tn + 1);
+    }
+    __device__ __forceinline__ double* tables() { return lds + 2 * (a.tn + 1) * QS + 4 * (a.tn + 1); }
+    __device__ __forceinline__ double* col0() { return tables(); }
+    __device__ __forceinline__ double* roww0() { return tables() + rows; }
+    __device__ __forceinline__ double* roww1() { return tables() + 2 * rows; }
+    __device__ __forceinline__ double* rowzc() { return tables() + 3 * rows; }
+    __device__ __forceinline__ double* rowzs() { return tables() + 4 * rows; }
+    __device__ __forceinline__ double* rowzn() { return tables() + 5 * rows; }
+    __device__ __forceinline__ int* rowk() { return (int*)(tables() + 6 * rows); }
+    static constexpr int kCRing = 8;  // up: coarse-correction rows, row K in slot K % kCRing
+    __device__ __forceinline__ double* cring() { return tables() + 7 * rows; }
+    // inverse diagonals of the rows from spec_lo to nz-2 (at most kMaxSpecial),
+    // per row [column pair t][2]
+    __device__ __forceinline__ double* sinv() { return cring() + kCRing * a.vc.nr; }
     __device__ __forceinline__ double* crow(int K) { return cring() + (K & (kCRing - 1)) * a.vc.nr; }
+
+    __device__ __forceinline__ bool interior_row(int x) const { return x >= 1 && x <= a.v.nz - 2; }
 
     __device__ __forceinline__ void setup() {
         const LevelView& v = a.v;
-        S = 2 * (a.tn + 1);
         t = threadIdx.x;
         c1 = 2 * t + 1;
         c2 = 2 * t + 2;
-        ex1 = c1 <= v.nr - 1;
-        ex2 = c2 <= v.nr - 1;
+        k1 = min(c1, v.nr - 1);
+        k2 = min(c2, v.nr - 1);
         act1 = c1 <= v.nr - 2;
         act2 = c2 <= v.nr - 2;
+        At = lds + t * QS;
+        Ar = At + QS;
+        Bt = lds + (a.tn + 1) * QS + (t + 1) * QS;
+        Bl = Bt - QS;
         const int b = blockIdx.x;
         if (a.xcd_major) {
             const int xcd = b & 7, idx = b >> 3;
@@ -120,24 +134,22 @@ struct Pass {
         }
         za = 1 + chunk * a.chunk;
         zb = min(v.nz - 1, za + a.chunk);
-        s = max(0, za - (2 * NU + 2));
+        s = max(0, za - (2 * NU + 2)) & ~1;
         lend = min(v.nz - 1, zb + 2 * NU + 1);
+        rows = a.chunk + 4 * NU + 6;
         lam = a.lam[p];
-        {
-            const int k1 = min(c1, v.nr - 1), k2 = min(c2, v.nr - 1);
-            rw1 = v.rw[k1];
-            re1 = v.re[k1];
-            rb1 = v.rb[k1];
-            rm1 = v.rm[k1];
-            rw2 = v.rw[k2];
-            re2 = v.re[k2];
-            rb2 = v.rb[k2];
-            rm2 = v.rm[k2];
-        }
+        rw1 = v.rw[k1];
+        re1 = v.re[k1];
+        rb1 = v.rb[k1];
+        rm1 = v.rm[k1];
+        rw2 = v.rw[k2];
+        re2 = v.re[k2];
+        rb2 = v.rb[k2];
+        rm2 = v.rm[k2];
         cu1 = make_coef(rw1, re1, rb1, rm1, a.zc0, a.zs0, a.zn0, lam);
         cu2 = make_coef(rw2, re2, rb2, rm2, a.zc0, a.zs0, a.zn0, lam);
-        ubase = a.u_in + (long long)p * v.pstride;
-        fbase = a.f + (long long)p * v.pstride;
+        urow = a.u_in + (long long)p * v.pstride;
+        frow = a.f + (long long)p * v.pstride;
         obase = a.u_out + (long long)p * v.pstride;
         r_m2[0] = r_m2[1] = r_m1[0] = r_m1[1] = r_0[0] = r_0[1] = 0.0;
         pendK = -1;
@@ -149,8 +161,7 @@ struct Pass {
             wp1 = I1 >= 0 ? a.tr.rwp[I1] : 0.0;
             wm2 = I2 >= 0 ? a.tr.rwm[I2] : 0.0;
             wp2 = I2 >= 0 ? a.tr.rwp[I2] : 0.0;
-            // restriction rows start at zero (the ring columns stay zero)
-            for (int i = t; i < 2 * S; i += blockDim.x) lds[WL * S + i] = 0.0;
+            for (int i = t; i < 4 * (a.tn + 1); i += blockDim.x) Vrow(0, 0)[i] = 0.0;
         } else {
             cK = -1;
             cnext = 0;
@@ -161,12 +172,12 @@ struct Pass {
             pl2 = act2 ? a.tr.pwl[c2] : 0.0;
             pr2 = act2 ? a.tr.pwr[c2] : 0.0;
         }
-        // radial ring column 0 and the axial transfer data of every row the chunk loads
+        // radial ring column 0, axial transfer data and axial tables of the loaded rows
         for (int x = s + t; x <= lend; x += blockDim.x) {
-            col0()[x - s] = ZERO_U ? 0.0 : ubase[(long long)x * v.pitch];
+            col0()[x - s] = ZERO_U ? 0.0 : urow[(long long)x * v.pitch];
             int k = -1;
             double w0 = 0.0, w1 = 0.0;
-            if (x >= 1 && x <= v.nz - 2) {
+            if (interior_row(x)) {
                 if (DOWN) {
                     k = a.rowc[x];
                     if (k >= 0) {
@@ -185,6 +196,11 @@ struct Pass {
             rowzc()[x - s] = v.zc[x];
             rowzs()[x - s] = v.zs[x];
             rowzn()[x - s] = v.zn[x];
+        }
+        for (int y = a.spec_lo; y <= v.nz - 2; ++y) {
+            double* row = sinv() + (y - a.spec_lo) * 2 * a.tn;
+            row[2 * t] = make_coef(rw1, re1, rb1, rm1, v.zc[y], v.zs[y], v.zn[y], lam).invd;
+            row[2 * t + 1] = make_coef(rw2, re2, rb2, rm2, v.zc[y], v.zs[y], v.zn[y], lam).invd;
         }
         if (!DOWN) {
             // coarse rows needed by the rows consumed in the first PD + 1 steps
@@ -205,171 +221,189 @@ struct Pass {
         }
     }
 
-    __device__ __forceinline__ bool interior_row(int x) const { return x >= 1 && x <= a.v.nz - 2; }
-
-    // Highest coarse row that fine row x interpolates from (or -1 on the ring).
-    __device__ __forceinline__ int coarse_hi(int x) {
-        return (x >= s && x <= lend && interior_row(x)) ? rowk()[x - s] + 1 : -1;
-    }
+    // ---- coarse-correction rows (up pass) ----
+    __device__ __forceinline__ bool carries() const { return t + 1 <= a.vc.nr - 2; }
     __device__ __forceinline__ const double* coarse_src(int K) const {
         return a.ec + (long long)p * a.vc.pstride + (long long)K * a.vc.pitch;
     }
-    // Up pass, once per step: store the coarse row that arrived, request the next
-    // one if fine row xn (consumed kCRing - 2 or fewer steps from now) needs it.
-    // Thread t carries coarse interior column t + 1; the coarse ring columns are
-    // zero (the correction has homogeneous Dirichlet data) and are set once.
-    __device__ __forceinline__ bool carries() const { return t + 1 <= a.vc.nr - 2; }
+    __device__ __forceinline__ int coarse_hi(int x) {
+        return (x >= s && x <= lend && interior_row(x)) ? rowk()[x - s] + 1 : -1;
+    }
+    // Once per step: store the coarse row that arrived and request the next one
+    // if the row consumed PD + 1 steps from now needs it.  Thread t carries
+    // coarse interior column t + 1; the coarse ring columns stay zero.  The
+    // load is issued every step (clamped) so the wait counts stay exact.
     __device__ __forceinline__ void coarse_stream(int xn) {
         if (cK >= 0) {
             if (carries()) crow(cK)[t + 1] = cval;
             cK = -1;
         }
-        // always issue one (clamped, valid) load so the wait counts stay exact
         const int need = coarse_hi(xn);
         const int kr = min(cnext, a.vc.nz - 1);
         cval = coarse_src(kr)[min(t + 1, a.vc.nr - 2)];
         if (cnext <= need) cK = cnext++;
     }
 
-    // Issue the loads of row x into register slot j.  Branch-free: every lane
-    // loads from a clamped, valid address, and consume() discards what is not
-    // needed, so the compiler can keep several rows of loads in flight.  With
-    // ZERO_U the whole input iterate (ring included) is zero and not read.
+    // ---- rows in and out ----
+    // Loads of row x into slot j: every lane loads from a clamped, valid address
+    // and consume() keeps what is needed, so several rows stay in flight.
     __device__ __forceinline__ void issue(int x, int j) {
-        const int xr = min(x, lend);
-        const int k1 = min(c1, a.v.nr - 1), k2 = min(c2, a.v.nr - 1);
-        const double* ur = ubase + (long long)xr * a.v.pitch;
-        const double* fr = fbase + (long long)xr * a.v.pitch;
+        const long long o = (long long)min(x, lend) * a.v.pitch;
         if (!ZERO_U) {
-            uu[j][0] = ur[k1];
-            uu[j][1] = ur[k2];
+            uu[j][0] = urow[o + k1];
+            uu[j][1] = urow[o + k2];
         }
-        ff[j][0] = fr[k1];
-        ff[j][1] = fr[k2];
+        ff[j][0] = frow[o + k1];
+        ff[j][1] = frow[o + k2];
     }
 
-    // Finish row x in slot j (prolongation correction on the up pass) and publish it.
-    __device__ __forceinline__ void consume(int x, int j) {
-        const bool in = interior_row(x);
+    template <int J, bool INTERIOR>
+    __device__ __forceinline__ void consume(int x) {
+        const bool in = INTERIOR || interior_row(x);
+        // a missing column c2 = nr keeps the clamped load (the ring value at
+        // nr - 1), so its unconditional store below rewrites that value unchanged
         if (ZERO_U) {
-            uu[j][0] = 0.0;
-            uu[j][1] = 0.0;
-        } else {
-            uu[j][0] = ex1 ? uu[j][0] : 0.0;
-            uu[j][1] = ex2 ? uu[j][1] : 0.0;
+            uu[J][0] = 0.0;
+            uu[J][1] = 0.0;
+        } else if (DOWN && a.zero_interior && in) {
+            uu[J][0] = act1 ? 0.0 : uu[J][0];
+            uu[J][1] = act2 ? 0.0 : uu[J][1];
         }
-        ff[j][0] = (in && act1) ? ff[j][0] : 0.0;
-        ff[j][1] = (in && act2) ? ff[j][1] : 0.0;
+        ff[J][0] = (in && act1) ? ff[J][0] : 0.0;
+        ff[J][1] = (in && act2) ? ff[J][1] : 0.0;
         if (!DOWN && in) {
             const int K = rowk()[x - s];
             const double wl = roww0()[x - s], wr = roww1()[x - s];
             const double* lo = crow(K);
             const double* hi = crow(K + 1);
-            if (act1) uu[j][0] += prolong2(lo + P1, hi + P1, pl1, pr1, wl, wr);
-            if (act2) uu[j][1] += prolong2(lo + P2, hi + P2, pl2, pr2, wl, wr);
+            const double e1 = prolong2(lo + P1, hi + P1, pl1, pr1, wl, wr);
+            const double e2 = prolong2(lo + P2, hi + P2, pl2, pr2, wl, wr);
+            uu[J][0] = act1 ? uu[J][0] + e1 : uu[J][0];
+            uu[J][1] = act2 ? uu[J][1] + e2 : uu[J][1];
         }
-        const int ls = x & (WL - 1);
-        if (ex1) A(ls, t) = uu[j][0];
-        if (ex2) B(ls, t + 1) = uu[j][1];
-        if (t == 0) B(ls, 0) = ZERO_U ? 0.0 : col0()[x - s];
+        At[J] = uu[J][0];
+        Bt[J] = uu[J][1];
+        if (t == 0) Bl[J] = col0()[x - s];
     }
 
-    // Coefficients of the two columns on row y; rows from spec_lo on have their
-    // own axial tables (held in LDS), so no global load sits in a branch.
+    // ---- arithmetic ----
+    // Coefficients of rows from spec_lo on: the conductances from the row's axial
+    // tables, the inverse diagonal from the table set up once (no division here).
+    __device__ __forceinline__ Coef special(double rw, double re, double rb, double rm, int y, int col) {
+        Coef c;
+        const double zc = rowzc()[y - s];
+        c.gw = rw * zc;
+        c.ge = re * zc;
+        c.gs = rb * rowzs()[y - s];
+        c.gn = rb * rowzn()[y - s];
+        c.diag = fma(lam, rm * zc, (c.gw + c.ge) + (c.gs + c.gn));
+        c.invd = sinv()[(y - a.spec_lo) * 2 * a.tn + 2 * t + col];
+        return c;
+    }
+    template <bool CHK>
     __device__ __forceinline__ Coef coef1(int y) {
-        if (y < a.spec_lo) return cu1;
-        return make_coef(rw1, re1, rb1, rm1, rowzc()[y - s], rowzs()[y - s], rowzn()[y - s], lam);
+        if (!CHK || y < a.spec_lo) return cu1;
+        return special(rw1, re1, rb1, rm1, y, 0);
     }
+    template <bool CHK>
     __device__ __forceinline__ Coef coef2(int y) {
-        if (y < a.spec_lo) return cu2;
-        return make_coef(rw2, re2, rb2, rm2, rowzc()[y - s], rowzs()[y - s], rowzn()[y - s], lam);
+        if (!CHK || y < a.spec_lo) return cu2;
+        return special(rw2, re2, rb2, rm2, y, 1);
     }
 
-    // Colour of column c1 = 2t+1 on row y is (y + 1) & 1; c2 has the other one.
-    static __device__ __forceinline__ bool c1_has(int y, int color) { return ((y + 1) & 1) == color; }
-
-    // Horizontal neighbour a half-sweep of colour `color` on row y needs from
-    // another thread: west of c1 or east of c2 (published at an earlier step).
-    __device__ __forceinline__ double neighbour(int y, int color) {
-        const int ls = y & (WL - 1);
-        return c1_has(y, color) ? B(ls, t) : A(ls, t + 1);
-    }
-
-    // Half-sweep of colour `color` on row y (register slots jy, jm = y-1, jp = y+1).
-    __device__ __forceinline__ void half_sweep(int y, int color, int jy, int jm, int jp, double nb) {
-        const int ls = y & (WL - 1);
-        if (c1_has(y, color)) {
-            if (act1) {
-                uu[jy][0] = relax(uu[jy][0], ff[jy][0], nb, uu[jy][1], uu[jm][0], uu[jp][0], coef1(y),
-                                  a.omega);
-                A(ls, t) = uu[jy][0];
-            }
+    // Half-sweep on row y (slot SY; SM = y-1, SP = y+1).  C1: the colour being
+    // relaxed sits on column c1 of this row.  NB: the horizontal neighbour from
+    // another thread (west of c1 or east of c2), published one step earlier.
+    template <int SY, int SM, int SP, bool C1, bool CHK>
+    __device__ __forceinline__ void half_sweep(int y, double nb) {
+        if (C1) {
+            const double v =
+                relax(uu[SY][0], ff[SY][0], nb, uu[SY][1], uu[SM][0], uu[SP][0], coef1<CHK>(y), a.omega);
+            uu[SY][0] = act1 ? v : uu[SY][0];
+            At[SY] = uu[SY][0];
         } else {
-            if (act2) {
-                uu[jy][1] = relax(uu[jy][1], ff[jy][1], uu[jy][0], nb, uu[jm][1], uu[jp][1], coef2(y),
-                                  a.omega);
-                B(ls, t + 1) = uu[jy][1];
-            }
+            const double v =
+                relax(uu[SY][1], ff[SY][1], uu[SY][0], nb, uu[SM][1], uu[SP][1], coef2<CHK>(y), a.omega);
+            uu[SY][1] = act2 ? v : uu[SY][1];
+            Bt[SY] = uu[SY][1];
         }
     }
 
-    __device__ __forceinline__ void residual_row(int y, int jy, int jm, int jp, double nw,
-                                                 double ne, double& r1, double& r2) {
-        r1 = act1 ? residual(uu[jy][0], ff[jy][0], nw, uu[jy][1], uu[jm][0], uu[jp][0], coef1(y)) : 0.0;
-        r2 = act2 ? residual(uu[jy][1], ff[jy][1], uu[jy][0], ne, uu[jm][1], uu[jp][1], coef2(y)) : 0.0;
+    template <int SY, int SM, int SP, bool CHK>
+    __device__ __forceinline__ void residual_row(int y, double nw, double ne, double& r1, double& r2) {
+        const double x1 = residual(uu[SY][0], ff[SY][0], nw, uu[SY][1], uu[SM][0], uu[SP][0], coef1<CHK>(y));
+        const double x2 = residual(uu[SY][1], ff[SY][1], uu[SY][0], ne, uu[SM][1], uu[SP][1], coef2<CHK>(y));
+        r1 = act1 ? x1 : 0.0;
+        r2 = act2 ? x2 : 0.0;
     }
 
     // Radial half of the restriction for coarse row pendK (vertical half done last step).
     __device__ __forceinline__ void finish_restriction() {
         const int buf = pendK & 1;
+        const double* VA = Vrow(buf, 0);
+        const double* VB = Vrow(buf, 1);
         double* out = a.fc + (long long)p * a.vc.pstride + (long long)pendK * a.vc.pitch;
-        if (I1 >= 0) out[I1] = restrict3(VB(buf, t), V(buf, t), VB(buf, t + 1), wm1, wp1);
-        if (I2 >= 0) out[I2] = restrict3(V(buf, t), VB(buf, t + 1), V(buf, t + 1), wm2, wp2);
+        // non-coincident columns write their (unused) value into the coarse ring column 0
+        const double f1 = restrict3(VB[t], VA[t], VB[t + 1], wm1, wp1);
+        const double f2 = restrict3(VA[t], VB[t + 1], VA[t + 1], wm2, wp2);
+        out[I1 >= 0 ? I1 : 0] = I1 >= 0 ? f1 : 0.0;
+        out[I2 >= 0 ? I2 : 0] = I2 >= 0 ? f2 : 0.0;
         pendK = -1;
     }
 
-    template <int J>
+    // One step: consume row x and run every half-sweep, the residual and the
+    // transfers on the rows behind it.  CHK = false in the steady middle of the
+    // chunk, where every row involved is interior, regular and inside the chunk.
+    template <int J, bool CHK>
     __device__ __forceinline__ void step(int x) {
         lds_barrier();
-        // Every LDS value this step reads was published at an earlier step, and
-        // this step only writes locations nobody reads during it: read them all
-        // now so their latency overlaps.
+        // every LDS value read here was published at an earlier step, and this
+        // step only writes locations nobody reads during it
         double nb[2 * NU];
-#pragma unroll
-        for (int h = 0; h < 2 * NU; ++h) nb[h] = neighbour(x - 1 - h, h & 1);
-        const int yr = x - 2 * NU - 1;
-        const double rnw = B(yr & (WL - 1), t), rne = A(yr & (WL - 1), t + 1);
+#define CP_NB(h)                                                                       \
+    if constexpr ((h) < 2 * NU) {                                                     \
+        constexpr int sy = (J - 1 - (h) + 4 * Q) % Q;                                 \
+        constexpr bool c1col = ((((J - 1 - (h)) & 1) + 1) & 1) == ((h) & 1);          \
+        nb[(h)] = c1col ? Bl[sy] : Ar[sy];                                            \
+    }
+        CP_NB(0) CP_NB(1) CP_NB(2) CP_NB(3) CP_NB(4) CP_NB(5) CP_NB(6) CP_NB(7)
+#undef CP_NB
+        constexpr int sr = (J - 2 * NU - 1 + 4 * Q) % Q;
+        const double rnw = Bl[sr], rne = Ar[sr];
         if (DOWN && pendK >= 0) finish_restriction();
         if (!DOWN) coarse_stream(x + PD + 1);
         issue(x + PD, (J + PD) % Q);
-        if (x <= lend) consume(x, J);
+        if (!CHK || x <= lend) consume<J, !CHK>(x);
         const int ylo = max(1, s + 1), yhi = min(a.v.nz - 2, lend - 1);
-#pragma unroll
-        for (int h = 0; h < 2 * NU; ++h) {
-            const int y = x - 1 - h;
-            if (y >= ylo && y <= yhi)
-                half_sweep(y, h & 1, (J - 1 - h + 2 * Q) % Q, (J - 2 - h + 2 * Q) % Q,
-                           (J - h + 2 * Q) % Q, nb[h]);
-        }
-        // rows that are final now: write the iterate
+#define CP_HS(h)                                                                              \
+    if constexpr ((h) < 2 * NU) {                                                            \
+        constexpr int sy = (J - 1 - (h) + 4 * Q) % Q;                                        \
+        constexpr int sm = (J - 2 - (h) + 4 * Q) % Q;                                        \
+        constexpr int sp = (J - (h) + 4 * Q) % Q;                                            \
+        constexpr bool c1col = ((((J - 1 - (h)) & 1) + 1) & 1) == ((h) & 1);                 \
+        const int y = x - 1 - (h);                                                           \
+        if (!CHK || (y >= ylo && y <= yhi)) half_sweep<sy, sm, sp, c1col, CHK>(y, nb[(h)]); \
+    }
+        CP_HS(0) CP_HS(1) CP_HS(2) CP_HS(3) CP_HS(4) CP_HS(5) CP_HS(6) CP_HS(7)
+#undef CP_HS
+        // row x - 2 nu is final now
         {
+            constexpr int jf = (J - 2 * NU + 4 * Q) % Q;
             const int yf = x - 2 * NU;
-            constexpr int jf = (J - 2 * NU + 2 * Q) % Q;
-            if (yf >= za && yf < zb) {
+            if (!CHK || (yf >= za && yf < zb)) {
                 double* orow = obase + (long long)yf * a.v.pitch;
-                if (act1) orow[c1] = uu[jf][0];
-                if (act2) orow[c2] = uu[jf][1];
+                orow[k1] = uu[jf][0];
+                orow[k2] = uu[jf][1];
             }
         }
-        // residual one row further back
         const int y = x - 2 * NU - 1;
-        constexpr int jy = (J - 2 * NU - 1 + 2 * Q) % Q;
-        constexpr int jm = (J - 2 * NU - 2 + 2 * Q) % Q;
-        constexpr int jq = (J - 2 * NU + 2 * Q) % Q;
+        constexpr int jy = (J - 2 * NU - 1 + 4 * Q) % Q;
+        constexpr int jm = (J - 2 * NU - 2 + 4 * Q) % Q;
+        constexpr int jq = (J - 2 * NU + 4 * Q) % Q;
         if (DOWN) {
             double r1 = 0.0, r2 = 0.0;
-            if (y >= max(1, za - 1) && y <= min(a.v.nz - 2, zb))
-                residual_row(y, jy, jm, jq, rnw, rne, r1, r2);
+            if (!CHK || (y >= max(1, za - 1) && y <= min(a.v.nz - 2, zb)))
+                residual_row<jy, jm, jq, CHK>(y, rnw, rne, r1, r2);
             r_m2[0] = r_m1[0];
             r_m2[1] = r_m1[1];
             r_m1[0] = r_0[0];
@@ -377,50 +411,61 @@ struct Pass {
             r_0[0] = r1;
             r_0[1] = r2;
             const int yc = y - 1;
-            if (yc >= za && yc < zb && yc >= 1) {
+            if (!CHK || (yc >= za && yc < zb && yc >= 1)) {
                 const int K = rowk()[yc - s];
                 if (K >= 0) {
                     const double wzm = roww0()[yc - s], wzp = roww1()[yc - s];
                     const int buf = K & 1;
-                    if (ex1) V(buf, t) = restrict3(r_m2[0], r_m1[0], r_0[0], wzm, wzp);
-                    if (ex2) VB(buf, t + 1) = restrict3(r_m2[1], r_m1[1], r_0[1], wzm, wzp);
+                    Vrow(buf, 0)[t] = restrict3(r_m2[0], r_m1[0], r_0[0], wzm, wzp);
+                    Vrow(buf, 1)[t + 1] = restrict3(r_m2[1], r_m1[1], r_0[1], wzm, wzp);
                     pendK = K;
                 }
             }
         } else if (a.partial) {
-            if (y >= za && y < zb && y <= a.v.nz - 2) {
+            if (!CHK || (y >= za && y < zb && y <= a.v.nz - 2)) {
                 double r1, r2;
-                residual_row(y, jy, jm, jq, rnw, rne, r1, r2);
+                residual_row<jy, jm, jq, CHK>(y, rnw, rne, r1, r2);
                 acc = fma(r1, r1, acc);
                 acc = fma(r2, r2, acc);
             }
         }
     }
 
+    template <bool CHK>
+    __device__ __forceinline__ void group(int x0, int xend) {
+        // Q consecutive steps with compile-time register and LDS slots
+#define CP_STEP(J)                                            \
+    if constexpr ((J) < Q) {                                  \
+        if (!CHK || x0 + (J) <= xend) step<(J), CHK>(x0 + (J)); \
+    }
+        CP_STEP(0) CP_STEP(1) CP_STEP(2) CP_STEP(3) CP_STEP(4) CP_STEP(5) CP_STEP(6) CP_STEP(7)
+        CP_STEP(8) CP_STEP(9) CP_STEP(10) CP_STEP(11) CP_STEP(12) CP_STEP(13) CP_STEP(14) CP_STEP(15)
+#undef CP_STEP
+    }
+
     __device__ __forceinline__ void run() {
         setup();
-        // last step: the residual of row zb (down) or zb - 1 (up) plus one step to
-        // finish the pending restriction
+        // last step: the residual of row zb (down) or zb - 1 (up), plus one step
+        // to finish the pending restriction
         const int ylast = DOWN ? min(a.v.nz - 1, zb) : zb - 1;
         const int xlast = ylast + 2 * NU + 1 + (DOWN ? 1 : 0);
+        // steady steps: every row they touch is interior, below spec_lo and in the chunk
+        const int lo = za + 2 * NU + 2;
+        const int hi = min(min(zb + 2 * NU - 1, a.v.nz - 2), min(lend, a.spec_lo));
+        int ga = s, gb = s;  // [ga, gb): whole groups of steady steps
+        if (hi >= lo) {
+            ga = s + ((lo - s + Q - 1) / Q) * Q;
+            gb = ga + ((hi + 1 - ga) / Q) * Q;
+            if (gb <= ga) ga = gb = s;
+        }
 #pragma unroll
         for (int d = 0; d < PD; ++d) issue(s + d, d);
+        // one instance of each step group: checked at both ends, steady between
         for (int x0 = s; x0 <= xlast; x0 += Q) {
-            // Q consecutive steps with compile-time register slots
-#define CP_STEP(J)                               \
-    if (x0 + (J) <= xlast) step<(J) % Q>(x0 + (J));
-            CP_STEP(0) CP_STEP(1) CP_STEP(2) CP_STEP(3) CP_STEP(4) CP_STEP(5)
-            if constexpr (Q > 6) { CP_STEP(6) }
-            if constexpr (Q > 7) { CP_STEP(7) }
-            if constexpr (Q > 8) { CP_STEP(8) }
-            if constexpr (Q > 9) { CP_STEP(9) }
-            if constexpr (Q > 10) { CP_STEP(10) }
-            if constexpr (Q > 11) { CP_STEP(11) }
-            if constexpr (Q > 12) { CP_STEP(12) }
-            if constexpr (Q > 13) { CP_STEP(13) }
-            if constexpr (Q > 14) { CP_STEP(14) }
-            if constexpr (Q > 15) { CP_STEP(15) }
-#undef CP_STEP
+            if (x0 >= ga && x0 < gb)
+                group<false>(x0, x0 + Q - 1);
+            else
+                group<true>(x0, xlast);
         }
         if (DOWN && pendK >= 0) {
             lds_barrier();
@@ -438,7 +483,7 @@ struct Pass {
                 if (t < w && t + w < (int)blockDim.x) red[t] += red[t + w];
                 lds_barrier();
             }
-            if (t == 0) a.partial[(long long)p * kMaxPartial + chunk] = red[0];
+            if (t == 0) a.partial[(long long)p * a.partial_ld + chunk] = red[0];
         }
     }
 };
@@ -501,8 +546,6 @@ hipError_t launch_nu(int nu, int pd, bool down, bool zero_u, const PassArgs& a, 
     }
 }
 
-int window_rows(int nu) { return (2 * nu + 2 <= 8) ? 8 : 16; }
-
 struct Shape {
     int tn, threads, chunk, nchunks, blocks;
     size_t lds;
@@ -511,23 +554,28 @@ struct Shape {
 Shape pass_shape(const cylpoisson_plan* p, int l, int nu) {
     const DeviceLevel& L = p->dl[l];
     Shape sh;
-    sh.tn = (L.v.nr - 1 + 1) / 2;  // column pairs covering columns 1 .. nr-1
-    sh.threads = ((sh.tn + 63) / 64) * 64;
+    sh.tn = L.v.nr / 2;  // column pairs covering columns 1 .. nr-1
+    sh.threads = sh.tn;
     const int rows = L.v.nz - 2;
-    int chunk = p->opt.chunk_rows;
+    int chunk = l == 0 ? p->opt.chunk_rows : p->opt.chunk_rows_coarse;
     if (chunk <= 0) {
-        // aim for about two resident workgroups per compute unit, chunks of 16 rows or more
-        const int want = 512;
+        // The finest level is bandwidth-bound: few long chunks (about two
+        // workgroups per compute unit) keep the recomputed halo small.  Coarser
+        // levels are latency-bound: more, shorter chunks.
+        const int want = l == 0 ? 512 : 1024;
         const int per_plane = std::max(1, want / std::max(1, p->nt));
-        chunk = std::max(16, (rows + per_plane - 1) / per_plane);
+        chunk = std::max(l == 0 ? 64 : 32, (rows + per_plane - 1) / per_plane);
     }
     chunk = std::min(std::max(chunk, 1), std::max(rows, 1));
     sh.chunk = chunk;
     sh.nchunks = (rows + chunk - 1) / chunk;
     sh.blocks = sh.nchunks * p->nt;
-    const int S = 2 * (sh.tn + 1);
-    sh.lds = ((size_t)(window_rows(nu) + 2) * S + (size_t)(chunk + 4 * nu + 4) * 7 +
-              (size_t)8 * p->dl[l + 1].v.nr) * sizeof(double);
+    const int q0 = 2 * nu + 3 + (nu == 2 ? p->opt.prefetch : 2);
+    const int qs = ((q0 & 1) ? q0 + 1 : q0) + 1;
+    const size_t trows = (size_t)(chunk + 4 * nu + 6);
+    const size_t nspecial = (size_t)std::max(0, L.v.nz - 1 - L.spec_lo);
+    sh.lds = ((size_t)2 * (sh.tn + 1) * qs + (size_t)4 * (sh.tn + 1) + 7 * trows +
+              (size_t)8 * p->dl[l + 1].v.nr + nspecial * 2 * sh.tn) * sizeof(double);
     sh.lds = std::max(sh.lds, (size_t)sh.threads * sizeof(double));  // final block reduction
     return sh;
 }
@@ -563,10 +611,12 @@ bool fused_supported(const cylpoisson_plan* p, int l) {
     const int nu = std::max(p->opt.nu1, p->opt.nu2);
     if (p->opt.nu1 > 4 || p->opt.nu2 > 4) return false;
     const Shape sh = pass_shape(p, l, nu);
-    return sh.threads <= 512 && sh.lds <= 64 * 1024 && sh.nchunks <= kMaxPartial;
+    const int nspecial = p->dl[l].v.nz - 1 - p->dl[l].spec_lo;
+    return sh.threads >= 1 && sh.threads <= 512 && sh.lds <= 64 * 1024 &&
+           sh.nchunks <= kMaxPartial && nspecial <= 4;
 }
 
-hipError_t fused_down(cylpoisson_plan* p, int l, bool zero_u, hipStream_t s) {
+hipError_t fused_down(cylpoisson_plan* p, int l, bool zero_u, bool zero_interior, hipStream_t s) {
     DeviceLevel& L = p->dl[l];
     DeviceLevel& C = p->dl[l + 1];
     const Shape sh = pass_shape(p, l, p->opt.nu1);
@@ -575,10 +625,14 @@ hipError_t fused_down(cylpoisson_plan* p, int l, bool zero_u, hipStream_t s) {
     a.f = L.f;
     a.u_out = L.u2;
     a.fc = C.f;
+    a.zero_interior = zero_interior ? 1 : 0;
     return launch_nu(p->opt.nu1, p->opt.prefetch, true, zero_u, a, sh.blocks, sh.threads, sh.lds, s);
 }
 
-hipError_t fused_up(cylpoisson_plan* p, int l, double* partial, int* nchunks, hipStream_t s) {
+int fused_chunks(const cylpoisson_plan* p, int l, int nu) { return pass_shape(p, l, nu).nchunks; }
+
+hipError_t fused_up(cylpoisson_plan* p, int l, double* partial, int partial_ld, int* nchunks,
+                    hipStream_t s) {
     DeviceLevel& L = p->dl[l];
     DeviceLevel& C = p->dl[l + 1];
     const Shape sh = pass_shape(p, l, p->opt.nu2);
@@ -588,6 +642,7 @@ hipError_t fused_up(cylpoisson_plan* p, int l, double* partial, int* nchunks, hi
     a.u_out = L.u;
     a.ec = C.u;
     a.partial = partial;
+    a.partial_ld = partial_ld;
     if (nchunks) *nchunks = sh.nchunks;
     return launch_nu(p->opt.nu2, p->opt.prefetch, false, false, a, sh.blocks, sh.threads, sh.lds, s);
 }

@@ -234,6 +234,68 @@ __global__ void __launch_bounds__(256) k_apply(LevelView v, const double* __rest
     out[o] = apply_row(u[o], u[o - 1], u[o + 1], u[o - v.pitch], u[o + v.pitch], c) * inv_s[i];
 }
 
+// Dirichlet ring of the fine-level iterate(s): plane 0 holds the face values
+// (axial faces win at corners), other planes zero (Eq. mode_rhs).
+__global__ void k_init_ring(LevelView v, double* u, double* u2, double prz, double prout,
+                            double pz0, double pzl) {
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    const int p = blockIdx.y;
+    const int n_rows = 2 * v.nr, n_cols = 2 * (v.nz - 2);
+    if (q >= n_rows + n_cols) return;
+    int i, k;
+    if (q < n_rows) {
+        i = q % v.nr;
+        k = q < v.nr ? 0 : v.nz - 1;
+    } else {
+        const int c = q - n_rows;
+        k = 1 + c % (v.nz - 2);
+        i = c < v.nz - 2 ? 0 : v.nr - 1;
+    }
+    double val = 0.0;
+    if (p == 0) {
+        if (i == 0) val = prz;
+        if (i == v.nr - 1) val = prout;
+        if (k == 0) val = pz0;
+        if (k == v.nz - 1) val = pzl;
+    }
+    const long long o = (long long)p * v.pstride + (long long)k * v.pitch + i;
+    u[o] = val;
+    u2[o] = val;
+}
+
+// Squared norms of the initial residual f - A u0 per plane, where u0 has the
+// ring of u and a zero interior (the interior of u is not read).
+__global__ void __launch_bounds__(256) k_rhs_norm_partial(LevelView v, const double* __restrict__ lam,
+                                                          const double* __restrict__ u,
+                                                          const double* __restrict__ f,
+                                                          double* __restrict__ partial) {
+    __shared__ double red[256];
+    const int p = blockIdx.y;
+    const int ni = v.nr - 2, nk = v.nz - 2;
+    const long long total = (long long)ni * nk;
+    const double* up = u + (long long)p * v.pstride;
+    const double* fp = f + (long long)p * v.pstride;
+    double s = 0.0;
+    for (long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x; q < total;
+         q += (long long)gridDim.x * blockDim.x) {
+        const int i = (int)(q % ni) + 1, k = (int)(q / ni) + 1;
+        const long long o = (long long)k * v.pitch + i;
+        const double uw = i == 1 ? up[o - 1] : 0.0;
+        const double ue = i == v.nr - 2 ? up[o + 1] : 0.0;
+        const double us = k == 1 ? up[o - v.pitch] : 0.0;
+        const double un = k == v.nz - 2 ? up[o + v.pitch] : 0.0;
+        const double r = residual(0.0, fp[o], uw, ue, us, un, coef_at(v, i, k, lam[p]));
+        s = fma(r, r, s);
+    }
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) partial[(long long)p * kMaxPartial + blockIdx.x] = red[0];
+}
+
 // Copy the Dirichlet ring (boundary rows and columns) of every plane.
 __global__ void k_copy_ring(LevelView v, const double* __restrict__ src, double* __restrict__ dst) {
     const int q = blockIdx.x * blockDim.x + threadIdx.x;  // index along the ring
@@ -335,6 +397,25 @@ hipError_t launch_plane_norms(const DeviceLevel& L, int nt, const double* r, dou
 
 hipError_t launch_norm_final(const double* partial, int nb, int nt, double* out, hipStream_t s) {
     k_norm_final<<<(nt + 63) / 64, 64, 0, s>>>(partial, nb, nt, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_init_ring(const DeviceLevel& L, int nt, const cylpoisson_bc& bc, hipStream_t s) {
+    const int n = 2 * L.v.nr + 2 * (L.v.nz - 2);
+    k_init_ring<<<dim3((n + 255) / 256, nt), 256, 0, s>>>(L.v, L.u, L.u2, bc.phi_r_in, bc.phi_r_out,
+                                                          bc.phi_z0, bc.phi_zL);
+    return hipGetLastError();
+}
+
+hipError_t launch_rhs_norms(const DeviceLevel& L, int nt, const double* lam, const double* u,
+                            const double* f, double* partial, double* norms_out, hipStream_t s) {
+    const long long total = (long long)(L.v.nr - 2) * (L.v.nz - 2);
+    int nb = (int)std::min<long long>(64, (total + 255) / 256);
+    if (nb < 1) nb = 1;
+    k_rhs_norm_partial<<<dim3(nb, nt), 256, 0, s>>>(L.v, lam, u, f, partial);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    k_norm_final<<<(nt + 63) / 64, 64, 0, s>>>(partial, nb, nt, norms_out);
     return hipGetLastError();
 }
 

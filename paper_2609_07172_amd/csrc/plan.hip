@@ -158,6 +158,8 @@ void free_plan(cylpoisson_plan* p) {
     p->allocations.clear();
     if (p->h_norms) (void)hipHostFree(p->h_norms);
     p->h_norms = nullptr;
+    if (p->h_slot_partial) (void)hipHostFree(p->h_slot_partial);
+    p->h_slot_partial = nullptr;
 }
 
 // Build the level hierarchy on the host.
@@ -506,6 +508,10 @@ cylpoisson_plan* cylpoisson_plan_create(int Nr, int Ntheta, int Nz, double r_in,
         CP_TRY(upload(p, &p->d_cinv, cinv));
         CP_TRY(dev_alloc(p, &p->d_partial, (size_t)Ntheta * kMaxPartial));
         CP_TRY(dev_alloc(p, &p->d_norms, (size_t)kNormSlots * Ntheta));
+        CP_TRY(dev_alloc(p, &p->d_slot_partial, (size_t)kNormSlots * Ntheta * kSlotPartial));
+        CP_TRY(hipHostMalloc((void**)&p->h_slot_partial,
+                             (size_t)kNormSlots * Ntheta * kSlotPartial * sizeof(double),
+                             hipHostMallocDefault));
         CP_TRY(dev_alloc(p, &p->d_tmp, (size_t)nodes));
         CP_TRY(hipHostMalloc((void**)&p->h_norms, (size_t)kNormSlots * Ntheta * sizeof(double),
                              hipHostMallocDefault));
@@ -551,6 +557,7 @@ int cylpoisson_plan_set_option(cylpoisson_plan* plan, const char* key, double va
     if (!std::strcmp(key, "check_every")) return int_in(1, 64, &plan->opt.check_every);
     if (!std::strcmp(key, "fused")) return int_in(0, 1, &plan->opt.fused);
     if (!std::strcmp(key, "chunk_rows")) return int_in(0, 1 << 20, &plan->opt.chunk_rows);
+    if (!std::strcmp(key, "chunk_rows_coarse")) return int_in(0, 1 << 20, &plan->opt.chunk_rows_coarse);
     if (!std::strcmp(key, "timing")) return int_in(0, 1, &plan->opt.timing);
     if (!std::strcmp(key, "prefetch")) return int_in(1, 4, &plan->opt.prefetch);
     if (!std::strcmp(key, "bottom")) return int_in(0, 1, &plan->opt.bottom);

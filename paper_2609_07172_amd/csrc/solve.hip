@@ -147,12 +147,18 @@ hipError_t smooth(cylpoisson_plan* p, DeviceLevel& L, int sweeps, hipStream_t s)
     return hipSuccess;
 }
 
+// Where the squared residual norms of a cycle went: reduced per plane into
+// d_norms[slot] (partial_chunks = 0), or left as per-chunk partial sums in
+// d_slot_partial[slot] for the host to add up in a fixed order.
+struct NormSlot {
+    int partial_chunks = -1;  // -1: not produced by the cycle
+};
+
 // One V-cycle from level l.  On levels l > 0 the iterate starts at zero; on
-// level 0 `zero_top` says its interior is still zero (first cycle).  If
-// `norms` is given and level 0 runs the fused passes, the up pass also
-// produces the per-plane squared residual norms there (and *norms_done is set).
-hipError_t vcycle(cylpoisson_plan* p, int l, hipStream_t s, bool zero_top, double* norms,
-                  bool* norms_done) {
+// level 0 `zero_top` says its interior is still to be treated as zero (first
+// cycle).  With `slot` >= 0 and level 0 on the fused passes, the up pass also
+// produces the squared residual norms of that cycle (recorded in *ns).
+hipError_t vcycle(cylpoisson_plan* p, int l, hipStream_t s, bool zero_top, int slot, NormSlot* ns) {
     const int nl = (int)p->dl.size();
     DeviceLevel& L = p->dl[l];
     hipError_t e = hipSuccess;
@@ -168,22 +174,29 @@ hipError_t vcycle(cylpoisson_plan* p, int l, hipStream_t s, bool zero_top, doubl
         {
             Timed tm(p, l == 0 ? kFineDown : -1, s);
             // coarser levels start from a zero iterate with a zero ring
-            e = fused_down(p, l, l > 0, s);
+            e = fused_down(p, l, l > 0, l == 0 && zero_top, s);
         }
         if (e == hipSuccess) {
             Timed tm(p, l == 0 ? kCoarse : -1, s);
-            e = vcycle(p, l + 1, s, true, nullptr, nullptr);
+            e = vcycle(p, l + 1, s, true, -1, nullptr);
         }
-        const bool want = l == 0 && norms != nullptr;
-        int nch = 0;
+        const bool want = l == 0 && slot >= 0;
+        const int nch = fused_chunks(p, l, p->opt.nu2);
+        const bool host_sum = want && nch <= kSlotPartial;
         if (e == hipSuccess) {
             Timed tm(p, l == 0 ? kFineUp : -1, s);
-            e = fused_up(p, l, want ? p->d_partial : nullptr, &nch, s);
+            double* part = host_sum ? p->d_slot_partial + (size_t)slot * p->nt * kSlotPartial
+                                    : (want ? p->d_partial : nullptr);
+            e = fused_up(p, l, part, host_sum ? kSlotPartial : kMaxPartial, nullptr, s);
         }
         if (e == hipSuccess && want) {
-            Timed tm(p, kOther, s);
-            e = launch_norm_final(p->d_partial, nch, p->nt, norms, s);
-            if (e == hipSuccess) *norms_done = true;
+            if (host_sum) {
+                ns->partial_chunks = nch;
+            } else {
+                Timed tm(p, kOther, s);
+                e = launch_norm_final(p->d_partial, nch, p->nt, p->d_norms + (size_t)slot * p->nt, s);
+                if (e == hipSuccess) ns->partial_chunks = 0;
+            }
         }
         return e;
     }
@@ -196,7 +209,7 @@ hipError_t vcycle(cylpoisson_plan* p, int l, hipStream_t s, bool zero_top, doubl
     }
     if (e == hipSuccess) {
         Timed tm(p, l == 0 ? kCoarse : -1, s);
-        e = vcycle(p, l + 1, s, true, nullptr, nullptr);
+        e = vcycle(p, l + 1, s, true, -1, nullptr);
     }
     {
         Timed tm(p, l == 0 ? kFineUp : -1, s);
@@ -223,12 +236,23 @@ void reset_stats(cylpoisson_plan* p) {
     p->events_used = 0;
 }
 
-// V-cycles on the level-0 planes (f and u with its Dirichlet ring already set).
-int run_cycles(cylpoisson_plan* p, double tol, hipStream_t s) {
+// V-cycles on the level-0 planes.  f is set; u holds its Dirichlet ring, and
+// its interior is zero unless `ring_only`, in which case the interior is
+// treated as zero without being read (fused finest level only).
+int run_cycles(cylpoisson_plan* p, double tol, hipStream_t s, bool ring_only) {
     cylpoisson_stats& st = p->stats;
     const int nt = p->nt;
+    const int maxc = p->opt.max_cycles;
+    std::vector<NormSlot> slots(maxc + 1);
 
-    CP_HIP(residual_norms(p, 0, s));
+    {
+        Timed tm(p, kOther, s);
+        DeviceLevel& L = p->dl[0];
+        if (ring_only)
+            CP_HIP(launch_rhs_norms(L, nt, p->d_lam, L.u, L.f, p->d_partial, p->d_norms, s));
+        else
+            CP_HIP(residual_norms(p, 0, s));
+    }
     CP_HIP(hipMemcpyAsync(p->h_norms, p->d_norms, nt * sizeof(double), hipMemcpyDeviceToHost, s));
     CP_HIP(hipStreamSynchronize(s));
     st.checks = 1;
@@ -245,26 +269,46 @@ int run_cycles(cylpoisson_plan* p, double tol, hipStream_t s) {
         return st.status;
     }
 
-    const int maxc = p->opt.max_cycles;
     int next_check = std::min(2, maxc);
     int last_read = 0;
     double prev_rel = 1.0;
     int status = CYLPOISSON_NOT_CONVERGED;
     int stagnant = 0;
+    std::vector<double> plane(nt);
     for (int c = 1; c <= maxc; ++c) {
-        bool norms_done = false;
-        CP_HIP(vcycle(p, 0, s, c == 1, p->d_norms + (size_t)c * nt, &norms_done));
-        if (!norms_done) CP_HIP(residual_norms(p, c, s));
+        CP_HIP(vcycle(p, 0, s, c == 1 && ring_only, c, &slots[c]));
+        if (slots[c].partial_chunks < 0) {
+            CP_HIP(residual_norms(p, c, s));
+            slots[c].partial_chunks = 0;
+        }
         st.cycles = c;
         if (c != next_check && c != maxc) continue;
         const int first = last_read + 1;
-        CP_HIP(hipMemcpyAsync(p->h_norms + (size_t)first * nt, p->d_norms + (size_t)first * nt,
-                              (size_t)(c - first + 1) * nt * sizeof(double),
-                              hipMemcpyDeviceToHost, s));
+        for (int t = first; t <= c; ++t) {
+            if (slots[t].partial_chunks > 0)
+                CP_HIP(hipMemcpyAsync(p->h_slot_partial + (size_t)t * nt * kSlotPartial,
+                                      p->d_slot_partial + (size_t)t * nt * kSlotPartial,
+                                      (size_t)nt * kSlotPartial * sizeof(double),
+                                      hipMemcpyDeviceToHost, s));
+            else
+                CP_HIP(hipMemcpyAsync(p->h_norms + (size_t)t * nt, p->d_norms + (size_t)t * nt,
+                                      (size_t)nt * sizeof(double), hipMemcpyDeviceToHost, s));
+        }
         CP_HIP(hipStreamSynchronize(s));
         ++st.checks;
         for (int t = first; t <= c; ++t) {
-            const double rel = std::sqrt(weighted(p, p->h_norms + (size_t)t * nt) / b2);
+            const double* norms = p->h_norms + (size_t)t * nt;
+            if (slots[t].partial_chunks > 0) {
+                // per-plane sums of the chunk partials, in chunk order
+                const double* part = p->h_slot_partial + (size_t)t * nt * kSlotPartial;
+                for (int q = 0; q < nt; ++q) {
+                    double sum = 0.0;
+                    for (int k = 0; k < slots[t].partial_chunks; ++k) sum += part[(size_t)q * kSlotPartial + k];
+                    plane[q] = sum;
+                }
+                norms = plane.data();
+            }
+            const double rel = std::sqrt(weighted(p, norms) / b2);
             if (t - 1 < CYLPOISSON_MAX_HISTORY) st.rel_residual_history[t - 1] = rel;
             st.n_history = t;
         }
@@ -342,12 +386,19 @@ int cylpoisson_solve(cylpoisson_plan* p, const double* rho, double* phi, double 
         Timed tm(p, kDftFwd, s);
         CP_HIP(transform(p, false, rho, L.f, p->d_s, s));
     }
+    // The fused finest level treats the interior as zero in the first cycle,
+    // so only the Dirichlet rings of the two iterate buffers are written.
+    const bool ring_only = fused_supported(p, 0);
     {
         Timed tm(p, kOther, s);
-        CP_HIP(launch_init_fine_u(L, p->nt, p->bc, s));
-        CP_HIP(launch_copy_ring(L, p->nt, L.u, L.u2, s));
+        if (ring_only) {
+            CP_HIP(launch_init_ring(L, p->nt, p->bc, s));
+        } else {
+            CP_HIP(launch_init_fine_u(L, p->nt, p->bc, s));
+            CP_HIP(launch_copy_ring(L, p->nt, L.u, L.u2, s));
+        }
     }
-    const int status = run_cycles(p, tol, s);
+    const int status = run_cycles(p, tol, s, ring_only);
     if (status == CYLPOISSON_OK || status == CYLPOISSON_NOT_CONVERGED) {
         Timed tm(p, kDftInv, s);
         CP_HIP(transform(p, true, L.u, phi, nullptr, s));
@@ -380,7 +431,7 @@ int cylpoisson_solve_planes(cylpoisson_plan* p, const double* b, double* u, doub
     CP_HIP(hipMemcpyAsync(L.u, u, bytes, hipMemcpyDeviceToDevice, s));
     CP_HIP(launch_zero_interior(L, p->nt, L.u, s));
     CP_HIP(launch_copy_ring(L, p->nt, L.u, L.u2, s));
-    const int status = run_cycles(p, tol, s);
+    const int status = run_cycles(p, tol, s, false);
     if (p->opt.timing) {
         CP_HIP(hipStreamSynchronize(s));
         collect_timing(p);
