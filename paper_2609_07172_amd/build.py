@@ -5,6 +5,8 @@ import glob
 import os
 import shutil
 import subprocess
+import tempfile
+from concurrent.futures import ThreadPoolExecutor
 
 PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
@@ -18,36 +20,46 @@ def hipcc() -> str:
     raise RuntimeError("hipcc not found")
 
 
-def command(out: str = LIB) -> list[str]:
-    srcs = sorted(glob.glob(os.path.join(PKG, "csrc", "*.hip")))
-    return [
-        hipcc(),
-        "--offload-arch=gfx950",
-        "-O3",
-        "-std=c++17",
-        "-fPIC",
-        "-shared",
-        "-Wall",
-        "-Wno-unused-function",
-        # packed FP32 instructions stay disabled in every HIP translation unit
-        "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-        "-I", os.path.join(ROOT, "include"),
-        "-I", os.path.join(PKG, "csrc"),
-        "-o", out,
-        *srcs,
-    ]
+FLAGS = [
+    "--offload-arch=gfx950",
+    "-O3",
+    "-std=c++17",
+    "-fPIC",
+    "-Wall",
+    "-Wno-unused-function",
+    # packed FP32 instructions stay disabled in every HIP translation unit
+    "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    "-I", os.path.join(ROOT, "include"),
+    "-I", os.path.join(PKG, "csrc"),
+]
 
 
-def build(verbose: bool = False) -> str:
-    """Compile every source under csrc/ into one shared library; return its path."""
-    tmp = LIB + ".tmp"
-    cmd = command(tmp)
+def sources() -> list[str]:
+    return sorted(glob.glob(os.path.join(PKG, "csrc", "*.hip")))
+
+
+def _run(cmd: list[str], verbose: bool) -> None:
     res = subprocess.run(cmd, capture_output=True, text=True)
     if verbose or res.returncode != 0:
         print(" ".join(cmd))
         print(res.stdout[-20000:], res.stderr[-20000:])
     if res.returncode != 0:
-        raise RuntimeError("hipcc failed (exit %d)" % res.returncode)
+        raise RuntimeError("hipcc failed (exit %d) on %s" % (res.returncode, cmd[-1]))
+
+
+def build(verbose: bool = False, jobs: int | None = None) -> str:
+    """Compile every source under csrc/ (in parallel) and link one shared library; return its path."""
+    cc = hipcc()
+    srcs = sources()
+    jobs = jobs or max(1, min(len(srcs), int(os.environ.get("MAX_JOBS", "8")), os.cpu_count() or 1))
+    with tempfile.TemporaryDirectory(prefix="cylpoisson_build_") as tmpdir:
+        objs = [os.path.join(tmpdir, os.path.basename(src) + ".o") for src in srcs]
+        cmds = [[cc, *FLAGS, "-c", "-o", obj, src] for src, obj in zip(srcs, objs)]
+        with ThreadPoolExecutor(jobs) as pool:
+            for f in [pool.submit(_run, c, verbose) for c in cmds]:
+                f.result()
+        tmp = LIB + ".tmp"
+        _run([cc, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp, *objs], verbose)
     os.replace(tmp, LIB)
     return LIB
 

@@ -495,6 +495,16 @@ __global__ void __launch_bounds__(512) k_pass(PassArgs a) {
     pass.run();
 }
 
+// The same pass under its own symbol, launched for the finest level with the
+// default sweep count and prefetch depth, so that kernel traces and counters
+// report the finest level apart from the coarser ones.
+template <int NU, int PD, bool DOWN, bool ZERO_U>
+__global__ void __launch_bounds__(512) k_pass_fine(PassArgs a) {
+    extern __shared__ double smem[];
+    Pass<NU, PD, DOWN, ZERO_U> pass(a, smem);
+    pass.run();
+}
+
 }  // namespace
 
 }  // namespace cp
@@ -504,44 +514,52 @@ namespace cp {
 namespace {
 
 template <int NU, int PD, bool DOWN, bool ZERO_U>
-hipError_t launch_t(const PassArgs& a, int blocks, int threads, size_t lds, hipStream_t s) {
+hipError_t launch_t(bool fine, const PassArgs& a, int blocks, int threads, size_t lds, hipStream_t s) {
+    if constexpr (NU == 2 && PD == 1) {
+        if (fine) {
+            k_pass_fine<NU, PD, DOWN, ZERO_U><<<blocks, threads, lds, s>>>(a);
+            return hipGetLastError();
+        }
+    } else {
+        (void)fine;
+    }
     k_pass<NU, PD, DOWN, ZERO_U><<<blocks, threads, lds, s>>>(a);
     return hipGetLastError();
 }
 
 template <int NU, int PD>
-hipError_t launch_pd(bool down, bool zero_u, const PassArgs& a, int blocks, int threads, size_t lds,
-                     hipStream_t s) {
+hipError_t launch_pd(bool fine, bool down, bool zero_u, const PassArgs& a, int blocks, int threads,
+                     size_t lds, hipStream_t s) {
     if (down)
-        return zero_u ? launch_t<NU, PD, true, true>(a, blocks, threads, lds, s)
-                      : launch_t<NU, PD, true, false>(a, blocks, threads, lds, s);
-    return launch_t<NU, PD, false, false>(a, blocks, threads, lds, s);
+        return zero_u ? launch_t<NU, PD, true, true>(fine, a, blocks, threads, lds, s)
+                      : launch_t<NU, PD, true, false>(fine, a, blocks, threads, lds, s);
+    return launch_t<NU, PD, false, false>(fine, a, blocks, threads, lds, s);
 }
 
 template <int NU>
-hipError_t launch_nu_pd(int pd, bool down, bool zero_u, const PassArgs& a, int blocks, int threads,
-                        size_t lds, hipStream_t s) {
+hipError_t launch_nu_pd(bool fine, int pd, bool down, bool zero_u, const PassArgs& a, int blocks,
+                        int threads, size_t lds, hipStream_t s) {
     if constexpr (NU == 2) {
         switch (pd) {
-            case 1: return launch_pd<NU, 1>(down, zero_u, a, blocks, threads, lds, s);
-            case 2: return launch_pd<NU, 2>(down, zero_u, a, blocks, threads, lds, s);
-            case 3: return launch_pd<NU, 3>(down, zero_u, a, blocks, threads, lds, s);
-            case 4: return launch_pd<NU, 4>(down, zero_u, a, blocks, threads, lds, s);
+            case 1: return launch_pd<NU, 1>(fine, down, zero_u, a, blocks, threads, lds, s);
+            case 2: return launch_pd<NU, 2>(fine, down, zero_u, a, blocks, threads, lds, s);
+            case 3: return launch_pd<NU, 3>(fine, down, zero_u, a, blocks, threads, lds, s);
+            case 4: return launch_pd<NU, 4>(fine, down, zero_u, a, blocks, threads, lds, s);
             default: return hipErrorInvalidValue;
         }
     } else {
         (void)pd;  // other sweep counts use a prefetch depth of two rows
-        return launch_pd<NU, 2>(down, zero_u, a, blocks, threads, lds, s);
+        return launch_pd<NU, 2>(fine, down, zero_u, a, blocks, threads, lds, s);
     }
 }
 
-hipError_t launch_nu(int nu, int pd, bool down, bool zero_u, const PassArgs& a, int blocks,
+hipError_t launch_nu(bool fine, int nu, int pd, bool down, bool zero_u, const PassArgs& a, int blocks,
                      int threads, size_t lds, hipStream_t s) {
     switch (nu) {
-        case 1: return launch_nu_pd<1>(pd, down, zero_u, a, blocks, threads, lds, s);
-        case 2: return launch_nu_pd<2>(pd, down, zero_u, a, blocks, threads, lds, s);
-        case 3: return launch_nu_pd<3>(pd, down, zero_u, a, blocks, threads, lds, s);
-        case 4: return launch_nu_pd<4>(pd, down, zero_u, a, blocks, threads, lds, s);
+        case 1: return launch_nu_pd<1>(fine, pd, down, zero_u, a, blocks, threads, lds, s);
+        case 2: return launch_nu_pd<2>(fine, pd, down, zero_u, a, blocks, threads, lds, s);
+        case 3: return launch_nu_pd<3>(fine, pd, down, zero_u, a, blocks, threads, lds, s);
+        case 4: return launch_nu_pd<4>(fine, pd, down, zero_u, a, blocks, threads, lds, s);
         default: return hipErrorInvalidValue;
     }
 }
@@ -626,7 +644,7 @@ hipError_t fused_down(cylpoisson_plan* p, int l, bool zero_u, bool zero_interior
     a.u_out = L.u2;
     a.fc = C.f;
     a.zero_interior = zero_interior ? 1 : 0;
-    return launch_nu(p->opt.nu1, p->opt.prefetch, true, zero_u, a, sh.blocks, sh.threads, sh.lds, s);
+    return launch_nu(l == 0, p->opt.nu1, p->opt.prefetch, true, zero_u, a, sh.blocks, sh.threads, sh.lds, s);
 }
 
 int fused_chunks(const cylpoisson_plan* p, int l, int nu) { return pass_shape(p, l, nu).nchunks; }
@@ -644,7 +662,7 @@ hipError_t fused_up(cylpoisson_plan* p, int l, double* partial, int partial_ld, 
     a.partial = partial;
     a.partial_ld = partial_ld;
     if (nchunks) *nchunks = sh.nchunks;
-    return launch_nu(p->opt.nu2, p->opt.prefetch, false, false, a, sh.blocks, sh.threads, sh.lds, s);
+    return launch_nu(l == 0, p->opt.nu2, p->opt.prefetch, false, false, a, sh.blocks, sh.threads, sh.lds, s);
 }
 
 }  // namespace cp
