@@ -151,6 +151,39 @@ def ingest_counters(fetch_dir: str, write_dir: str, probe_mib: int):
     print(json.dumps(out, indent=1))
 
 
+def time_variant(plan, rho_d, phi_d, args, ref, phit, options):
+    """Time the same solve with other solver options (same inputs, same protocol)."""
+    import torch
+
+    for k, v in options.items():
+        plan.set_option(k, v)
+    for _ in range(args.warmup):
+        plan.solve(rho_d, tol=args.tol, phi=phi_d)
+    torch.cuda.synchronize()
+    plan.set_option("timing", 1)
+    sums = {}
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        _, st = plan.solve(rho_d, tol=args.tol, phi=phi_d)
+        for k, v in st["kernel_ms"].items():
+            sums[k] = sums.get(k, 0.0) + v
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) / args.steps * 1e3
+    plan.set_option("timing", 0)
+    out = {"options": options, "ms": round(ms, 4), "cycles": st["cycles"],
+           "refinements": st["refinements"], "rel_residual": st["rel_residual"],
+           "kernel_ms_per_solve": {k: round(v / args.steps, 4) for k, v in sums.items()}}
+    if ref is not None:
+        phi = phi_d.cpu().numpy()
+        out["rel_l2_vs_oracle"] = interior_rel(phi, ref)
+        out["rel_l2_vs_phi_true"] = interior_rel(phi, phit)
+    log(f"variant {options}: {ms:.3f} ms/solve, cycles {st['cycles']}, "
+        f"refinements {st['refinements']}, rel residual {st['rel_residual']:.3e}")
+    for k in options:
+        plan.set_option(k, {"precision": 64, "inner_cycles": 2}.get(k, 0))
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -160,6 +193,8 @@ def main():
     ap.add_argument("--workload", choices=["paper", "batched", "small"], default="paper")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg (blob rho)")
     ap.add_argument("--option", action="append", default=[], help="solver option key=value")
+    ap.add_argument("--no-variants", action="store_true",
+                    help="time only the plain FP64 solve (skip the mixed-precision variant)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="after the timed region, copy MIB MiB on the device three times "
                          "(the reference kernel for the HBM byte counters)")
@@ -245,6 +280,11 @@ def main():
     torch.cuda.synchronize()
     ms_plain = (time.perf_counter() - t0) / args.steps * 1e3
 
+    variants = {}
+    if not args.no_variants:
+        variants["mixed_fp32"] = time_variant(plan, rho_d, phi_d, args, ref, phit,
+                                              {"precision": 32, "inner_cycles": 2})
+
     if args.copy_probe > 0:
         # a plain device copy of known size: the scale for the HBM byte counters
         n = args.copy_probe * (1 << 20) // 8
@@ -299,6 +339,7 @@ def main():
         "poisson_cells_per_s": problem.nodes / (ms * 1e-3),
         "kernel_ms_per_solve": {k: round(v / args.steps, 4) for k, v in sums.items()},
         "kernel_launches_per_solve": {k: v / args.steps for k, v in launches.items()},
+        "variants": variants,
     }
     if ref is not None:
         out["rel_l2_vs_oracle"] = interior_rel(phi, ref)

@@ -83,9 +83,15 @@ typedef struct {
      * (all zero otherwise).  Classes: 0 forward DFT, 1 inverse DFT, 2 finest-level
      * down pass (smoothing, residual, restriction), 3 finest-level up pass
      * (prolongation, smoothing, residual norm), 4 all coarser levels (one
-     * interval per cycle), 5 other work (initialisation, norm reductions). */
+     * interval per cycle), 5 other work (initialisation, norm reductions, the
+     * FP64 refinement steps of a mixed-precision solve). */
     int kernel_launches[CYLPOISSON_KERNEL_CLASSES];
     double kernel_ms[CYLPOISSON_KERNEL_CLASSES];
+    /* Mixed precision ("precision" = 32): FP64 refinement steps after the
+     * first residual, i.e. the number of FP32 inner solves; `cycles` counts
+     * their FP32 V-cycles and the history holds the FP64 relative residual
+     * after each inner solve (at index cycles - 1).  0 on the FP64 path. */
+    int refinements;
 } cylpoisson_stats;
 
 typedef struct {
@@ -126,12 +132,22 @@ void cylpoisson_plan_destroy(cylpoisson_plan* plan);
  *                    kernel (with "fused" = 1; default 1)
  *   "fft"            1 = azimuthal transforms as register FFTs when Ntheta is 16,
  *                    32, 64 or 128; 0 = dense DFT product (default 1)
- * Returns CYLPOISSON_OK or CYLPOISSON_EINVAL. */
+ *   "precision"      64 = FP64 V-cycles (default); 32 = mixed precision: FP64
+ *                    iterative refinement (residual, solution accumulation, DFTs)
+ *                    around V-cycles whose smoothing, restriction and prolongation
+ *                    run in FP32, with the coarsest solve still in FP64.  Setting
+ *                    32 allocates the FP32 level buffers (ENOMEM on failure); it
+ *                    needs the fused passes and the LDS bottom kernel on this grid
+ *                    (EINVAL otherwise, also at solve time if options changed)
+ *   "inner_cycles"   FP32 V-cycles per refinement step (1 .. 8; default 2)
+ * Returns CYLPOISSON_OK, CYLPOISSON_EINVAL or CYLPOISSON_ENOMEM. */
 int cylpoisson_plan_set_option(cylpoisson_plan* plan, const char* key, double value);
 
 /* Solve for phi given rho (both device node arrays).  Zero initial guess,
  * V-cycles until the relative residual (cylpoisson_stats) is <= tol or
- * max_cycles is reached.  rho is read only at interior nodes; every node of
+ * max_cycles is reached (with "precision" = 32: refinement steps of
+ * "inner_cycles" FP32 V-cycles each, while the total stays within max_cycles;
+ * the residual is always the FP64 one).  rho is read only at interior nodes; every node of
  * phi is written, boundary nodes with the Dirichlet values.  tol > 0.
  * Returns OK, NOT_CONVERGED (phi holds the last iterate), ENONFINITE (phi not
  * written), EINVAL, EDEVICE or EHIP.  Blocks until the result is decided;

@@ -51,7 +51,8 @@ class Stats(ctypes.Structure):
                 ("initial_residual_norm", ctypes.c_double),
                 ("rel_residual_history", ctypes.c_double * MAX_HISTORY),
                 ("kernel_launches", ctypes.c_int * len(KERNEL_CLASSES)),
-                ("kernel_ms", ctypes.c_double * len(KERNEL_CLASSES))]
+                ("kernel_ms", ctypes.c_double * len(KERNEL_CLASSES)),
+                ("refinements", ctypes.c_int)]
 
     def as_dict(self) -> dict:
         hist = [self.rel_residual_history[i] for i in range(min(self.n_history, MAX_HISTORY))]
@@ -60,7 +61,8 @@ class Stats(ctypes.Structure):
                 "initial_residual_norm": self.initial_residual_norm,
                 "history": [None if math.isnan(h) else h for h in hist],
                 "kernel_launches": dict(zip(KERNEL_CLASSES, list(self.kernel_launches))),
-                "kernel_ms": dict(zip(KERNEL_CLASSES, list(self.kernel_ms)))}
+                "kernel_ms": dict(zip(KERNEL_CLASSES, list(self.kernel_ms))),
+                "refinements": self.refinements}
 
 
 class Info(ctypes.Structure):

@@ -4,6 +4,10 @@
 // small levels are launch- and latency-bound as separate kernels; here they
 // cost a few workgroup barriers each.  Same schedule and point arithmetic as
 // kernels.hip (red-black order, R = P^T, bilinear P, dense coarsest inverse).
+// Generic in the value type T of the levels' arrays: double on the FP64 path,
+// float in the inner V-cycles of the mixed-precision solve, where the coarsest
+// correction is still computed in FP64 (the inverse is FP64; the FP32
+// residual is widened before the product and the result rounded once).
 #include "cp_internal.h"
 #include "stencil.h"
 
@@ -11,12 +15,13 @@ namespace cp {
 
 namespace {
 
+template <typename T>
 struct BottomArgs {
     const BottomLevel* lv;  // levels handled here, finest first
     int nlev;
     int off_r;              // LDS offset of the residual scratch (finest level's size)
-    const double* f_in;     // right-hand side of the finest level here (global)
-    double* u_out;          // its solution (global, interior written)
+    const T* f_in;          // right-hand side of the finest level here (global)
+    T* u_out;               // its solution (global, interior written)
     const double* lam;
     const double* cinv;     // coarsest dense inverse per plane
     int ncoarse;
@@ -27,11 +32,11 @@ struct BottomArgs {
 __device__ __forceinline__ int interior(const LevelView& v) { return (v.nr - 2) * (v.nz - 2); }
 
 // One red-black colour on level L in LDS.
-__device__ void lds_half_sweep(const BottomLevel& L, double* sm, double lam, int color,
-                               double omega) {
+template <typename T>
+__device__ void lds_half_sweep(const BottomLevel& L, T* sm, double lam, int color, T omega) {
     const LevelView& v = L.v;
-    double* u = sm + L.off_u;
-    const double* f = sm + L.off_f;
+    T* u = sm + L.off_u;
+    const T* f = sm + L.off_f;
     const int ni = v.nr - 2, nk = v.nz - 2;
     const int hw = (ni + 1) / 2;
     for (int q = threadIdx.x; q < hw * nk; q += blockDim.x) {
@@ -39,35 +44,39 @@ __device__ void lds_half_sweep(const BottomLevel& L, double* sm, double lam, int
         const int i = 2 - (color ^ (k & 1)) + 2 * (q % hw);
         if (i > v.nr - 2) continue;
         const int o = k * v.nr + i;
-        const Coef c = coef_at(v, i, k, lam);
+        const CoefT<T> c = coef_as<T>(coef_at(v, i, k, lam));
         u[o] = relax(u[o], f[o], u[o - 1], u[o + 1], u[o - v.nr], u[o + v.nr], c, omega);
     }
     __syncthreads();
 }
 
-__device__ void lds_smooth(const BottomLevel& L, double* sm, double lam, int sweeps, double omega) {
+template <typename T>
+__device__ void lds_smooth(const BottomLevel& L, T* sm, double lam, int sweeps, T omega) {
     for (int s = 0; s < sweeps; ++s) {
         lds_half_sweep(L, sm, lam, 0, omega);
         lds_half_sweep(L, sm, lam, 1, omega);
     }
 }
 
-__global__ void __launch_bounds__(512) k_bottom(BottomArgs a) {
-    extern __shared__ double sm[];
+template <typename T>
+__global__ void __launch_bounds__(512) k_bottom(BottomArgs<T> a) {
+    extern __shared__ double smem_bottom[];
+    T* sm = (T*)smem_bottom;
     const int p = blockIdx.x;
     const double lam = a.lam[p];
+    const T omega = (T)a.omega;
     // zero every level's arrays (rings stay zero), then load the right-hand side
     {
         const BottomLevel& C = a.lv[a.nlev - 1];
         const int total = C.off_f + C.v.nr * C.v.nz;
-        for (int q = threadIdx.x; q < total; q += blockDim.x) sm[q] = 0.0;
+        for (int q = threadIdx.x; q < total; q += blockDim.x) sm[q] = T(0);
         const BottomLevel& F = a.lv[0];
-        for (int q = threadIdx.x; q < F.v.nr * F.v.nz; q += blockDim.x) sm[a.off_r + q] = 0.0;
+        for (int q = threadIdx.x; q < F.v.nr * F.v.nz; q += blockDim.x) sm[a.off_r + q] = T(0);
     }
     __syncthreads();
     {
         const BottomLevel& F = a.lv[0];
-        const double* fg = a.f_in + (long long)p * F.v.pstride;
+        const T* fg = a.f_in + (long long)p * F.v.pstride;
         const int ni = F.v.nr - 2;
         for (int q = threadIdx.x; q < interior(F.v); q += blockDim.x) {
             const int i = q % ni + 1, k = q / ni + 1;
@@ -79,35 +88,35 @@ __global__ void __launch_bounds__(512) k_bottom(BottomArgs a) {
     for (int l = 0; l + 1 < a.nlev; ++l) {
         const BottomLevel& L = a.lv[l];
         const BottomLevel& C = a.lv[l + 1];
-        lds_smooth(L, sm, lam, a.nu1, a.omega);
+        lds_smooth(L, sm, lam, a.nu1, omega);
         const LevelView& v = L.v;
         const int ni = v.nr - 2;
-        double* r = sm + a.off_r;
-        const double* u = sm + L.off_u;
-        const double* f = sm + L.off_f;
+        T* r = sm + a.off_r;
+        const T* u = sm + L.off_u;
+        const T* f = sm + L.off_f;
         for (int q = threadIdx.x; q < interior(v); q += blockDim.x) {
             const int i = q % ni + 1, k = q / ni + 1;
             const int o = k * v.nr + i;
             r[o] = residual(u[o], f[o], u[o - 1], u[o + 1], u[o - v.nr], u[o + v.nr],
-                            coef_at(v, i, k, lam));
+                            coef_as<T>(coef_at(v, i, k, lam)));
         }
         __syncthreads();
         const int nci = C.v.nr - 2;
-        double* fc = sm + C.off_f;
+        T* fc = sm + C.off_f;
         for (int q = threadIdx.x; q < interior(C.v); q += blockDim.x) {
             const int I = q % nci + 1, K = q / nci + 1;
             const int fi = L.tr.cidx[I], fk = L.tz.cidx[K];
-            const double* rp = r + fk * v.nr + fi;
-            const double wzm = L.tz.rwm[K], wzp = L.tz.rwp[K];
-            double col[3];
+            const T* rp = r + fk * v.nr + fi;
+            const T wzm = (T)L.tz.rwm[K], wzp = (T)L.tz.rwp[K];
+            T col[3];
 #pragma unroll
             for (int d = 0; d < 3; ++d)
                 col[d] = restrict3(rp[d - 1 - v.nr], rp[d - 1], rp[d - 1 + v.nr], wzm, wzp);
-            fc[K * C.v.nr + I] = restrict3(col[0], col[1], col[2], L.tr.rwm[I], L.tr.rwp[I]);
+            fc[K * C.v.nr + I] = restrict3(col[0], col[1], col[2], (T)L.tr.rwm[I], (T)L.tr.rwp[I]);
         }
         __syncthreads();
         // the residual scratch must be zero on the next level's ring columns it reads
-        for (int q = threadIdx.x; q < v.nr * v.nz; q += blockDim.x) r[q] = 0.0;
+        for (int q = threadIdx.x; q < v.nr * v.nz; q += blockDim.x) r[q] = T(0);
         __syncthreads();
     }
     // coarsest: u = A^{-1} f (zero initial guess), inverse precomputed per plane
@@ -115,21 +124,21 @@ __global__ void __launch_bounds__(512) k_bottom(BottomArgs a) {
         const BottomLevel& C = a.lv[a.nlev - 1];
         const int ni = C.v.nr - 2, n = a.ncoarse;
         const double* Ci = a.cinv + (long long)p * n * n;
-        double* u = sm + C.off_u;
-        const double* f = sm + C.off_f;
-        double* tmp = sm + a.off_r;  // coarsest right-hand side in unknown order
+        T* u = sm + C.off_u;
+        const T* f = sm + C.off_f;
+        T* tmp = sm + a.off_r;  // coarsest right-hand side in unknown order
         for (int q = threadIdx.x; q < n; q += blockDim.x) {
             const int i = q % ni + 1, k = q / ni + 1;
             const int o = k * C.v.nr + i;
             tmp[q] = residual(u[o], f[o], u[o - 1], u[o + 1], u[o - C.v.nr], u[o + C.v.nr],
-                              coef_at(C.v, i, k, lam));
+                              coef_as<T>(coef_at(C.v, i, k, lam)));
         }
         __syncthreads();
-        double* corr = tmp + n;
+        T* corr = tmp + n;
         for (int q = threadIdx.x; q < n; q += blockDim.x) {
             double s = 0.0;
-            for (int t = 0; t < n; ++t) s = fma(Ci[(long long)q * n + t], tmp[t], s);
-            corr[q] = s;
+            for (int t = 0; t < n; ++t) s = fma(Ci[(long long)q * n + t], (double)tmp[t], s);
+            corr[q] = (T)s;
         }
         __syncthreads();
         for (int q = threadIdx.x; q < n; q += blockDim.x) {
@@ -137,7 +146,7 @@ __global__ void __launch_bounds__(512) k_bottom(BottomArgs a) {
             u[k * C.v.nr + i] += corr[q];
         }
         __syncthreads();
-        for (int q = threadIdx.x; q < 2 * n; q += blockDim.x) tmp[q] = 0.0;
+        for (int q = threadIdx.x; q < 2 * n; q += blockDim.x) tmp[q] = T(0);
         __syncthreads();
     }
     // up
@@ -146,20 +155,20 @@ __global__ void __launch_bounds__(512) k_bottom(BottomArgs a) {
         const BottomLevel& C = a.lv[l + 1];
         const LevelView& v = L.v;
         const int ni = v.nr - 2;
-        double* u = sm + L.off_u;
-        const double* uc = sm + C.off_u;
+        T* u = sm + L.off_u;
+        const T* uc = sm + C.off_u;
         for (int q = threadIdx.x; q < interior(v); q += blockDim.x) {
             const int i = q % ni + 1, k = q / ni + 1;
             const int I = L.tr.pidx[i], K = L.tz.pidx[k];
-            u[k * v.nr + i] += prolong_value(uc + K * C.v.nr + I, C.v.nr, L.tr.pwl[i], L.tr.pwr[i],
-                                             L.tz.pwl[k], L.tz.pwr[k]);
+            u[k * v.nr + i] += prolong_value(uc + K * C.v.nr + I, C.v.nr, (T)L.tr.pwl[i], (T)L.tr.pwr[i],
+                                             (T)L.tz.pwl[k], (T)L.tz.pwr[k]);
         }
         __syncthreads();
-        lds_smooth(L, sm, lam, a.nu2, a.omega);
+        lds_smooth(L, sm, lam, a.nu2, omega);
     }
     {
         const BottomLevel& F = a.lv[0];
-        double* ug = a.u_out + (long long)p * F.v.pstride;
+        T* ug = a.u_out + (long long)p * F.v.pstride;
         const int ni = F.v.nr - 2;
         for (int q = threadIdx.x; q < interior(F.v); q += blockDim.x) {
             const int i = q % ni + 1, k = q / ni + 1;
@@ -170,6 +179,7 @@ __global__ void __launch_bounds__(512) k_bottom(BottomArgs a) {
 
 }  // namespace
 
+// LDS of the FP64 bottom kernel; the FP32 one has the same layout in floats.
 size_t bottom_lds_bytes(const cylpoisson_plan* p, int lb) {
     const int nl = (int)p->hl.size();
     size_t n = 0;
@@ -179,30 +189,53 @@ size_t bottom_lds_bytes(const cylpoisson_plan* p, int lb) {
     return (n + r) * sizeof(double);
 }
 
-hipError_t bottom_prepare(const cylpoisson_plan* p, int lb) {
-    const size_t bytes = bottom_lds_bytes(p, lb);
+namespace {
+
+template <typename T>
+hipError_t bottom_prepare_t(size_t bytes) {
     if (bytes > 64 * 1024)
-        return hipFuncSetAttribute((const void*)k_bottom, hipFuncAttributeMaxDynamicSharedMemorySize,
+        return hipFuncSetAttribute((const void*)k_bottom<T>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                    (int)bytes);
     return hipSuccess;
 }
 
-hipError_t launch_bottom(cylpoisson_plan* p, hipStream_t s) {
+template <typename T>
+hipError_t launch_bottom_t(cylpoisson_plan* p, const T* f_in, T* u_out, hipStream_t s) {
     const int lb = p->bottom_level;
-    BottomArgs a{};
+    BottomArgs<T> a{};
     a.lv = p->d_bottom;
     a.nlev = (int)p->hl.size() - lb;
     a.off_r = p->bottom_off_r;
-    a.f_in = p->dl[lb].f;
-    a.u_out = p->dl[lb].u;
+    a.f_in = f_in;
+    a.u_out = u_out;
     a.lam = p->d_lam;
     a.cinv = p->d_cinv;
     a.ncoarse = p->coarse_n;
     a.nu1 = p->opt.nu1;
     a.nu2 = p->opt.nu2;
     a.omega = p->opt.omega;
-    k_bottom<<<p->nt, 512, bottom_lds_bytes(p, lb), s>>>(a);
+    const size_t bytes = bottom_lds_bytes(p, lb) / sizeof(double) * sizeof(T);
+    k_bottom<T><<<p->nt, 512, bytes, s>>>(a);
     return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t bottom_prepare(const cylpoisson_plan* p, int lb) {
+    const size_t bytes = bottom_lds_bytes(p, lb);
+    hipError_t e = bottom_prepare_t<double>(bytes);
+    if (e == hipSuccess) e = bottom_prepare_t<float>(bytes / 2);
+    return e;
+}
+
+hipError_t launch_bottom(cylpoisson_plan* p, hipStream_t s) {
+    const int lb = p->bottom_level;
+    return launch_bottom_t<double>(p, p->dl[lb].f, p->dl[lb].u, s);
+}
+
+hipError_t launch_bottom32(cylpoisson_plan* p, hipStream_t s) {
+    const int lb = p->bottom_level;
+    return launch_bottom_t<float>(p, p->dl32[lb].f, p->dl32[lb].u, s);
 }
 
 }  // namespace cp

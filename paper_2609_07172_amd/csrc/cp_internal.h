@@ -67,6 +67,16 @@ struct DeviceLevel {
     double zc0 = 0, zs0 = 0, zn0 = 0;
 };
 
+// FP32 copies of a level's iterate buffers and right-hand side, used by the
+// inner V-cycles of the mixed-precision solve (same layout as the FP64 ones).
+// On level 0, f holds the FP32 residual of the FP64 refinement and u the
+// correction it solves for.
+struct DeviceLevel32 {
+    float* u = nullptr;
+    float* u2 = nullptr;
+    float* f = nullptr;
+};
+
 // A level handled by the bottom kernel: its global tables and where its
 // iterate and right-hand side live in LDS (full node arrays, pitch nr).
 struct BottomLevel {
@@ -97,6 +107,8 @@ struct Options {
     int timing = 0;      // record per-kernel-class device times with HIP events
     int bottom = 1;      // run the small levels in one LDS-resident kernel per plane
     int fft = 1;         // azimuthal transforms as register FFTs where Ntheta allows
+    int precision = 64;  // 64: FP64 V-cycles; 32: FP32 inner V-cycles under FP64 refinement
+    int inner_cycles = 2;  // FP32 V-cycles per FP64 refinement step
 };
 
 }  // namespace cp
@@ -110,6 +122,7 @@ struct cylpoisson_plan {
 
     std::vector<cp::HostLevel> hl;
     std::vector<cp::DeviceLevel> dl;
+    std::vector<cp::DeviceLevel32> dl32;  // levels 0 .. bottom_level (mixed precision only)
     std::vector<double> lam;  // per plane
     int coarse_n = 0;         // interior unknowns of the coarsest plane
 
@@ -178,6 +191,13 @@ hipError_t launch_rhs_norms(const DeviceLevel& L, int nt, const double* lam, con
                             const double* f, double* partial, double* norms_out, hipStream_t s);
 hipError_t launch_copy_ring(const DeviceLevel& L, int nt, const double* src, double* dst,
                             hipStream_t s);
+// FP64 refinement step of the mixed-precision solve on the finest level:
+// u_out = u_in + e (when e is given, u_out != u_in; else the interior of u_in
+// is taken as zero and u_out's interior written so, in place allowed),
+// r = f - A u_out rounded to FP32, per-plane FP64 sums of r^2.
+hipError_t launch_refine(const DeviceLevel& L, int nt, const double* lam, const double* uin,
+                         double* uout, const float* e, const double* f, float* r32,
+                         double* partial, double* norms_out, hipStream_t s);
 
 // ---- register FFTs (fft.hip) ----
 bool fft_supported(int n);
@@ -185,9 +205,12 @@ hipError_t launch_fft(bool inverse, int n, const double* in, double* out, long l
                       const double* cs, int nr, const double* tw, hipStream_t s);
 
 // ---- bottom of the V-cycle (bottom.hip) ----
-size_t bottom_lds_bytes(const cylpoisson_plan* p, int lb);
+size_t bottom_lds_bytes(const cylpoisson_plan* p, int lb);  // FP64 values
 hipError_t bottom_prepare(const cylpoisson_plan* p, int lb);
 hipError_t launch_bottom(cylpoisson_plan* p, hipStream_t s);
+// The same V-cycle bottom on the FP32 levels; the coarsest correction is
+// computed in FP64 from the FP32 residual.
+hipError_t launch_bottom32(cylpoisson_plan* p, hipStream_t s);
 
 // ---- fused passes (fused.hip) ----
 bool fused_supported(const cylpoisson_plan* p, int l);
@@ -195,5 +218,10 @@ hipError_t fused_down(cylpoisson_plan* p, int l, bool zero_u, bool zero_interior
 hipError_t fused_up(cylpoisson_plan* p, int l, double* partial, int partial_ld, int* nchunks,
                     hipStream_t s);
 int fused_chunks(const cylpoisson_plan* p, int l, int nu);
+// FP32 passes on the dl32 buffers (mixed precision), no residual norms.
+hipError_t fused_down32(cylpoisson_plan* p, int l, bool zero_u, hipStream_t s);
+// Every level above the bottom kernel has fused passes (plan.hip).
+bool mixed_supported(const cylpoisson_plan* p);
+hipError_t fused_up32(cylpoisson_plan* p, int l, hipStream_t s);
 
 }  // namespace cp

@@ -1,634 +1,14 @@
-// Fused streaming multigrid passes for gfx950.
-//
-// One workgroup owns one plane and a chunk of axial rows, with the full
-// radial width in the block: thread t holds radial columns 2t+1 and 2t+2.
-// The block marches along z.  At step x it consumes row x (loaded one step
-// ahead), and in the same step runs every red-black half-sweep of the pass
-// on the rows behind it (half-sweep h on row x-1-h), so all sweeps of a
-// pass stream u and f through registers once.  Vertical neighbours stay in
-// the owning thread's registers; horizontal neighbours are exchanged through
-// a small LDS ring of rows, one barrier per step.  Each half-sweep only reads
-// neighbour values published one step earlier, so the schedule is exactly
-// the global red-black order (same arithmetic per node as kernels.hip).
-//
-// Down pass (level l -> l+1): nu1 sweeps, residual, restriction f_{l+1} = P^T r.
-// Up pass (level l): u += P e_{l+1}, nu2 sweeps, optional residual norm.
-//
-// A chunk [za, zb) recomputes a halo of 2 nu + 2 rows below and 2 nu + 1
-// rows above, reading the input iterate only: outputs go to another buffer.
-#include "cp_internal.h"
-#include "stencil.h"
+// Fused streaming multigrid passes, FP64 instantiations and the entry points
+// of the FP64 V-cycle (the pass itself is in fused_pass.h).
+#include "fused_pass.h"
 
 namespace cp {
-
-namespace {
-
-__device__ __forceinline__ void lds_barrier() {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
-    __builtin_amdgcn_s_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
-}
-
-struct PassArgs {
-    LevelView v;   // this level
-    LevelView vc;  // next coarser level
-    Transfer1D tr, tz;
-    const double* u_in;
-    const double* f;
-    double* u_out;
-    double* fc;          // down: coarse right-hand side
-    const double* ec;    // up: coarse correction
-    const double* lam;
-    const int* colc;     // fine column -> coarse interior column it coincides with, else -1
-    const int* rowc;     // fine row -> coarse interior row it coincides with, else -1
-    int spec_lo;         // rows >= spec_lo have axial coefficients other than (zc0, zs0, zn0)
-    double* partial;     // up: per (plane, chunk) sum of squared residuals, or nullptr
-    int partial_ld;      // stride between planes in `partial`
-    double omega, zc0, zs0, zn0;
-    int zero_interior;   // down: treat the interior of the input iterate as zero (ring is read)
-    int chunk, nchunks, nt, tn;  // rows per chunk, chunks per plane, planes, columns pairs
-    int xcd_major;       // map consecutive chunks of a plane to one XCD
-};
-
-template <int NU, int PD, bool DOWN, bool ZERO_U>
-struct Pass {
-    // Register history: rows x+PD (prefetch) down to x-2NU-2.  Q is even and
-    // the first row s is even, so slot J holds rows of one parity and the
-    // colour of each column in every half-sweep is known at compile time.
-    static constexpr int Q0 = 2 * NU + 3 + PD;
-    static constexpr int Q = (Q0 & 1) ? Q0 + 1 : Q0;
-    static constexpr int QS = Q + 1;  // LDS doubles per column history (odd stride)
-
-    const PassArgs& a;
-    double* lds;
-    // LDS layout (doubles): column histories A[tn + 1][QS] (column 2t+1 of thread t)
-    // and B[tn + 1][QS] (column 2j; j = 0 is the radial ring column, j = t + 1 is
-    // column 2t+2 of thread t); restriction rows V[2][2][tn + 1]; per-row tables.
-    double* At;  // own column c1
-    double* Bt;  // own column c2
-    double* Bl;  // column 2t (west of c1)
-    double* Ar;  // column 2t+3 (east of c2)
-    int t, c1, c2, k1, k2;
-    bool act1, act2;
-    int p, chunk, za, zb, s, lend, rows;
-    double lam;
-    Coef cu1, cu2;
-    double rw1, re1, rb1, rm1, rw2, re2, rb2, rm2;  // radial tables of the two columns
-    const double* urow;  // row s + ... of the input iterate (advanced per issued row)
-    const double* frow;
-    double* obase;
-    double uu[Q][2], ff[Q][2];
-    double r_m2[2], r_m1[2], r_0[2];
-    int I1, I2;  // down: coincident coarse columns (or -1)
-    double wm1, wp1, wm2, wp2;
-    int pendK;
-    int P1, P2;  // up: prolongation columns and weights
-    double pl1, pr1, pl2, pr2;
-    int cK, cnext;
-    double cval;
-    double acc;
-
-    __device__ __forceinline__ Pass(const PassArgs& args, double* smem) : a(args), lds(smem) {}
-
-    __device__ __forceinline__ double* Vrow(int buf, int half) {
-        return lds + 2 * (a.tn + 1) * QS + (2 * buf + half) * (a.tn + 1);
-    }
-    __device__ __forceinline__ double* tables() { return lds + 2 * (a.tn + 1) * QS + 4 * (a.tn + 1); }
-    __device__ __forceinline__ double* col0() { return tables(); }
-    __device__ __forceinline__ double* roww0() { return tables() + rows; }
-    __device__ __forceinline__ double* roww1() { return tables() + 2 * rows; }
-    __device__ __forceinline__ double* rowzc() { return tables() + 3 * rows; }
-    __device__ __forceinline__ double* rowzs() { return tables() + 4 * rows; }
-    __device__ __forceinline__ double* rowzn() { return tables() + 5 * rows; }
-    __device__ __forceinline__ int* rowk() { return (int*)(tables() + 6 * rows); }
-    static constexpr int kCRing = 8;  // up: coarse-correction rows, row K in slot K % kCRing
-    __device__ __forceinline__ double* cring() { return tables() + 7 * rows; }
-    // inverse diagonals of the rows from spec_lo to nz-2 (at most kMaxSpecial),
-    // per row [column pair t][2]
-    __device__ __forceinline__ double* sinv() { return cring() + kCRing * a.vc.nr; }
-    __device__ __forceinline__ double* crow(int K) { return cring() + (K & (kCRing - 1)) * a.vc.nr; }
-
-    __device__ __forceinline__ bool interior_row(int x) const { return x >= 1 && x <= a.v.nz - 2; }
-
-    __device__ __forceinline__ void setup() {
-        const LevelView& v = a.v;
-        t = threadIdx.x;
-        c1 = 2 * t + 1;
-        c2 = 2 * t + 2;
-        k1 = min(c1, v.nr - 1);
-        k2 = min(c2, v.nr - 1);
-        act1 = c1 <= v.nr - 2;
-        act2 = c2 <= v.nr - 2;
-        At = lds + t * QS;
-        Ar = At + QS;
-        Bt = lds + (a.tn + 1) * QS + (t + 1) * QS;
-        Bl = Bt - QS;
-        const int b = blockIdx.x;
-        if (a.xcd_major) {
-            const int xcd = b & 7, idx = b >> 3;
-            p = (idx / a.nchunks) * 8 + xcd;
-            chunk = idx % a.nchunks;
-        } else {
-            p = b / a.nchunks;
-            chunk = b % a.nchunks;
-        }
-        za = 1 + chunk * a.chunk;
-        zb = min(v.nz - 1, za + a.chunk);
-        s = max(0, za - (2 * NU + 2)) & ~1;
-        lend = min(v.nz - 1, zb + 2 * NU + 1);
-        rows = a.chunk + 4 * NU + 6;
-        lam = a.lam[p];
-        rw1 = v.rw[k1];
-        re1 = v.re[k1];
-        rb1 = v.rb[k1];
-        rm1 = v.rm[k1];
-        rw2 = v.rw[k2];
-        re2 = v.re[k2];
-        rb2 = v.rb[k2];
-        rm2 = v.rm[k2];
-        cu1 = make_coef(rw1, re1, rb1, rm1, a.zc0, a.zs0, a.zn0, lam);
-        cu2 = make_coef(rw2, re2, rb2, rm2, a.zc0, a.zs0, a.zn0, lam);
-        urow = a.u_in + (long long)p * v.pstride;
-        frow = a.f + (long long)p * v.pstride;
-        obase = a.u_out + (long long)p * v.pstride;
-        r_m2[0] = r_m2[1] = r_m1[0] = r_m1[1] = r_0[0] = r_0[1] = 0.0;
-        pendK = -1;
-        acc = 0.0;
-        if (DOWN) {
-            I1 = act1 ? a.colc[c1] : -1;
-            I2 = act2 ? a.colc[c2] : -1;
-            wm1 = I1 >= 0 ? a.tr.rwm[I1] : 0.0;
-            wp1 = I1 >= 0 ? a.tr.rwp[I1] : 0.0;
-            wm2 = I2 >= 0 ? a.tr.rwm[I2] : 0.0;
-            wp2 = I2 >= 0 ? a.tr.rwp[I2] : 0.0;
-            for (int i = t; i < 4 * (a.tn + 1); i += blockDim.x) Vrow(0, 0)[i] = 0.0;
-        } else {
-            cK = -1;
-            cnext = 0;
-            P1 = act1 ? a.tr.pidx[c1] : 0;
-            P2 = act2 ? a.tr.pidx[c2] : 0;
-            pl1 = act1 ? a.tr.pwl[c1] : 0.0;
-            pr1 = act1 ? a.tr.pwr[c1] : 0.0;
-            pl2 = act2 ? a.tr.pwl[c2] : 0.0;
-            pr2 = act2 ? a.tr.pwr[c2] : 0.0;
-        }
-        // radial ring column 0, axial transfer data and axial tables of the loaded rows
-        for (int x = s + t; x <= lend; x += blockDim.x) {
-            col0()[x - s] = ZERO_U ? 0.0 : urow[(long long)x * v.pitch];
-            int k = -1;
-            double w0 = 0.0, w1 = 0.0;
-            if (interior_row(x)) {
-                if (DOWN) {
-                    k = a.rowc[x];
-                    if (k >= 0) {
-                        w0 = a.tz.rwm[k];
-                        w1 = a.tz.rwp[k];
-                    }
-                } else {
-                    k = a.tz.pidx[x];
-                    w0 = a.tz.pwl[x];
-                    w1 = a.tz.pwr[x];
-                }
-            }
-            rowk()[x - s] = k;
-            roww0()[x - s] = w0;
-            roww1()[x - s] = w1;
-            rowzc()[x - s] = v.zc[x];
-            rowzs()[x - s] = v.zs[x];
-            rowzn()[x - s] = v.zn[x];
-        }
-        for (int y = a.spec_lo; y <= v.nz - 2; ++y) {
-            double* row = sinv() + (y - a.spec_lo) * 2 * a.tn;
-            row[2 * t] = make_coef(rw1, re1, rb1, rm1, v.zc[y], v.zs[y], v.zn[y], lam).invd;
-            row[2 * t + 1] = make_coef(rw2, re2, rb2, rm2, v.zc[y], v.zs[y], v.zn[y], lam).invd;
-        }
-        if (!DOWN) {
-            // coarse rows needed by the rows consumed in the first PD + 1 steps
-            lds_barrier();
-            int klo = a.vc.nz, khi = -1;
-            for (int x = s; x <= min(lend, s + PD); ++x)
-                if (interior_row(x)) {
-                    klo = min(klo, rowk()[x - s]);
-                    khi = max(khi, rowk()[x - s] + 1);
-                }
-            for (int q = t; q < kCRing; q += blockDim.x) {
-                cring()[q * a.vc.nr] = 0.0;
-                cring()[q * a.vc.nr + a.vc.nr - 1] = 0.0;
-            }
-            for (int K = klo; K <= khi; ++K)
-                if (carries()) crow(K)[t + 1] = coarse_src(K)[t + 1];
-            cnext = khi + 1;
-        }
-    }
-
-    // ---- coarse-correction rows (up pass) ----
-    __device__ __forceinline__ bool carries() const { return t + 1 <= a.vc.nr - 2; }
-    __device__ __forceinline__ const double* coarse_src(int K) const {
-        return a.ec + (long long)p * a.vc.pstride + (long long)K * a.vc.pitch;
-    }
-    __device__ __forceinline__ int coarse_hi(int x) {
-        return (x >= s && x <= lend && interior_row(x)) ? rowk()[x - s] + 1 : -1;
-    }
-    // Once per step: store the coarse row that arrived and request the next one
-    // if the row consumed PD + 1 steps from now needs it.  Thread t carries
-    // coarse interior column t + 1; the coarse ring columns stay zero.  The
-    // load is issued every step (clamped) so the wait counts stay exact.
-    __device__ __forceinline__ void coarse_stream(int xn) {
-        if (cK >= 0) {
-            if (carries()) crow(cK)[t + 1] = cval;
-            cK = -1;
-        }
-        const int need = coarse_hi(xn);
-        const int kr = min(cnext, a.vc.nz - 1);
-        cval = coarse_src(kr)[min(t + 1, a.vc.nr - 2)];
-        if (cnext <= need) cK = cnext++;
-    }
-
-    // ---- rows in and out ----
-    // Loads of row x into slot j: every lane loads from a clamped, valid address
-    // and consume() keeps what is needed, so several rows stay in flight.
-    __device__ __forceinline__ void issue(int x, int j) {
-        const long long o = (long long)min(x, lend) * a.v.pitch;
-        if (!ZERO_U) {
-            uu[j][0] = urow[o + k1];
-            uu[j][1] = urow[o + k2];
-        }
-        ff[j][0] = frow[o + k1];
-        ff[j][1] = frow[o + k2];
-    }
-
-    template <int J, bool INTERIOR>
-    __device__ __forceinline__ void consume(int x) {
-        const bool in = INTERIOR || interior_row(x);
-        // a missing column c2 = nr keeps the clamped load (the ring value at
-        // nr - 1), so its unconditional store below rewrites that value unchanged
-        if (ZERO_U) {
-            uu[J][0] = 0.0;
-            uu[J][1] = 0.0;
-        } else if (DOWN && a.zero_interior && in) {
-            uu[J][0] = act1 ? 0.0 : uu[J][0];
-            uu[J][1] = act2 ? 0.0 : uu[J][1];
-        }
-        ff[J][0] = (in && act1) ? ff[J][0] : 0.0;
-        ff[J][1] = (in && act2) ? ff[J][1] : 0.0;
-        if (!DOWN && in) {
-            const int K = rowk()[x - s];
-            const double wl = roww0()[x - s], wr = roww1()[x - s];
-            const double* lo = crow(K);
-            const double* hi = crow(K + 1);
-            const double e1 = prolong2(lo + P1, hi + P1, pl1, pr1, wl, wr);
-            const double e2 = prolong2(lo + P2, hi + P2, pl2, pr2, wl, wr);
-            uu[J][0] = act1 ? uu[J][0] + e1 : uu[J][0];
-            uu[J][1] = act2 ? uu[J][1] + e2 : uu[J][1];
-        }
-        At[J] = uu[J][0];
-        Bt[J] = uu[J][1];
-        if (t == 0) Bl[J] = col0()[x - s];
-    }
-
-    // ---- arithmetic ----
-    // Coefficients of rows from spec_lo on: the conductances from the row's axial
-    // tables, the inverse diagonal from the table set up once (no division here).
-    __device__ __forceinline__ Coef special(double rw, double re, double rb, double rm, int y, int col) {
-        Coef c;
-        const double zc = rowzc()[y - s];
-        c.gw = rw * zc;
-        c.ge = re * zc;
-        c.gs = rb * rowzs()[y - s];
-        c.gn = rb * rowzn()[y - s];
-        c.diag = fma(lam, rm * zc, (c.gw + c.ge) + (c.gs + c.gn));
-        c.invd = sinv()[(y - a.spec_lo) * 2 * a.tn + 2 * t + col];
-        return c;
-    }
-    template <bool CHK>
-    __device__ __forceinline__ Coef coef1(int y) {
-        if (!CHK || y < a.spec_lo) return cu1;
-        return special(rw1, re1, rb1, rm1, y, 0);
-    }
-    template <bool CHK>
-    __device__ __forceinline__ Coef coef2(int y) {
-        if (!CHK || y < a.spec_lo) return cu2;
-        return special(rw2, re2, rb2, rm2, y, 1);
-    }
-
-    // Half-sweep on row y (slot SY; SM = y-1, SP = y+1).  C1: the colour being
-    // relaxed sits on column c1 of this row.  NB: the horizontal neighbour from
-    // another thread (west of c1 or east of c2), published one step earlier.
-    template <int SY, int SM, int SP, bool C1, bool CHK>
-    __device__ __forceinline__ void half_sweep(int y, double nb) {
-        if (C1) {
-            const double v =
-                relax(uu[SY][0], ff[SY][0], nb, uu[SY][1], uu[SM][0], uu[SP][0], coef1<CHK>(y), a.omega);
-            uu[SY][0] = act1 ? v : uu[SY][0];
-            At[SY] = uu[SY][0];
-        } else {
-            const double v =
-                relax(uu[SY][1], ff[SY][1], uu[SY][0], nb, uu[SM][1], uu[SP][1], coef2<CHK>(y), a.omega);
-            uu[SY][1] = act2 ? v : uu[SY][1];
-            Bt[SY] = uu[SY][1];
-        }
-    }
-
-    template <int SY, int SM, int SP, bool CHK>
-    __device__ __forceinline__ void residual_row(int y, double nw, double ne, double& r1, double& r2) {
-        const double x1 = residual(uu[SY][0], ff[SY][0], nw, uu[SY][1], uu[SM][0], uu[SP][0], coef1<CHK>(y));
-        const double x2 = residual(uu[SY][1], ff[SY][1], uu[SY][0], ne, uu[SM][1], uu[SP][1], coef2<CHK>(y));
-        r1 = act1 ? x1 : 0.0;
-        r2 = act2 ? x2 : 0.0;
-    }
-
-    // Radial half of the restriction for coarse row pendK (vertical half done last step).
-    __device__ __forceinline__ void finish_restriction() {
-        const int buf = pendK & 1;
-        const double* VA = Vrow(buf, 0);
-        const double* VB = Vrow(buf, 1);
-        double* out = a.fc + (long long)p * a.vc.pstride + (long long)pendK * a.vc.pitch;
-        // non-coincident columns write their (unused) value into the coarse ring column 0
-        const double f1 = restrict3(VB[t], VA[t], VB[t + 1], wm1, wp1);
-        const double f2 = restrict3(VA[t], VB[t + 1], VA[t + 1], wm2, wp2);
-        out[I1 >= 0 ? I1 : 0] = I1 >= 0 ? f1 : 0.0;
-        out[I2 >= 0 ? I2 : 0] = I2 >= 0 ? f2 : 0.0;
-        pendK = -1;
-    }
-
-    // One step: consume row x and run every half-sweep, the residual and the
-    // transfers on the rows behind it.  CHK = false in the steady middle of the
-    // chunk, where every row involved is interior, regular and inside the chunk.
-    template <int J, bool CHK>
-    __device__ __forceinline__ void step(int x) {
-        lds_barrier();
-        // every LDS value read here was published at an earlier step, and this
-        // step only writes locations nobody reads during it
-        double nb[2 * NU];
-#define CP_NB(h)                                                                       \
-    if constexpr ((h) < 2 * NU) {                                                     \
-        constexpr int sy = (J - 1 - (h) + 4 * Q) % Q;                                 \
-        constexpr bool c1col = ((((J - 1 - (h)) & 1) + 1) & 1) == ((h) & 1);          \
-        nb[(h)] = c1col ? Bl[sy] : Ar[sy];                                            \
-    }
-        CP_NB(0) CP_NB(1) CP_NB(2) CP_NB(3) CP_NB(4) CP_NB(5) CP_NB(6) CP_NB(7)
-#undef CP_NB
-        constexpr int sr = (J - 2 * NU - 1 + 4 * Q) % Q;
-        const double rnw = Bl[sr], rne = Ar[sr];
-        if (DOWN && pendK >= 0) finish_restriction();
-        if (!DOWN) coarse_stream(x + PD + 1);
-        issue(x + PD, (J + PD) % Q);
-        if (!CHK || x <= lend) consume<J, !CHK>(x);
-        const int ylo = max(1, s + 1), yhi = min(a.v.nz - 2, lend - 1);
-#define CP_HS(h)                                                                              \
-    if constexpr ((h) < 2 * NU) {                                                            \
-        constexpr int sy = (J - 1 - (h) + 4 * Q) % Q;                                        \
-        constexpr int sm = (J - 2 - (h) + 4 * Q) % Q;                                        \
-        constexpr int sp = (J - (h) + 4 * Q) % Q;                                            \
-        constexpr bool c1col = ((((J - 1 - (h)) & 1) + 1) & 1) == ((h) & 1);                 \
-        const int y = x - 1 - (h);                                                           \
-        if (!CHK || (y >= ylo && y <= yhi)) half_sweep<sy, sm, sp, c1col, CHK>(y, nb[(h)]); \
-    }
-        CP_HS(0) CP_HS(1) CP_HS(2) CP_HS(3) CP_HS(4) CP_HS(5) CP_HS(6) CP_HS(7)
-#undef CP_HS
-        // row x - 2 nu is final now
-        {
-            constexpr int jf = (J - 2 * NU + 4 * Q) % Q;
-            const int yf = x - 2 * NU;
-            if (!CHK || (yf >= za && yf < zb)) {
-                double* orow = obase + (long long)yf * a.v.pitch;
-                orow[k1] = uu[jf][0];
-                orow[k2] = uu[jf][1];
-            }
-        }
-        const int y = x - 2 * NU - 1;
-        constexpr int jy = (J - 2 * NU - 1 + 4 * Q) % Q;
-        constexpr int jm = (J - 2 * NU - 2 + 4 * Q) % Q;
-        constexpr int jq = (J - 2 * NU + 4 * Q) % Q;
-        if (DOWN) {
-            double r1 = 0.0, r2 = 0.0;
-            if (!CHK || (y >= max(1, za - 1) && y <= min(a.v.nz - 2, zb)))
-                residual_row<jy, jm, jq, CHK>(y, rnw, rne, r1, r2);
-            r_m2[0] = r_m1[0];
-            r_m2[1] = r_m1[1];
-            r_m1[0] = r_0[0];
-            r_m1[1] = r_0[1];
-            r_0[0] = r1;
-            r_0[1] = r2;
-            const int yc = y - 1;
-            if (!CHK || (yc >= za && yc < zb && yc >= 1)) {
-                const int K = rowk()[yc - s];
-                if (K >= 0) {
-                    const double wzm = roww0()[yc - s], wzp = roww1()[yc - s];
-                    const int buf = K & 1;
-                    Vrow(buf, 0)[t] = restrict3(r_m2[0], r_m1[0], r_0[0], wzm, wzp);
-                    Vrow(buf, 1)[t + 1] = restrict3(r_m2[1], r_m1[1], r_0[1], wzm, wzp);
-                    pendK = K;
-                }
-            }
-        } else if (a.partial) {
-            if (!CHK || (y >= za && y < zb && y <= a.v.nz - 2)) {
-                double r1, r2;
-                residual_row<jy, jm, jq, CHK>(y, rnw, rne, r1, r2);
-                acc = fma(r1, r1, acc);
-                acc = fma(r2, r2, acc);
-            }
-        }
-    }
-
-    template <bool CHK>
-    __device__ __forceinline__ void group(int x0, int xend) {
-        // Q consecutive steps with compile-time register and LDS slots
-#define CP_STEP(J)                                            \
-    if constexpr ((J) < Q) {                                  \
-        if (!CHK || x0 + (J) <= xend) step<(J), CHK>(x0 + (J)); \
-    }
-        CP_STEP(0) CP_STEP(1) CP_STEP(2) CP_STEP(3) CP_STEP(4) CP_STEP(5) CP_STEP(6) CP_STEP(7)
-        CP_STEP(8) CP_STEP(9) CP_STEP(10) CP_STEP(11) CP_STEP(12) CP_STEP(13) CP_STEP(14) CP_STEP(15)
-#undef CP_STEP
-    }
-
-    __device__ __forceinline__ void run() {
-        setup();
-        // last step: the residual of row zb (down) or zb - 1 (up), plus one step
-        // to finish the pending restriction
-        const int ylast = DOWN ? min(a.v.nz - 1, zb) : zb - 1;
-        const int xlast = ylast + 2 * NU + 1 + (DOWN ? 1 : 0);
-        // steady steps: every row they touch is interior, below spec_lo and in the chunk
-        const int lo = za + 2 * NU + 2;
-        const int hi = min(min(zb + 2 * NU - 1, a.v.nz - 2), min(lend, a.spec_lo));
-        int ga = s, gb = s;  // [ga, gb): whole groups of steady steps
-        if (hi >= lo) {
-            ga = s + ((lo - s + Q - 1) / Q) * Q;
-            gb = ga + ((hi + 1 - ga) / Q) * Q;
-            if (gb <= ga) ga = gb = s;
-        }
-#pragma unroll
-        for (int d = 0; d < PD; ++d) issue(s + d, d);
-        // one instance of each step group: checked at both ends, steady between
-        for (int x0 = s; x0 <= xlast; x0 += Q) {
-            if (x0 >= ga && x0 < gb)
-                group<false>(x0, x0 + Q - 1);
-            else
-                group<true>(x0, xlast);
-        }
-        if (DOWN && pendK >= 0) {
-            lds_barrier();
-            finish_restriction();
-        }
-        if (!DOWN && a.partial) {
-            // fixed-order block reduction of the squared residual
-            lds_barrier();
-            double* red = lds;
-            red[t] = acc;
-            lds_barrier();
-            int w = 1;
-            while (w < (int)blockDim.x) w <<= 1;
-            for (w >>= 1; w > 0; w >>= 1) {
-                if (t < w && t + w < (int)blockDim.x) red[t] += red[t + w];
-                lds_barrier();
-            }
-            if (t == 0) a.partial[(long long)p * a.partial_ld + chunk] = red[0];
-        }
-    }
-};
-
-template <int NU, int PD, bool DOWN, bool ZERO_U>
-__global__ void __launch_bounds__(512) k_pass(PassArgs a) {
-    extern __shared__ double smem[];
-    Pass<NU, PD, DOWN, ZERO_U> pass(a, smem);
-    pass.run();
-}
-
-// The same pass under its own symbol, launched for the finest level with the
-// default sweep count and prefetch depth, so that kernel traces and counters
-// report the finest level apart from the coarser ones.
-template <int NU, int PD, bool DOWN, bool ZERO_U>
-__global__ void __launch_bounds__(512) k_pass_fine(PassArgs a) {
-    extern __shared__ double smem[];
-    Pass<NU, PD, DOWN, ZERO_U> pass(a, smem);
-    pass.run();
-}
-
-}  // namespace
-
-}  // namespace cp
-
-namespace cp {
-
-namespace {
-
-template <int NU, int PD, bool DOWN, bool ZERO_U>
-hipError_t launch_t(bool fine, const PassArgs& a, int blocks, int threads, size_t lds, hipStream_t s) {
-    if constexpr (NU == 2 && PD == 1) {
-        if (fine) {
-            k_pass_fine<NU, PD, DOWN, ZERO_U><<<blocks, threads, lds, s>>>(a);
-            return hipGetLastError();
-        }
-    } else {
-        (void)fine;
-    }
-    k_pass<NU, PD, DOWN, ZERO_U><<<blocks, threads, lds, s>>>(a);
-    return hipGetLastError();
-}
-
-template <int NU, int PD>
-hipError_t launch_pd(bool fine, bool down, bool zero_u, const PassArgs& a, int blocks, int threads,
-                     size_t lds, hipStream_t s) {
-    if (down)
-        return zero_u ? launch_t<NU, PD, true, true>(fine, a, blocks, threads, lds, s)
-                      : launch_t<NU, PD, true, false>(fine, a, blocks, threads, lds, s);
-    return launch_t<NU, PD, false, false>(fine, a, blocks, threads, lds, s);
-}
-
-template <int NU>
-hipError_t launch_nu_pd(bool fine, int pd, bool down, bool zero_u, const PassArgs& a, int blocks,
-                        int threads, size_t lds, hipStream_t s) {
-    if constexpr (NU == 2) {
-        switch (pd) {
-            case 1: return launch_pd<NU, 1>(fine, down, zero_u, a, blocks, threads, lds, s);
-            case 2: return launch_pd<NU, 2>(fine, down, zero_u, a, blocks, threads, lds, s);
-            case 3: return launch_pd<NU, 3>(fine, down, zero_u, a, blocks, threads, lds, s);
-            case 4: return launch_pd<NU, 4>(fine, down, zero_u, a, blocks, threads, lds, s);
-            default: return hipErrorInvalidValue;
-        }
-    } else {
-        (void)pd;  // other sweep counts use a prefetch depth of two rows
-        return launch_pd<NU, 2>(fine, down, zero_u, a, blocks, threads, lds, s);
-    }
-}
-
-hipError_t launch_nu(bool fine, int nu, int pd, bool down, bool zero_u, const PassArgs& a, int blocks,
-                     int threads, size_t lds, hipStream_t s) {
-    switch (nu) {
-        case 1: return launch_nu_pd<1>(fine, pd, down, zero_u, a, blocks, threads, lds, s);
-        case 2: return launch_nu_pd<2>(fine, pd, down, zero_u, a, blocks, threads, lds, s);
-        case 3: return launch_nu_pd<3>(fine, pd, down, zero_u, a, blocks, threads, lds, s);
-        case 4: return launch_nu_pd<4>(fine, pd, down, zero_u, a, blocks, threads, lds, s);
-        default: return hipErrorInvalidValue;
-    }
-}
-
-struct Shape {
-    int tn, threads, chunk, nchunks, blocks;
-    size_t lds;
-};
-
-Shape pass_shape(const cylpoisson_plan* p, int l, int nu) {
-    const DeviceLevel& L = p->dl[l];
-    Shape sh;
-    sh.tn = L.v.nr / 2;  // column pairs covering columns 1 .. nr-1
-    sh.threads = sh.tn;
-    const int rows = L.v.nz - 2;
-    int chunk = l == 0 ? p->opt.chunk_rows : p->opt.chunk_rows_coarse;
-    if (chunk <= 0) {
-        // The finest level is bandwidth-bound: few long chunks (about two
-        // workgroups per compute unit) keep the recomputed halo small.  Coarser
-        // levels are latency-bound: more, shorter chunks.
-        const int want = l == 0 ? 512 : 1024;
-        const int per_plane = std::max(1, want / std::max(1, p->nt));
-        chunk = std::max(l == 0 ? 64 : 32, (rows + per_plane - 1) / per_plane);
-    }
-    chunk = std::min(std::max(chunk, 1), std::max(rows, 1));
-    sh.chunk = chunk;
-    sh.nchunks = (rows + chunk - 1) / chunk;
-    sh.blocks = sh.nchunks * p->nt;
-    const int q0 = 2 * nu + 3 + (nu == 2 ? p->opt.prefetch : 2);
-    const int qs = ((q0 & 1) ? q0 + 1 : q0) + 1;
-    const size_t trows = (size_t)(chunk + 4 * nu + 6);
-    const size_t nspecial = (size_t)std::max(0, L.v.nz - 1 - L.spec_lo);
-    sh.lds = ((size_t)2 * (sh.tn + 1) * qs + (size_t)4 * (sh.tn + 1) + 7 * trows +
-              (size_t)8 * p->dl[l + 1].v.nr + nspecial * 2 * sh.tn) * sizeof(double);
-    sh.lds = std::max(sh.lds, (size_t)sh.threads * sizeof(double));  // final block reduction
-    return sh;
-}
-
-PassArgs make_args(const cylpoisson_plan* p, int l, const Shape& sh) {
-    const DeviceLevel& L = p->dl[l];
-    const DeviceLevel& C = p->dl[l + 1];
-    PassArgs a{};
-    a.v = L.v;
-    a.vc = C.v;
-    a.tr = L.tr;
-    a.tz = L.tz;
-    a.lam = p->d_lam;
-    a.colc = L.colc;
-    a.rowc = L.rowc;
-    a.spec_lo = L.spec_lo;
-    a.omega = p->opt.omega;
-    a.zc0 = L.zc0;
-    a.zs0 = L.zs0;
-    a.zn0 = L.zn0;
-    a.chunk = sh.chunk;
-    a.nchunks = sh.nchunks;
-    a.nt = p->nt;
-    a.tn = sh.tn;
-    a.xcd_major = (p->nt % 8 == 0) ? 1 : 0;
-    return a;
-}
-
-}  // namespace
 
 bool fused_supported(const cylpoisson_plan* p, int l) {
     if (!p->opt.fused || l + 1 >= (int)p->dl.size()) return false;
     const int nu = std::max(p->opt.nu1, p->opt.nu2);
     if (p->opt.nu1 > 4 || p->opt.nu2 > 4) return false;
-    const Shape sh = pass_shape(p, l, nu);
+    const Shape sh = pass_shape<double>(p, l, nu);
     const int nspecial = p->dl[l].v.nz - 1 - p->dl[l].spec_lo;
     return sh.threads >= 1 && sh.threads <= 512 && sh.lds <= 64 * 1024 &&
            sh.nchunks <= kMaxPartial && nspecial <= 4;
@@ -637,24 +17,25 @@ bool fused_supported(const cylpoisson_plan* p, int l) {
 hipError_t fused_down(cylpoisson_plan* p, int l, bool zero_u, bool zero_interior, hipStream_t s) {
     DeviceLevel& L = p->dl[l];
     DeviceLevel& C = p->dl[l + 1];
-    const Shape sh = pass_shape(p, l, p->opt.nu1);
-    PassArgs a = make_args(p, l, sh);
+    const Shape sh = pass_shape<double>(p, l, p->opt.nu1);
+    PassArgs<double> a = make_args<double>(p, l, sh);
     a.u_in = L.u;
     a.f = L.f;
     a.u_out = L.u2;
     a.fc = C.f;
     a.zero_interior = zero_interior ? 1 : 0;
-    return launch_nu(l == 0, p->opt.nu1, p->opt.prefetch, true, zero_u, a, sh.blocks, sh.threads, sh.lds, s);
+    return launch_nu<double>(l == 0, p->opt.nu1, p->opt.prefetch, true, zero_u, a, sh.blocks,
+                             sh.threads, sh.lds, s);
 }
 
-int fused_chunks(const cylpoisson_plan* p, int l, int nu) { return pass_shape(p, l, nu).nchunks; }
+int fused_chunks(const cylpoisson_plan* p, int l, int nu) { return pass_shape<double>(p, l, nu).nchunks; }
 
 hipError_t fused_up(cylpoisson_plan* p, int l, double* partial, int partial_ld, int* nchunks,
                     hipStream_t s) {
     DeviceLevel& L = p->dl[l];
     DeviceLevel& C = p->dl[l + 1];
-    const Shape sh = pass_shape(p, l, p->opt.nu2);
-    PassArgs a = make_args(p, l, sh);
+    const Shape sh = pass_shape<double>(p, l, p->opt.nu2);
+    PassArgs<double> a = make_args<double>(p, l, sh);
     a.u_in = L.u2;
     a.f = L.f;
     a.u_out = L.u;
@@ -662,7 +43,8 @@ hipError_t fused_up(cylpoisson_plan* p, int l, double* partial, int partial_ld, 
     a.partial = partial;
     a.partial_ld = partial_ld;
     if (nchunks) *nchunks = sh.nchunks;
-    return launch_nu(l == 0, p->opt.nu2, p->opt.prefetch, false, false, a, sh.blocks, sh.threads, sh.lds, s);
+    return launch_nu<double>(l == 0, p->opt.nu2, p->opt.prefetch, false, false, a, sh.blocks,
+                             sh.threads, sh.lds, s);
 }
 
 }  // namespace cp

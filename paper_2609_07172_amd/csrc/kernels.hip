@@ -206,6 +206,81 @@ __global__ void __launch_bounds__(256) k_norm_partial(LevelView v, const double*
     if (threadIdx.x == 0) partial[(long long)p * kMaxPartial + blockIdx.x] = red[0];
 }
 
+// FP64 refinement step of the mixed-precision solve, finest level:
+//   u_out = u_in + e (interior; HAS_E) or 0 (interior; !HAS_E), ring of u_in kept,
+//   r  = f - A_p u            (FP64, the same point expression as everywhere)
+//   r32 = r rounded to FP32,  partial = per-block sum of r^2 (FP64).
+// Without WRITE only the partial sums are produced: with !HAS_E these are the
+// norms of the right-hand side b = f + (Dirichlet ring terms) that start every
+// solve (the interior of u_in is not read).  u_out must not be u_in when
+// HAS_E: workgroups read the rows next to their chunk from u_in while the
+// neighbouring chunk writes them.
+// One workgroup per (plane, chunk of rows, group of columns); one thread per
+// radial column marches along z with the three rows of its column in
+// registers and the row being evaluated shared through LDS (double buffered,
+// one barrier per row).  A group of bw threads covers bw - 2 interior columns
+// plus one neighbour column on each side.
+template <bool HAS_E, bool WRITE>
+__global__ void __launch_bounds__(1024) k_refine(LevelView v, const double* __restrict__ lam,
+                                                 const double* __restrict__ uin,
+                                                 double* __restrict__ uout, const float* __restrict__ e,
+                                                 const double* __restrict__ f, float* __restrict__ r32,
+                                                 double* __restrict__ partial, int chunk, int nchunks,
+                                                 int ngroups) {
+    extern __shared__ double srow[];  // [2][bw] rows, then [bw] reduction
+    const int bw = blockDim.x, t = threadIdx.x;
+    const int p = blockIdx.y;
+    const int ch = blockIdx.x / ngroups, g = blockIdx.x % ngroups;
+    const int c = min(g * (bw - 2) + t, v.nr - 1);  // this thread's column (clamped)
+    const bool own = t >= 1 && t <= bw - 2 && g * (bw - 2) + t <= v.nr - 2;
+    const bool int_col = c >= 1 && c <= v.nr - 2;
+    const int za = 1 + ch * chunk, zb = min(v.nz - 1, za + chunk);
+    const long long base = (long long)p * v.pstride + c;
+    const double lp = lam[p];
+    auto value = [&](int x) -> double {
+        const long long o = base + (long long)x * v.pitch;
+        const bool in = int_col && x >= 1 && x <= v.nz - 2;
+        if (HAS_E) return in ? uin[o] + (double)e[o] : uin[o];
+        return in ? 0.0 : uin[o];
+    };
+    double* buf0 = srow;
+    double* buf1 = srow + bw;
+    double acc = 0.0;
+    double prev = value(za - 1), cur = value(za);
+    buf0[t] = cur;
+    for (int x = za; x < zb; ++x) {
+        const double next = value(x + 1);
+        const double fx = f[base + (long long)x * v.pitch];
+        __syncthreads();
+        const double* row = (x - za) & 1 ? buf1 : buf0;
+        double* out = (x - za) & 1 ? buf0 : buf1;
+        const double w = row[t > 0 ? t - 1 : 0], ea = row[t < bw - 1 ? t + 1 : bw - 1];
+        const double r = residual(cur, fx, w, ea, prev, next, coef_at(v, c, x, lp));
+        if (own) {
+            if (WRITE) {
+                const long long o = base + (long long)x * v.pitch;
+                uout[o] = cur;
+                r32[o] = (float)r;
+            }
+            acc = fma(r, r, acc);
+        }
+        out[t] = next;
+        prev = cur;
+        cur = next;
+    }
+    // fixed-order block reduction (bw is a multiple of 64, not always a power of two)
+    double* red = srow + 2 * bw;
+    red[t] = acc;
+    __syncthreads();
+    int w2 = 1;
+    while (w2 < bw) w2 <<= 1;
+    for (w2 >>= 1; w2 > 0; w2 >>= 1) {
+        if (t < w2 && t + w2 < bw) red[t] += red[t + w2];
+        __syncthreads();
+    }
+    if (t == 0) partial[(long long)p * kMaxPartial + blockIdx.x] = red[0];
+}
+
 __global__ void k_norm_final(const double* __restrict__ partial, int nb, int nt,
                              double* __restrict__ out) {
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
@@ -261,39 +336,6 @@ __global__ void k_init_ring(LevelView v, double* u, double* u2, double prz, doub
     const long long o = (long long)p * v.pstride + (long long)k * v.pitch + i;
     u[o] = val;
     u2[o] = val;
-}
-
-// Squared norms of the initial residual f - A u0 per plane, where u0 has the
-// ring of u and a zero interior (the interior of u is not read).
-__global__ void __launch_bounds__(256) k_rhs_norm_partial(LevelView v, const double* __restrict__ lam,
-                                                          const double* __restrict__ u,
-                                                          const double* __restrict__ f,
-                                                          double* __restrict__ partial) {
-    __shared__ double red[256];
-    const int p = blockIdx.y;
-    const int ni = v.nr - 2, nk = v.nz - 2;
-    const long long total = (long long)ni * nk;
-    const double* up = u + (long long)p * v.pstride;
-    const double* fp = f + (long long)p * v.pstride;
-    double s = 0.0;
-    for (long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x; q < total;
-         q += (long long)gridDim.x * blockDim.x) {
-        const int i = (int)(q % ni) + 1, k = (int)(q / ni) + 1;
-        const long long o = (long long)k * v.pitch + i;
-        const double uw = i == 1 ? up[o - 1] : 0.0;
-        const double ue = i == v.nr - 2 ? up[o + 1] : 0.0;
-        const double us = k == 1 ? up[o - v.pitch] : 0.0;
-        const double un = k == v.nz - 2 ? up[o + v.pitch] : 0.0;
-        const double r = residual(0.0, fp[o], uw, ue, us, un, coef_at(v, i, k, lam[p]));
-        s = fma(r, r, s);
-    }
-    red[threadIdx.x] = s;
-    __syncthreads();
-    for (int w = 128; w > 0; w >>= 1) {
-        if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) partial[(long long)p * kMaxPartial + blockIdx.x] = red[0];
 }
 
 // Copy the Dirichlet ring (boundary rows and columns) of every plane.
@@ -407,17 +449,6 @@ hipError_t launch_init_ring(const DeviceLevel& L, int nt, const cylpoisson_bc& b
     return hipGetLastError();
 }
 
-hipError_t launch_rhs_norms(const DeviceLevel& L, int nt, const double* lam, const double* u,
-                            const double* f, double* partial, double* norms_out, hipStream_t s) {
-    const long long total = (long long)(L.v.nr - 2) * (L.v.nz - 2);
-    int nb = (int)std::min<long long>(64, (total + 255) / 256);
-    if (nb < 1) nb = 1;
-    k_rhs_norm_partial<<<dim3(nb, nt), 256, 0, s>>>(L.v, lam, u, f, partial);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    k_norm_final<<<(nt + 63) / 64, 64, 0, s>>>(partial, nb, nt, norms_out);
-    return hipGetLastError();
-}
 
 hipError_t launch_copy_ring(const DeviceLevel& L, int nt, const double* src, double* dst,
                             hipStream_t s) {
@@ -431,6 +462,49 @@ hipError_t launch_apply(const DeviceLevel& L, int nt, const double* lam, const d
     dim3 grid((L.v.nr + kTx - 1) / kTx, (L.v.nz + kTy - 1) / kTy, nt);
     k_apply<<<grid, dim3(kTx, kTy), 0, s>>>(L.v, lam, u, inv_s, out);
     return hipGetLastError();
+}
+
+namespace {
+
+template <bool HAS_E, bool WRITE>
+hipError_t refine_t(const DeviceLevel& L, int nt, const double* lam, const double* uin, double* uout,
+                    const float* e, const double* f, float* r32, double* partial, double* norms_out,
+                    hipStream_t s) {
+    const LevelView& v = L.v;
+    // column groups of at most 1024 threads (a multiple of the wavefront)
+    const int bw = std::min(1024, ((v.nr + 63) / 64) * 64);
+    const int ngroups = (v.nr - 2 + (bw - 2) - 1) / (bw - 2);
+    const int rows = v.nz - 2;
+    // about 1024 workgroups in all, at most kMaxPartial per plane
+    int nchunks = std::max(1, std::min(rows, 1024 / std::max(1, nt * ngroups)));
+    nchunks = std::min(nchunks, std::max(1, kMaxPartial / ngroups));
+    const int chunk = (rows + nchunks - 1) / nchunks;
+    nchunks = (rows + chunk - 1) / chunk;
+    const int nb = nchunks * ngroups;
+    const size_t lds = (size_t)3 * bw * sizeof(double);
+    k_refine<HAS_E, WRITE><<<dim3(nb, nt), bw, lds, s>>>(v, lam, uin, uout, e, f, r32, partial,
+                                                         chunk, nchunks, ngroups);
+    hipError_t err = hipGetLastError();
+    if (err != hipSuccess) return err;
+    k_norm_final<<<(nt + 63) / 64, 64, 0, s>>>(partial, nb, nt, norms_out);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_refine(const DeviceLevel& L, int nt, const double* lam, const double* uin,
+                         double* uout, const float* e, const double* f, float* r32, double* partial,
+                         double* norms_out, hipStream_t s) {
+    if (e) {
+        if (uin == uout) return hipErrorInvalidValue;
+        return refine_t<true, true>(L, nt, lam, uin, uout, e, f, r32, partial, norms_out, s);
+    }
+    return refine_t<false, true>(L, nt, lam, uin, uout, e, f, r32, partial, norms_out, s);
+}
+
+hipError_t launch_rhs_norms(const DeviceLevel& L, int nt, const double* lam, const double* u,
+                            const double* f, double* partial, double* norms_out, hipStream_t s) {
+    return refine_t<false, false>(L, nt, lam, u, nullptr, nullptr, f, nullptr, partial, norms_out, s);
 }
 
 }  // namespace cp

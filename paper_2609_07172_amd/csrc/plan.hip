@@ -282,6 +282,55 @@ void dft_matrices(int N, std::vector<double>& F, std::vector<double>& G) {
 
 using namespace cp;
 
+namespace cp {
+
+bool mixed_supported(const cylpoisson_plan* p) {
+    if (p->bottom_level < 1 || !p->opt.bottom || !p->opt.fused) return false;
+    for (int l = 0; l < p->bottom_level; ++l)
+        if (!fused_supported(p, l)) return false;
+    return true;
+}
+
+namespace {
+
+// FP32 level buffers of the mixed-precision solve (levels 0 .. bottom_level),
+// zeroed once so that the Dirichlet rings of the corrections stay zero.
+int alloc_mixed(cylpoisson_plan* p) {
+    if (!p->dl32.empty()) return CYLPOISSON_OK;
+    if (p->bottom_level < 1) {
+        set_error("mixed precision needs the LDS bottom kernel below a fused finest level "
+                  "(this grid has %d level(s), bottom level %d)", (int)p->dl.size(), p->bottom_level);
+        return CYLPOISSON_EINVAL;
+    }
+    int prev = 0;
+    (void)hipGetDevice(&prev);
+    (void)hipSetDevice(p->device);
+    std::vector<DeviceLevel32> lv(p->bottom_level + 1);
+    hipError_t e = hipSuccess;
+    for (int l = 0; l <= p->bottom_level && e == hipSuccess; ++l) {
+        const size_t n = (size_t)p->nt * p->dl[l].v.pstride;
+        DeviceLevel32& D = lv[l];
+        e = dev_alloc(p, &D.u, n);
+        if (e == hipSuccess) e = hipMemset(D.u, 0, n * sizeof(float));
+        if (e == hipSuccess) e = dev_alloc(p, &D.f, n);
+        if (e == hipSuccess) e = hipMemset(D.f, 0, n * sizeof(float));
+        if (e == hipSuccess && l < p->bottom_level) e = dev_alloc(p, &D.u2, n);
+        if (e == hipSuccess && l < p->bottom_level) e = hipMemset(D.u2, 0, n * sizeof(float));
+    }
+    (void)hipSetDevice(prev);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        set_error("allocating the FP32 levels failed: %s", hipGetErrorString(e));
+        return e == hipErrorOutOfMemory ? CYLPOISSON_ENOMEM : CYLPOISSON_EHIP;
+    }
+    p->dl32 = lv;
+    return CYLPOISSON_OK;
+}
+
+}  // namespace
+
+}  // namespace cp
+
 extern "C" {
 
 const char* cylpoisson_last_error(void) { return cp::last_error(); }
@@ -562,6 +611,19 @@ int cylpoisson_plan_set_option(cylpoisson_plan* plan, const char* key, double va
     if (!std::strcmp(key, "prefetch")) return int_in(1, 4, &plan->opt.prefetch);
     if (!std::strcmp(key, "bottom")) return int_in(0, 1, &plan->opt.bottom);
     if (!std::strcmp(key, "fft")) return int_in(0, 1, &plan->opt.fft);
+    if (!std::strcmp(key, "inner_cycles")) return int_in(1, 8, &plan->opt.inner_cycles);
+    if (!std::strcmp(key, "precision")) {
+        if (value != 32.0 && value != 64.0) {
+            set_error("precision must be 64 (FP64 V-cycles) or 32 (FP32 inner V-cycles)");
+            return CYLPOISSON_EINVAL;
+        }
+        if (value == 32.0) {
+            const int st = cp::alloc_mixed(plan);
+            if (st != CYLPOISSON_OK) return st;
+        }
+        plan->opt.precision = (int)value;
+        return CYLPOISSON_OK;
+    }
     if (!std::strcmp(key, "omega")) {
         if (!(value > 0.0 && value < 2.0)) {
             set_error("omega must lie in (0, 2)");

@@ -222,6 +222,27 @@ hipError_t vcycle(cylpoisson_plan* p, int l, hipStream_t s, bool zero_top, int s
     return e;
 }
 
+// One FP32 V-cycle from level l on the FP32 buffers (mixed precision): fused
+// passes on every level above the bottom kernel.  Level 0 starts from a zero
+// correction when `zero_top`; coarser levels always do.
+hipError_t vcycle32(cylpoisson_plan* p, int l, bool zero_top, hipStream_t s) {
+    if (l == p->bottom_level) return launch_bottom32(p, s);
+    hipError_t e;
+    {
+        Timed tm(p, l == 0 ? kFineDown : -1, s);
+        e = fused_down32(p, l, l > 0 || zero_top, s);
+    }
+    if (e == hipSuccess) {
+        Timed tm(p, l == 0 ? kCoarse : -1, s);
+        e = vcycle32(p, l + 1, true, s);
+    }
+    if (e == hipSuccess) {
+        Timed tm(p, l == 0 ? kFineUp : -1, s);
+        e = fused_up32(p, l, s);
+    }
+    return e;
+}
+
 // Azimuthal transform of node/plane arrays: register FFT where supported,
 // dense DFT product otherwise.  colscale (forward only) multiplies column c by
 // colscale[c % Nr].
@@ -352,6 +373,89 @@ int run_cycles(cylpoisson_plan* p, double tol, hipStream_t s, bool ring_only) {
     return status;
 }
 
+// Mixed-precision cycles on the level-0 planes (f set, u holding its
+// Dirichlet ring): FP64 iterative refinement around FP32 V-cycles.  Each
+// refinement step adds the last FP32 correction to the FP64 iterate, forms the
+// FP64 residual and its plane norms, and (unless converged) solves
+// A e = r with `inner_cycles` FP32 V-cycles from e = 0.  The FP32 residual is
+// the right-hand side of the inner cycles; the coarsest correction inside
+// them is computed in FP64.
+int run_mixed(cylpoisson_plan* p, double tol, hipStream_t s, double** result) {
+    cylpoisson_stats& st = p->stats;
+    const int nt = p->nt;
+    DeviceLevel& L = p->dl[0];
+    DeviceLevel32& E = p->dl32[0];
+    const int ic = p->opt.inner_cycles;
+    const int maxc = p->opt.max_cycles;
+    int cycles = 0, stagnant = 0;
+    double b2 = 0.0, prev = 0.0;
+    int status = CYLPOISSON_NOT_CONVERGED;
+    // the FP64 iterate alternates between u and u2 (both hold the Dirichlet ring)
+    double* ucur = L.u;
+    double* unext = L.u2;
+    *result = ucur;
+    for (int it = 0;; ++it) {
+        {
+            Timed tm(p, kOther, s);
+            if (it == 0) {
+                CP_HIP(launch_refine(L, nt, p->d_lam, ucur, ucur, nullptr, L.f, E.f, p->d_partial,
+                                     p->d_norms, s));
+            } else {
+                CP_HIP(launch_refine(L, nt, p->d_lam, ucur, unext, E.u, L.f, E.f, p->d_partial,
+                                     p->d_norms, s));
+                std::swap(ucur, unext);
+                *result = ucur;
+            }
+        }
+        CP_HIP(hipMemcpyAsync(p->h_norms, p->d_norms, nt * sizeof(double), hipMemcpyDeviceToHost, s));
+        CP_HIP(hipStreamSynchronize(s));
+        ++st.checks;
+        st.refinements = it;
+        const double r2 = weighted(p, p->h_norms);
+        if (it == 0) {
+            b2 = r2;
+            if (!std::isfinite(b2)) {
+                set_error("right-hand side holds NaN or Inf");
+                return st.status = CYLPOISSON_ENONFINITE;
+            }
+            st.initial_residual_norm = std::sqrt(b2);
+            if (b2 == 0.0) {
+                st.rel_residual = 0.0;
+                return st.status = CYLPOISSON_OK;
+            }
+        }
+        const double rel = std::sqrt(r2 / b2);
+        st.rel_residual = rel;
+        if (it > 0) {
+            if (cycles - 1 < CYLPOISSON_MAX_HISTORY) st.rel_residual_history[cycles - 1] = rel;
+            st.n_history = cycles;
+        }
+        if (!std::isfinite(rel)) {
+            set_error("iteration produced NaN or Inf");
+            status = CYLPOISSON_ENONFINITE;
+            break;
+        }
+        if (rel <= tol) {
+            status = CYLPOISSON_OK;
+            break;
+        }
+        stagnant = (it > 0 && rel > 0.6 * prev) ? stagnant + 1 : 0;
+        if (stagnant >= 3) {
+            set_error("residual stagnated at %.3e (tolerance %.3e)", rel, tol);
+            break;
+        }
+        prev = rel;
+        if (cycles + ic > maxc) {
+            set_error("tolerance %.3e not reached in %d cycles (relative residual %.3e)", tol, cycles, rel);
+            break;
+        }
+        for (int c = 0; c < ic; ++c) CP_HIP(vcycle32(p, 0, c == 0, s));
+        cycles += ic;
+        st.cycles = cycles;
+    }
+    return st.status = status;
+}
+
 }  // namespace
 
 }  // namespace cp
@@ -380,6 +484,12 @@ int cylpoisson_solve(cylpoisson_plan* p, const double* rho, double* phi, double 
         set_error("rho and phi overlap");
         return p->stats.status = CYLPOISSON_EINVAL;
     }
+    const bool mixed = p->opt.precision == 32;
+    if (mixed && (p->dl32.empty() || !mixed_supported(p))) {
+        set_error("mixed precision needs fused passes on every level above the LDS bottom kernel "
+                  "(check the options fused, bottom, nu1, nu2 and chunk sizes)");
+        return p->stats.status = CYLPOISSON_EINVAL;
+    }
     hipStream_t s = static_cast<hipStream_t>(stream);
     DeviceLevel& L = p->dl[0];
     reset_stats(p);
@@ -390,8 +500,9 @@ int cylpoisson_solve(cylpoisson_plan* p, const double* rho, double* phi, double 
         CP_HIP(transform(p, false, rho, L.f, p->d_s, s));
     }
     // The fused finest level treats the interior as zero in the first cycle,
-    // so only the Dirichlet rings of the two iterate buffers are written.
-    const bool ring_only = fused_supported(p, 0);
+    // so only the Dirichlet rings of the two iterate buffers are written (the
+    // mixed-precision refinement writes the zero interior itself).
+    const bool ring_only = mixed || fused_supported(p, 0);
     {
         Timed tm(p, kOther, s);
         if (ring_only) {
@@ -401,10 +512,11 @@ int cylpoisson_solve(cylpoisson_plan* p, const double* rho, double* phi, double 
             CP_HIP(launch_copy_ring(L, p->nt, L.u, L.u2, s));
         }
     }
-    const int status = run_cycles(p, tol, s, ring_only);
+    double* result = L.u;
+    const int status = mixed ? run_mixed(p, tol, s, &result) : run_cycles(p, tol, s, ring_only);
     if (status == CYLPOISSON_OK || status == CYLPOISSON_NOT_CONVERGED) {
         Timed tm(p, kDftInv, s);
-        CP_HIP(transform(p, true, L.u, phi, nullptr, s));
+        CP_HIP(transform(p, true, result, phi, nullptr, s));
     }
     if (p->opt.timing) {
         CP_HIP(hipStreamSynchronize(s));

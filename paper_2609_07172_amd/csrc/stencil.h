@@ -1,5 +1,8 @@
 // Point operations of the matrix-free mode operator, shared by every kernel so
-// that each one evaluates exactly the same floating-point expression.
+// that each one evaluates exactly the same floating-point expression.  They
+// are generic in the value type T: double on the FP64 path, float in the inner
+// V-cycles of the mixed-precision solve (whose coefficients are still formed
+// in double and rounded once).
 //
 // Row q of A_p (Eq. matrix_free_mode_operator / appendix_matrix_row):
 //   (A_p u)_q = (D0_q + lambda_p mu_q) u_q - G_W u_W - G_E u_E - G_S u_S - G_N u_N
@@ -10,9 +13,17 @@
 
 namespace cp {
 
-struct Coef {
-    double gw, ge, gs, gn, diag, invd;
+template <typename T>
+struct CoefT {
+    T gw, ge, gs, gn, diag, invd;
 };
+using Coef = CoefT<double>;
+
+// Coefficients rounded to the value type of a kernel.
+template <typename T>
+__device__ __forceinline__ CoefT<T> coef_as(const Coef& c) {
+    return CoefT<T>{(T)c.gw, (T)c.ge, (T)c.gs, (T)c.gn, (T)c.diag, (T)c.invd};
+}
 
 // Coefficients of one node from its radial and axial table entries and the
 // plane's shift lambda: the face conductances of App. A and the diagonal
@@ -35,9 +46,9 @@ __device__ __forceinline__ Coef coef_at(const LevelView& v, int i, int k, double
 }
 
 // Sum of conductance-weighted neighbours, in one fixed order.
-__device__ __forceinline__ double neighbour_sum(double uw, double ue, double us, double un,
-                                                const Coef& c) {
-    double s = c.gw * uw;
+template <typename T>
+__device__ __forceinline__ T neighbour_sum(T uw, T ue, T us, T un, const CoefT<T>& c) {
+    T s = c.gw * uw;
     s = fma(c.ge, ue, s);
     s = fma(c.gs, us, s);
     s = fma(c.gn, un, s);
@@ -45,42 +56,43 @@ __device__ __forceinline__ double neighbour_sum(double uw, double ue, double us,
 }
 
 // (A_p u)_q
-__device__ __forceinline__ double apply_row(double uc, double uw, double ue, double us,
-                                            double un, const Coef& c) {
+template <typename T>
+__device__ __forceinline__ T apply_row(T uc, T uw, T ue, T us, T un, const CoefT<T>& c) {
     return fma(c.diag, uc, -neighbour_sum(uw, ue, us, un, c));
 }
 
 // f_q - (A_p u)_q
-__device__ __forceinline__ double residual(double uc, double f, double uw, double ue, double us,
-                                           double un, const Coef& c) {
+template <typename T>
+__device__ __forceinline__ T residual(T uc, T f, T uw, T ue, T us, T un, const CoefT<T>& c) {
     return f - apply_row(uc, uw, ue, us, un, c);
 }
 
 // Over-relaxed Gauss-Seidel update of one node:
 //   u <- u + omega ((f + sum G u_nb) / diag - u)
-__device__ __forceinline__ double relax(double uc, double f, double uw, double ue, double us,
-                                        double un, const Coef& c, double omega) {
-    const double t = (f + neighbour_sum(uw, ue, us, un, c)) * c.invd;
+template <typename T>
+__device__ __forceinline__ T relax(T uc, T f, T uw, T ue, T us, T un, const CoefT<T>& c, T omega) {
+    const T t = (f + neighbour_sum(uw, ue, us, un, c)) * c.invd;
     return fma(omega, t - uc, uc);
 }
 
 // Weighted three-point sum x0 + wm xm + wp xp of the restriction R = P^T,
 // used first along z and then along r.
-__device__ __forceinline__ double restrict3(double xm, double x0, double xp, double wm, double wp) {
+template <typename T>
+__device__ __forceinline__ T restrict3(T xm, T x0, T xp, T wm, T wp) {
     return fma(wp, xp, fma(wm, xm, x0));
 }
 
 // Bilinear prolongation value from coarse rows `lo` and `hi` at columns 0 and 1.
-__device__ __forceinline__ double prolong2(const double* lo, const double* hi, double wl_r,
-                                           double wr_r, double wl_z, double wr_z) {
-    const double a = fma(wr_r, lo[1], wl_r * lo[0]);
-    const double b = fma(wr_r, hi[1], wl_r * hi[0]);
+template <typename T>
+__device__ __forceinline__ T prolong2(const T* lo, const T* hi, T wl_r, T wr_r, T wl_z, T wr_z) {
+    const T a = fma(wr_r, lo[1], wl_r * lo[0]);
+    const T b = fma(wr_r, hi[1], wl_r * hi[0]);
     return fma(wr_z, b, wl_z * a);
 }
 
 // Bilinear prolongation value from the 2x2 coarse block at c0 (row pitch `pitch`).
-__device__ __forceinline__ double prolong_value(const double* c0, int pitch, double wl_r,
-                                                double wr_r, double wl_z, double wr_z) {
+template <typename T>
+__device__ __forceinline__ T prolong_value(const T* c0, int pitch, T wl_r, T wr_r, T wl_z, T wr_z) {
     return prolong2(c0, c0 + pitch, wl_r, wr_r, wl_z, wr_z);
 }
 

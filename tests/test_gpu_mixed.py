@@ -1,0 +1,145 @@
+"""Mixed precision ("precision" = 32): FP64 iterative refinement around FP32
+V-cycles, against the same CPU oracle and the same 1e-12 relative-L2 bar as
+the FP64 solve.  The residual that decides convergence is the FP64 one, so
+the converged answer must reach the FP64 floor; a broken FP32 pass shows up
+as a refinement step that no longer contracts the residual.
+"""
+import numpy as np
+import pytest
+import torch
+
+import workloads as W
+from oracle import fv, solvers
+
+from gpu_util import dev, host, rel_l2, say
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def P():
+    import paper_2609_07172_amd as P
+    P.library()
+    assert torch.cuda.is_available()
+    return P
+
+
+def manufactured(p, seed=12345):
+    phit = W.manufactured_potential(p, seed, np.longdouble)
+    rho = fv.charge_from_potential(fv.Grid.of(p, np.longdouble), phit).astype(np.float64)
+    return phit.astype(np.float64), rho
+
+
+def mixed_plan(P, prob, **opts):
+    plan = P.Plan.for_problem(prob, **opts)
+    plan.set_option("precision", 32)
+    return plan
+
+
+def test_mixed_small_matches_sparse_direct(P):
+    p = W.SMALL
+    phit, rho = manufactured(p)
+    ref = solvers.solve_sparse(fv.Grid.of(p), rho, p.bc)
+    say("mixed solve", p.name)
+    phi, st = mixed_plan(P, p).solve(dev(rho), tol=1e-14)
+    got = host(phi)
+    assert st["status"] == P.OK and st["rel_residual"] <= 1e-14, st
+    assert st["refinements"] >= 1 and st["cycles"] == 2 * st["refinements"], st
+    assert rel_l2(got, ref) <= 1e-12, rel_l2(got, ref)
+    assert rel_l2(got, phit) <= 1e-12
+    # the boundary comes from the FP64 ring of plane 0 exactly
+    np.testing.assert_array_equal(got[:, -1, :], p.phi_zL)
+    np.testing.assert_array_equal(got[:, 1:-1, 0], p.phi_r_in)
+
+
+@pytest.mark.parametrize("prob", [W.BATCHED, W.HIGH_SHIFT])
+def test_mixed_matches_separable(P, prob):
+    rho = W.blob_charge(prob, seed=24680)
+    ref = solvers.solve_separable(fv.Grid.of(prob), rho, prob.bc)
+    say("mixed solve", prob.name)
+    phi, st = mixed_plan(P, prob).solve(dev(rho), tol=1e-14)
+    assert st["status"] == P.OK, st
+    assert rel_l2(host(phi), ref) <= 1e-12, rel_l2(host(phi), ref)
+
+
+def test_mixed_refinement_contracts(P):
+    """Every refinement step (two FP32 V-cycles) cuts the FP64 residual by at
+    least 100x until the FP64 floor; the FP32 V-cycle alone contracts by about
+    0.02 per cycle, so a correct inner solve gives about 4e-4 per step."""
+    prob = W.BATCHED
+    rho = W.blob_charge(prob, seed=24680)
+    say("mixed contraction", prob.name)
+    _, st = mixed_plan(P, prob).solve(dev(rho), tol=1e-15, allow=(P.OK, P.NOT_CONVERGED))
+    hist = [h for h in st["history"] if h is not None]
+    assert len(hist) == st["refinements"] >= 3, st
+    prev = 1.0
+    for h in hist:
+        if prev > 1e-12:
+            assert h < 1e-2 * prev, (hist, h, prev)
+        prev = h
+
+
+def test_mixed_initial_residual_is_the_fp64_one(P):
+    p = W.SMALL.with_sizes(33, 8, 41)
+    rho = W.blob_charge(p, seed=7)
+    _, a = P.Plan.for_problem(p).solve(dev(rho), tol=1e-14)
+    _, b = mixed_plan(P, p).solve(dev(rho), tol=1e-14)
+    assert b["initial_residual_norm"] == pytest.approx(a["initial_residual_norm"], rel=1e-13)
+
+
+@pytest.mark.parametrize("inner", [1, 3])
+def test_mixed_inner_cycle_counts(P, inner):
+    p = W.SMALL
+    phit, rho = manufactured(p)
+    ref = solvers.solve_sparse(fv.Grid.of(p), rho, p.bc)
+    say("mixed inner cycles", inner)
+    phi, st = mixed_plan(P, p, inner_cycles=inner).solve(dev(rho), tol=1e-14)
+    assert st["status"] == P.OK and st["cycles"] == inner * st["refinements"], st
+    assert rel_l2(host(phi), ref) <= 1e-12
+
+
+def test_mixed_is_reproducible(P):
+    p = W.SMALL.with_sizes(65, 16, 49)
+    rho = dev(W.blob_charge(p, seed=3))
+    plan = mixed_plan(P, p)
+    a, _ = plan.solve(rho, tol=1e-14)
+    a = host(a).copy()
+    b, _ = plan.solve(rho, tol=1e-14)
+    np.testing.assert_array_equal(a, host(b))
+
+
+def test_mixed_option_errors(P):
+    # a single-level grid has no V-cycle to run in FP32
+    tiny = P.Plan(5, 4, 5, 0.02, 0.05, 0.01)
+    with pytest.raises(P.CylPoissonError) as e:
+        tiny.set_option("precision", 32)
+    assert e.value.status == P.EINVAL
+    plan = P.Plan.for_problem(W.SMALL)
+    with pytest.raises(P.CylPoissonError) as e:
+        plan.set_option("precision", 16)
+    assert e.value.status == P.EINVAL
+    with pytest.raises(P.CylPoissonError):
+        plan.set_option("inner_cycles", 0)
+    # options changed after enabling mixed precision are checked at solve time
+    plan.set_option("precision", 32)
+    plan.set_option("fused", 0)
+    with pytest.raises(P.CylPoissonError) as e:
+        plan.solve(dev(np.zeros(W.SMALL.shape)), tol=1e-12)
+    assert e.value.status == P.EINVAL
+    plan.set_option("fused", 1)
+    phi, st = plan.solve(dev(np.zeros(W.SMALL.shape)), tol=1e-12)
+    assert st["status"] == P.OK
+
+
+@pytest.mark.slow
+def test_mixed_paper_scale_matches_separable_oracle(P):
+    p = W.PAPER_SCALE
+    say("paper-scale mixed: forming rho on the CPU")
+    phit, rho = manufactured(p)
+    ref = solvers.solve_separable(fv.Grid.of(p), rho, p.bc, workers=16)
+    say("paper-scale mixed solve")
+    phi, st = mixed_plan(P, p).solve(dev(rho), tol=1e-14)
+    got = host(phi)
+    assert st["status"] == P.OK, st
+    assert rel_l2(got, ref) <= 1e-12, rel_l2(got, ref)
+    assert rel_l2(got, phit) <= 1e-12
