@@ -27,6 +27,7 @@ struct BottomArgs {
     int ncoarse;
     int nu1, nu2;
     double omega;
+    int p0;                 // first plane (workgroup b solves plane p0 + b)
 };
 
 __device__ __forceinline__ int interior(const LevelView& v) { return (v.nr - 2) * (v.nz - 2); }
@@ -62,7 +63,7 @@ template <typename T>
 __global__ void __launch_bounds__(512) k_bottom(BottomArgs<T> a) {
     extern __shared__ double smem_bottom[];
     T* sm = (T*)smem_bottom;
-    const int p = blockIdx.x;
+    const int p = a.p0 + blockIdx.x;
     const double lam = a.lam[p];
     const T omega = (T)a.omega;
     // zero every level's arrays (rings stay zero), then load the right-hand side
@@ -200,7 +201,8 @@ hipError_t bottom_prepare_t(size_t bytes) {
 }
 
 template <typename T>
-hipError_t launch_bottom_t(cylpoisson_plan* p, const T* f_in, T* u_out, hipStream_t s) {
+hipError_t launch_bottom_t(cylpoisson_plan* p, const T* f_in, T* u_out, hipStream_t s, int p0, int np) {
+    if (np < 0) np = p->nt;
     const int lb = p->bottom_level;
     BottomArgs<T> a{};
     a.lv = p->d_bottom;
@@ -214,8 +216,9 @@ hipError_t launch_bottom_t(cylpoisson_plan* p, const T* f_in, T* u_out, hipStrea
     a.nu1 = p->opt.nu1;
     a.nu2 = p->opt.nu2;
     a.omega = p->opt.omega;
+    a.p0 = p0;
     const size_t bytes = bottom_lds_bytes(p, lb) / sizeof(double) * sizeof(T);
-    k_bottom<T><<<p->nt, 512, bytes, s>>>(a);
+    k_bottom<T><<<np, 512, bytes, s>>>(a);
     return hipGetLastError();
 }
 
@@ -228,14 +231,14 @@ hipError_t bottom_prepare(const cylpoisson_plan* p, int lb) {
     return e;
 }
 
-hipError_t launch_bottom(cylpoisson_plan* p, hipStream_t s) {
+hipError_t launch_bottom(cylpoisson_plan* p, hipStream_t s, int p0, int np) {
     const int lb = p->bottom_level;
-    return launch_bottom_t<double>(p, p->dl[lb].f, p->dl[lb].u, s);
+    return launch_bottom_t<double>(p, p->dl[lb].f, p->dl[lb].u, s, p0, np);
 }
 
-hipError_t launch_bottom32(cylpoisson_plan* p, hipStream_t s) {
+hipError_t launch_bottom32(cylpoisson_plan* p, hipStream_t s, int p0, int np) {
     const int lb = p->bottom_level;
-    return launch_bottom_t<float>(p, p->dl32[lb].f, p->dl32[lb].u, s);
+    return launch_bottom_t<float>(p, p->dl32[lb].f, p->dl32[lb].u, s, p0, np);
 }
 
 }  // namespace cp

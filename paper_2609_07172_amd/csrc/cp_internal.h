@@ -108,6 +108,7 @@ struct Options {
     int bottom = 1;      // run the small levels in one LDS-resident kernel per plane
     int fft = 1;         // azimuthal transforms as register FFTs where Ntheta allows
     int precision = 64;  // 64: FP64 V-cycles; 32: FP32 inner V-cycles under FP64 refinement
+    int groups = 1;      // plane groups whose V-cycles run on separate streams
     int inner_cycles = 2;  // FP32 V-cycles per FP64 refinement step
 };
 
@@ -152,6 +153,11 @@ struct cylpoisson_plan {
     std::vector<hipEvent_t> events;
     std::vector<int> event_class;
     int events_used = 0;
+
+    // plane groups: one extra stream per group after the first, and events to
+    // fork from / join into the caller's stream (created on first use)
+    std::vector<hipStream_t> gstreams;
+    std::vector<hipEvent_t> gevents;
 };
 
 namespace cp {
@@ -207,21 +213,25 @@ hipError_t launch_fft(bool inverse, int n, const double* in, double* out, long l
 // ---- bottom of the V-cycle (bottom.hip) ----
 size_t bottom_lds_bytes(const cylpoisson_plan* p, int lb);  // FP64 values
 hipError_t bottom_prepare(const cylpoisson_plan* p, int lb);
-hipError_t launch_bottom(cylpoisson_plan* p, hipStream_t s);
+// Launches over a range of planes take (p0, np): planes p0 .. p0 + np - 1,
+// all planes when np < 0.
+hipError_t launch_bottom(cylpoisson_plan* p, hipStream_t s, int p0 = 0, int np = -1);
 // The same V-cycle bottom on the FP32 levels; the coarsest correction is
 // computed in FP64 from the FP32 residual.
-hipError_t launch_bottom32(cylpoisson_plan* p, hipStream_t s);
+hipError_t launch_bottom32(cylpoisson_plan* p, hipStream_t s, int p0 = 0, int np = -1);
 
 // ---- fused passes (fused.hip) ----
 bool fused_supported(const cylpoisson_plan* p, int l);
-hipError_t fused_down(cylpoisson_plan* p, int l, bool zero_u, bool zero_interior, hipStream_t s);
+hipError_t fused_down(cylpoisson_plan* p, int l, bool zero_u, bool zero_interior, hipStream_t s,
+                      int p0 = 0, int np = -1);
 hipError_t fused_up(cylpoisson_plan* p, int l, double* partial, int partial_ld, int* nchunks,
-                    hipStream_t s);
+                    hipStream_t s, int p0 = 0, int np = -1);
 int fused_chunks(const cylpoisson_plan* p, int l, int nu);
 // FP32 passes on the dl32 buffers (mixed precision), no residual norms.
-hipError_t fused_down32(cylpoisson_plan* p, int l, bool zero_u, hipStream_t s);
+hipError_t fused_down32(cylpoisson_plan* p, int l, bool zero_u, hipStream_t s, int p0 = 0,
+                        int np = -1);
 // Every level above the bottom kernel has fused passes (plan.hip).
 bool mixed_supported(const cylpoisson_plan* p);
-hipError_t fused_up32(cylpoisson_plan* p, int l, hipStream_t s);
+hipError_t fused_up32(cylpoisson_plan* p, int l, hipStream_t s, int p0 = 0, int np = -1);
 
 }  // namespace cp

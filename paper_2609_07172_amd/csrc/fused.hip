@@ -6,36 +6,41 @@ namespace cp {
 
 bool fused_supported(const cylpoisson_plan* p, int l) {
     if (!p->opt.fused || l + 1 >= (int)p->dl.size()) return false;
-    const int nu = std::max(p->opt.nu1, p->opt.nu2);
     if (p->opt.nu1 > 4 || p->opt.nu2 > 4) return false;
-    const Shape sh = pass_shape<double>(p, l, nu);
+    const Shape sd = pass_shape<double>(p, l, p->opt.nu1, true);
+    const Shape su = pass_shape<double>(p, l, p->opt.nu2, false);
     const int nspecial = p->dl[l].v.nz - 1 - p->dl[l].spec_lo;
-    return sh.threads >= 1 && sh.threads <= 512 && sh.lds <= 64 * 1024 &&
-           sh.nchunks <= kMaxPartial && nspecial <= 4;
+    return su.threads >= 1 && su.threads <= 512 && std::max(sd.lds, su.lds) <= 64 * 1024 &&
+           std::max(sd.nchunks, su.nchunks) <= kMaxPartial && nspecial <= 4;
 }
 
-hipError_t fused_down(cylpoisson_plan* p, int l, bool zero_u, bool zero_interior, hipStream_t s) {
+hipError_t fused_down(cylpoisson_plan* p, int l, bool zero_u, bool zero_interior, hipStream_t s,
+                      int p0, int np) {
+    if (np < 0) np = p->nt;
     DeviceLevel& L = p->dl[l];
     DeviceLevel& C = p->dl[l + 1];
-    const Shape sh = pass_shape<double>(p, l, p->opt.nu1);
-    PassArgs<double> a = make_args<double>(p, l, sh);
+    const Shape sh = pass_shape<double>(p, l, p->opt.nu1, true);
+    PassArgs<double> a = make_args<double>(p, l, sh, p0, np);
     a.u_in = L.u;
     a.f = L.f;
     a.u_out = L.u2;
     a.fc = C.f;
     a.zero_interior = zero_interior ? 1 : 0;
-    return launch_nu<double>(l == 0, p->opt.nu1, p->opt.prefetch, true, zero_u, a, sh.blocks,
+    return launch_nu<double>(l == 0, p->opt.nu1, p->opt.prefetch, true, zero_u, a, sh.nchunks * np,
                              sh.threads, sh.lds, s);
 }
 
-int fused_chunks(const cylpoisson_plan* p, int l, int nu) { return pass_shape<double>(p, l, nu).nchunks; }
+int fused_chunks(const cylpoisson_plan* p, int l, int nu) {
+    return pass_shape<double>(p, l, nu, false).nchunks;
+}
 
 hipError_t fused_up(cylpoisson_plan* p, int l, double* partial, int partial_ld, int* nchunks,
-                    hipStream_t s) {
+                    hipStream_t s, int p0, int np) {
+    if (np < 0) np = p->nt;
     DeviceLevel& L = p->dl[l];
     DeviceLevel& C = p->dl[l + 1];
-    const Shape sh = pass_shape<double>(p, l, p->opt.nu2);
-    PassArgs<double> a = make_args<double>(p, l, sh);
+    const Shape sh = pass_shape<double>(p, l, p->opt.nu2, false);
+    PassArgs<double> a = make_args<double>(p, l, sh, p0, np);
     a.u_in = L.u2;
     a.f = L.f;
     a.u_out = L.u;
@@ -43,7 +48,7 @@ hipError_t fused_up(cylpoisson_plan* p, int l, double* partial, int partial_ld, 
     a.partial = partial;
     a.partial_ld = partial_ld;
     if (nchunks) *nchunks = sh.nchunks;
-    return launch_nu<double>(l == 0, p->opt.nu2, p->opt.prefetch, false, false, a, sh.blocks,
+    return launch_nu<double>(l == 0, p->opt.nu2, p->opt.prefetch, false, false, a, sh.nchunks * np,
                              sh.threads, sh.lds, s);
 }
 

@@ -65,6 +65,7 @@ struct PassArgs {
     double omega, zc0, zs0, zn0;
     int zero_interior;   // down: treat the interior of the input iterate as zero (ring is read)
     int chunk, nchunks, nt, tn;  // rows per chunk, chunks per plane, planes, columns pairs
+    int p0;              // first plane of this launch (planes p0 .. p0 + nt - 1)
     int xcd_major;       // map consecutive chunks of a plane to one XCD
 };
 
@@ -76,7 +77,10 @@ struct Pass {
     static constexpr int Q0 = 2 * NU + 3 + PD;
     static constexpr int Q = (Q0 & 1) ? Q0 + 1 : Q0;
     static constexpr int QS = Q + 1;  // LDS values per column history (odd stride)
-    static constexpr int kCRing = 8;  // up: coarse-correction rows, row K in slot K % kCRing
+    // up: coarse-correction rows in LDS, row K in slot K % kCRing.  The rows live
+    // at one step are K(x) .. K(x + PD + 1) + 1 for the consumed row x: at most
+    // 4 with one row of prefetch (a coarse interval spans one or two fine rows).
+    static constexpr int kCRing = PD == 1 ? 4 : 8;
 
     const PassArgs<T>& a;
     char* smem;
@@ -128,7 +132,7 @@ struct Pass {
         tab = (double*)(smem + off);
         off += (size_t)7 * rows * sizeof(double);
         cringp = (T*)(smem + off);
-        off += (size_t)kCRing * a.vc.nr * sizeof(T);
+        if (!DOWN) off += (size_t)kCRing * a.vc.nr * sizeof(T);
         sinvp = (T*)(smem + off);
     }
 
@@ -167,10 +171,10 @@ struct Pass {
         const int b = blockIdx.x;
         if (a.xcd_major) {
             const int xcd = b & 7, idx = b >> 3;
-            p = (idx / a.nchunks) * 8 + xcd;
+            p = a.p0 + (idx / a.nchunks) * 8 + xcd;
             chunk = idx % a.nchunks;
         } else {
-            p = b / a.nchunks;
+            p = a.p0 + b / a.nchunks;
             chunk = b % a.nchunks;
         }
         za = 1 + chunk * a.chunk;
@@ -609,7 +613,7 @@ struct Shape {
 };
 
 template <typename T>
-Shape pass_shape(const cylpoisson_plan* p, int l, int nu) {
+Shape pass_shape(const cylpoisson_plan* p, int l, int nu, bool down) {
     const DeviceLevel& L = p->dl[l];
     Shape sh;
     sh.tn = L.v.nr / 2;  // column pairs covering columns 1 .. nr-1
@@ -628,21 +632,23 @@ Shape pass_shape(const cylpoisson_plan* p, int l, int nu) {
     sh.chunk = chunk;
     sh.nchunks = (rows + chunk - 1) / chunk;
     sh.blocks = sh.nchunks * p->nt;
-    const int q0 = 2 * nu + 3 + pass_prefetch<T>(nu, p->opt.prefetch);
+    const int pd = pass_prefetch<T>(nu, p->opt.prefetch);
+    const int q0 = 2 * nu + 3 + pd;
     const size_t qs = (size_t)((q0 & 1) ? q0 + 1 : q0) + 1;
     const size_t trows = (size_t)(chunk + 4 * nu + 6);
     const size_t nspecial = (size_t)std::max(0, L.v.nz - 1 - L.spec_lo);
     size_t off = (2 * (sh.tn + 1) * qs + 4 * (sh.tn + 1)) * sizeof(T);
     off = (off + 7) & ~(size_t)7;
     off += 7 * trows * sizeof(double);
-    off += (size_t)8 * p->dl[l + 1].v.nr * sizeof(T);
+    if (!down) off += (size_t)(pd == 1 ? 4 : 8) * p->dl[l + 1].v.nr * sizeof(T);
     off += nspecial * 2 * sh.tn * sizeof(T);
     sh.lds = std::max(off, (size_t)sh.threads * sizeof(double));  // final block reduction
     return sh;
 }
 
+// Arguments of a pass over planes p0 .. p0 + np - 1 (its grid is sh.nchunks * np).
 template <typename T>
-PassArgs<T> make_args(const cylpoisson_plan* p, int l, const Shape& sh) {
+PassArgs<T> make_args(const cylpoisson_plan* p, int l, const Shape& sh, int p0, int np) {
     const DeviceLevel& L = p->dl[l];
     const DeviceLevel& C = p->dl[l + 1];
     PassArgs<T> a{};
@@ -660,9 +666,10 @@ PassArgs<T> make_args(const cylpoisson_plan* p, int l, const Shape& sh) {
     a.zn0 = L.zn0;
     a.chunk = sh.chunk;
     a.nchunks = sh.nchunks;
-    a.nt = p->nt;
+    a.nt = np;
+    a.p0 = p0;
     a.tn = sh.tn;
-    a.xcd_major = (p->nt % 8 == 0) ? 1 : 0;
+    a.xcd_major = (np % 8 == 0) ? 1 : 0;
     return a;
 }
 

@@ -154,6 +154,10 @@ hipError_t upload(cylpoisson_plan* p, T** out, const std::vector<T>& host) {
 void free_plan(cylpoisson_plan* p) {
     for (hipEvent_t e : p->events) (void)hipEventDestroy(e);
     p->events.clear();
+    for (hipEvent_t e : p->gevents) (void)hipEventDestroy(e);
+    p->gevents.clear();
+    for (hipStream_t st : p->gstreams) (void)hipStreamDestroy(st);
+    p->gstreams.clear();
     for (void* ptr : p->allocations) (void)hipFree(ptr);
     p->allocations.clear();
     if (p->h_norms) (void)hipHostFree(p->h_norms);
@@ -612,6 +616,7 @@ int cylpoisson_plan_set_option(cylpoisson_plan* plan, const char* key, double va
     if (!std::strcmp(key, "bottom")) return int_in(0, 1, &plan->opt.bottom);
     if (!std::strcmp(key, "fft")) return int_in(0, 1, &plan->opt.fft);
     if (!std::strcmp(key, "inner_cycles")) return int_in(1, 8, &plan->opt.inner_cycles);
+    if (!std::strcmp(key, "groups")) return int_in(1, 8, &plan->opt.groups);
     if (!std::strcmp(key, "precision")) {
         if (value != 32.0 && value != 64.0) {
             set_error("precision must be 64 (FP64 V-cycles) or 32 (FP32 inner V-cycles)");

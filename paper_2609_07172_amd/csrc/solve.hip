@@ -161,7 +161,10 @@ struct NormSlot {
 // level 0 `zero_top` says its interior is still to be treated as zero (first
 // cycle).  With `slot` >= 0 and level 0 on the fused passes, the up pass also
 // produces the squared residual norms of that cycle (recorded in *ns).
-hipError_t vcycle(cylpoisson_plan* p, int l, hipStream_t s, bool zero_top, int slot, NormSlot* ns) {
+// Planes p0 .. p0 + np - 1 (all when np < 0); a partial range needs the fused
+// passes down to the bottom kernel (groups_active).
+hipError_t vcycle(cylpoisson_plan* p, int l, hipStream_t s, bool zero_top, int slot, NormSlot* ns,
+                  int p0 = 0, int np = -1) {
     const int nl = (int)p->dl.size();
     DeviceLevel& L = p->dl[l];
     hipError_t e = hipSuccess;
@@ -171,17 +174,17 @@ hipError_t vcycle(cylpoisson_plan* p, int l, hipStream_t s, bool zero_top, int s
             e = launch_coarse_solve(L, p->nt, p->d_lam, p->d_cinv, p->coarse_n, L.f, L.u, s);
         return e;
     }
-    if (l > 0 && l == p->bottom_level && p->opt.bottom && p->opt.fused) return launch_bottom(p, s);
+    if (l > 0 && l == p->bottom_level && p->opt.bottom && p->opt.fused) return launch_bottom(p, s, p0, np);
     DeviceLevel& C = p->dl[l + 1];
     if (fused_supported(p, l)) {
         {
             Timed tm(p, l == 0 ? kFineDown : -1, s);
             // coarser levels start from a zero iterate with a zero ring
-            e = fused_down(p, l, l > 0, l == 0 && zero_top, s);
+            e = fused_down(p, l, l > 0, l == 0 && zero_top, s, p0, np);
         }
         if (e == hipSuccess) {
             Timed tm(p, l == 0 ? kCoarse : -1, s);
-            e = vcycle(p, l + 1, s, true, -1, nullptr);
+            e = vcycle(p, l + 1, s, true, -1, nullptr, p0, np);
         }
         const bool want = l == 0 && slot >= 0;
         const int nch = fused_chunks(p, l, p->opt.nu2);
@@ -190,7 +193,7 @@ hipError_t vcycle(cylpoisson_plan* p, int l, hipStream_t s, bool zero_top, int s
             Timed tm(p, l == 0 ? kFineUp : -1, s);
             double* part = host_sum ? p->d_slot_partial + (size_t)slot * p->nt * kSlotPartial
                                     : (want ? p->d_partial : nullptr);
-            e = fused_up(p, l, part, host_sum ? kSlotPartial : kMaxPartial, nullptr, s);
+            e = fused_up(p, l, part, host_sum ? kSlotPartial : kMaxPartial, nullptr, s, p0, np);
         }
         if (e == hipSuccess && want) {
             if (host_sum) {
@@ -225,20 +228,78 @@ hipError_t vcycle(cylpoisson_plan* p, int l, hipStream_t s, bool zero_top, int s
 // One FP32 V-cycle from level l on the FP32 buffers (mixed precision): fused
 // passes on every level above the bottom kernel.  Level 0 starts from a zero
 // correction when `zero_top`; coarser levels always do.
-hipError_t vcycle32(cylpoisson_plan* p, int l, bool zero_top, hipStream_t s) {
-    if (l == p->bottom_level) return launch_bottom32(p, s);
+hipError_t vcycle32(cylpoisson_plan* p, int l, bool zero_top, hipStream_t s, int p0 = 0, int np = -1) {
+    if (l == p->bottom_level) return launch_bottom32(p, s, p0, np);
     hipError_t e;
     {
         Timed tm(p, l == 0 ? kFineDown : -1, s);
-        e = fused_down32(p, l, l > 0 || zero_top, s);
+        e = fused_down32(p, l, l > 0 || zero_top, s, p0, np);
     }
     if (e == hipSuccess) {
         Timed tm(p, l == 0 ? kCoarse : -1, s);
-        e = vcycle32(p, l + 1, true, s);
+        e = vcycle32(p, l + 1, true, s, p0, np);
     }
     if (e == hipSuccess) {
         Timed tm(p, l == 0 ? kFineUp : -1, s);
-        e = fused_up32(p, l, s);
+        e = fused_up32(p, l, s, p0, np);
+    }
+    return e;
+}
+
+// ---- plane groups on separate streams ----
+// The planes are independent between convergence checks, so G groups of
+// planes run their V-cycles on G streams (the caller's and G - 1 of the
+// plan's), which lets one group's latency-bound coarse levels overlap another
+// group's bandwidth-bound finest-level passes.  Needs the fused passes on
+// every level above the bottom kernel and per-chunk norm partials kept for
+// the host.
+
+int groups_active(const cylpoisson_plan* p) {
+    const int g = std::min(p->opt.groups, p->nt);
+    if (g <= 1 || !mixed_supported(p)) return 1;
+    if (fused_chunks(p, 0, p->opt.nu2) > kSlotPartial) return 1;
+    return g;
+}
+
+void group_range(const cylpoisson_plan* p, int G, int g, int* p0, int* np) {
+    *p0 = (int)((long long)g * p->nt / G);
+    *np = (int)((long long)(g + 1) * p->nt / G) - *p0;
+}
+
+hipStream_t group_stream(const cylpoisson_plan* p, int g, hipStream_t s) {
+    return g == 0 ? s : p->gstreams[g - 1];
+}
+
+hipError_t ensure_groups(cylpoisson_plan* p, int G) {
+    while ((int)p->gstreams.size() < G - 1) {
+        hipStream_t st;
+        hipError_t e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
+        if (e != hipSuccess) return e;
+        p->gstreams.push_back(st);
+    }
+    while ((int)p->gevents.size() < G) {
+        hipEvent_t ev;
+        hipError_t e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+        if (e != hipSuccess) return e;
+        p->gevents.push_back(ev);
+    }
+    return hipSuccess;
+}
+
+// Work enqueued on the group streams after this starts after everything on s so far.
+hipError_t fork_groups(cylpoisson_plan* p, int G, hipStream_t s) {
+    if (G <= 1) return hipSuccess;
+    hipError_t e = hipEventRecord(p->gevents[0], s);
+    for (int g = 1; g < G && e == hipSuccess; ++g) e = hipStreamWaitEvent(p->gstreams[g - 1], p->gevents[0], 0);
+    return e;
+}
+
+// Work enqueued on s after this starts after everything on the group streams so far.
+hipError_t join_groups(cylpoisson_plan* p, int G, hipStream_t s) {
+    hipError_t e = hipSuccess;
+    for (int g = 1; g < G && e == hipSuccess; ++g) {
+        e = hipEventRecord(p->gevents[g], p->gstreams[g - 1]);
+        if (e == hipSuccess) e = hipStreamWaitEvent(s, p->gevents[g], 0);
     }
     return e;
 }
@@ -293,6 +354,11 @@ int run_cycles(cylpoisson_plan* p, double tol, hipStream_t s, bool ring_only) {
         return st.status;
     }
 
+    const int G = groups_active(p);
+    if (G > 1) {
+        CP_HIP(ensure_groups(p, G));
+        CP_HIP(fork_groups(p, G, s));
+    }
     int next_check = std::min(2, maxc);
     int last_read = 0;
     double prev_rel = 1.0;
@@ -300,13 +366,18 @@ int run_cycles(cylpoisson_plan* p, double tol, hipStream_t s, bool ring_only) {
     int stagnant = 0;
     std::vector<double> plane(nt);
     for (int c = 1; c <= maxc; ++c) {
-        CP_HIP(vcycle(p, 0, s, c == 1 && ring_only, c, &slots[c]));
+        for (int g = 0; g < G; ++g) {
+            int p0, np;
+            group_range(p, G, g, &p0, &np);
+            CP_HIP(vcycle(p, 0, group_stream(p, g, s), c == 1 && ring_only, c, &slots[c], p0, np));
+        }
         if (slots[c].partial_chunks < 0) {
             CP_HIP(residual_norms(p, c, s));
             slots[c].partial_chunks = 0;
         }
         st.cycles = c;
         if (c != next_check && c != maxc) continue;
+        CP_HIP(join_groups(p, G, s));
         const int first = last_read + 1;
         for (int t = first; t <= c; ++t) {
             if (slots[t].partial_chunks > 0)
@@ -449,7 +520,18 @@ int run_mixed(cylpoisson_plan* p, double tol, hipStream_t s, double** result) {
             set_error("tolerance %.3e not reached in %d cycles (relative residual %.3e)", tol, cycles, rel);
             break;
         }
-        for (int c = 0; c < ic; ++c) CP_HIP(vcycle32(p, 0, c == 0, s));
+        const int G = groups_active(p);
+        if (G > 1) {
+            CP_HIP(ensure_groups(p, G));
+            CP_HIP(fork_groups(p, G, s));
+        }
+        for (int c = 0; c < ic; ++c)
+            for (int g = 0; g < G; ++g) {
+                int p0, np;
+                group_range(p, G, g, &p0, &np);
+                CP_HIP(vcycle32(p, 0, c == 0, group_stream(p, g, s), p0, np));
+            }
+        CP_HIP(join_groups(p, G, s));
         cycles += ic;
         st.cycles = cycles;
     }
