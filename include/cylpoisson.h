@@ -92,6 +92,8 @@ typedef struct {
      * their FP32 V-cycles and the history holds the FP64 relative residual
      * after each inner solve (at index cycles - 1).  0 on the FP64 path. */
     int refinements;
+    /* Planes frozen by the option "masks" when the solve ended (0 otherwise). */
+    int frozen_planes;
 } cylpoisson_stats;
 
 typedef struct {
@@ -140,11 +142,55 @@ void cylpoisson_plan_destroy(cylpoisson_plan* plan);
  *                    needs the fused passes and the LDS bottom kernel on this grid
  *                    (EINVAL otherwise, also at solve time if options changed)
  *   "inner_cycles"   FP32 V-cycles per refinement step (1 .. 8; default 2)
+ *   "groups"         plane groups whose V-cycles run on separate streams between
+ *                    convergence checks (1 .. 8; default 1; used when every level
+ *                    above the bottom kernel has fused passes, else 1).  Results
+ *                    do not depend on it
+ *   "warm_start"     1 = cylpoisson_solve takes the phi it is given as the initial
+ *                    guess (its interior nodes; boundary nodes are ignored and
+ *                    rewritten); 0 = zero initial guess, phi not read (default 0)
+ *   "masks"          1 = per-plane convergence masks: a plane whose weighted squared
+ *                    residual is within tol^2 ||b||^2 / Ntheta stops being cycled
+ *                    (its last iterate is kept), FP64 path with fused passes
+ *                    (default 0)
+ *   "graph"          1 = each V-cycle is captured once into a HIP graph and replayed
+ *                    (single plane group, "timing" 0; default 0).  Setting any
+ *                    option releases the captured graphs
  * Returns CYLPOISSON_OK, CYLPOISSON_EINVAL or CYLPOISSON_ENOMEM. */
 int cylpoisson_plan_set_option(cylpoisson_plan* plan, const char* key, double value);
 
-/* Solve for phi given rho (both device node arrays).  Zero initial guess,
- * V-cycles until the relative residual (cylpoisson_stats) is <= tol or
+/* Read back an option (keys as for cylpoisson_plan_set_option).  Returns OK or
+ * EINVAL (unknown key, NULL argument). */
+int cylpoisson_plan_get_option(const cylpoisson_plan* plan, const char* key, double* value);
+
+/* Autotuner for the launch shapes of the fused passes: times short solves (two
+ * V-cycles, synthetic charge in two temporary node arrays it allocates and
+ * frees) on `stream`, varying one option at a time over candidate values of
+ * "chunk_rows", "chunk_rows_coarse", "prefetch" and "groups", and keeps a value
+ * only when it is at least 3% faster.  Leaves those four options at the chosen
+ * values (read them with cylpoisson_plan_get_option) and every other option as
+ * it was.  Results of later solves do not depend on the choice beyond rounding
+ * order (tile shapes do not change the arithmetic of a node).  Blocks; returns
+ * OK, ENOMEM or an error of the trial solves. */
+int cylpoisson_autotune(cylpoisson_plan* plan, void* stream);
+
+/* Solve `count` independent problems (distinct plans, each with its own grid)
+ * together: problem i solves plans[i] with rho[i] -> phi[i] exactly as
+ * cylpoisson_solve would, all problems running concurrently on streams of
+ * their own (ordered after the work already on `stream`; `stream` waits for
+ * all of them on return), so small problems fill the GPU together.  The same
+ * tol for all; statuses (optional, count entries) receives each problem's
+ * status, and each plan's stats hold its own history.  Returns the first
+ * negative status, else NOT_CONVERGED if any problem did not converge, else
+ * OK.  Blocks until every problem's result is decided. */
+int cylpoisson_solve_batch(cylpoisson_plan* const* plans, const double* const* rho,
+                           double* const* phi, int count, double tol, void* stream,
+                           int* statuses);
+
+/* Solve for phi given rho (both device node arrays).  Zero initial guess
+ * (or phi itself with the option "warm_start"; a guess already within tol
+ * returns after 0 cycles), V-cycles until the relative residual
+ * (cylpoisson_stats, always relative to the right-hand side) is <= tol or
  * max_cycles is reached (with "precision" = 32: refinement steps of
  * "inner_cycles" FP32 V-cycles each, while the total stays within max_cycles;
  * the residual is always the FP64 one).  rho is read only at interior nodes; every node of

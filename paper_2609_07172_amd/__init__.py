@@ -21,6 +21,7 @@ __all__ = [
     "CylPoissonError", "library", "library_path", "plan_create", "plan_destroy",
     "plan_set_option", "solve", "solve_planes", "apply", "dft_forward", "dft_inverse",
     "get_stats", "get_info", "last_error", "status_string", "Plan", "EXPORTED_SYMBOLS",
+    "plan_get_option", "autotune", "solve_batch", "solve_plans",
 ]
 
 OK, NOT_CONVERGED = 0, 1
@@ -33,7 +34,8 @@ EXPORTED_SYMBOLS = (
     "cylpoisson_plan_create", "cylpoisson_plan_destroy", "cylpoisson_plan_set_option",
     "cylpoisson_solve", "cylpoisson_get_stats", "cylpoisson_get_info", "cylpoisson_apply",
     "cylpoisson_dft_forward", "cylpoisson_dft_inverse", "cylpoisson_solve_planes",
-    "cylpoisson_last_error", "cylpoisson_status_string",
+    "cylpoisson_last_error", "cylpoisson_status_string", "cylpoisson_plan_get_option",
+    "cylpoisson_autotune", "cylpoisson_solve_batch",
 )
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -52,7 +54,7 @@ class Stats(ctypes.Structure):
                 ("rel_residual_history", ctypes.c_double * MAX_HISTORY),
                 ("kernel_launches", ctypes.c_int * len(KERNEL_CLASSES)),
                 ("kernel_ms", ctypes.c_double * len(KERNEL_CLASSES)),
-                ("refinements", ctypes.c_int)]
+                ("refinements", ctypes.c_int), ("frozen_planes", ctypes.c_int)]
 
     def as_dict(self) -> dict:
         hist = [self.rel_residual_history[i] for i in range(min(self.n_history, MAX_HISTORY))]
@@ -62,7 +64,7 @@ class Stats(ctypes.Structure):
                 "history": [None if math.isnan(h) else h for h in hist],
                 "kernel_launches": dict(zip(KERNEL_CLASSES, list(self.kernel_launches))),
                 "kernel_ms": dict(zip(KERNEL_CLASSES, list(self.kernel_ms))),
-                "refinements": self.refinements}
+                "refinements": self.refinements, "frozen_planes": self.frozen_planes}
 
 
 class Info(ctypes.Structure):
@@ -110,6 +112,13 @@ def library() -> ctypes.CDLL:
     for name in ("cylpoisson_apply", "cylpoisson_dft_forward", "cylpoisson_dft_inverse"):
         getattr(L, name).restype = i
         getattr(L, name).argtypes = [vp, vp, vp, vp]
+    L.cylpoisson_plan_get_option.restype = i
+    L.cylpoisson_plan_get_option.argtypes = [vp, ctypes.c_char_p, ctypes.POINTER(d)]
+    L.cylpoisson_autotune.restype = i
+    L.cylpoisson_autotune.argtypes = [vp, vp]
+    L.cylpoisson_solve_batch.restype = i
+    L.cylpoisson_solve_batch.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(vp), i,
+                                         d, vp, ctypes.POINTER(i)]
     L.cylpoisson_get_stats.restype = i
     L.cylpoisson_get_stats.argtypes = [vp, ctypes.POINTER(Stats)]
     L.cylpoisson_get_info.restype = i
@@ -172,6 +181,30 @@ def plan_set_option(plan, key: str, value: float) -> None:
     _check(library().cylpoisson_plan_set_option(plan, key.encode(), float(value)))
 
 
+def plan_get_option(plan, key: str) -> float:
+    v = ctypes.c_double()
+    _check(library().cylpoisson_plan_get_option(plan, key.encode(), ctypes.byref(v)))
+    return v.value
+
+
+def autotune(plan, stream=None) -> None:
+    _check(library().cylpoisson_autotune(plan, _stream(stream)))
+
+
+def solve_batch(plans, rhos, phis, tol=1e-12, stream=None, allow=(OK,)):
+    """``cylpoisson_solve_batch``: returns (batch status, per-problem statuses)."""
+    n = len(plans)
+    if not (len(rhos) == len(phis) == n):
+        raise ValueError("plans, rhos and phis must have the same length")
+    arr = ctypes.c_void_p * max(n, 1)
+    st = (ctypes.c_int * max(n, 1))()
+    status = library().cylpoisson_solve_batch(arr(*[p for p in plans]), arr(*[_ptr(r) for r in rhos]),
+                                              arr(*[_ptr(f) for f in phis]), n, float(tol),
+                                              _stream(stream), st)
+    _check(status, allow)
+    return status, [st[i] for i in range(n)]
+
+
 def solve(plan, rho, phi, tol=1e-12, stream=None, allow=(OK,)) -> int:
     return _check(library().cylpoisson_solve(plan, _ptr(rho), _ptr(phi), float(tol),
                                              _stream(stream)), allow)
@@ -222,6 +255,12 @@ class Plan:
     def set_option(self, key, value):
         plan_set_option(self.handle, key, value)
 
+    def get_option(self, key) -> float:
+        return plan_get_option(self.handle, key)
+
+    def autotune(self, stream=None) -> None:
+        autotune(self.handle, stream)
+
     def _check_shape(self, *tensors):
         for t in tensors:
             if tuple(t.shape) != self.shape:
@@ -250,3 +289,13 @@ class Plan:
             self.close()
         except Exception:
             pass
+
+
+def solve_plans(plans, rhos, tol=1e-12, stream=None, allow=(OK,)):
+    """Batch-solve Plan objects: returns (phis, per-problem stats)."""
+    for plan, rho in zip(plans, rhos):
+        plan._check_shape(rho)
+    phis = [torch.empty_like(r) for r in rhos]
+    status, sts = solve_batch([p.handle for p in plans], rhos, phis, tol, stream, allow)
+    return phis, [p.stats() for p in plans]
+

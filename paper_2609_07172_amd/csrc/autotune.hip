@@ -1,0 +1,199 @@
+// Tile-shape autotuner and batched solves of independent problems.
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <thread>
+#include <vector>
+
+#include "cp_internal.h"
+
+namespace cp {
+
+namespace {
+
+// Deterministic synthetic charge for timing: a hash of the node index mapped
+// to [-1, 1] x 1e-4 C/m^3 (only the launch shapes are being timed).
+__global__ void k_fill_hash(double* x, long long n) {
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    unsigned long long h = (unsigned long long)i * 0x9E3779B97F4A7C15ull;
+    h ^= h >> 31;
+    h *= 0xBF58476D1CE4E5B9ull;
+    h ^= h >> 29;
+    x[i] = ((double)(h >> 11) * (1.0 / 9007199254740992.0) * 2.0 - 1.0) * 1e-4;
+}
+
+struct Candidate {
+    const char* key;
+    std::vector<double> values;
+};
+
+}  // namespace
+
+}  // namespace cp
+
+using namespace cp;
+
+extern "C" {
+
+int cylpoisson_autotune(cylpoisson_plan* p, void* stream) {
+    if (!p) {
+        set_error("plan must not be NULL");
+        return CYLPOISSON_EINVAL;
+    }
+    int prev_dev = 0;
+    (void)hipGetDevice(&prev_dev);
+    (void)hipSetDevice(p->device);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const long long n = (long long)p->nt * p->nz * p->nr;
+    double* rho = nullptr;
+    double* phi = nullptr;
+    int status = CYLPOISSON_OK;
+    if (hipMalloc(&rho, n * sizeof(double)) != hipSuccess || hipMalloc(&phi, n * sizeof(double)) != hipSuccess) {
+        (void)hipGetLastError();
+        if (rho) (void)hipFree(rho);
+        (void)hipSetDevice(prev_dev);
+        set_error("autotune: cannot allocate two node arrays");
+        return CYLPOISSON_ENOMEM;
+    }
+    k_fill_hash<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(rho, n);
+    const Options saved = p->opt;
+    // a fixed amount of work per trial: two cycles, never converged
+    p->opt.max_cycles = 2;
+    p->opt.timing = 0;
+    p->opt.warm_start = 0;
+    auto trial = [&](double* ms) -> int {
+        drop_graphs(p);
+        for (int rep = 0; rep < 4; ++rep) {
+            const auto t0 = std::chrono::steady_clock::now();
+            const int st = cylpoisson_solve(p, rho, phi, 1e-300, stream);
+            if (st != CYLPOISSON_OK && st != CYLPOISSON_NOT_CONVERGED) return st;
+            if (hipStreamSynchronize(s) != hipSuccess) return CYLPOISSON_EHIP;
+            const double t = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+            if (rep == 1 || (rep > 1 && t < *ms)) *ms = t;  // first run warms up
+        }
+        return CYLPOISSON_OK;
+    };
+    const int rows = p->nz - 2;
+    std::vector<Candidate> cands = {
+        {"chunk_rows", {0, 32, 48, 64, 96, 128, 192, 256}},
+        {"chunk_rows_coarse", {0, 16, 24, 32, 48, 64}},
+        {"prefetch", {1, 2, 3}},
+        {"groups", {1, 2, 4}},
+    };
+    double best = INFINITY;
+    status = trial(&best);
+    for (const Candidate& c : cands) {
+        double keep = 0.0;
+        (void)cylpoisson_plan_get_option(p, c.key, &keep);
+        for (double v : c.values) {
+            if (v == keep) continue;
+            if ((!std::strcmp(c.key, "chunk_rows") || !std::strcmp(c.key, "chunk_rows_coarse")) && v > rows)
+                continue;
+            if (cylpoisson_plan_set_option(p, c.key, v) != CYLPOISSON_OK) continue;
+            double t = INFINITY;
+            const int st = trial(&t);
+            if (st != CYLPOISSON_OK) {
+                status = st;
+                break;
+            }
+            if (t < 0.97 * best) {  // keep a change only for a clear gain
+                best = t;
+                keep = v;
+            }
+        }
+        (void)cylpoisson_plan_set_option(p, c.key, keep);
+        if (status != CYLPOISSON_OK) break;
+    }
+    const Options tuned = p->opt;
+    p->opt = saved;
+    p->opt.chunk_rows = tuned.chunk_rows;
+    p->opt.chunk_rows_coarse = tuned.chunk_rows_coarse;
+    p->opt.prefetch = tuned.prefetch;
+    p->opt.groups = tuned.groups;
+    drop_graphs(p);
+    (void)hipFree(rho);
+    (void)hipFree(phi);
+    (void)hipSetDevice(prev_dev);
+    return status;
+}
+
+int cylpoisson_solve_batch(cylpoisson_plan* const* plans, const double* const* rho, double* const* phi,
+                           int count, double tol, void* stream, int* statuses) {
+    if (count < 0 || (count > 0 && (!plans || !rho || !phi))) {
+        set_error("batch arrays must not be NULL and count must be >= 0");
+        return CYLPOISSON_EINVAL;
+    }
+    for (int i = 0; i < count; ++i)
+        for (int j = 0; j < i; ++j)
+            if (plans[i] == plans[j] || !plans[i]) {
+                set_error("batch entry %d: plans must be distinct and not NULL", i);
+                return CYLPOISSON_EINVAL;
+            }
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    // one stream and one host thread per problem; each solve runs exactly as alone
+    std::vector<hipStream_t> st(count, nullptr);
+    std::vector<hipEvent_t> ev(count, nullptr);
+    std::vector<int> res(count, CYLPOISSON_OK);
+    std::vector<std::string> msg(count);
+    hipEvent_t start = nullptr;
+    int status = CYLPOISSON_OK;
+    if (hipEventCreateWithFlags(&start, hipEventDisableTiming) != hipSuccess ||
+        hipEventRecord(start, s) != hipSuccess) {
+        (void)hipGetLastError();
+        set_error("batch: cannot order the problems after the caller's stream");
+        if (start) (void)hipEventDestroy(start);
+        return CYLPOISSON_EHIP;
+    }
+    for (int i = 0; i < count && status == CYLPOISSON_OK; ++i) {
+        int prev = 0;
+        (void)hipGetDevice(&prev);
+        (void)hipSetDevice(plans[i]->device);
+        if (hipStreamCreateWithFlags(&st[i], hipStreamNonBlocking) != hipSuccess ||
+            hipEventCreateWithFlags(&ev[i], hipEventDisableTiming) != hipSuccess ||
+            hipStreamWaitEvent(st[i], start, 0) != hipSuccess) {
+            (void)hipGetLastError();
+            set_error("batch: cannot create the stream of problem %d", i);
+            status = CYLPOISSON_EHIP;
+        }
+        (void)hipSetDevice(prev);
+    }
+    if (status == CYLPOISSON_OK) {
+        std::vector<std::thread> threads;
+        threads.reserve(count);
+        for (int i = 0; i < count; ++i)
+            threads.emplace_back([&, i] {
+                res[i] = cylpoisson_solve(plans[i], rho[i], phi[i], tol, st[i]);
+                msg[i] = cylpoisson_last_error();
+                if (hipEventRecord(ev[i], st[i]) != hipSuccess) res[i] = CYLPOISSON_EHIP;
+            });
+        for (auto& t : threads) t.join();
+        for (int i = 0; i < count; ++i) {
+            if (statuses) statuses[i] = res[i];
+            if (hipStreamWaitEvent(s, ev[i], 0) != hipSuccess) res[i] = CYLPOISSON_EHIP;
+        }
+        // the batch status: the first error, else NOT_CONVERGED if any, else OK
+        for (int i = 0; i < count; ++i)
+            if (res[i] < 0) {
+                set_error("batch problem %d: %s", i, msg[i].c_str());
+                status = res[i];
+                break;
+            }
+        if (status == CYLPOISSON_OK)
+            for (int i = 0; i < count; ++i)
+                if (res[i] == CYLPOISSON_NOT_CONVERGED) {
+                    set_error("batch problem %d: %s", i, msg[i].c_str());
+                    status = CYLPOISSON_NOT_CONVERGED;
+                    break;
+                }
+    }
+    for (int i = 0; i < count; ++i) {
+        if (st[i]) (void)hipStreamSynchronize(st[i]);
+        if (st[i]) (void)hipStreamDestroy(st[i]);
+        if (ev[i]) (void)hipEventDestroy(ev[i]);
+    }
+    (void)hipEventDestroy(start);
+    return status;
+}
+
+}  // extern "C"

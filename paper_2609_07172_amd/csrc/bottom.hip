@@ -28,6 +28,7 @@ struct BottomArgs {
     int nu1, nu2;
     double omega;
     int p0;                 // first plane (workgroup b solves plane p0 + b)
+    const int* mask;        // per plane: 0 = frozen (skipped), or nullptr
 };
 
 __device__ __forceinline__ int interior(const LevelView& v) { return (v.nr - 2) * (v.nz - 2); }
@@ -64,6 +65,7 @@ __global__ void __launch_bounds__(512) k_bottom(BottomArgs<T> a) {
     extern __shared__ double smem_bottom[];
     T* sm = (T*)smem_bottom;
     const int p = a.p0 + blockIdx.x;
+    if (a.mask && a.mask[p] == 0) return;  // whole workgroup, before any barrier
     const double lam = a.lam[p];
     const T omega = (T)a.omega;
     // zero every level's arrays (rings stay zero), then load the right-hand side
@@ -217,6 +219,7 @@ hipError_t launch_bottom_t(cylpoisson_plan* p, const T* f_in, T* u_out, hipStrea
     a.nu2 = p->opt.nu2;
     a.omega = p->opt.omega;
     a.p0 = p0;
+    a.mask = p->opt.masks ? p->d_mask : nullptr;
     const size_t bytes = bottom_lds_bytes(p, lb) / sizeof(double) * sizeof(T);
     k_bottom<T><<<np, 512, bytes, s>>>(a);
     return hipGetLastError();

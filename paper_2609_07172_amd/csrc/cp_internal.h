@@ -109,6 +109,9 @@ struct Options {
     int fft = 1;         // azimuthal transforms as register FFTs where Ntheta allows
     int precision = 64;  // 64: FP64 V-cycles; 32: FP32 inner V-cycles under FP64 refinement
     int groups = 1;      // plane groups whose V-cycles run on separate streams
+    int warm_start = 0;  // 1: cylpoisson_solve starts from the phi it is given
+    int masks = 0;       // 1: planes that met their share of the tolerance stop cycling
+    int graph = 0;       // 1: replay captured HIP graphs of the V-cycles
     int inner_cycles = 2;  // FP32 V-cycles per FP64 refinement step
 };
 
@@ -158,6 +161,15 @@ struct cylpoisson_plan {
     // fork from / join into the caller's stream (created on first use)
     std::vector<hipStream_t> gstreams;
     std::vector<hipEvent_t> gevents;
+
+    // per-plane convergence masks (1 = active), device and pinned host copies
+    int* d_mask = nullptr;
+    int* h_mask = nullptr;
+
+    // captured V-cycles: key (cycle index, first-cycle flag) -> executable graph
+    hipStream_t cap_stream = nullptr;
+    std::vector<std::pair<int, hipGraphExec_t>> graphs;
+    std::vector<int> graph_chunks;  // norm partial chunks recorded per captured cycle
 };
 
 namespace cp {
@@ -198,9 +210,10 @@ hipError_t launch_rhs_norms(const DeviceLevel& L, int nt, const double* lam, con
 hipError_t launch_copy_ring(const DeviceLevel& L, int nt, const double* src, double* dst,
                             hipStream_t s);
 // FP64 refinement step of the mixed-precision solve on the finest level:
-// u_out = u_in + e (when e is given, u_out != u_in; else the interior of u_in
-// is taken as zero and u_out's interior written so, in place allowed),
-// r = f - A u_out rounded to FP32, per-plane FP64 sums of r^2.
+// u_out = u_in + e (when e is given, u_out != u_in); else with u_out given the
+// interior of u_in is taken as zero and u_out's interior written so (in place
+// allowed); else (no e, no u_out) u_in is taken as it is.  r = f - A u rounded
+// to FP32 into r32, per-plane FP64 sums of r^2 into norms_out.
 hipError_t launch_refine(const DeviceLevel& L, int nt, const double* lam, const double* uin,
                          double* uout, const float* e, const double* f, float* r32,
                          double* partial, double* norms_out, hipStream_t s);
@@ -230,6 +243,8 @@ int fused_chunks(const cylpoisson_plan* p, int l, int nu);
 // FP32 passes on the dl32 buffers (mixed precision), no residual norms.
 hipError_t fused_down32(cylpoisson_plan* p, int l, bool zero_u, hipStream_t s, int p0 = 0,
                         int np = -1);
+// Release the captured V-cycle graphs (plan.hip).
+void drop_graphs(cylpoisson_plan* p);
 // Every level above the bottom kernel has fused passes (plan.hip).
 bool mixed_supported(const cylpoisson_plan* p);
 hipError_t fused_up32(cylpoisson_plan* p, int l, hipStream_t s, int p0 = 0, int np = -1);

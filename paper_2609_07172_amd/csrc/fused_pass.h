@@ -66,6 +66,7 @@ struct PassArgs {
     int zero_interior;   // down: treat the interior of the input iterate as zero (ring is read)
     int chunk, nchunks, nt, tn;  // rows per chunk, chunks per plane, planes, columns pairs
     int p0;              // first plane of this launch (planes p0 .. p0 + nt - 1)
+    const int* mask;     // per plane: 0 = frozen (its workgroups return at once), or nullptr
     int xcd_major;       // map consecutive chunks of a plane to one XCD
 };
 
@@ -488,7 +489,15 @@ struct Pass {
 #undef CP_STEP
     }
 
+    __device__ __forceinline__ int plane_of_block() const {
+        const int b = blockIdx.x;
+        if (a.xcd_major) return a.p0 + ((b >> 3) / a.nchunks) * 8 + (b & 7);
+        return a.p0 + b / a.nchunks;
+    }
+
     __device__ __forceinline__ void run() {
+        // a frozen plane keeps its iterate: the whole workgroup leaves before any barrier
+        if (a.mask && a.mask[plane_of_block()] == 0) return;
         setup();
         // last step: the residual of row zb (down) or zb - 1 (up), plus one step
         // to finish the pending restriction
@@ -668,6 +677,7 @@ PassArgs<T> make_args(const cylpoisson_plan* p, int l, const Shape& sh, int p0, 
     a.nchunks = sh.nchunks;
     a.nt = np;
     a.p0 = p0;
+    a.mask = p->opt.masks ? p->d_mask : nullptr;
     a.tn = sh.tn;
     a.xcd_major = (np % 8 == 0) ? 1 : 0;
     return a;

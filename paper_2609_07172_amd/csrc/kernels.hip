@@ -206,21 +206,26 @@ __global__ void __launch_bounds__(256) k_norm_partial(LevelView v, const double*
     if (threadIdx.x == 0) partial[(long long)p * kMaxPartial + blockIdx.x] = red[0];
 }
 
-// FP64 refinement step of the mixed-precision solve, finest level:
-//   u_out = u_in + e (interior; HAS_E) or 0 (interior; !HAS_E), ring of u_in kept,
-//   r  = f - A_p u            (FP64, the same point expression as everywhere)
-//   r32 = r rounded to FP32,  partial = per-block sum of r^2 (FP64).
-// Without WRITE only the partial sums are produced: with !HAS_E these are the
-// norms of the right-hand side b = f + (Dirichlet ring terms) that start every
-// solve (the interior of u_in is not read).  u_out must not be u_in when
-// HAS_E: workgroups read the rows next to their chunk from u_in while the
+// FP64 refinement step of the mixed-precision solve, finest level, with the
+// iterate u taken (MODE) as
+//   kZero: the ring of u_in and a zero interior (u_in's interior is not read),
+//   kAsIs: u_in,
+//   kAddE: u_in + e on the interior,
+// computes r = f - A_p u (FP64, the same point expression as everywhere) and
+// per-block partial sums of r^2 (FP64).  With WRITE it also stores r rounded
+// to FP32 and, for kZero and kAddE, u into u_out (the interior).  Without
+// WRITE and kZero the sums are the norms of the right-hand side
+// b = f + (Dirichlet ring terms).  u_out must not be u_in for kAddE:
+// workgroups read the rows next to their chunk from u_in while the
 // neighbouring chunk writes them.
 // One workgroup per (plane, chunk of rows, group of columns); one thread per
 // radial column marches along z with the three rows of its column in
 // registers and the row being evaluated shared through LDS (double buffered,
 // one barrier per row).  A group of bw threads covers bw - 2 interior columns
 // plus one neighbour column on each side.
-template <bool HAS_E, bool WRITE>
+enum RefineMode { kZero = 0, kAsIs = 1, kAddE = 2 };
+
+template <int MODE, bool WRITE>
 __global__ void __launch_bounds__(1024) k_refine(LevelView v, const double* __restrict__ lam,
                                                  const double* __restrict__ uin,
                                                  double* __restrict__ uout, const float* __restrict__ e,
@@ -240,7 +245,8 @@ __global__ void __launch_bounds__(1024) k_refine(LevelView v, const double* __re
     auto value = [&](int x) -> double {
         const long long o = base + (long long)x * v.pitch;
         const bool in = int_col && x >= 1 && x <= v.nz - 2;
-        if (HAS_E) return in ? uin[o] + (double)e[o] : uin[o];
+        if (MODE == kAddE) return in ? uin[o] + (double)e[o] : uin[o];
+        if (MODE == kAsIs) return uin[o];
         return in ? 0.0 : uin[o];
     };
     double* buf0 = srow;
@@ -259,7 +265,7 @@ __global__ void __launch_bounds__(1024) k_refine(LevelView v, const double* __re
         if (own) {
             if (WRITE) {
                 const long long o = base + (long long)x * v.pitch;
-                uout[o] = cur;
+                if (MODE != kAsIs) uout[o] = cur;
                 r32[o] = (float)r;
             }
             acc = fma(r, r, acc);
@@ -466,7 +472,7 @@ hipError_t launch_apply(const DeviceLevel& L, int nt, const double* lam, const d
 
 namespace {
 
-template <bool HAS_E, bool WRITE>
+template <int MODE, bool WRITE>
 hipError_t refine_t(const DeviceLevel& L, int nt, const double* lam, const double* uin, double* uout,
                     const float* e, const double* f, float* r32, double* partial, double* norms_out,
                     hipStream_t s) {
@@ -482,7 +488,7 @@ hipError_t refine_t(const DeviceLevel& L, int nt, const double* lam, const doubl
     nchunks = (rows + chunk - 1) / chunk;
     const int nb = nchunks * ngroups;
     const size_t lds = (size_t)3 * bw * sizeof(double);
-    k_refine<HAS_E, WRITE><<<dim3(nb, nt), bw, lds, s>>>(v, lam, uin, uout, e, f, r32, partial,
+    k_refine<MODE, WRITE><<<dim3(nb, nt), bw, lds, s>>>(v, lam, uin, uout, e, f, r32, partial,
                                                          chunk, nchunks, ngroups);
     hipError_t err = hipGetLastError();
     if (err != hipSuccess) return err;
@@ -497,14 +503,15 @@ hipError_t launch_refine(const DeviceLevel& L, int nt, const double* lam, const 
                          double* norms_out, hipStream_t s) {
     if (e) {
         if (uin == uout) return hipErrorInvalidValue;
-        return refine_t<true, true>(L, nt, lam, uin, uout, e, f, r32, partial, norms_out, s);
+        return refine_t<kAddE, true>(L, nt, lam, uin, uout, e, f, r32, partial, norms_out, s);
     }
-    return refine_t<false, true>(L, nt, lam, uin, uout, e, f, r32, partial, norms_out, s);
+    if (uout) return refine_t<kZero, true>(L, nt, lam, uin, uout, e, f, r32, partial, norms_out, s);
+    return refine_t<kAsIs, true>(L, nt, lam, uin, uout, e, f, r32, partial, norms_out, s);
 }
 
 hipError_t launch_rhs_norms(const DeviceLevel& L, int nt, const double* lam, const double* u,
                             const double* f, double* partial, double* norms_out, hipStream_t s) {
-    return refine_t<false, false>(L, nt, lam, u, nullptr, nullptr, f, nullptr, partial, norms_out, s);
+    return refine_t<kZero, false>(L, nt, lam, u, nullptr, nullptr, f, nullptr, partial, norms_out, s);
 }
 
 }  // namespace cp

@@ -151,6 +151,16 @@ hipError_t upload(cylpoisson_plan* p, T** out, const std::vector<T>& host) {
     return hipMemcpy(*out, host.data(), host.size() * sizeof(T), hipMemcpyHostToDevice);
 }
 
+}  // namespace
+
+void drop_graphs(cylpoisson_plan* p) {
+    for (auto& g : p->graphs) (void)hipGraphExecDestroy(g.second);
+    p->graphs.clear();
+    p->graph_chunks.clear();
+}
+
+namespace {
+
 void free_plan(cylpoisson_plan* p) {
     for (hipEvent_t e : p->events) (void)hipEventDestroy(e);
     p->events.clear();
@@ -158,6 +168,11 @@ void free_plan(cylpoisson_plan* p) {
     p->gevents.clear();
     for (hipStream_t st : p->gstreams) (void)hipStreamDestroy(st);
     p->gstreams.clear();
+    drop_graphs(p);
+    if (p->cap_stream) (void)hipStreamDestroy(p->cap_stream);
+    p->cap_stream = nullptr;
+    if (p->h_mask) (void)hipHostFree(p->h_mask);
+    p->h_mask = nullptr;
     for (void* ptr : p->allocations) (void)hipFree(ptr);
     p->allocations.clear();
     if (p->h_norms) (void)hipHostFree(p->h_norms);
@@ -176,8 +191,16 @@ void build_levels(cylpoisson_plan* p) {
         const auto& r = lr.back();
         const auto& z = lz.back();
         const long long interior = (long long)(r.size() - 2) * (long long)(z.size() - 2);
-        const bool cr = r.size() >= 4, cz = z.size() >= 4;
+        bool cr = r.size() >= 4, cz = z.size() >= 4;
         if (interior <= kCoarseMax || (!cr && !cz)) break;
+        // Semicoarsening: a point smoother only smooths the error along the
+        // direction of the stronger coupling (the smaller spacing), so while
+        // the cells are more than 2:1 only that direction is coarsened.
+        const double hr = p->dr * (r[1] - r[0]), hz = p->dz * (z[1] - z[0]);
+        if (cr && cz) {
+            if (hz > 2.0 * hr) cz = false;
+            else if (hr > 2.0 * hz) cr = false;
+        }
         lr.push_back(cr ? coarsen_positions(r) : r);
         lz.push_back(cz ? coarsen_positions(z) : z);
     }
@@ -568,6 +591,8 @@ cylpoisson_plan* cylpoisson_plan_create(int Nr, int Ntheta, int Nz, double r_in,
         CP_TRY(dev_alloc(p, &p->d_tmp, (size_t)nodes));
         CP_TRY(hipHostMalloc((void**)&p->h_norms, (size_t)kNormSlots * Ntheta * sizeof(double),
                              hipHostMallocDefault));
+        CP_TRY(dev_alloc(p, &p->d_mask, (size_t)Ntheta));
+        CP_TRY(hipHostMalloc((void**)&p->h_mask, (size_t)Ntheta * sizeof(int), hipHostMallocDefault));
         CP_TRY(hipDeviceSynchronize());
     }
 #undef CP_TRY
@@ -596,6 +621,8 @@ int cylpoisson_plan_set_option(cylpoisson_plan* plan, const char* key, double va
         set_error("plan and key must not be NULL");
         return CYLPOISSON_EINVAL;
     }
+    // captured graphs hold launch parameters that options change
+    cp::drop_graphs(plan);
     auto int_in = [&](int lo, int hi, int* dst) {
         if (!(value >= lo && value <= hi) || value != std::floor(value)) {
             set_error("option %s must be an integer in [%d, %d]", key, lo, hi);
@@ -617,6 +644,9 @@ int cylpoisson_plan_set_option(cylpoisson_plan* plan, const char* key, double va
     if (!std::strcmp(key, "fft")) return int_in(0, 1, &plan->opt.fft);
     if (!std::strcmp(key, "inner_cycles")) return int_in(1, 8, &plan->opt.inner_cycles);
     if (!std::strcmp(key, "groups")) return int_in(1, 8, &plan->opt.groups);
+    if (!std::strcmp(key, "warm_start")) return int_in(0, 1, &plan->opt.warm_start);
+    if (!std::strcmp(key, "masks")) return int_in(0, 1, &plan->opt.masks);
+    if (!std::strcmp(key, "graph")) return int_in(0, 1, &plan->opt.graph);
     if (!std::strcmp(key, "precision")) {
         if (value != 32.0 && value != 64.0) {
             set_error("precision must be 64 (FP64 V-cycles) or 32 (FP32 inner V-cycles)");
@@ -637,6 +667,32 @@ int cylpoisson_plan_set_option(cylpoisson_plan* plan, const char* key, double va
         plan->opt.omega = value;
         return CYLPOISSON_OK;
     }
+    set_error("unknown option '%s'", key);
+    return CYLPOISSON_EINVAL;
+}
+
+int cylpoisson_plan_get_option(const cylpoisson_plan* plan, const char* key, double* value) {
+    if (!plan || !key || !value) {
+        set_error("plan, key and value must not be NULL");
+        return CYLPOISSON_EINVAL;
+    }
+    const cp::Options& o = plan->opt;
+    const struct {
+        const char* name;
+        double v;
+    } table[] = {{"nu1", (double)o.nu1}, {"nu2", (double)o.nu2}, {"omega", o.omega},
+                 {"max_cycles", (double)o.max_cycles}, {"check_every", (double)o.check_every},
+                 {"fused", (double)o.fused}, {"chunk_rows", (double)o.chunk_rows},
+                 {"chunk_rows_coarse", (double)o.chunk_rows_coarse}, {"prefetch", (double)o.prefetch},
+                 {"timing", (double)o.timing}, {"bottom", (double)o.bottom}, {"fft", (double)o.fft},
+                 {"precision", (double)o.precision}, {"inner_cycles", (double)o.inner_cycles},
+                 {"groups", (double)o.groups}, {"warm_start", (double)o.warm_start},
+                 {"masks", (double)o.masks}, {"graph", (double)o.graph}};
+    for (const auto& t : table)
+        if (!std::strcmp(key, t.name)) {
+            *value = t.v;
+            return CYLPOISSON_OK;
+        }
     set_error("unknown option '%s'", key);
     return CYLPOISSON_EINVAL;
 }

@@ -321,10 +321,99 @@ void reset_stats(cylpoisson_plan* p) {
     p->events_used = 0;
 }
 
+// ---- captured V-cycles ----
+// With the option "graph", each V-cycle (the launches from the finest level
+// down and back) is captured once per cycle index into a HIP graph on a
+// stream of the plan, then replayed on the caller's stream; the kernel
+// arguments depend only on the plan, its options and the cycle index (norm
+// slot), so a replay equals the eager launches.  Options that change launch
+// parameters drop the cache.
+bool graphs_active(const cylpoisson_plan* p, int G) {
+    return p->opt.graph && G == 1 && !p->opt.timing && mixed_supported(p);
+}
+
+hipError_t graph_cycle(cylpoisson_plan* p, hipStream_t s, int c, bool zero_top, NormSlot* ns) {
+    const int key = 2 * c + (zero_top ? 1 : 0);
+    for (size_t i = 0; i < p->graphs.size(); ++i)
+        if (p->graphs[i].first == key) {
+            ns->partial_chunks = p->graph_chunks[i];
+            return hipGraphLaunch(p->graphs[i].second, s);
+        }
+    hipError_t e = hipSuccess;
+    if (!p->cap_stream) e = hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking);
+    if (e != hipSuccess) return e;
+    e = hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return e;
+    NormSlot cap;
+    hipError_t ev = vcycle(p, 0, p->cap_stream, zero_top, c, &cap);
+    hipGraph_t graph = nullptr;
+    e = hipStreamEndCapture(p->cap_stream, &graph);
+    if (ev != hipSuccess) e = ev;
+    hipGraphExec_t exec = nullptr;
+    if (e == hipSuccess) e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    if (graph) (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) return e;
+    p->graphs.emplace_back(key, exec);
+    p->graph_chunks.push_back(cap.partial_chunks);
+    ns->partial_chunks = cap.partial_chunks;
+    return hipGraphLaunch(exec, s);
+}
+
+// ---- per-plane convergence masks ----
+// A plane whose weighted squared residual is within its share tol^2 ||b||^2 / N
+// of the budget is frozen: its workgroups return at once and its last norm
+// stands in the sum, so the global criterion still holds once every active
+// plane meets it.  Needs the fused passes (the kernels read the mask).
+bool masks_active(const cylpoisson_plan* p) {
+    return p->opt.masks && mixed_supported(p) && fused_chunks(p, 0, p->opt.nu2) <= kSlotPartial;
+}
+
+// Freeze the planes whose norms meet their share; upload the mask on s.
+hipError_t update_masks(cylpoisson_plan* p, const double* norms, double budget, std::vector<double>& frozen,
+                        hipStream_t s) {
+    bool changed = false;
+    for (int q = 0; q < p->nt; ++q)
+        if (frozen[q] < 0.0 && plane_weight(p->nt, q) * norms[q] <= budget) {
+            frozen[q] = norms[q];
+            changed = true;
+        }
+    if (!changed) return hipSuccess;
+    int n = 0;
+    for (int q = 0; q < p->nt; ++q) {
+        p->h_mask[q] = frozen[q] < 0.0 ? 1 : 0;
+        n += frozen[q] < 0.0 ? 0 : 1;
+    }
+    p->stats.frozen_planes = n;
+    return hipMemcpyAsync(p->d_mask, p->h_mask, p->nt * sizeof(int), hipMemcpyHostToDevice, s);
+}
+
+// Norm slot (in d_norms / h_norms) that holds the right-hand-side norms of a
+// warm-started solve; slots 0 .. CYLPOISSON_MAX_HISTORY are per cycle.
+constexpr int kRhsSlot = kNormSlots - 1;
+
+// ||b||^2 and ||f - A u0||^2 (Parseval-weighted) of a warm-started solve: b is
+// the residual of the zero-interior iterate, u0 the given iterate.  Returns
+// false (status set) when either is not finite.  A zero b with a nonzero
+// initial residual (the answer is zero) measures against the initial residual.
+bool warm_norms(cylpoisson_plan* p, double* b2, double* r02) {
+    const double* hb = p->h_norms + (size_t)kRhsSlot * p->nt;
+    *b2 = weighted(p, hb);
+    *r02 = weighted(p, p->h_norms);
+    if (!std::isfinite(*b2) || !std::isfinite(*r02)) {
+        set_error("right-hand side or initial guess holds NaN or Inf");
+        p->stats.status = CYLPOISSON_ENONFINITE;
+        return false;
+    }
+    if (*b2 == 0.0) *b2 = *r02;
+    return true;
+}
+
 // V-cycles on the level-0 planes.  f is set; u holds its Dirichlet ring, and
 // its interior is zero unless `ring_only`, in which case the interior is
-// treated as zero without being read (fused finest level only).
-int run_cycles(cylpoisson_plan* p, double tol, hipStream_t s, bool ring_only) {
+// treated as zero without being read (fused finest level only), or `warm`, in
+// which case it is the initial guess.  The relative residual is always
+// measured against the right-hand side b (the residual of the zero interior).
+int run_cycles(cylpoisson_plan* p, double tol, hipStream_t s, bool ring_only, bool warm = false) {
     cylpoisson_stats& st = p->stats;
     const int nt = p->nt;
     const int maxc = p->opt.max_cycles;
@@ -333,43 +422,64 @@ int run_cycles(cylpoisson_plan* p, double tol, hipStream_t s, bool ring_only) {
     {
         Timed tm(p, kOther, s);
         DeviceLevel& L = p->dl[0];
-        if (ring_only)
+        if (ring_only) {
             CP_HIP(launch_rhs_norms(L, nt, p->d_lam, L.u, L.f, p->d_partial, p->d_norms, s));
-        else
+        } else {
             CP_HIP(residual_norms(p, 0, s));
+            if (warm)
+                CP_HIP(launch_rhs_norms(L, nt, p->d_lam, L.u, L.f, p->d_partial,
+                                        p->d_norms + (size_t)kRhsSlot * nt, s));
+        }
     }
     CP_HIP(hipMemcpyAsync(p->h_norms, p->d_norms, nt * sizeof(double), hipMemcpyDeviceToHost, s));
+    if (warm)
+        CP_HIP(hipMemcpyAsync(p->h_norms + (size_t)kRhsSlot * nt, p->d_norms + (size_t)kRhsSlot * nt,
+                              nt * sizeof(double), hipMemcpyDeviceToHost, s));
     CP_HIP(hipStreamSynchronize(s));
     st.checks = 1;
-    const double b2 = weighted(p, p->h_norms);
+    double b2 = weighted(p, p->h_norms), r02 = b2;
+    if (warm && !warm_norms(p, &b2, &r02)) return st.status;
     if (!std::isfinite(b2)) {
         set_error("right-hand side holds NaN or Inf");
         st.status = CYLPOISSON_ENONFINITE;
         return st.status;
     }
     st.initial_residual_norm = std::sqrt(b2);
-    if (b2 == 0.0) {
-        st.rel_residual = 0.0;
+    if (b2 == 0.0 || std::sqrt(r02 / b2) <= tol) {
+        st.rel_residual = b2 == 0.0 ? 0.0 : std::sqrt(r02 / b2);
         st.status = CYLPOISSON_OK;
         return st.status;
     }
 
     const int G = groups_active(p);
+    const bool graphs = graphs_active(p, G);
+    const bool masks = masks_active(p);
+    const double budget = tol * tol * b2 / nt;
+    std::vector<double> frozen(nt, -1.0);  // last norm of a frozen plane, -1 while active
+    if (masks) {
+        for (int q = 0; q < nt; ++q) p->h_mask[q] = 1;
+        CP_HIP(hipMemcpyAsync(p->d_mask, p->h_mask, nt * sizeof(int), hipMemcpyHostToDevice, s));
+        CP_HIP(update_masks(p, p->h_norms, budget, frozen, s));
+    }
     if (G > 1) {
         CP_HIP(ensure_groups(p, G));
         CP_HIP(fork_groups(p, G, s));
     }
     int next_check = std::min(2, maxc);
     int last_read = 0;
-    double prev_rel = 1.0;
+    double prev_rel = std::sqrt(r02 / b2);
     int status = CYLPOISSON_NOT_CONVERGED;
     int stagnant = 0;
-    std::vector<double> plane(nt);
+    std::vector<double> plane(nt), last(nt);
     for (int c = 1; c <= maxc; ++c) {
-        for (int g = 0; g < G; ++g) {
-            int p0, np;
-            group_range(p, G, g, &p0, &np);
-            CP_HIP(vcycle(p, 0, group_stream(p, g, s), c == 1 && ring_only, c, &slots[c], p0, np));
+        if (graphs) {
+            CP_HIP(graph_cycle(p, s, c, c == 1 && ring_only, &slots[c]));
+        } else {
+            for (int g = 0; g < G; ++g) {
+                int p0, np;
+                group_range(p, G, g, &p0, &np);
+                CP_HIP(vcycle(p, 0, group_stream(p, g, s), c == 1 && ring_only, c, &slots[c], p0, np));
+            }
         }
         if (slots[c].partial_chunks < 0) {
             CP_HIP(residual_norms(p, c, s));
@@ -402,6 +512,16 @@ int run_cycles(cylpoisson_plan* p, double tol, hipStream_t s, bool ring_only) {
                     plane[q] = sum;
                 }
                 norms = plane.data();
+            }
+            if (masks) {
+                // frozen planes wrote nothing in these cycles: their last norm stands
+                if (norms != plane.data()) {
+                    std::copy(norms, norms + nt, plane.begin());
+                    norms = plane.data();
+                }
+                for (int q = 0; q < nt; ++q)
+                    if (frozen[q] >= 0.0) plane[q] = frozen[q];
+                if (t == c) std::copy(norms, norms + nt, last.begin());
             }
             const double rel = std::sqrt(weighted(p, norms) / b2);
             if (t - 1 < CYLPOISSON_MAX_HISTORY) st.rel_residual_history[t - 1] = rel;
@@ -436,6 +556,10 @@ int run_cycles(cylpoisson_plan* p, double tol, hipStream_t s, bool ring_only) {
         }
         next_check = std::min(maxc, c + step);
         prev_rel = rel;
+        if (masks) {
+            CP_HIP(update_masks(p, last.data(), budget, frozen, s));
+            if (G > 1) CP_HIP(fork_groups(p, G, s));
+        }
     }
     st.status = status;
     if (status == CYLPOISSON_NOT_CONVERGED && st.cycles >= maxc)
@@ -451,7 +575,7 @@ int run_cycles(cylpoisson_plan* p, double tol, hipStream_t s, bool ring_only) {
 // A e = r with `inner_cycles` FP32 V-cycles from e = 0.  The FP32 residual is
 // the right-hand side of the inner cycles; the coarsest correction inside
 // them is computed in FP64.
-int run_mixed(cylpoisson_plan* p, double tol, hipStream_t s, double** result) {
+int run_mixed(cylpoisson_plan* p, double tol, hipStream_t s, double** result, bool warm = false) {
     cylpoisson_stats& st = p->stats;
     const int nt = p->nt;
     DeviceLevel& L = p->dl[0];
@@ -468,7 +592,13 @@ int run_mixed(cylpoisson_plan* p, double tol, hipStream_t s, double** result) {
     for (int it = 0;; ++it) {
         {
             Timed tm(p, kOther, s);
-            if (it == 0) {
+            if (it == 0 && warm) {
+                // right-hand side norms, then the residual of the given iterate
+                CP_HIP(launch_rhs_norms(L, nt, p->d_lam, ucur, L.f, p->d_partial,
+                                        p->d_norms + (size_t)kRhsSlot * nt, s));
+                CP_HIP(launch_refine(L, nt, p->d_lam, ucur, nullptr, nullptr, L.f, E.f, p->d_partial,
+                                     p->d_norms, s));
+            } else if (it == 0) {
                 CP_HIP(launch_refine(L, nt, p->d_lam, ucur, ucur, nullptr, L.f, E.f, p->d_partial,
                                      p->d_norms, s));
             } else {
@@ -479,11 +609,23 @@ int run_mixed(cylpoisson_plan* p, double tol, hipStream_t s, double** result) {
             }
         }
         CP_HIP(hipMemcpyAsync(p->h_norms, p->d_norms, nt * sizeof(double), hipMemcpyDeviceToHost, s));
+        if (it == 0 && warm)
+            CP_HIP(hipMemcpyAsync(p->h_norms + (size_t)kRhsSlot * nt, p->d_norms + (size_t)kRhsSlot * nt,
+                                  nt * sizeof(double), hipMemcpyDeviceToHost, s));
         CP_HIP(hipStreamSynchronize(s));
         ++st.checks;
         st.refinements = it;
-        const double r2 = weighted(p, p->h_norms);
-        if (it == 0) {
+        double r2 = weighted(p, p->h_norms);
+        if (it == 0 && warm) {
+            double r02;
+            if (!warm_norms(p, &b2, &r02)) return st.status;
+            r2 = r02;
+            st.initial_residual_norm = std::sqrt(b2);
+            if (b2 == 0.0) {
+                st.rel_residual = 0.0;
+                return st.status = CYLPOISSON_OK;
+            }
+        } else if (it == 0) {
             b2 = r2;
             if (!std::isfinite(b2)) {
                 set_error("right-hand side holds NaN or Inf");
@@ -584,10 +726,15 @@ int cylpoisson_solve(cylpoisson_plan* p, const double* rho, double* phi, double 
     // The fused finest level treats the interior as zero in the first cycle,
     // so only the Dirichlet rings of the two iterate buffers are written (the
     // mixed-precision refinement writes the zero interior itself).
-    const bool ring_only = mixed || fused_supported(p, 0);
+    const bool warm = p->opt.warm_start != 0;
+    const bool ring_only = !warm && (mixed || fused_supported(p, 0));
     {
         Timed tm(p, kOther, s);
-        if (ring_only) {
+        if (warm) {
+            // the planes of the given phi, with the Dirichlet rings rewritten
+            CP_HIP(transform(p, false, phi, L.u, nullptr, s));
+            CP_HIP(launch_init_ring(L, p->nt, p->bc, s));
+        } else if (ring_only) {
             CP_HIP(launch_init_ring(L, p->nt, p->bc, s));
         } else {
             CP_HIP(launch_init_fine_u(L, p->nt, p->bc, s));
@@ -595,7 +742,7 @@ int cylpoisson_solve(cylpoisson_plan* p, const double* rho, double* phi, double 
         }
     }
     double* result = L.u;
-    const int status = mixed ? run_mixed(p, tol, s, &result) : run_cycles(p, tol, s, ring_only);
+    const int status = mixed ? run_mixed(p, tol, s, &result, warm) : run_cycles(p, tol, s, ring_only, warm);
     if (status == CYLPOISSON_OK || status == CYLPOISSON_NOT_CONVERGED) {
         Timed tm(p, kDftInv, s);
         CP_HIP(transform(p, true, result, phi, nullptr, s));

@@ -1,5 +1,6 @@
 """The C-ABI library loads, exports every declared symbol, and validates its
 arguments before touching a device (runs without a GPU)."""
+import ctypes
 import os
 import re
 
@@ -57,6 +58,11 @@ def test_null_plan_and_status_strings():
     assert lib.cylpoisson_get_stats(None, None) == P.EINVAL
     assert lib.cylpoisson_get_info(None, None) == P.EINVAL
     assert lib.cylpoisson_plan_set_option(None, b"nu1", 2.0) == P.EINVAL
+    v = ctypes.c_double()
+    assert lib.cylpoisson_plan_get_option(None, b"nu1", ctypes.byref(v)) == P.EINVAL
+    assert lib.cylpoisson_autotune(None, None) == P.EINVAL
+    # a negative count is rejected before any HIP call
+    assert lib.cylpoisson_solve_batch(None, None, None, -1, 1e-12, None, None) == P.EINVAL
     for code in (P.OK, P.NOT_CONVERGED, P.EINVAL, P.ENOMEM, P.EHIP, P.ENONFINITE, P.EDEVICE):
         assert P.status_string(code) != "unknown status"
     assert P.status_string(42) == "unknown status"

@@ -1,0 +1,165 @@
+"""Warm starts, per-plane convergence masks, captured graphs, the launch-shape
+autotuner and batched solves of uneven problems: each against the CPU oracle
+(relative L2 <= 1e-12) or, where the arithmetic is the same, bitwise against
+the plain solve.
+"""
+import numpy as np
+import pytest
+import torch
+
+import workloads as W
+from oracle import fv, solvers
+
+from gpu_util import dev, host, rel_l2, say
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def P():
+    import paper_2609_07172_amd as P
+    P.library()
+    assert torch.cuda.is_available()
+    return P
+
+
+def manufactured(p, seed=12345):
+    phit = W.manufactured_potential(p, seed, np.longdouble)
+    rho = fv.charge_from_potential(fv.Grid.of(p, np.longdouble), phit).astype(np.float64)
+    return phit.astype(np.float64), rho
+
+
+# ------------------------------------------------------------ warm starts
+@pytest.mark.parametrize("precision", [64, 32])
+def test_warm_start_from_the_solution_needs_no_cycle(P, precision):
+    p = W.BATCHED.with_sizes(65, 16, 65)
+    rho = dev(W.blob_charge(p, seed=5))
+    plan = P.Plan.for_problem(p)
+    if precision == 32:
+        plan.set_option("precision", 32)
+    phi, st = plan.solve(rho, tol=1e-13)
+    ref = host(phi).copy()
+    plan.set_option("warm_start", 1)
+    phi2, st2 = plan.solve(rho, tol=1e-13, phi=phi)
+    assert st2["status"] == P.OK and st2["cycles"] == 0, st2
+    assert rel_l2(host(phi2), ref) <= 1e-14
+
+
+@pytest.mark.parametrize("precision", [64, 32])
+def test_warm_start_after_a_drift_is_faster_and_exact(P, precision):
+    """A 1 % change of rho, started from the previous answer: fewer cycles than
+    from zero, the same oracle answer (boundary nodes of the guess are garbage)."""
+    p = W.BATCHED
+    rho0 = W.blob_charge(p, seed=24680)
+    rho1 = rho0 + 0.01 * np.abs(rho0).max() * W.blob_charge(p, seed=97531) / np.abs(
+        W.blob_charge(p, seed=97531)).max()
+    ref = solvers.solve_separable(fv.Grid.of(p), rho1, p.bc)
+    say("warm start", precision)
+    cold = P.Plan.for_problem(p)
+    warm = P.Plan.for_problem(p, warm_start=0)
+    if precision == 32:
+        cold.set_option("precision", 32)
+        warm.set_option("precision", 32)
+    phi, _ = warm.solve(dev(rho0), tol=1e-14)
+    g = host(phi).copy()
+    g[:, 0, :] = 1e6  # the guess's boundary nodes must be ignored
+    g[:, :, -1] = -7.0
+    guess = dev(g)
+    warm.set_option("warm_start", 1)
+    phiw, sw = warm.solve(dev(rho1), tol=1e-14, phi=guess)
+    phic, sc = cold.solve(dev(rho1), tol=1e-14)
+    assert sw["status"] == P.OK and sw["cycles"] < sc["cycles"], (sw["cycles"], sc["cycles"])
+    assert rel_l2(host(phiw), ref) <= 1e-12
+    got = host(phiw)
+    np.testing.assert_array_equal(got[:, 0, :], p.phi_z0)
+    np.testing.assert_array_equal(got[:, 1:-1, -1], p.phi_r_out)
+
+
+# -------------------------------------------------------------- masks
+def test_masks_freeze_empty_planes_and_match_the_oracle(P):
+    """The manufactured potential has harmonics m <= 3 only: every other plane
+    has a right-hand side at rounding level and is frozen from the start."""
+    p = W.SMALL.with_sizes(65, 32, 65)
+    phit, rho = manufactured(p)
+    ref = solvers.solve_sparse(fv.Grid.of(p), rho, p.bc) if False else solvers.solve_separable(
+        fv.Grid.of(p), rho, p.bc)
+    plan = P.Plan.for_problem(p, masks=1)
+    phi, st = plan.solve(dev(rho), tol=1e-14)
+    assert st["status"] == P.OK, st
+    assert st["frozen_planes"] >= 32 - 7, st
+    assert rel_l2(host(phi), ref) <= 1e-12
+
+
+def test_masks_on_a_full_spectrum_match_the_oracle(P):
+    p = W.BATCHED
+    rho = W.blob_charge(p, seed=24680)
+    ref = solvers.solve_separable(fv.Grid.of(p), rho, p.bc)
+    phi, st = P.Plan.for_problem(p, masks=1).solve(dev(rho), tol=1e-14)
+    assert st["status"] == P.OK and st["rel_residual"] <= 1e-14, st
+    assert rel_l2(host(phi), ref) <= 1e-12
+
+
+# -------------------------------------------------------------- graphs
+def test_graph_replays_equal_eager_launches(P):
+    """Each cycle's graph is captured on the first solve and replayed on later
+    ones; every replay (with eager work and synchronisations in between) must
+    give the eager result bit for bit."""
+    p = W.BATCHED.with_sizes(129, 16, 97)
+    rhos = [dev(W.blob_charge(p, seed=s)) for s in (1, 2, 3)]
+    eager = P.Plan.for_problem(p)
+    graph = P.Plan.for_problem(p, graph=1)
+    for rep in range(3):
+        for r in rhos:
+            a, sa = eager.solve(r, tol=1e-14)
+            a = host(a).copy()
+            torch.cuda.synchronize()
+            b, sb = graph.solve(r, tol=1e-14)
+            np.testing.assert_array_equal(a, host(b))
+            assert sa["history"] == sb["history"]
+
+
+# ------------------------------------------------------------- autotune
+def test_autotune_picks_candidates_and_keeps_results(P):
+    p = W.BATCHED
+    rho = W.blob_charge(p, seed=24680)
+    ref = solvers.solve_separable(fv.Grid.of(p), rho, p.bc)
+    plan = P.Plan.for_problem(p, omega=1.15, max_cycles=30)
+    say("autotune", p.name)
+    plan.autotune()
+    assert plan.get_option("chunk_rows") in (0, 32, 48, 64, 96, 128)
+    assert plan.get_option("chunk_rows_coarse") in (0, 16, 24, 32, 48, 64)
+    assert plan.get_option("prefetch") in (1, 2, 3)
+    assert plan.get_option("groups") in (1, 2, 4)
+    assert plan.get_option("max_cycles") == 30 and plan.get_option("omega") == 1.15
+    phi, st = plan.solve(dev(rho), tol=1e-14)
+    assert rel_l2(host(phi), ref) <= 1e-12
+
+
+# ---------------------------------------------------------------- batch
+def test_batch_of_uneven_problems_matches_each_oracle(P):
+    probs = [W.SMALL.with_sizes(nr, nt, nz) for nr, nt, nz in
+             [(65, 32, 97), (33, 16, 33), (97, 8, 65), (40, 12, 71), (129, 4, 33), (17, 64, 129)]]
+    rhos = [W.blob_charge(q, seed=100 + i) for i, q in enumerate(probs)]
+    plans = [P.Plan.for_problem(q) for q in probs]
+    say("batch of", len(probs))
+    phis, sts = P.solve_plans(plans, [dev(r) for r in rhos], tol=1e-13)
+    for q, r, phi, st in zip(probs, rhos, phis, sts):
+        ref = solvers.solve_separable(fv.Grid.of(q), r, q.bc)
+        assert st["status"] == P.OK, st
+        assert rel_l2(host(phi), ref) <= 1e-12, q.shape
+    # the same plans alone give the same bits
+    for plan, r, phi in zip(plans, rhos, phis):
+        alone, _ = plan.solve(dev(r), tol=1e-13)
+        np.testing.assert_array_equal(host(alone), host(phi))
+
+
+def test_batch_reports_each_status(P):
+    p = W.SMALL
+    rho = dev(W.blob_charge(p, seed=1))
+    a = P.Plan.for_problem(p)
+    b = P.Plan.for_problem(p, max_cycles=1)
+    status, sts = P.solve_batch([a.handle, b.handle], [rho, rho], [torch.empty_like(rho), torch.empty_like(rho)],
+                                tol=1e-14, allow=(P.OK, P.NOT_CONVERGED))
+    assert status == P.NOT_CONVERGED and sts == [P.OK, P.NOT_CONVERGED]
+    with pytest.raises(P.CylPoissonError):
+        P.solve_batch([a.handle, a.handle], [rho, rho], [torch.empty_like(rho), torch.empty_like(rho)])
