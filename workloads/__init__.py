@@ -212,3 +212,32 @@ def random_problems(count: int = 16, seed: int = 24680) -> list[Problem]:
         nz = int(rng.integers(65, 514))
         out.append(SMALL.with_sizes(nr, nt, nz, name=f"uneven-{i}-{nr}x{nt}x{nz}"))
     return out
+
+
+def drift_fields(p: Problem, count: int = 8, seed: int = 97531) -> list[np.ndarray]:
+    """Smooth seeded charge perturbations for a time sequence of solves: each is
+    sin(a pi (r - r_in)/W) * sin(b pi z/L) * cos(m theta + psi) with a, b in
+    1..4, m in 0..8 and psi in [0, 2 pi), scaled to max |.| = 1, zero on the
+    boundary nodes.  Separable, so cheap at any size."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    th, z, r = node_coordinates(p)
+    W_, L_ = p.r_out - p.r_in, p.length
+    out = []
+    for _ in range(count):
+        a, b = int(rng.integers(1, 5)), int(rng.integers(1, 5))
+        m, psi = int(rng.integers(0, 9)), float(rng.uniform(0.0, 2.0 * math.pi))
+        fr = np.sin(a * math.pi * (r - p.r_in) / W_)
+        fz = np.sin(b * math.pi * z / L_)
+        ft = np.cos(m * th + psi)
+        f = ft[:, None, None] * fz[None, :, None] * fr[None, None, :]
+        f /= np.abs(f).max()
+        f[:, :, 0] = f[:, :, -1] = 0.0
+        f[:, 0, :] = f[:, -1, :] = 0.0
+        out.append(np.ascontiguousarray(f))
+    return out
+
+
+def drift_signs(steps: int = 200, seed: int = 97531) -> np.ndarray:
+    """Seeded +-1 signs of the per-step perturbations of a time sequence."""
+    rng = np.random.Generator(np.random.PCG64(seed + 1))
+    return rng.choice(np.array([-1.0, 1.0]), size=steps)
