@@ -14,6 +14,10 @@ What it computes (plain FP64, or extended precision where stated):
 * ``spectral``  -- the azimuthal DFT of Eq. (azimuthal_dft) written out as sums,
                    split into real "planes", its inverse, and the exact discrete
                    eigenvalue of Eq. (discrete_azimuthal_eigenvalue).
+* ``nn``        -- the learned preconditioner's three-layer 3x3 convolution
+                   network: forward, loss, back-propagated gradients and an
+                   Adam step in FP64, optionally with the GPU's BF16 operand
+                   rounding (the brief fixes the network; the paper has none).
 * ``solvers``   -- the plain definition: a direct solve of the undecomposed 3-D
                    system (dense for tiny grids, sparse LU otherwise), the 2-D
                    shifted mode system of Eq. (shifted_operator_family), and an
@@ -24,5 +28,5 @@ Every function names the passage it follows.  Each is pinned by the
 ``-m "not gpu"`` tests against values the paper prints, closed forms,
 brute force or library routines; no function here is "parity unpinned".
 """
-from . import fv, spectral, solvers  # noqa: F401
+from . import fv, nn, spectral, solvers  # noqa: F401
 from .fv import EPS0  # noqa: F401
