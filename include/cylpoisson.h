@@ -57,6 +57,7 @@ extern "C" {
 #define CYLPOISSON_KERNEL_CLASSES 6
 
 typedef struct cylpoisson_plan cylpoisson_plan; /* opaque */
+typedef struct cylpoisson_nn cylpoisson_nn;     /* opaque: the learned preconditioner's network */
 
 /* Dirichlet values (volts) on the four faces, invariant in theta, so that only
  * the m = 0 mode carries a boundary term (Eq. mode_rhs).  The axial faces win
@@ -94,6 +95,14 @@ typedef struct {
     int refinements;
     /* Planes frozen by the option "masks" when the solve ended (0 otherwise). */
     int frozen_planes;
+    /* Learned solve (option "krylov" = 1): FGMRES steps taken, the relative
+     * residual after the judging V-cycle (its contraction from zero), the
+     * network's mean contraction per FGMRES step over the judged restart, and
+     * 1 if V-cycles finished the solve because the network contracted less. */
+    int krylov_iterations;
+    int learned_fallback;
+    double vcycle_rate;
+    double learned_rate;
 } cylpoisson_stats;
 
 typedef struct {
@@ -153,6 +162,16 @@ void cylpoisson_plan_destroy(cylpoisson_plan* plan);
  *                    residual is within tol^2 ||b||^2 / Ntheta stops being cycled
  *                    (its last iterate is kept), FP64 path with fused passes
  *                    (default 0)
+ *   "krylov"         1 = learned solve: flexible GMRES with the attached network
+ *                    (cylpoisson_plan_set_net) as right preconditioner, judged
+ *                    against one plain V-cycle and replaced by V-cycles when it
+ *                    contracts less per step (FP64 only; default 0)
+ *   "krylov_precond" 1 = the network preconditions FGMRES; 0 = no preconditioner;
+ *                    2 = four red-black SOR sweeps, the map the network is trained
+ *                    to imitate (0 and 2 for comparison; default 1)
+ *   "krylov_restart" FGMRES restart length, also the judged steps (1 .. 16; default 8)
+ *   "krylov_max"     FGMRES steps in all (default 200)
+ *   "fallback"       1 = V-cycles take over from a worse network (default 1)
  *   "graph"          1 = each V-cycle is captured once into a HIP graph and replayed
  *                    (single plane group, "timing" 0; default 0).  Setting any
  *                    option releases the captured graphs
@@ -234,6 +253,55 @@ int cylpoisson_dft_inverse(cylpoisson_plan* plan, const double* planes, double* 
  * Same convergence rule and return values as cylpoisson_solve. */
 int cylpoisson_solve_planes(cylpoisson_plan* plan, const double* b, double* u, double tol,
                             void* stream);
+
+/* ---- Learned preconditioner (a network of the brief, not of the paper) ----
+ * A three-layer 3x3 convolution network, 4 -> 16 -> 16 -> 2 channels, ReLU
+ * after the first two layers, no biases, BF16 operands with FP32 accumulation
+ * on the matrix cores, FP32 master weights trained with Adam.  Inputs per
+ * interior node of a cos/sin plane pair: the pair's values / the pair's RMS s,
+ * (r - r_in)/(r_out - r_in), and lambda mu / D (D the node's diagonal);
+ * outputs y give the pair's correction s y / D.  Images for the network are
+ * FP32 device arrays [B][H][W][C] (C fastest), zero outside the image.
+ * Weights: layers in order, each [9][Cin][Cout], tap = (dy + 1) * 3 + (dx + 1),
+ * y[i][j][o] = sum_{tap, c} x[i + dy][j + dx][c] w[tap][c][o]. */
+
+/* New network on the current device, He-normal weights from a SplitMix64
+ * stream seeded with `seed`.  NULL on failure. */
+cylpoisson_nn* cylpoisson_nn_create(unsigned long long seed);
+void cylpoisson_nn_destroy(cylpoisson_nn* nn); /* NULL-safe */
+/* Number of weights (all layers). */
+int cylpoisson_nn_weight_count(void);
+/* Copy the FP32 master weights out / in (host buffers of count floats). */
+int cylpoisson_nn_get_weights(const cylpoisson_nn* nn, float* out, int count);
+int cylpoisson_nn_set_weights(cylpoisson_nn* nn, const float* in, int count);
+/* Gradients of the last cylpoisson_nn_loss_grad (host buffer of count floats). */
+int cylpoisson_nn_get_grads(const cylpoisson_nn* nn, float* out, int count);
+/* y (B x H x W x 2) = network(x (B x H x W x 4)), device arrays. */
+int cylpoisson_nn_forward(cylpoisson_nn* nn, const float* x, float* y, int B, int H, int W, void* stream);
+/* Forward, loss = sum over inner pixels (3 from every edge) and both channels of
+ * (y - t)^2 / (2 n), and back-propagated weight gradients.  *loss (optional,
+ * host) is written after the stream synchronises. */
+int cylpoisson_nn_loss_grad(cylpoisson_nn* nn, const float* x, const float* t, int B, int H, int W,
+                            double* loss, void* stream);
+/* One Adam step (beta 0.9, 0.999, eps 1e-8) with learning rate lr. */
+int cylpoisson_nn_adam_step(cylpoisson_nn* nn, float lr, void* stream);
+/* Training data from the plain solver: runs `cycles` V-cycles on rho from
+ * zero; for the residual r of each iterate it takes the correction c that four
+ * red-black SOR sweeps of the solver's smoother compute on A c = r from c = 0,
+ * and stores `patches_per_cycle` random 32 x 32 patches (seeded positions over
+ * the mode pairs) of r (input) and c (target), appended to the network's
+ * store.  The network thus learns a local map the size of its receptive field;
+ * the Krylov iteration around it supplies the global coupling.  rho is a
+ * device node array of the plan's grid. */
+int cylpoisson_nn_collect(cylpoisson_plan* plan, cylpoisson_nn* nn, const double* rho, int cycles,
+                          int patches_per_cycle, unsigned long long seed, void* stream);
+long long cylpoisson_nn_patch_count(const cylpoisson_nn* nn);
+/* Adam over the stored patches in batches, `epochs` passes; *loss_out = the
+ * last epoch's mean loss. */
+int cylpoisson_nn_train(cylpoisson_nn* nn, int epochs, int batch, float lr, double* loss_out, void* stream);
+/* Attach (or with NULL detach) the network used by the option "krylov"; the
+ * plan does not own it. */
+int cylpoisson_plan_set_net(cylpoisson_plan* plan, cylpoisson_nn* nn);
 
 /* Thread-local message describing the last failure in this thread ("" if none). */
 const char* cylpoisson_last_error(void);

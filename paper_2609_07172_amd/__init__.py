@@ -21,7 +21,7 @@ __all__ = [
     "CylPoissonError", "library", "library_path", "plan_create", "plan_destroy",
     "plan_set_option", "solve", "solve_planes", "apply", "dft_forward", "dft_inverse",
     "get_stats", "get_info", "last_error", "status_string", "Plan", "EXPORTED_SYMBOLS",
-    "plan_get_option", "autotune", "solve_batch", "solve_plans",
+    "plan_get_option", "autotune", "solve_batch", "solve_plans", "Net",
 ]
 
 OK, NOT_CONVERGED = 0, 1
@@ -35,7 +35,10 @@ EXPORTED_SYMBOLS = (
     "cylpoisson_solve", "cylpoisson_get_stats", "cylpoisson_get_info", "cylpoisson_apply",
     "cylpoisson_dft_forward", "cylpoisson_dft_inverse", "cylpoisson_solve_planes",
     "cylpoisson_last_error", "cylpoisson_status_string", "cylpoisson_plan_get_option",
-    "cylpoisson_autotune", "cylpoisson_solve_batch",
+    "cylpoisson_autotune", "cylpoisson_solve_batch", "cylpoisson_nn_create", "cylpoisson_nn_destroy",
+    "cylpoisson_nn_weight_count", "cylpoisson_nn_get_weights", "cylpoisson_nn_set_weights",
+    "cylpoisson_nn_get_grads", "cylpoisson_nn_forward", "cylpoisson_nn_loss_grad", "cylpoisson_nn_adam_step",
+    "cylpoisson_nn_collect", "cylpoisson_nn_patch_count", "cylpoisson_nn_train", "cylpoisson_plan_set_net",
 )
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -54,7 +57,9 @@ class Stats(ctypes.Structure):
                 ("rel_residual_history", ctypes.c_double * MAX_HISTORY),
                 ("kernel_launches", ctypes.c_int * len(KERNEL_CLASSES)),
                 ("kernel_ms", ctypes.c_double * len(KERNEL_CLASSES)),
-                ("refinements", ctypes.c_int), ("frozen_planes", ctypes.c_int)]
+                ("refinements", ctypes.c_int), ("frozen_planes", ctypes.c_int),
+                ("krylov_iterations", ctypes.c_int), ("learned_fallback", ctypes.c_int),
+                ("vcycle_rate", ctypes.c_double), ("learned_rate", ctypes.c_double)]
 
     def as_dict(self) -> dict:
         hist = [self.rel_residual_history[i] for i in range(min(self.n_history, MAX_HISTORY))]
@@ -64,7 +69,9 @@ class Stats(ctypes.Structure):
                 "history": [None if math.isnan(h) else h for h in hist],
                 "kernel_launches": dict(zip(KERNEL_CLASSES, list(self.kernel_launches))),
                 "kernel_ms": dict(zip(KERNEL_CLASSES, list(self.kernel_ms))),
-                "refinements": self.refinements, "frozen_planes": self.frozen_planes}
+                "refinements": self.refinements, "frozen_planes": self.frozen_planes,
+                "krylov_iterations": self.krylov_iterations, "learned_fallback": self.learned_fallback,
+                "vcycle_rate": self.vcycle_rate, "learned_rate": self.learned_rate}
 
 
 class Info(ctypes.Structure):
@@ -119,6 +126,30 @@ def library() -> ctypes.CDLL:
     L.cylpoisson_solve_batch.restype = i
     L.cylpoisson_solve_batch.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(vp), i,
                                          d, vp, ctypes.POINTER(i)]
+    ull, fp = ctypes.c_ulonglong, ctypes.POINTER(ctypes.c_float)
+    L.cylpoisson_nn_create.restype = vp
+    L.cylpoisson_nn_create.argtypes = [ull]
+    L.cylpoisson_nn_destroy.restype = None
+    L.cylpoisson_nn_destroy.argtypes = [vp]
+    L.cylpoisson_nn_weight_count.restype = i
+    L.cylpoisson_nn_weight_count.argtypes = []
+    for name in ("cylpoisson_nn_get_weights", "cylpoisson_nn_set_weights", "cylpoisson_nn_get_grads"):
+        getattr(L, name).restype = i
+        getattr(L, name).argtypes = [vp, fp, i]
+    L.cylpoisson_nn_forward.restype = i
+    L.cylpoisson_nn_forward.argtypes = [vp, vp, vp, i, i, i, vp]
+    L.cylpoisson_nn_loss_grad.restype = i
+    L.cylpoisson_nn_loss_grad.argtypes = [vp, vp, vp, i, i, i, ctypes.POINTER(d), vp]
+    L.cylpoisson_nn_adam_step.restype = i
+    L.cylpoisson_nn_adam_step.argtypes = [vp, ctypes.c_float, vp]
+    L.cylpoisson_nn_collect.restype = i
+    L.cylpoisson_nn_collect.argtypes = [vp, vp, vp, i, i, ull, vp]
+    L.cylpoisson_nn_patch_count.restype = ctypes.c_longlong
+    L.cylpoisson_nn_patch_count.argtypes = [vp]
+    L.cylpoisson_nn_train.restype = i
+    L.cylpoisson_nn_train.argtypes = [vp, i, i, ctypes.c_float, ctypes.POINTER(d), vp]
+    L.cylpoisson_plan_set_net.restype = i
+    L.cylpoisson_plan_set_net.argtypes = [vp, vp]
     L.cylpoisson_get_stats.restype = i
     L.cylpoisson_get_stats.argtypes = [vp, ctypes.POINTER(Stats)]
     L.cylpoisson_get_info.restype = i
@@ -298,4 +329,89 @@ def solve_plans(plans, rhos, tol=1e-12, stream=None, allow=(OK,)):
     phis = [torch.empty_like(r) for r in rhos]
     status, sts = solve_batch([p.handle for p in plans], rhos, phis, tol, stream, allow)
     return phis, [p.stats() for p in plans]
+
+
+class Net:
+    """The learned preconditioner's network (``cylpoisson_nn_*``)."""
+
+    def __init__(self, seed: int = 2024):
+        self.handle = library().cylpoisson_nn_create(int(seed))
+        if not self.handle:
+            raise CylPoissonError(ENOMEM, last_error())
+
+    @staticmethod
+    def weight_count() -> int:
+        return library().cylpoisson_nn_weight_count()
+
+    def get_weights(self):
+        import numpy as np
+        out = np.empty(self.weight_count(), dtype=np.float32)
+        _check(library().cylpoisson_nn_get_weights(self.handle, out.ctypes.data_as(ctypes.POINTER(ctypes.c_float)),
+                                                   out.size))
+        return out
+
+    def set_weights(self, w) -> None:
+        import numpy as np
+        a = np.ascontiguousarray(w, dtype=np.float32)
+        _check(library().cylpoisson_nn_set_weights(self.handle, a.ctypes.data_as(ctypes.POINTER(ctypes.c_float)),
+                                                   a.size))
+
+    def get_grads(self):
+        import numpy as np
+        out = np.empty(self.weight_count(), dtype=np.float32)
+        _check(library().cylpoisson_nn_get_grads(self.handle, out.ctypes.data_as(ctypes.POINTER(ctypes.c_float)),
+                                                 out.size))
+        return out
+
+    @staticmethod
+    def _f32(t):
+        if not isinstance(t, torch.Tensor) or t.dtype != torch.float32 or not t.is_contiguous():
+            raise TypeError("network images must be contiguous torch.float32 tensors")
+        return t.data_ptr()
+
+    def forward(self, x, stream=None):
+        B, H, W, C = x.shape
+        if C != 4:
+            raise ValueError("the network takes 4 input channels")
+        y = torch.empty((B, H, W, 2), dtype=torch.float32, device=x.device)
+        _check(library().cylpoisson_nn_forward(self.handle, self._f32(x), self._f32(y), B, H, W, _stream(stream)))
+        return y
+
+    def loss_grad(self, x, t, stream=None) -> float:
+        B, H, W, _ = x.shape
+        loss = ctypes.c_double()
+        _check(library().cylpoisson_nn_loss_grad(self.handle, self._f32(x), self._f32(t), B, H, W,
+                                                 ctypes.byref(loss), _stream(stream)))
+        return loss.value
+
+    def adam_step(self, lr: float, stream=None) -> None:
+        _check(library().cylpoisson_nn_adam_step(self.handle, float(lr), _stream(stream)))
+
+    def collect(self, plan, rho, cycles=6, patches_per_cycle=256, seed=1, stream=None) -> None:
+        _check(library().cylpoisson_nn_collect(plan.handle, self.handle, _ptr(rho), int(cycles),
+                                               int(patches_per_cycle), int(seed), _stream(stream)))
+
+    def patch_count(self) -> int:
+        return library().cylpoisson_nn_patch_count(self.handle)
+
+    def train(self, epochs=4, batch=128, lr=1e-3, stream=None) -> float:
+        loss = ctypes.c_double()
+        _check(library().cylpoisson_nn_train(self.handle, int(epochs), int(batch), float(lr), ctypes.byref(loss),
+                                             _stream(stream)))
+        return loss.value
+
+    def close(self):
+        if getattr(self, "handle", None):
+            library().cylpoisson_nn_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def plan_set_net(plan, net) -> None:
+    _check(library().cylpoisson_plan_set_net(plan.handle, net.handle if net is not None else None))
 

@@ -112,6 +112,11 @@ struct Options {
     int warm_start = 0;  // 1: cylpoisson_solve starts from the phi it is given
     int masks = 0;       // 1: planes that met their share of the tolerance stop cycling
     int graph = 0;       // 1: replay captured HIP graphs of the V-cycles
+    int krylov = 0;      // 1: FGMRES with the learned preconditioner (judged, with fallback)
+    int krylov_precond = 1;  // 1: the network preconditions FGMRES; 0: no preconditioner
+    int krylov_restart = 8;  // FGMRES restart length (also the judged iterations)
+    int krylov_max = 200;    // FGMRES iterations in all
+    int fallback = 1;        // 1: V-cycles take over when the network contracts less than a V-cycle
     int inner_cycles = 2;  // FP32 V-cycles per FP64 refinement step
 };
 
@@ -170,13 +175,26 @@ struct cylpoisson_plan {
     hipStream_t cap_stream = nullptr;
     std::vector<std::pair<int, hipGraphExec_t>> graphs;
     std::vector<int> graph_chunks;  // norm partial chunks recorded per captured cycle
+
+    // learned preconditioner: the network (not owned), FGMRES vectors V_0..V_m
+    // and Z_0..Z_m-1 (node arrays, zero rings), dot partials, network scratch
+    cylpoisson_nn* net = nullptr;
+    std::vector<double*> kv;
+    double* d_kdots = nullptr;
+    double* h_kdots = nullptr;
+    float* net_x = nullptr;
+    float* net_y = nullptr;
+    float* net_sc = nullptr;
+    long long net_pixels = 0;
 };
 
 namespace cp {
 
 constexpr int kMaxPartial = 256;
 constexpr int kSlotPartial = 64;  // per-slot partial sums kept for the host (chunks per plane)
-constexpr int kNormSlots = CYLPOISSON_MAX_HISTORY + 2;
+// norm slots: 0 .. MAX_HISTORY per cycle, then a scratch slot and the
+// right-hand-side slot of warm starts
+constexpr int kNormSlots = CYLPOISSON_MAX_HISTORY + 3;
 
 // Error reporting (thread-local message).
 void set_error(const char* fmt, ...);
@@ -243,6 +261,20 @@ int fused_chunks(const cylpoisson_plan* p, int l, int nu);
 // FP32 passes on the dl32 buffers (mixed precision), no residual norms.
 hipError_t fused_down32(cylpoisson_plan* p, int l, bool zero_u, hipStream_t s, int p0 = 0,
                         int np = -1);
+// ---- learned preconditioner (learned.hip) ----
+int net_pairs(int nt);
+hipError_t krylov_reserve(cylpoisson_plan* p, int m);
+hipError_t plane_apply(cylpoisson_plan* p, const double* z, double* w, hipStream_t s);
+// out[j * nt + plane] = <a_j, w> over the plane's interior; synchronises s
+hipError_t plane_dots(cylpoisson_plan* p, const double* const* a, int na, const double* w, double* out,
+                      hipStream_t s);
+// dst = alpha dst + sum_j c_j a_j (interior)
+hipError_t plane_lincomb(cylpoisson_plan* p, double* dst, double alpha, const double* const* a,
+                         const double* c, int na, hipStream_t s);
+hipError_t learned_precond(cylpoisson_plan* p, const double* v, double* z, hipStream_t s);
+// one plain V-cycle on level 0 from the current iterate (solve.hip)
+hipError_t vcycle_step(cylpoisson_plan* p, hipStream_t s);
+
 // Release the captured V-cycle graphs (plan.hip).
 void drop_graphs(cylpoisson_plan* p);
 // Every level above the bottom kernel has fused passes (plan.hip).

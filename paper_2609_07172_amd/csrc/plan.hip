@@ -173,6 +173,16 @@ void free_plan(cylpoisson_plan* p) {
     p->cap_stream = nullptr;
     if (p->h_mask) (void)hipHostFree(p->h_mask);
     p->h_mask = nullptr;
+    for (double* v : p->kv) (void)hipFree(v);
+    p->kv.clear();
+    if (p->d_kdots) (void)hipFree(p->d_kdots);
+    p->d_kdots = nullptr;
+    if (p->h_kdots) (void)hipHostFree(p->h_kdots);
+    p->h_kdots = nullptr;
+    for (float* q : {p->net_x, p->net_y, p->net_sc})
+        if (q) (void)hipFree(q);
+    p->net_x = p->net_y = p->net_sc = nullptr;
+    p->net_pixels = 0;
     for (void* ptr : p->allocations) (void)hipFree(ptr);
     p->allocations.clear();
     if (p->h_norms) (void)hipHostFree(p->h_norms);
@@ -647,6 +657,11 @@ int cylpoisson_plan_set_option(cylpoisson_plan* plan, const char* key, double va
     if (!std::strcmp(key, "warm_start")) return int_in(0, 1, &plan->opt.warm_start);
     if (!std::strcmp(key, "masks")) return int_in(0, 1, &plan->opt.masks);
     if (!std::strcmp(key, "graph")) return int_in(0, 1, &plan->opt.graph);
+    if (!std::strcmp(key, "krylov")) return int_in(0, 1, &plan->opt.krylov);
+    if (!std::strcmp(key, "krylov_precond")) return int_in(0, 2, &plan->opt.krylov_precond);
+    if (!std::strcmp(key, "krylov_restart")) return int_in(1, 16, &plan->opt.krylov_restart);
+    if (!std::strcmp(key, "krylov_max")) return int_in(1, 100000, &plan->opt.krylov_max);
+    if (!std::strcmp(key, "fallback")) return int_in(0, 1, &plan->opt.fallback);
     if (!std::strcmp(key, "precision")) {
         if (value != 32.0 && value != 64.0) {
             set_error("precision must be 64 (FP64 V-cycles) or 32 (FP32 inner V-cycles)");
@@ -687,7 +702,9 @@ int cylpoisson_plan_get_option(const cylpoisson_plan* plan, const char* key, dou
                  {"timing", (double)o.timing}, {"bottom", (double)o.bottom}, {"fft", (double)o.fft},
                  {"precision", (double)o.precision}, {"inner_cycles", (double)o.inner_cycles},
                  {"groups", (double)o.groups}, {"warm_start", (double)o.warm_start},
-                 {"masks", (double)o.masks}, {"graph", (double)o.graph}};
+                 {"masks", (double)o.masks}, {"graph", (double)o.graph}, {"krylov", (double)o.krylov},
+                 {"krylov_precond", (double)o.krylov_precond}, {"krylov_restart", (double)o.krylov_restart},
+                 {"krylov_max", (double)o.krylov_max}, {"fallback", (double)o.fallback}};
     for (const auto& t : table)
         if (!std::strcmp(key, t.name)) {
             *value = t.v;

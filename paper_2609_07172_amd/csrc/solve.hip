@@ -680,7 +680,166 @@ int run_mixed(cylpoisson_plan* p, double tol, hipStream_t s, double** result, bo
     return st.status = status;
 }
 
+// ---- learned preconditioner: FGMRES judged against the plain V-cycle ----
+// Parseval-weighted sum over planes of per-plane values.
+double wsum(const cylpoisson_plan* p, const double* per_plane) { return weighted(p, per_plane); }
+
+// One restart of flexible GMRES on the correction d of A d = f - A u (right
+// preconditioning with the variable map z = M(v)), at most `maxit` steps or
+// until the residual estimate reaches tol2 = tol^2 ||b||^2; u += sum y_j z_j.
+// Classical Gram-Schmidt with one reorthogonalisation; Givens rotations and
+// the small triangular solve on the host.  Returns the number of steps and
+// the residual estimate (absolute, weighted 2-norm).
+int fgmres_restart(cylpoisson_plan* p, double tol2, int maxit, double* res, hipStream_t s, int* err) {
+    const int nt = p->nt;
+    const int m = std::min(maxit, p->opt.krylov_restart);
+    DeviceLevel& L = p->dl[0];
+    double* const* V = p->kv.data();
+    double* const* Z = p->kv.data() + p->opt.krylov_restart + 1;
+    std::vector<double> dots((size_t)(m + 1) * nt), h((size_t)(m + 1) * m, 0.0), cs(m), sn(m), g(m + 1, 0.0);
+    *err = 0;
+    auto fail = [&](hipError_t e) {
+        set_error("FGMRES: %s", hipGetErrorString(e));
+        (void)hipGetLastError();
+        *err = CYLPOISSON_EHIP;
+        return 0;
+    };
+    hipError_t e = launch_residual(L, nt, p->d_lam, L.u, L.f, L.r, s);
+    const double* rr[1] = {L.r};
+    if (e == hipSuccess) e = plane_dots(p, rr, 1, L.r, dots.data(), s);
+    if (e != hipSuccess) return fail(e);
+    const double beta = std::sqrt(wsum(p, dots.data()));
+    *res = beta;
+    if (beta == 0.0 || beta * beta <= tol2) return 0;
+    {
+        const double c = 1.0 / beta;
+        e = plane_lincomb(p, V[0], 0.0, rr, &c, 1, s);
+        if (e != hipSuccess) return fail(e);
+    }
+    g[0] = beta;
+    int k = 0;
+    for (int j = 0; j < m; ++j) {
+        e = learned_precond(p, V[j], Z[j], s);
+        if (e == hipSuccess) e = plane_apply(p, Z[j], V[j + 1], s);
+        if (e != hipSuccess) return fail(e);
+        std::vector<double> hj(j + 2, 0.0);
+        for (int pass = 0; pass < 2; ++pass) {  // CGS2
+            e = plane_dots(p, V, j + 1, V[j + 1], dots.data(), s);
+            if (e != hipSuccess) return fail(e);
+            std::vector<double> c(j + 1);
+            for (int i = 0; i <= j; ++i) {
+                c[i] = wsum(p, dots.data() + (size_t)i * nt);
+                hj[i] += c[i];
+                c[i] = -c[i];
+            }
+            e = plane_lincomb(p, V[j + 1], 1.0, V, c.data(), j + 1, s);
+            if (e != hipSuccess) return fail(e);
+        }
+        const double* w1[1] = {V[j + 1]};
+        e = plane_dots(p, w1, 1, V[j + 1], dots.data(), s);
+        if (e != hipSuccess) return fail(e);
+        hj[j + 1] = std::sqrt(wsum(p, dots.data()));
+        if (hj[j + 1] > 0.0) {
+            e = plane_lincomb(p, V[j + 1], 1.0 / hj[j + 1], nullptr, nullptr, 0, s);
+            if (e != hipSuccess) return fail(e);
+        }
+        for (int i = 0; i < j; ++i) {  // earlier rotations
+            const double a = hj[i], b = hj[i + 1];
+            hj[i] = cs[i] * a + sn[i] * b;
+            hj[i + 1] = -sn[i] * a + cs[i] * b;
+        }
+        const double rnorm = std::hypot(hj[j], hj[j + 1]);
+        cs[j] = rnorm > 0.0 ? hj[j] / rnorm : 1.0;
+        sn[j] = rnorm > 0.0 ? hj[j + 1] / rnorm : 0.0;
+        hj[j] = rnorm;
+        hj[j + 1] = 0.0;
+        g[j + 1] = -sn[j] * g[j];
+        g[j] = cs[j] * g[j];
+        for (int i = 0; i <= j; ++i) h[(size_t)i * m + j] = hj[i];
+        k = j + 1;
+        *res = std::fabs(g[j + 1]);
+        if ((*res) * (*res) <= tol2 || rnorm == 0.0) break;
+    }
+    std::vector<double> y(k);
+    for (int i = k - 1; i >= 0; --i) {
+        double t = g[i];
+        for (int q = i + 1; q < k; ++q) t -= h[(size_t)i * m + q] * y[q];
+        y[i] = h[(size_t)i * m + i] != 0.0 ? t / h[(size_t)i * m + i] : 0.0;
+    }
+    e = plane_lincomb(p, L.u, 1.0, Z, y.data(), k, s);
+    if (e != hipSuccess) return fail(e);
+    return k;
+}
+
+// The learned solve: one plain V-cycle from zero measures the V-cycle's
+// contraction; one FGMRES restart with the network measures the network's
+// contraction per step; the faster one finishes the solve (V-cycles from the
+// current iterate when the network is worse and "fallback" is set).  u holds
+// the Dirichlet rings and a zero interior on entry.
+int run_learned(cylpoisson_plan* p, double tol, hipStream_t s) {
+    cylpoisson_stats& st = p->stats;
+    const int nt = p->nt;
+    DeviceLevel& L = p->dl[0];
+    CP_HIP(krylov_reserve(p, p->opt.krylov_restart));
+    CP_HIP(launch_rhs_norms(L, nt, p->d_lam, L.u, L.f, p->d_partial, p->d_norms, s));
+    CP_HIP(hipMemcpyAsync(p->h_norms, p->d_norms, nt * sizeof(double), hipMemcpyDeviceToHost, s));
+    CP_HIP(hipStreamSynchronize(s));
+    const double b2 = weighted(p, p->h_norms);
+    if (!std::isfinite(b2)) {
+        set_error("right-hand side holds NaN or Inf");
+        return st.status = CYLPOISSON_ENONFINITE;
+    }
+    st.initial_residual_norm = std::sqrt(b2);
+    if (b2 == 0.0) return st.status = CYLPOISSON_OK;
+    const double tol2 = tol * tol * b2;
+    // the plain V-cycle's contraction from the zero iterate
+    CP_HIP(vcycle_step(p, s));
+    CP_HIP(residual_norms(p, 1, s));
+    CP_HIP(hipMemcpyAsync(p->h_norms + nt, p->d_norms + nt, nt * sizeof(double), hipMemcpyDeviceToHost, s));
+    CP_HIP(hipStreamSynchronize(s));
+    const double rel1 = std::sqrt(weighted(p, p->h_norms + nt) / b2);
+    st.vcycle_rate = rel1;
+    st.cycles = 1;
+    st.rel_residual = rel1;
+    if (rel1 <= tol) return st.status = CYLPOISSON_OK;
+    // the network's contraction per FGMRES step over one restart
+    int err = 0;
+    double res = 0.0;
+    int k = fgmres_restart(p, tol2, p->opt.krylov_max, &res, s, &err);
+    if (err) return st.status = err;
+    st.krylov_iterations = k;
+    double rel = res / std::sqrt(b2);
+    st.learned_rate = k > 0 ? std::pow(rel / rel1, 1.0 / k) : 1.0;
+    st.rel_residual = rel;
+    if (rel <= tol) return st.status = CYLPOISSON_OK;
+    if (p->opt.fallback && st.learned_rate >= st.vcycle_rate) {
+        st.learned_fallback = 1;
+        const int judged = st.krylov_iterations;
+        const double vr = st.vcycle_rate, lr = st.learned_rate;
+        const int status = run_cycles(p, tol, s, false, true);
+        st.cycles += 1;  // the judging cycle
+        st.krylov_iterations = judged;
+        st.vcycle_rate = vr;
+        st.learned_rate = lr;
+        st.learned_fallback = 1;
+        return st.status = status;
+    }
+    while (st.krylov_iterations < p->opt.krylov_max) {
+        k = fgmres_restart(p, tol2, p->opt.krylov_max - st.krylov_iterations, &res, s, &err);
+        if (err) return st.status = err;
+        st.krylov_iterations += k;
+        st.rel_residual = res / std::sqrt(b2);
+        if (st.rel_residual <= tol) return st.status = CYLPOISSON_OK;
+        if (k == 0) break;
+    }
+    set_error("FGMRES: tolerance %.3e not reached in %d steps (relative residual %.3e)", tol,
+              st.krylov_iterations, st.rel_residual);
+    return st.status = CYLPOISSON_NOT_CONVERGED;
+}
+
 }  // namespace
+
+hipError_t vcycle_step(cylpoisson_plan* p, hipStream_t s) { return vcycle(p, 0, s, false, -1, nullptr); }
 
 }  // namespace cp
 
@@ -709,6 +868,11 @@ int cylpoisson_solve(cylpoisson_plan* p, const double* rho, double* phi, double 
         return p->stats.status = CYLPOISSON_EINVAL;
     }
     const bool mixed = p->opt.precision == 32;
+    const bool learned = p->opt.krylov != 0;
+    if (learned && mixed) {
+        set_error("the learned (FGMRES) solve runs in FP64: set precision 64 or krylov 0");
+        return p->stats.status = CYLPOISSON_EINVAL;
+    }
     if (mixed && (p->dl32.empty() || !mixed_supported(p))) {
         set_error("mixed precision needs fused passes on every level above the LDS bottom kernel "
                   "(check the options fused, bottom, nu1, nu2 and chunk sizes)");
@@ -726,8 +890,8 @@ int cylpoisson_solve(cylpoisson_plan* p, const double* rho, double* phi, double 
     // The fused finest level treats the interior as zero in the first cycle,
     // so only the Dirichlet rings of the two iterate buffers are written (the
     // mixed-precision refinement writes the zero interior itself).
-    const bool warm = p->opt.warm_start != 0;
-    const bool ring_only = !warm && (mixed || fused_supported(p, 0));
+    const bool warm = p->opt.warm_start != 0 && !learned;
+    const bool ring_only = !warm && !learned && (mixed || fused_supported(p, 0));
     {
         Timed tm(p, kOther, s);
         if (warm) {
@@ -742,7 +906,9 @@ int cylpoisson_solve(cylpoisson_plan* p, const double* rho, double* phi, double 
         }
     }
     double* result = L.u;
-    const int status = mixed ? run_mixed(p, tol, s, &result, warm) : run_cycles(p, tol, s, ring_only, warm);
+    const int status = learned ? run_learned(p, tol, s)
+                       : mixed ? run_mixed(p, tol, s, &result, warm)
+                               : run_cycles(p, tol, s, ring_only, warm);
     if (status == CYLPOISSON_OK || status == CYLPOISSON_NOT_CONVERGED) {
         Timed tm(p, kDftInv, s);
         CP_HIP(transform(p, true, result, phi, nullptr, s));
