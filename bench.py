@@ -296,6 +296,84 @@ def time_batch(args):
     return out
 
 
+def time_learned(problem, rho_d, args, ref, phit):
+    """The learned preconditioner at this size: a network trained on the GPU on
+    about 20k pairs from a sequence of charges of this grid (the manufactured
+    one plus seeded smooth drifts), then the learned solve (FGMRES with the
+    network, judged against one V-cycle, V-cycles taking over when it loses),
+    timed like the plain solve; the per-step contraction of FGMRES without a
+    preconditioner and with the smoother the network imitates beside it; and
+    the network's forward pass over all mode pairs (MFMA throughput)."""
+    import torch
+
+    import paper_2609_07172_amd as P
+    import workloads as W
+
+    fields = [torch.from_numpy(f).to(rho_d.device) for f in W.drift_fields(problem, count=5, seed=4242)]
+    amp = 0.05 * float(rho_d.abs().max())
+    plan = P.Plan.for_problem(problem)
+    net = P.Net(seed=2024)
+    t0 = time.perf_counter()
+    for k, f in enumerate(fields):
+        net.collect(plan, rho_d + amp * f, cycles=8, patches_per_cycle=512, seed=k)
+    collect_s = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    net.train(epochs=30, batch=256, lr=2e-3)
+    loss = net.train(epochs=10, batch=256, lr=5e-4)
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t0
+    out = {"pairs": net.patch_count(), "collect_s": round(collect_s, 2), "train_s": round(train_s, 2),
+           "final_loss": loss}
+    lplan = P.Plan.for_problem(problem, krylov=1)
+    P.plan_set_net(lplan, net)
+    phi_d = torch.empty_like(rho_d)
+    lplan.solve(rho_d, tol=args.tol, phi=phi_d)
+    torch.cuda.synchronize()
+    reps = max(1, args.steps // 4)
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        _, st = lplan.solve(rho_d, tol=args.tol, phi=phi_d)
+    torch.cuda.synchronize()
+    out.update({"ms": round((time.perf_counter() - t0) / reps * 1e3, 4), "status": st["status"],
+                "krylov_iterations": st["krylov_iterations"], "vcycles": st["cycles"],
+                "fell_back": st["learned_fallback"], "vcycle_rate": st["vcycle_rate"],
+                "learned_rate": st["learned_rate"], "rel_residual": st["rel_residual"]})
+    if ref is not None:
+        got = phi_d.cpu().numpy()
+        out["rel_l2_vs_oracle"] = interior_rel(got, ref)
+        out["rel_l2_vs_phi_true"] = interior_rel(got, phit)
+    rates = {}
+    for label, precond in (("none", 0), ("smoother", 2), ("network", 1)):
+        pl = P.Plan.for_problem(problem, krylov=1, krylov_precond=precond, fallback=0, krylov_max=8)
+        P.plan_set_net(pl, net)
+        _, s2 = pl.solve(rho_d, tol=args.tol, phi=phi_d, allow=(P.OK, P.NOT_CONVERGED))
+        rates[label] = s2["learned_rate"]
+        pl.close()
+    out["fgmres_rate_per_step"] = rates
+    # the network's forward pass over every mode pair of this grid
+    npairs, H, Wd = problem.ntheta // 2 + 1, problem.nz - 2, problem.nr - 2
+    x = torch.randn((npairs, H, Wd, 4), dtype=torch.float32, device=rho_d.device)
+    net.forward(x)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(5):
+        net.forward(x)
+    e1.record()
+    torch.cuda.synchronize()
+    fwd_ms = e0.elapsed_time(e1) / 5
+    flops = 2.0 * npairs * H * Wd * (9 * 4 * 16 + 9 * 16 * 16 + 9 * 16 * 2)
+    out["network_forward"] = {"pixels": npairs * H * Wd, "ms": round(fwd_ms, 4),
+                              "tflops": round(flops / (fwd_ms * 1e-3) / 1e12, 2),
+                              "mfma_bf16_peak_tflops": 2500.0}
+    log(f"learned: {out['ms']:.3f} ms/solve, FGMRES rates {rates}, V-cycle {st['vcycle_rate']:.3f}, "
+        f"fell back {st['learned_fallback']}; network forward {fwd_ms:.3f} ms")
+    for q in (lplan, plan):
+        q.close()
+    net.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -401,6 +479,7 @@ def main():
         variants["autotuned"] = time_autotuned(problem, rho_d, args, ref, phit)
         variants["warm_start_sequence"] = time_sequence(problem, rho_d, args)
         variants["batch_uneven"] = time_batch(args)
+        variants["learned_preconditioner"] = time_learned(problem, rho_d, args, ref, phit)
 
     if args.copy_probe > 0:
         # a plain device copy of known size: the scale for the HBM byte counters
