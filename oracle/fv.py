@@ -15,6 +15,14 @@ Dirichlet faces; interior node (i, k), 1 <= i <= Nr-2, 1 <= k <= Nz-2, owns the
 control volume whose faces lie half-way to its neighbours.  With uniform
 spacing its centre is the node, its widths are dr and dz, and a boundary
 neighbour sits one full spacing away.
+
+General geometry (``Grid.general``, ``Grid.vertex``, ``Grid.cell_centred``):
+explicit, possibly non-uniform points in r and z with the faces of every
+control volume.  In the cell-centred reading of App. A the unknowns sit at
+cell centres and the Dirichlet values on the outer faces, half a cell from the
+first centre, which gives the half-cell boundary conductance.  Pinned by the
+paper's Dirichlet worked cell, SPD/M-matrix structure, dense-vs-sparse
+agreement, exact mode decomposition and measured second-order convergence.
 """
 from __future__ import annotations
 
@@ -99,10 +107,77 @@ class Grid:
         self.D0, self.mu = c["D0"], c["mu"]
         self.s_eps0 = c["s_eps0"]
 
+        self.uniform = True
+
     @classmethod
     def of(cls, problem, dtype=np.float64):
         p = problem
         return cls(p.nr, p.ntheta, p.nz, p.r_in, p.r_out, p.dz, dtype=dtype)
+
+    @classmethod
+    def general(cls, r, z, r_lo, r_hi, z_lo, z_hi, ntheta, dtype=np.float64):
+        """Grid from explicit geometry (App. A with general spacing).
+
+        ``r`` (nr) and ``z`` (nz) are the points, boundary points included;
+        ``r_lo, r_hi`` (nr - 2) and ``z_lo, z_hi`` (nz - 2) are the faces of the
+        control volume of each interior point.  Conductances use the distances
+        between neighbouring points, so a boundary point on a face gives the
+        half-cell Dirichlet conductance of Eq. (dirichlet_face_conductances).
+        """
+        t = dtype
+        g = cls.__new__(cls)
+        r = np.asarray(r, dtype=t)
+        z = np.asarray(z, dtype=t)
+        nr, nz = len(r), len(z)
+        if nr < 3 or nz < 3 or ntheta < 1:
+            raise ValueError("need nr >= 3, nz >= 3, ntheta >= 1")
+        if not (r[0] > 0 and np.all(np.diff(r) > 0) and np.all(np.diff(z) > 0)):
+            raise ValueError("need 0 < r[0] and increasing points")
+        g.nr, g.ntheta, g.nz, g.dtype = nr, int(ntheta), nz, dtype
+        g.r, g.z = r, z
+        g.r_in, g.r_out = r[0], r[-1]
+        g.dr = g.dz = None  # no single spacing
+        g.dtheta = t(2) * np.arccos(t(-1)) / t(ntheta)
+        R = np.broadcast_to(r[None, 1:-1], (nz - 2, nr - 2))
+        rlo = np.broadcast_to(np.asarray(r_lo, dtype=t)[None, :], R.shape)
+        rhi = np.broadcast_to(np.asarray(r_hi, dtype=t)[None, :], R.shape)
+        zlo = np.asarray(z_lo, dtype=t)[:, None]
+        zhi = np.asarray(z_hi, dtype=t)[:, None]
+        d_w = (r[1:-1] - r[:-2])[None, :]
+        d_e = (r[2:] - r[1:-1])[None, :]
+        d_s = (z[1:-1] - z[:-2])[:, None]
+        d_n = (z[2:] - z[1:-1])[:, None]
+        c = cell_coefficients(rlo, rhi, R, rhi - rlo, zhi - zlo, d_w, d_e, d_s, d_n)
+        c = {k: np.broadcast_to(v, R.shape).copy() for k, v in c.items()}
+        g.coef = c
+        g.G_rm, g.G_rp = c["G_rm"], c["G_rp"]
+        g.G_zm, g.G_zp = c["G_zm"], c["G_zp"]
+        g.D0, g.mu = c["D0"], c["mu"]
+        g.s_eps0 = c["s_eps0"]
+        g.uniform = False
+        return g
+
+    @classmethod
+    def vertex(cls, r, z, ntheta, dtype=np.float64):
+        """Vertex-centred grid on the given (possibly non-uniform) points: the
+        control-volume faces lie halfway between neighbouring points."""
+        r = np.asarray(r, dtype=dtype)
+        z = np.asarray(z, dtype=dtype)
+        h = dtype(0.5)
+        return cls.general(r, z, h * (r[:-2] + r[1:-1]), h * (r[1:-1] + r[2:]),
+                           h * (z[:-2] + z[1:-1]), h * (z[1:-1] + z[2:]), ntheta, dtype)
+
+    @classmethod
+    def cell_centred(cls, r_faces, z_faces, ntheta, dtype=np.float64):
+        """Cell-centred grid (App. A): cells between the given faces, unknowns at
+        the cell centres (face midpoints), Dirichlet values on the outer faces,
+        which are the boundary points (half a cell from the first centres)."""
+        rf = np.asarray(r_faces, dtype=dtype)
+        zf = np.asarray(z_faces, dtype=dtype)
+        h = dtype(0.5)
+        r = np.concatenate([rf[:1], h * (rf[:-1] + rf[1:]), rf[-1:]])
+        z = np.concatenate([zf[:1], h * (zf[:-1] + zf[1:]), zf[-1:]])
+        return cls.general(r, z, rf[:-1], rf[1:], zf[:-1], zf[1:], ntheta, dtype)
 
     @property
     def interior_shape(self):

@@ -89,6 +89,8 @@ def solve_separable(grid: fv.Grid, rho, bc=None, phi_boundary=None, workers=None
     solved with ``scipy.linalg.solve_banded``-equivalent Thomas elimination
     vectorised over all (m, p).
     """
+    if not getattr(grid, "uniform", True):
+        raise ValueError("the separable solver needs the uniform vertex-centred grid")
     b, pb = _problem_rhs(grid, rho, bc, phi_boundary)
     nt, nz, nr = grid.interior_shape
     gz = grid.G_zm[0]
