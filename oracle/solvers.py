@@ -10,7 +10,8 @@ that definition.  ``solve_separable`` is a second exact direct method for
 grids too large for sparse LU: FFT in theta, sine transform in z, tridiagonal
 solve in r (the classical fast Poisson solver; it needs uniform z, which this
 grid has).  ``solve_mode`` solves one 2-D system ``(A_0 + lambda M) u = b`` of
-Eq. (shifted_operator_family).
+Eq. (shifted_operator_family); ``solve_modes`` is the whole method of Sec. 3
+with a direct solve per mode, for meshes of any spacing.
 """
 from __future__ import annotations
 
@@ -20,7 +21,7 @@ import scipy.linalg
 import scipy.sparse as sp
 import scipy.sparse.linalg as spla
 
-from . import fv
+from . import fv, spectral
 from .spectral import discrete_eigenvalue
 
 
@@ -75,6 +76,26 @@ def solve_mode(grid: fv.Grid, lam: float, b_plane: np.ndarray) -> np.ndarray:
     """Solve the 2-D mode system ``(A_0 + lambda M) u = b`` (interior nodes of one plane)."""
     A = mode_operator(plane_matrix(grid), grid.mu, lam).tocsc()
     return spla.spsolve(A, np.ravel(b_plane)).reshape(grid.nz - 2, grid.nr - 2)
+
+
+def solve_modes(grid: fv.Grid, rho, bc=None, phi_boundary=None) -> np.ndarray:
+    """The method of Sec. 3 with exact mode solves: the right-hand side's
+    azimuthal DFT (Eq. (azimuthal_dft)), a sparse direct solve of
+    ``A_0 + lambda_m M`` on every real plane (Eqs. (shifted_operator_family),
+    (mode_rhs)), and the inverse DFT.  Exact up to rounding on any mesh; the
+    cosine and sine planes of one mode share a factorisation."""
+    b, pb = _problem_rhs(grid, rho, bc, phi_boundary)
+    planes = spectral.forward(np.reshape(b, grid.interior_shape))
+    lam = spectral.plane_eigenvalues(grid.ntheta, float(grid.dtheta))
+    A0 = plane_matrix(grid)
+    out = np.empty_like(planes)
+    factors = {}
+    for p in range(grid.ntheta):
+        key = float(lam[p])
+        if key not in factors:
+            factors[key] = spla.splu(mode_operator(A0, grid.mu, key).tocsc())
+        out[p] = factors[key].solve(planes[p].ravel()).reshape(planes[p].shape)
+    return fv.with_boundary(grid, spectral.inverse(out).ravel(), pb)
 
 
 def solve_separable(grid: fv.Grid, rho, bc=None, phi_boundary=None, workers=None) -> np.ndarray:

@@ -77,7 +77,8 @@ def test_dense_and_sparse_agree_on_stretched_grids(builder):
 
 
 def test_mode_decomposition_is_exact_on_a_cell_centred_grid():
-    """3-D dense solve vs azimuthal DFT, per-plane solves of A_0 + lambda M, inverse DFT."""
+    """3-D dense solve vs the mode path (azimuthal DFT, per-plane direct solves of
+    A_0 + lambda M, inverse DFT), written out here and as solvers.solve_modes."""
     rng = np.random.Generator(np.random.PCG64(5))
     g = fv.Grid.cell_centred(stretched(0.02, 0.05, 5, 1.3), stretched(0.0, 0.05, 4, 1.0), 6)
     rho = rng.standard_normal(g.shape) * 1e-6
@@ -90,6 +91,22 @@ def test_mode_decomposition_is_exact_on_a_cell_centred_grid():
         sol[p] = solvers.solve_mode(g, lam[p], planes[p].ravel()).reshape(planes[p].shape)
     back = spectral.inverse(sol)
     np.testing.assert_allclose(back, full[:, 1:-1, 1:-1], rtol=0, atol=1e-12 * np.abs(full).max())
+    np.testing.assert_allclose(solvers.solve_modes(g, rho, (0.0, 0.0, 0.0, 0.0)), full, rtol=0,
+                               atol=1e-12 * np.abs(full).max())
+
+
+@pytest.mark.parametrize("builder,ntheta", [("cell", 7), ("vertex", 8)])
+def test_solve_modes_matches_the_sparse_3d_solve_with_boundary_data(builder, ntheta):
+    rng = np.random.Generator(np.random.PCG64(8))
+    if builder == "cell":
+        g = fv.Grid.cell_centred(stretched(0.02, 0.05, 9, 1.15), stretched(0.0, 0.05, 11, 0.9), ntheta)
+    else:
+        g = fv.Grid.vertex(stretched(0.02, 0.05, 12, 0.9), stretched(0.0, 0.05, 10, 1.2), ntheta)
+    rho = rng.standard_normal(g.shape) * 1e-6
+    bc = (5.0, -3.0, 1.0, 200.0)
+    a = solvers.solve_sparse(g, rho, bc)
+    b = solvers.solve_modes(g, rho, bc)
+    assert np.linalg.norm(a - b) / np.linalg.norm(a) < 1e-13
 
 
 def _manufactured_axisymmetric(r, z, r_in, W, L):
