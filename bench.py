@@ -26,7 +26,8 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published peak
 METRIC = "ms per full-spectrum Poisson solve to rel-L2 1e-12; achieved HBM GB/s vs peak"
-FUSED_SOURCES = ("paper_2609_07172_amd/csrc/fused.hip", "paper_2609_07172_amd/csrc/stencil.h")
+FUSED_SOURCES = ("paper_2609_07172_amd/csrc/fused.hip", "paper_2609_07172_amd/csrc/fused_pass.h",
+                 "paper_2609_07172_amd/csrc/stencil.h")
 
 
 def source_hash() -> str:

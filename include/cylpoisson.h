@@ -5,9 +5,10 @@
  *
  * The equation is the cylindrical Poisson equation of Sec. 3.1,
  *     -[ (1/r) d/dr (r dphi/dr) + (1/r^2) d2phi/dtheta^2 + d2phi/dz^2 ] = rho/eps0,
- * discretised by the finite-volume cell balance of App. A on a vertex-centred
- * annular grid, with the periodic three-point azimuthal difference of
- * Sec. 3.1.  The solve follows Sec. 3: the azimuthal DFT (Eq. azimuthal_dft)
+ * discretised by the finite-volume cell balance of App. A on an annular
+ * tensor-product mesh (vertex-centred, or cell-centred with half-cell
+ * Dirichlet faces, uniform or not in r and z), with the periodic three-point
+ * azimuthal difference of Sec. 3.1.  The solve follows Sec. 3: the azimuthal DFT (Eq. azimuthal_dft)
  * splits the 3-D system into independent 2-D systems A_m = A_0 + lambda_m M
  * (Eq. shifted_operator_family) with the exact discrete eigenvalue
  * lambda_m = (4/dtheta^2) sin^2(pi m / Ntheta) (Eq. discrete_azimuthal_eigenvalue),
@@ -16,9 +17,11 @@
  *
  * Conventions
  * -----------
- * Grid.  Nr radial nodes r_i = r_in + i (r_out - r_in)/(Nr - 1) and Nz axial
- *   nodes z_k = k dz, both counts including the two Dirichlet faces; Ntheta
- *   periodic nodes theta_j = 2 pi j / Ntheta over the full annulus.
+ * Grid.  Nr radial and Nz axial nodes, both counts including the two
+ *   Dirichlet nodes of the direction; Ntheta periodic nodes
+ *   theta_j = 2 pi j / Ntheta over the full annulus.  cylpoisson_plan_create
+ *   builds the uniform vertex-centred mesh r_i = r_in + i (r_out - r_in)/(Nr - 1),
+ *   z_k = k dz; cylpoisson_plan_create_mesh takes explicit coordinates.
  * Arrays.  Node arrays are C-contiguous double[Ntheta][Nz][Nr] (r fastest) in
  *   device memory of the plan's device.  rho in C/m^3, phi in volts,
  *   eps0 = 8.8541878128e-12 F/m.
@@ -51,6 +54,10 @@ extern "C" {
 #define CYLPOISSON_EHIP (-3)       /* a HIP runtime call failed */
 #define CYLPOISSON_ENONFINITE (-4) /* rho (or a plane right-hand side) holds NaN or Inf */
 #define CYLPOISSON_EDEVICE (-5)    /* a pointer is not device memory of the plan's device */
+
+/* Mesh layouts of cylpoisson_plan_create_mesh (App. A). */
+#define CYLPOISSON_VERTEX 0 /* unknowns at the given nodes, control-volume faces half-way */
+#define CYLPOISSON_CELL 1   /* unknowns at cell centres, Dirichlet values on the outer faces */
 
 #define CYLPOISSON_MAX_HISTORY 64
 #define CYLPOISSON_MAX_LEVELS 24
@@ -114,6 +121,11 @@ typedef struct {
     int bottom_level;                       /* first level run by the LDS bottom kernel, -1 if none */
     long long workspace_bytes;              /* device memory owned by the plan */
     int device;                             /* HIP device ordinal */
+    int fused_levels;   /* levels from the finest whose V-cycle work runs in fused streaming
+                         * passes under the current options (the others above the bottom
+                         * kernel run one kernel per sweep) */
+    int layout;         /* CYLPOISSON_VERTEX or CYLPOISSON_CELL */
+    int uniform;        /* 1 = built by cylpoisson_plan_create (uniform vertex-centred mesh) */
 } cylpoisson_info;
 
 /* Create a plan for an Nr x Ntheta x Nz grid.  Requires Nr >= 3, Nz >= 3,
@@ -123,6 +135,28 @@ typedef struct {
  * Returns NULL on error (see cylpoisson_last_error; EINVAL or ENOMEM). */
 cylpoisson_plan* cylpoisson_plan_create(int Nr, int Ntheta, int Nz, double r_in, double r_out,
                                         double dz, const cylpoisson_bc* bc);
+
+/* Create a plan on an explicit, possibly non-uniform mesh (App. A: the cell
+ * balance with conductances from the actual face positions and node
+ * distances).  r and z are host arrays, read during the call only.
+ *   layout CYLPOISSON_VERTEX: r holds the Nr node radii and z the Nz node
+ *     heights, boundary nodes included; the control volume of an interior node
+ *     reaches half-way to each neighbour.
+ *   layout CYLPOISSON_CELL: r holds the Nr - 1 radial faces of the Nr - 2
+ *     cells and z the Nz - 1 axial faces of the Nz - 2 cells.  The unknowns sit
+ *     at the cell centres (face midpoints); the outer faces are the Dirichlet
+ *     nodes, half a cell from the first centre, which gives the half-cell
+ *     boundary conductance of Eq. (dirichlet_face_conductances).
+ * In both layouts node arrays keep the shape [Ntheta][Nz][Nr]: the ring holds
+ * the Dirichlet values, the interior the unknowns.  Requires Nr, Nz >= 3,
+ * Ntheta >= 1, finite strictly increasing coordinates, r[0] > 0, finite
+ * boundary values.  Coarser multigrid levels keep every other node of each
+ * coarsened direction and rediscretise with faces half-way between their
+ * nodes; grid transfers interpolate linearly in the coordinates, and a
+ * direction is coarsened alone while the median spacings differ more than
+ * 2:1.  Returns NULL on error (EINVAL or ENOMEM, see cylpoisson_last_error). */
+cylpoisson_plan* cylpoisson_plan_create_mesh(int Nr, int Ntheta, int Nz, const double* r, const double* z,
+                                             int layout, const cylpoisson_bc* bc);
 
 /* Release the plan and its device memory.  NULL-safe.  The plan must be idle. */
 void cylpoisson_plan_destroy(cylpoisson_plan* plan);
@@ -168,7 +202,13 @@ void cylpoisson_plan_destroy(cylpoisson_plan* plan);
  *                    contracts less per step (FP64 only; default 0)
  *   "krylov_precond" 1 = the network preconditions FGMRES; 0 = no preconditioner;
  *                    2 = four red-black SOR sweeps, the map the network is trained
- *                    to imitate (0 and 2 for comparison; default 1)
+ *                    to imitate (0 and 2 for comparison); 3 = one V-cycle from
+ *                    zero: multigrid-preconditioned FGMRES, which needs fewer
+ *                    steps than plain V-cycles where the point smoother is weak
+ *                    (strongly stretched meshes), at one V-cycle plus the Arnoldi
+ *                    work per step (counted in `cycles`); not judged (no judging
+ *                    cycle, no fallback, vcycle_rate 0) since the plain V-cycle
+ *                    iterates lie in the space FGMRES minimises over (default 1)
  *   "krylov_restart" FGMRES restart length, also the judged steps (1 .. 16; default 8)
  *   "krylov_max"     FGMRES steps in all (default 200)
  *   "fallback"       1 = V-cycles take over from a worse network (default 1)
@@ -230,8 +270,8 @@ int cylpoisson_get_info(const cylpoisson_plan* plan, cylpoisson_info* out);
  *     rho_out = (A_full phi) / s_q   at interior nodes,  0 at boundary nodes,
  * where A_full is the seven-point cell balance of App. A plus the azimuthal
  * three-point term (the left-hand side of Eq. full_finite_volume_row with the
- * boundary nodes of phi as neighbours) and s_q = r_i dr dz / eps0.  So
- * solving with rho_out returns phi.  Computed as DFT, per-plane
+ * boundary nodes of phi as neighbours) and s_q = r_i dr_i dz_k / eps0 with the
+ * control-volume widths dr_i, dz_k.  So solving with rho_out returns phi.  Computed as DFT, per-plane
  * A_0 + lambda_m M (Eq. shifted_operator_family), inverse DFT.  Enqueues on
  * stream without synchronising.  Returns OK, EINVAL, EDEVICE or EHIP. */
 int cylpoisson_apply(cylpoisson_plan* plan, const double* phi, double* rho_out, void* stream);

@@ -21,17 +21,20 @@ __all__ = [
     "CylPoissonError", "library", "library_path", "plan_create", "plan_destroy",
     "plan_set_option", "solve", "solve_planes", "apply", "dft_forward", "dft_inverse",
     "get_stats", "get_info", "last_error", "status_string", "Plan", "EXPORTED_SYMBOLS",
-    "plan_get_option", "autotune", "solve_batch", "solve_plans", "Net",
+    "plan_get_option", "autotune", "solve_batch", "solve_plans", "Net", "plan_create_mesh",
+    "VERTEX", "CELL",
 ]
 
 OK, NOT_CONVERGED = 0, 1
 EINVAL, ENOMEM, EHIP, ENONFINITE, EDEVICE = -1, -2, -3, -4, -5
+VERTEX, CELL = 0, 1  # mesh layouts of cylpoisson_plan_create_mesh
 MAX_HISTORY = 64
 MAX_LEVELS = 24
 KERNEL_CLASSES = ("dft_forward", "dft_inverse", "fine_down", "fine_up", "coarse_levels", "other")
 
 EXPORTED_SYMBOLS = (
-    "cylpoisson_plan_create", "cylpoisson_plan_destroy", "cylpoisson_plan_set_option",
+    "cylpoisson_plan_create", "cylpoisson_plan_create_mesh", "cylpoisson_plan_destroy",
+    "cylpoisson_plan_set_option",
     "cylpoisson_solve", "cylpoisson_get_stats", "cylpoisson_get_info", "cylpoisson_apply",
     "cylpoisson_dft_forward", "cylpoisson_dft_inverse", "cylpoisson_solve_planes",
     "cylpoisson_last_error", "cylpoisson_status_string", "cylpoisson_plan_get_option",
@@ -79,13 +82,15 @@ class Info(ctypes.Structure):
                 ("levels", ctypes.c_int), ("level_nr", ctypes.c_int * MAX_LEVELS),
                 ("level_nz", ctypes.c_int * MAX_LEVELS), ("coarse_unknowns", ctypes.c_int),
                 ("bottom_level", ctypes.c_int),
-                ("workspace_bytes", ctypes.c_longlong), ("device", ctypes.c_int)]
+                ("workspace_bytes", ctypes.c_longlong), ("device", ctypes.c_int),
+                ("fused_levels", ctypes.c_int), ("layout", ctypes.c_int), ("uniform", ctypes.c_int)]
 
     def as_dict(self) -> dict:
         return {"nr": self.nr, "ntheta": self.ntheta, "nz": self.nz, "levels": self.levels,
                 "level_shapes": [(self.level_nr[i], self.level_nz[i]) for i in range(self.levels)],
                 "coarse_unknowns": self.coarse_unknowns, "bottom_level": self.bottom_level,
-                "workspace_bytes": self.workspace_bytes, "device": self.device}
+                "workspace_bytes": self.workspace_bytes, "device": self.device,
+                "fused_levels": self.fused_levels, "layout": self.layout, "uniform": self.uniform}
 
 
 class CylPoissonError(RuntimeError):
@@ -110,6 +115,8 @@ def library() -> ctypes.CDLL:
     L.cylpoisson_plan_create.restype = vp
     L.cylpoisson_plan_create.argtypes = [i, i, i, d, d, d, ctypes.POINTER(BC)]
     L.cylpoisson_plan_destroy.restype = None
+    L.cylpoisson_plan_create_mesh.restype = vp
+    L.cylpoisson_plan_create_mesh.argtypes = [i, i, i, ctypes.POINTER(d), ctypes.POINTER(d), i, ctypes.POINTER(BC)]
     L.cylpoisson_plan_destroy.argtypes = [vp]
     L.cylpoisson_plan_set_option.restype = i
     L.cylpoisson_plan_set_option.argtypes = [vp, ctypes.c_char_p, d]
@@ -204,6 +211,25 @@ def plan_create(nr, ntheta, nz, r_in, r_out, dz, bc=(0.0, 0.0, 0.0, 0.0)) -> int
     return h
 
 
+def plan_create_mesh(nr, ntheta, nz, r, z, layout=VERTEX, bc=(0.0, 0.0, 0.0, 0.0)) -> int:
+    """``cylpoisson_plan_create_mesh``: r and z are sequences of floats (node
+    coordinates for VERTEX, the nr - 1 / nz - 1 cell faces for CELL)."""
+    need = (nr, nz) if layout == VERTEX else (nr - 1, nz - 1)
+    r = [float(x) for x in r]
+    z = [float(x) for x in z]
+    if (len(r), len(z)) != tuple(need):
+        raise ValueError(f"layout {layout} needs {need[0]} radial and {need[1]} axial values, "
+                         f"got {len(r)} and {len(z)}")
+    b = BC(*[float(x) for x in bc])
+    ra = (ctypes.c_double * max(1, len(r)))(*r)
+    za = (ctypes.c_double * max(1, len(z)))(*z)
+    h = library().cylpoisson_plan_create_mesh(int(nr), int(ntheta), int(nz), ra, za, int(layout),
+                                              ctypes.byref(b))
+    if not h:
+        raise CylPoissonError(EINVAL, last_error())
+    return h
+
+
 def plan_destroy(plan) -> None:
     library().cylpoisson_plan_destroy(plan)
 
@@ -282,6 +308,20 @@ class Plan:
     @classmethod
     def for_problem(cls, p, **options) -> "Plan":
         return cls(p.nr, p.ntheta, p.nz, p.r_in, p.r_out, p.dz, p.bc, **options)
+
+    @classmethod
+    def from_mesh(cls, r, z, ntheta, layout=VERTEX, bc=(0.0, 0.0, 0.0, 0.0), **options) -> "Plan":
+        """Plan on an explicit mesh (``cylpoisson_plan_create_mesh``): node
+        coordinates for VERTEX, cell faces for CELL (one node per cell centre
+        plus the two outer faces)."""
+        extra = 0 if layout == VERTEX else 1
+        nr, nz = len(r) + extra, len(z) + extra
+        self = cls.__new__(cls)
+        self.shape = (int(ntheta), int(nz), int(nr))
+        self.handle = plan_create_mesh(nr, ntheta, nz, r, z, layout, bc)
+        for k, v in options.items():
+            plan_set_option(self.handle, k, v)
+        return self
 
     def set_option(self, key, value):
         plan_set_option(self.handle, key, value)

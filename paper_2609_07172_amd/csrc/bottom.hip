@@ -219,7 +219,7 @@ hipError_t launch_bottom_t(cylpoisson_plan* p, const T* f_in, T* u_out, hipStrea
     a.nu2 = p->opt.nu2;
     a.omega = p->opt.omega;
     a.p0 = p0;
-    a.mask = p->opt.masks ? p->d_mask : nullptr;
+    a.mask = p->mask_live ? p->d_mask : nullptr;
     const size_t bytes = bottom_lds_bytes(p, lb) / sizeof(double) * sizeof(T);
     k_bottom<T><<<np, 512, bytes, s>>>(a);
     return hipGetLastError();

@@ -19,12 +19,13 @@ constexpr double kEps0 = 8.8541878128e-12;
 // [Ntheta][nz][pitch] doubles, node (k, i) of plane p at p*pstride + k*pitch + i;
 // nodes include the Dirichlet ring (i = 0, nr-1; k = 0, nz-1).
 //
-// Finite-volume coefficients (App. A, vertex-centred, separable in r and z):
+// Finite-volume coefficients (App. A, separable in r and z on any tensor-product mesh):
 //   G_W(i,k) = rw[i] * zc[k]   G_E(i,k) = re[i] * zc[k]
 //   G_S(i,k) = rb[i] * zs[k]   G_N(i,k) = rb[i] * zn[k]
 //   mu(i,k)  = rm[i] * zc[k]
 // with rw = r_{i-1/2}/h_w, re = r_{i+1/2}/h_e, rb = r_i dr_i, rm = dr_i/r_i,
-// zc = dz_k, zs = 1/h_s, zn = 1/h_n (h = centre-to-centre distances).
+// zc = dz_k, zs = 1/h_s, zn = 1/h_n (dr_i, dz_k control-volume widths between
+// the faces r_{i-1/2}, r_{i+1/2}; h = distances to the neighbouring nodes).
 struct LevelView {
     int nr, nz, pitch;
     int pad_;
@@ -63,7 +64,10 @@ struct DeviceLevel {
     // fused-pass tables (towards the next coarser level)
     const int* colc = nullptr;             // fine column -> coincident coarse interior column or -1
     const int* rowc = nullptr;             // fine row -> coincident coarse interior row or -1
-    int spec_lo = 0;  // rows >= spec_lo have axial coefficients other than (zc0, zs0, zn0)
+    // rows reg_lo <= k < reg_hi share the axial coefficients (zc0, zs0, zn0);
+    // the rows outside that band are irregular (uneven spacing near the faces
+    // or everywhere on a stretched mesh)
+    int reg_lo = 1, reg_hi = 1;
     double zc0 = 0, zs0 = 0, zn0 = 0;
 };
 
@@ -125,8 +129,21 @@ struct Options {
 struct cylpoisson_plan {
     int device = 0;
     int nr = 0, nt = 0, nz = 0;
-    double r_in = 0, r_out = 0, dz = 0, dr = 0, dtheta = 0;
+    double r_in = 0, r_out = 0, dtheta = 0;
     cylpoisson_bc bc{};
+    // Level-0 mesh.  uniform: r_i = r_in + i dr, z_k = k dz, faces half-way
+    // between nodes (the arithmetic of every level stays in integer node
+    // positions times the spacing).  Otherwise explicit node coordinates and the
+    // control-volume faces of every interior node (ring entries unused).
+    bool uniform = true;
+    int layout = 0;  // CYLPOISSON_VERTEX or CYLPOISSON_CELL
+    double dr = 0, dz = 0;
+    std::vector<double> xr, xz;
+    std::vector<double> r_lo, r_hi, z_lo, z_hi;
+    double* d_r0 = nullptr;  // level-0 radii (nr), for the learned preconditioner's input
+    // the kernels read d_mask only while a masked V-cycle iteration keeps it
+    // current (set for the duration of run_cycles with masks active)
+    bool mask_live = false;
     cp::Options opt;
 
     std::vector<cp::HostLevel> hl;
@@ -140,8 +157,8 @@ struct cylpoisson_plan {
     double* d_F = nullptr;       // forward DFT matrix [N][N]
     double* d_G = nullptr;       // inverse DFT matrix [N][N]
     double* d_tw = nullptr;      // (cos, sin)(2 pi k / N), k < N, for the register FFTs
-    double* d_s = nullptr;       // s_i = r_i dr dz / eps0, per radial node (fine level)
-    double* d_inv_s = nullptr;   // 1 / s_i (0 on the ring)
+    double* d_s = nullptr;       // s_q = r_i dr_i dz_k / eps0 per level-0 node [nz][nr] (0 on the ring)
+    double* d_inv_s = nullptr;   // 1 / s_q (0 on the ring)
     double* d_cinv = nullptr;    // coarsest-level inverse per plane [N][n][n]
     double* d_partial = nullptr; // per-plane partial sums [N][kMaxPartial]
     double* d_slot_partial = nullptr;  // finest up-pass partials per cycle [slots][N][kSlotPartial]
@@ -201,7 +218,7 @@ void set_error(const char* fmt, ...);
 
 // ---- kernel launchers (kernels.hip) ----
 hipError_t launch_dft(const double* M, const double* X, double* Y, int n, long long ncols,
-                      const double* colscale, int nr, hipStream_t s);
+                      const double* colscale, hipStream_t s);
 hipError_t launch_init_fine_u(const DeviceLevel& L, int nt, const cylpoisson_bc& bc, hipStream_t s);
 hipError_t launch_zero_interior(const DeviceLevel& L, int nt, double* u, hipStream_t s);
 hipError_t launch_zero(double* p, long long n, hipStream_t s);
@@ -239,7 +256,7 @@ hipError_t launch_refine(const DeviceLevel& L, int nt, const double* lam, const 
 // ---- register FFTs (fft.hip) ----
 bool fft_supported(int n);
 hipError_t launch_fft(bool inverse, int n, const double* in, double* out, long long ncols,
-                      const double* cs, int nr, const double* tw, hipStream_t s);
+                      const double* cs, const double* tw, hipStream_t s);
 
 // ---- bottom of the V-cycle (bottom.hip) ----
 size_t bottom_lds_bytes(const cylpoisson_plan* p, int lb);  // FP64 values
@@ -274,6 +291,9 @@ hipError_t plane_lincomb(cylpoisson_plan* p, double* dst, double alpha, const do
 hipError_t learned_precond(cylpoisson_plan* p, const double* v, double* z, hipStream_t s);
 // one plain V-cycle on level 0 from the current iterate (solve.hip)
 hipError_t vcycle_step(cylpoisson_plan* p, hipStream_t s);
+// One V-cycle on level 0 whose iterate's interior is zero on entry (the
+// interior of dl[0].u is not read by the fused passes; the other paths need it zero).
+hipError_t vcycle_from_zero(cylpoisson_plan* p, hipStream_t s);
 
 // Release the captured V-cycle graphs (plan.hip).
 void drop_graphs(cylpoisson_plan* p);

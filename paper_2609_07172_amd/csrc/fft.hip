@@ -62,7 +62,7 @@ __device__ __forceinline__ void cfft(double (&re)[M], double (&im)[M], const dou
 template <int M>
 __global__ void __launch_bounds__(64) k_rfft_fwd(const double* __restrict__ X, double* __restrict__ Y,
                                                  long long ncols, const double* __restrict__ cs,
-                                                 int nr, const double* __restrict__ tw) {
+                                                 const double* __restrict__ tw) {
     constexpr int N = 2 * M;
     const long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= ncols) return;
@@ -73,7 +73,7 @@ __global__ void __launch_bounds__(64) k_rfft_fwd(const double* __restrict__ X, d
         im[bitrev<M>(n)] = X[(long long)(2 * n + 1) * ncols + c];
     }
     cfft<M, -1>(re, im, tw);
-    const double scale = (cs ? cs[c % nr] : 1.0) / (double)N;
+    const double scale = (cs ? cs[c] : 1.0) / (double)N;
     // k = 0 and k = M (both real)
     Y[c] = (re[0] + im[0]) * scale;
     Y[(long long)M * ncols + c] = (re[0] - im[0]) * scale;
@@ -125,12 +125,12 @@ __global__ void __launch_bounds__(64) k_rfft_inv(const double* __restrict__ P, d
 
 template <int M>
 hipError_t launch_m(bool inverse, const double* in, double* out, long long ncols, const double* cs,
-                    int nr, const double* tw, hipStream_t s) {
+                    const double* tw, hipStream_t s) {
     const unsigned blocks = (unsigned)((ncols + 63) / 64);
     if (inverse)
         k_rfft_inv<M><<<blocks, 64, 0, s>>>(in, out, ncols, tw);
     else
-        k_rfft_fwd<M><<<blocks, 64, 0, s>>>(in, out, ncols, cs, nr, tw);
+        k_rfft_fwd<M><<<blocks, 64, 0, s>>>(in, out, ncols, cs, tw);
     return hipGetLastError();
 }
 
@@ -139,12 +139,12 @@ hipError_t launch_m(bool inverse, const double* in, double* out, long long ncols
 bool fft_supported(int n) { return n == 16 || n == 32 || n == 64 || n == 128; }
 
 hipError_t launch_fft(bool inverse, int n, const double* in, double* out, long long ncols,
-                      const double* cs, int nr, const double* tw, hipStream_t s) {
+                      const double* cs, const double* tw, hipStream_t s) {
     switch (n) {
-        case 16: return launch_m<8>(inverse, in, out, ncols, cs, nr, tw, s);
-        case 32: return launch_m<16>(inverse, in, out, ncols, cs, nr, tw, s);
-        case 64: return launch_m<32>(inverse, in, out, ncols, cs, nr, tw, s);
-        case 128: return launch_m<64>(inverse, in, out, ncols, cs, nr, tw, s);
+        case 16: return launch_m<8>(inverse, in, out, ncols, cs, tw, s);
+        case 32: return launch_m<16>(inverse, in, out, ncols, cs, tw, s);
+        case 64: return launch_m<32>(inverse, in, out, ncols, cs, tw, s);
+        case 128: return launch_m<64>(inverse, in, out, ncols, cs, tw, s);
         default: return hipErrorInvalidValue;
     }
 }

@@ -9,12 +9,11 @@ bool fused_supported(const cylpoisson_plan* p, int l) {
     if (p->opt.nu1 > 4 || p->opt.nu2 > 4) return false;
     const Shape sd = pass_shape<double>(p, l, p->opt.nu1, true);
     const Shape su = pass_shape<double>(p, l, p->opt.nu2, false);
-    const int nspecial = p->dl[l].v.nz - 1 - p->dl[l].spec_lo;
     // the up pass has thread t carry coarse interior column t + 1: the coarse
     // level must be coarsened in r (a level coarsened in z only is not fused)
     const bool coarse_cols = p->dl[l + 1].v.nr - 2 <= su.threads;
     return su.threads >= 1 && su.threads <= 512 && std::max(sd.lds, su.lds) <= 64 * 1024 &&
-           std::max(sd.nchunks, su.nchunks) <= kMaxPartial && nspecial <= 4 && coarse_cols;
+           std::max(sd.nchunks, su.nchunks) <= kMaxPartial && coarse_cols;
 }
 
 hipError_t fused_down(cylpoisson_plan* p, int l, bool zero_u, bool zero_interior, hipStream_t s,

@@ -59,7 +59,7 @@ struct PassArgs {
     const double* lam;
     const int* colc;     // fine column -> coarse interior column it coincides with, else -1
     const int* rowc;     // fine row -> coarse interior row it coincides with, else -1
-    int spec_lo;         // rows >= spec_lo have axial coefficients other than (zc0, zs0, zn0)
+    int reg_lo, reg_hi;  // rows reg_lo <= y < reg_hi share the axial coefficients (zc0, zs0, zn0)
     double* partial;     // up: per (plane, chunk) sum of squared residuals, or nullptr
     int partial_ld;      // stride between planes in `partial`
     double omega, zc0, zs0, zn0;
@@ -88,14 +88,12 @@ struct Pass {
     // LDS layout: column histories A[tn + 1][QS] (column 2t+1 of thread t) and
     // B[tn + 1][QS] (column 2j; j = 0 is the radial ring column, j = t + 1 is
     // column 2t+2 of thread t) and restriction rows V[2][2][tn + 1], all of T;
-    // then (8-byte aligned) seven per-row tables of doubles, the coarse ring
-    // rows (T) and the special rows' inverse diagonals (T).  pass_lds_bytes()
-    // on the host is the same layout.
+    // then (8-byte aligned) seven per-row tables of doubles and the coarse ring
+    // rows (T).  pass_shape() on the host is the same layout.
     T* hist;
     T* vrows;
     double* tab;
     T* cringp;
-    T* sinvp;
     T* At;  // own column c1
     T* Bt;  // own column c2
     T* Bl;  // column 2t (west of c1)
@@ -133,8 +131,6 @@ struct Pass {
         tab = (double*)(smem + off);
         off += (size_t)7 * rows * sizeof(double);
         cringp = (T*)(smem + off);
-        if (!DOWN) off += (size_t)kCRing * a.vc.nr * sizeof(T);
-        sinvp = (T*)(smem + off);
     }
 
     __device__ __forceinline__ T* Vrow(int buf, int half) { return vrows + (2 * buf + half) * (a.tn + 1); }
@@ -147,9 +143,6 @@ struct Pass {
     __device__ __forceinline__ double* rowzn() { return tables() + 5 * rows; }
     __device__ __forceinline__ int* rowk() { return (int*)(tables() + 6 * rows); }
     __device__ __forceinline__ T* cring() { return cringp; }
-    // inverse diagonals of the rows from spec_lo to nz-2 (at most kMaxSpecial),
-    // per row [column pair t][2]
-    __device__ __forceinline__ T* sinv() { return sinvp; }
     __device__ __forceinline__ T* crow(int K) { return cring() + (K & (kCRing - 1)) * a.vc.nr; }
 
     __device__ __forceinline__ bool interior_row(int x) const { return x >= 1 && x <= a.v.nz - 2; }
@@ -243,11 +236,6 @@ struct Pass {
             rowzs()[x - s] = v.zs[x];
             rowzn()[x - s] = v.zn[x];
         }
-        for (int y = a.spec_lo; y <= v.nz - 2; ++y) {
-            T* row = sinv() + (y - a.spec_lo) * 2 * a.tn;
-            row[2 * t] = (T)make_coef(rw1, re1, rb1, rm1, v.zc[y], v.zs[y], v.zn[y], lam).invd;
-            row[2 * t + 1] = (T)make_coef(rw2, re2, rb2, rm2, v.zc[y], v.zs[y], v.zn[y], lam).invd;
-        }
         if (!DOWN) {
             // coarse rows needed by the rows consumed in the first PD + 1 steps
             lds_barrier();
@@ -333,30 +321,21 @@ struct Pass {
     }
 
     // ---- arithmetic ----
-    // Coefficients of rows from spec_lo on: the conductances from the row's axial
-    // tables, the inverse diagonal from the table set up once (no division here).
-    __device__ __forceinline__ CoefT<T> special(double rw, double re, double rb, double rm, int y, int col) {
-        Coef c;
-        const double zc = rowzc()[y - s];
-        c.gw = rw * zc;
-        c.ge = re * zc;
-        c.gs = rb * rowzs()[y - s];
-        c.gn = rb * rowzn()[y - s];
-        c.diag = fma(lam, rm * zc, (c.gw + c.ge) + (c.gs + c.gn));
-        c.invd = 0.0;
-        CoefT<T> ct = coef_as<T>(c);
-        ct.invd = sinv()[(y - a.spec_lo) * 2 * a.tn + 2 * t + col];
-        return ct;
+    // Coefficients of a row outside the regular band, from the row's axial
+    // tables in LDS (the same expression as every other kernel evaluates).
+    __device__ __forceinline__ bool regular(int y) const { return y >= a.reg_lo && y < a.reg_hi; }
+    __device__ __forceinline__ CoefT<T> irregular(double rw, double re, double rb, double rm, int y) {
+        return coef_as<T>(make_coef(rw, re, rb, rm, rowzc()[y - s], rowzs()[y - s], rowzn()[y - s], lam));
     }
     template <bool CHK>
     __device__ __forceinline__ CoefT<T> coef1(int y) {
-        if (!CHK || y < a.spec_lo) return cu1;
-        return special(rw1, re1, rb1, rm1, y, 0);
+        if (!CHK || regular(y)) return cu1;
+        return irregular(rw1, re1, rb1, rm1, y);
     }
     template <bool CHK>
     __device__ __forceinline__ CoefT<T> coef2(int y) {
-        if (!CHK || y < a.spec_lo) return cu2;
-        return special(rw2, re2, rb2, rm2, y, 1);
+        if (!CHK || regular(y)) return cu2;
+        return irregular(rw2, re2, rb2, rm2, y);
     }
 
     // Half-sweep on row y (slot SY; SM = y-1, SP = y+1).  C1: the colour being
@@ -503,9 +482,10 @@ struct Pass {
         // to finish the pending restriction
         const int ylast = DOWN ? min(a.v.nz - 1, zb) : zb - 1;
         const int xlast = ylast + 2 * NU + 1 + (DOWN ? 1 : 0);
-        // steady steps: every row they touch is interior, below spec_lo and in the chunk
-        const int lo = za + 2 * NU + 2;
-        const int hi = min(min(zb + 2 * NU - 1, a.v.nz - 2), min(lend, a.spec_lo));
+        // steady steps: every row they touch (x - 2 NU - 1 .. x) is interior,
+        // regular and in the chunk
+        const int lo = max(za + 2 * NU + 2, a.reg_lo + 2 * NU + 1);
+        const int hi = min(min(zb + 2 * NU - 1, a.v.nz - 2), min(lend, a.reg_hi));
         int ga = s, gb = s;  // [ga, gb): whole groups of steady steps
         if (hi >= lo) {
             ga = s + ((lo - s + Q - 1) / Q) * Q;
@@ -645,12 +625,10 @@ Shape pass_shape(const cylpoisson_plan* p, int l, int nu, bool down) {
     const int q0 = 2 * nu + 3 + pd;
     const size_t qs = (size_t)((q0 & 1) ? q0 + 1 : q0) + 1;
     const size_t trows = (size_t)(chunk + 4 * nu + 6);
-    const size_t nspecial = (size_t)std::max(0, L.v.nz - 1 - L.spec_lo);
     size_t off = (2 * (sh.tn + 1) * qs + 4 * (sh.tn + 1)) * sizeof(T);
     off = (off + 7) & ~(size_t)7;
     off += 7 * trows * sizeof(double);
     if (!down) off += (size_t)(pd == 1 ? 4 : 8) * p->dl[l + 1].v.nr * sizeof(T);
-    off += nspecial * 2 * sh.tn * sizeof(T);
     sh.lds = std::max(off, (size_t)sh.threads * sizeof(double));  // final block reduction
     return sh;
 }
@@ -668,7 +646,8 @@ PassArgs<T> make_args(const cylpoisson_plan* p, int l, const Shape& sh, int p0, 
     a.lam = p->d_lam;
     a.colc = L.colc;
     a.rowc = L.rowc;
-    a.spec_lo = L.spec_lo;
+    a.reg_lo = L.reg_lo;
+    a.reg_hi = L.reg_hi;
     a.omega = p->opt.omega;
     a.zc0 = L.zc0;
     a.zs0 = L.zs0;
@@ -677,7 +656,7 @@ PassArgs<T> make_args(const cylpoisson_plan* p, int l, const Shape& sh, int p0, 
     a.nchunks = sh.nchunks;
     a.nt = np;
     a.p0 = p0;
-    a.mask = p->opt.masks ? p->d_mask : nullptr;
+    a.mask = p->mask_live ? p->d_mask : nullptr;
     a.tn = sh.tn;
     a.xcd_major = (np % 8 == 0) ? 1 : 0;
     return a;

@@ -20,7 +20,7 @@ constexpr int kDftRows = 16;
 __global__ void __launch_bounds__(256) k_dft(const double* __restrict__ M,
                                              const double* __restrict__ X,
                                              double* __restrict__ Y, int n, long long ncols,
-                                             const double* __restrict__ cs, int nr) {
+                                             const double* __restrict__ cs) {
     const long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     const int p0 = blockIdx.y * kDftRows;
     if (c >= ncols) return;
@@ -35,7 +35,7 @@ __global__ void __launch_bounds__(256) k_dft(const double* __restrict__ M,
         for (int q = 0; q < kDftRows; ++q)
             if (q < rows) acc[q] = fma(m[(long long)q * n], x, acc[q]);
     }
-    const double scale = cs ? cs[c % nr] : 1.0;
+    const double scale = cs ? cs[c] : 1.0;
 #pragma unroll
     for (int q = 0; q < kDftRows; ++q)
         if (q < rows) Y[(long long)(p0 + q) * ncols + c] = acc[q] * scale;
@@ -312,7 +312,7 @@ __global__ void __launch_bounds__(256) k_apply(LevelView v, const double* __rest
         return;
     }
     const Coef c = coef_at(v, i, k, lam[p]);
-    out[o] = apply_row(u[o], u[o - 1], u[o + 1], u[o - v.pitch], u[o + v.pitch], c) * inv_s[i];
+    out[o] = apply_row(u[o], u[o - 1], u[o + 1], u[o - v.pitch], u[o + v.pitch], c) * inv_s[(long long)k * v.pitch + i];
 }
 
 // Dirichlet ring of the fine-level iterate(s): plane 0 holds the face values
@@ -371,9 +371,9 @@ dim3 grid_interior(const LevelView& v, int nt, int xdiv = 1) {
 }  // namespace
 
 hipError_t launch_dft(const double* M, const double* X, double* Y, int n, long long ncols,
-                      const double* colscale, int nr, hipStream_t s) {
+                      const double* colscale, hipStream_t s) {
     dim3 grid((unsigned)((ncols + 255) / 256), (n + kDftRows - 1) / kDftRows);
-    k_dft<<<grid, 256, 0, s>>>(M, X, Y, n, ncols, colscale, nr);
+    k_dft<<<grid, 256, 0, s>>>(M, X, Y, n, ncols, colscale);
     return hipGetLastError();
 }
 

@@ -58,8 +58,8 @@ __device__ __forceinline__ double node_diag(const LevelView& v, int i, int k, do
 // X[q][y][x][0..3] from the plane values v of pair q (interior node k = y + 1,
 // i = x + 1), with the pair scale sc[q].
 __global__ void k_net_input(LevelView v, const double* __restrict__ lam, const double* __restrict__ planes,
-                            const float* __restrict__ sc, float* __restrict__ X, int nt, double r_in,
-                            double dr, double width) {
+                            const float* __restrict__ sc, float* __restrict__ X, int nt,
+                            const double* __restrict__ r0, double width) {
     const int q = blockIdx.y;
     const int H = v.nz - 2, W = v.nr - 2;
     const long long n = (long long)H * W;
@@ -76,7 +76,7 @@ __global__ void k_net_input(LevelView v, const double* __restrict__ lam, const d
     float* out = X + ((long long)q * n + idx) * 4;
     out[0] = (float)planes[(long long)q * v.pstride + o] * inv;
     out[1] = ps >= 0 ? (float)planes[(long long)ps * v.pstride + o] * inv : 0.f;
-    out[2] = (float)((r_in + i * dr - r_in) / width);
+    out[2] = (float)((r0[i] - r0[0]) / width);
     out[3] = (float)(l * mu / D);
 }
 
@@ -115,7 +115,7 @@ __global__ void k_pair_scale(const double* __restrict__ norms, float* __restrict
 __global__ void k_patches(LevelView v, const double* __restrict__ lam, const double* __restrict__ r,
                           const double* __restrict__ e, const int* __restrict__ pos,
                           const float* __restrict__ sc, float* __restrict__ X, float* __restrict__ T, int nt,
-                          double r_in, double dr, double width) {
+                          const double* __restrict__ r0, double width) {
     const int j = blockIdx.y;
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= kPatch * kPatch) return;
@@ -132,7 +132,7 @@ __global__ void k_patches(LevelView v, const double* __restrict__ lam, const dou
     float* to = T + ((long long)j * kPatch * kPatch + t) * 2;
     xo[0] = (float)(r[(long long)q * v.pstride + o] * inv);
     xo[1] = ps >= 0 ? (float)(r[(long long)ps * v.pstride + o] * inv) : 0.f;
-    xo[2] = (float)((r_in + i * dr - r_in) / width);
+    xo[2] = (float)((r0[i] - r0[0]) / width);
     xo[3] = (float)(l * mu / D);
     to[0] = (float)(e[(long long)q * v.pstride + o] * D * inv);
     to[1] = ps >= 0 ? (float)(e[(long long)ps * v.pstride + o] * D * inv) : 0.f;
@@ -212,7 +212,9 @@ int net_pairs(int nt) { return nt / 2 + 1; }
 
 hipError_t krylov_reserve(cylpoisson_plan* p, int m) {
     const size_t bytes = (size_t)p->nt * p->dl[0].v.pstride * sizeof(double);
-    while ((int)p->kv.size() < 2 * m + 1) {
+    // m + 1 Arnoldi vectors, m preconditioned ones, one ping-pong buffer for
+    // the V-cycle preconditioner
+    while ((int)p->kv.size() < 2 * m + 2) {
         double* ptr = nullptr;
         hipError_t e = hipMalloc(&ptr, bytes);
         if (e != hipSuccess) return e;
@@ -278,9 +280,29 @@ hipError_t plane_lincomb(cylpoisson_plan* p, double* dst, double alpha, const do
 }
 
 // z = M(v): the network on every cos/sin pair (or, without a network or with
-// the option "krylov_precond" = 0, the identity).
+// the option "krylov_precond" = 0, the identity; 2: four SOR sweeps; 3: one
+// V-cycle).
 hipError_t learned_precond(cylpoisson_plan* p, const double* v, double* z, hipStream_t s) {
     const LevelView& lv = p->dl[0].v;
+    if (p->opt.krylov_precond == 3) {
+        // one V-cycle on A z = v from z = 0; the level-0 iterate, its ping-pong
+        // buffer and right-hand side are lent to z, a spare Krylov vector and v
+        // (all with zero rings) and restored afterwards
+        DeviceLevel& L = p->dl[0];
+        double* const u = L.u;
+        double* const u2 = L.u2;
+        double* const f = L.f;
+        hipError_t e = plane_lincomb(p, z, 0.0, nullptr, nullptr, 0, s);
+        L.u = z;
+        L.u2 = p->kv[2 * p->opt.krylov_restart + 1];
+        L.f = const_cast<double*>(v);  // read only by the V-cycle
+        if (e == hipSuccess) e = vcycle_from_zero(p, s);
+        ++p->stats.cycles;
+        L.u = u;
+        L.u2 = u2;
+        L.f = f;
+        return e;
+    }
     if (p->opt.krylov_precond == 2) {
         // the map the network is trained to imitate: four red-black SOR sweeps
         // on A z = v from z = 0 (z's ring is zero)
@@ -316,7 +338,7 @@ hipError_t learned_precond(cylpoisson_plan* p, const double* v, double* z, hipSt
     k_pair_scale<<<(npairs + 63) / 64, 64, 0, s>>>(p->d_norms + (size_t)(kNormSlots - 2) * p->nt, p->net_sc,
                                                   npairs, p->nt, (double)H * W);
     const dim3 g((unsigned)(((long long)H * W + 255) / 256), npairs);
-    k_net_input<<<g, 256, 0, s>>>(lv, p->d_lam, v, p->net_sc, p->net_x, p->nt, p->r_in, p->dr,
+    k_net_input<<<g, 256, 0, s>>>(lv, p->d_lam, v, p->net_sc, p->net_x, p->nt, p->d_r0,
                                   p->r_out - p->r_in);
     e = hipGetLastError();
     if (e == hipSuccess) e = net_forward(n, p->net_x, p->net_y, npairs, H, W, s);
@@ -529,7 +551,7 @@ int cylpoisson_nn_collect(cylpoisson_plan* p, cylpoisson_nn* nn, const double* r
                 const size_t px = (size_t)kPatch * kPatch;
                 k_patches<<<dim3((unsigned)((px + 255) / 256), patches_per_cycle), 256, 0, s>>>(
                     v, p->d_lam, L.r, phi, d_pos, d_sc, n.px + n.patches * px * 4, n.pt + n.patches * px * 2,
-                    p->nt, p->r_in, p->dr, p->r_out - p->r_in);
+                    p->nt, p->d_r0, p->r_out - p->r_in);
                 e = hipGetLastError();
             }
             // the host rewrites pos next cycle: wait for the copy

@@ -38,37 +38,73 @@ std::vector<int> coarsen_positions(const std::vector<int>& pos) {
     return out;
 }
 
-// Finite-volume tables of one direction from integer node positions (in units
-// of the fine spacing h).  Vertex-centred control volume of node i: faces
-// half-way to the neighbours (App. A, Eq. cell_geometry_appendix with the
-// node as centre).
+// Level-0 nodes of one direction.  Uniform: x_i = origin + i h, and every
+// distance is an integer number of spacings (so the tables of a uniform mesh
+// are exact multiples of h).  General: explicit coordinates, with the faces of
+// each interior node's control volume on level 0.
+struct AxisMesh {
+    bool uniform = true;
+    double origin = 0.0, h = 1.0;
+    const std::vector<double>* x = nullptr;
+    const std::vector<double>* lo = nullptr;
+    const std::vector<double>* hi = nullptr;
+    double at(int i) const { return uniform ? origin + i * h : (*x)[i]; }
+    double dist(int a, int b) const { return uniform ? (b - a) * h : (*x)[b] - (*x)[a]; }
+    // a length whose ratios are those of dist (index differences when uniform)
+    double span(int a, int b) const { return uniform ? (double)(b - a) : (*x)[b] - (*x)[a]; }
+};
+
+// Finite-volume tables of one direction on the level whose nodes are the
+// level-0 nodes `pos` (App. A, Eqs. cell_geometry_appendix and
+// interior_face_conductances).  The control volume of a node has the given
+// faces on a general level 0 and faces half-way to its neighbours otherwise
+// (the vertex-centred rediscretisation of every coarser level).
 struct Axis {
     std::vector<double> x;         // coordinates
     std::vector<double> hm, hp;    // distances to the lower / upper neighbour
+    std::vector<double> lo, hi;    // control-volume faces
     std::vector<double> width;     // control-volume width
 };
 
-Axis axis_geometry(const std::vector<int>& pos, double origin, double h) {
+Axis axis_geometry(const std::vector<int>& pos, const AxisMesh& m, bool level0) {
     const int n = (int)pos.size();
     Axis a;
     a.x.resize(n);
     a.hm.assign(n, 0.0);
     a.hp.assign(n, 0.0);
+    a.lo.assign(n, 0.0);
+    a.hi.assign(n, 0.0);
     a.width.assign(n, 0.0);
-    for (int i = 0; i < n; ++i) a.x[i] = origin + pos[i] * h;
+    for (int i = 0; i < n; ++i) a.x[i] = m.at(pos[i]);
     for (int i = 1; i + 1 < n; ++i) {
-        a.hm[i] = (pos[i] - pos[i - 1]) * h;
-        a.hp[i] = (pos[i + 1] - pos[i]) * h;
-        a.width[i] = 0.5 * (a.hm[i] + a.hp[i]);
+        a.hm[i] = m.dist(pos[i - 1], pos[i]);
+        a.hp[i] = m.dist(pos[i], pos[i + 1]);
+        if (level0 && !m.uniform) {
+            a.lo[i] = (*m.lo)[pos[i]];
+            a.hi[i] = (*m.hi)[pos[i]];
+            a.width[i] = a.hi[i] - a.lo[i];
+        } else {
+            a.lo[i] = a.x[i] - 0.5 * a.hm[i];
+            a.hi[i] = a.x[i] + 0.5 * a.hp[i];
+            a.width[i] = 0.5 * (a.hm[i] + a.hp[i]);
+        }
     }
     return a;
 }
 
-// 1-D linear interpolation between node sets pf (fine) and pc (coarse), and
-// its transpose, as described by Transfer1D.
-void transfer_tables(const std::vector<int>& pf, const std::vector<int>& pc, std::vector<int>& pidx,
-                     std::vector<double>& pwl, std::vector<double>& pwr, std::vector<int>& cidx,
-                     std::vector<double>& rwm, std::vector<double>& rwp) {
+// Typical node spacing of a level: the median distance between neighbours.
+double median_gap(const std::vector<int>& pos, const AxisMesh& m) {
+    std::vector<double> g;
+    for (size_t i = 1; i < pos.size(); ++i) g.push_back(m.dist(pos[i - 1], pos[i]));
+    std::nth_element(g.begin(), g.begin() + g.size() / 2, g.end());
+    return g[g.size() / 2];
+}
+
+// 1-D linear interpolation (in the node coordinates) between node sets pf
+// (fine) and pc (coarse), and its transpose, as described by Transfer1D.
+void transfer_tables(const std::vector<int>& pf, const std::vector<int>& pc, const AxisMesh& m,
+                     std::vector<int>& pidx, std::vector<double>& pwl, std::vector<double>& pwr,
+                     std::vector<int>& cidx, std::vector<double>& rwm, std::vector<double>& rwp) {
     const int nf = (int)pf.size(), nc = (int)pc.size();
     pidx.assign(nf, 0);
     pwl.assign(nf, 0.0);
@@ -81,10 +117,10 @@ void transfer_tables(const std::vector<int>& pf, const std::vector<int>& pc, std
             pwl[i] = 1.0;
             pwr[i] = 0.0;
         } else {
-            const double span = (double)(pc[I + 1] - pc[I]);
+            const double span = m.span(pc[I], pc[I + 1]);
             pidx[i] = I;
-            pwl[i] = (double)(pc[I + 1] - pf[i]) / span;
-            pwr[i] = (double)(pf[i] - pc[I]) / span;
+            pwl[i] = m.span(pf[i], pc[I + 1]) / span;
+            pwr[i] = m.span(pc[I], pf[i]) / span;
         }
     }
     cidx.assign(nc, 0);
@@ -191,8 +227,31 @@ void free_plan(cylpoisson_plan* p) {
     p->h_slot_partial = nullptr;
 }
 
+AxisMesh radial_mesh(const cylpoisson_plan* p) {
+    AxisMesh m;
+    m.uniform = p->uniform;
+    m.origin = p->r_in;
+    m.h = p->dr;
+    m.x = &p->xr;
+    m.lo = &p->r_lo;
+    m.hi = &p->r_hi;
+    return m;
+}
+
+AxisMesh axial_mesh(const cylpoisson_plan* p) {
+    AxisMesh m;
+    m.uniform = p->uniform;
+    m.origin = 0.0;
+    m.h = p->dz;
+    m.x = &p->xz;
+    m.lo = &p->z_lo;
+    m.hi = &p->z_hi;
+    return m;
+}
+
 // Build the level hierarchy on the host.
 void build_levels(cylpoisson_plan* p) {
+    const AxisMesh mr = radial_mesh(p), mz = axial_mesh(p);
     std::vector<int> pr(p->nr), pz(p->nz);
     for (int i = 0; i < p->nr; ++i) pr[i] = i;
     for (int k = 0; k < p->nz; ++k) pz[k] = k;
@@ -205,8 +264,8 @@ void build_levels(cylpoisson_plan* p) {
         if (interior <= kCoarseMax || (!cr && !cz)) break;
         // Semicoarsening: a point smoother only smooths the error along the
         // direction of the stronger coupling (the smaller spacing), so while
-        // the cells are more than 2:1 only that direction is coarsened.
-        const double hr = p->dr * (r[1] - r[0]), hz = p->dz * (z[1] - z[0]);
+        // the typical cells are more than 2:1 only that direction is coarsened.
+        const double hr = median_gap(r, mr), hz = median_gap(z, mz);
         if (cr && cz) {
             if (hz > 2.0 * hr) cz = false;
             else if (hr > 2.0 * hz) cr = false;
@@ -221,8 +280,8 @@ void build_levels(cylpoisson_plan* p) {
         H.nr = (int)lr[l].size();
         H.nz = (int)lz[l].size();
         H.pitch = H.nr;
-        const Axis ar = axis_geometry(lr[l], p->r_in, p->dr);
-        const Axis az = axis_geometry(lz[l], 0.0, p->dz);
+        const Axis ar = axis_geometry(lr[l], mr, l == 0);
+        const Axis az = axis_geometry(lz[l], mz, l == 0);
         H.r = ar.x;
         H.z = az.x;
         H.rw.assign(H.nr, 0.0);
@@ -231,10 +290,8 @@ void build_levels(cylpoisson_plan* p) {
         H.rm.assign(H.nr, 0.0);
         for (int i = 1; i + 1 < H.nr; ++i) {
             const double rc = ar.x[i];
-            const double rlo = rc - 0.5 * ar.hm[i];
-            const double rhi = rc + 0.5 * ar.hp[i];
-            H.rw[i] = rlo / ar.hm[i];
-            H.re[i] = rhi / ar.hp[i];
+            H.rw[i] = ar.lo[i] / ar.hm[i];
+            H.re[i] = ar.hi[i] / ar.hp[i];
             H.rb[i] = rc * ar.width[i];
             H.rm[i] = ar.width[i] / rc;
         }
@@ -247,8 +304,8 @@ void build_levels(cylpoisson_plan* p) {
             H.zn[k] = 1.0 / az.hp[k];
         }
         if (l + 1 < nl) {
-            transfer_tables(lr[l], lr[l + 1], H.pidx_r, H.pwl_r, H.pwr_r, H.cidx_r, H.rwm_r, H.rwp_r);
-            transfer_tables(lz[l], lz[l + 1], H.pidx_z, H.pwl_z, H.pwr_z, H.cidx_z, H.rwm_z, H.rwp_z);
+            transfer_tables(lr[l], lr[l + 1], mr, H.pidx_r, H.pwl_r, H.pwr_r, H.cidx_r, H.rwm_r, H.rwp_r);
+            transfer_tables(lz[l], lz[l + 1], mz, H.pidx_z, H.pwl_z, H.pwr_z, H.cidx_z, H.rwm_z, H.rwp_z);
         }
     }
 }
@@ -368,63 +425,15 @@ int alloc_mixed(cylpoisson_plan* p) {
 
 }  // namespace cp
 
-extern "C" {
+namespace cp {
+namespace {
 
-const char* cylpoisson_last_error(void) { return cp::last_error(); }
-
-const char* cylpoisson_status_string(int status) {
-    switch (status) {
-        case CYLPOISSON_OK: return "ok";
-        case CYLPOISSON_NOT_CONVERGED: return "not converged";
-        case CYLPOISSON_EINVAL: return "invalid argument";
-        case CYLPOISSON_ENOMEM: return "out of memory";
-        case CYLPOISSON_EHIP: return "HIP runtime error";
-        case CYLPOISSON_ENONFINITE: return "non-finite input";
-        case CYLPOISSON_EDEVICE: return "pointer is not device memory of the plan's device";
-        default: return "unknown status";
-    }
-}
-
-cylpoisson_plan* cylpoisson_plan_create(int Nr, int Ntheta, int Nz, double r_in, double r_out,
-                                        double dz, const cylpoisson_bc* bc) {
-    set_error("%s", "");
-    if (Nr < 3 || Nz < 3 || Ntheta < 1) {
-        set_error("need Nr >= 3, Nz >= 3 and Ntheta >= 1 (got %d, %d, %d)", Nr, Nz, Ntheta);
-        return nullptr;
-    }
-    if (!(std::isfinite(r_in) && std::isfinite(r_out) && std::isfinite(dz)) || !(r_in > 0.0) ||
-        !(r_out > r_in) || !(dz > 0.0)) {
-        set_error("need finite 0 < r_in < r_out and dz > 0");
-        return nullptr;
-    }
-    if (!bc) {
-        set_error("bc must not be NULL");
-        return nullptr;
-    }
-    if (!(std::isfinite(bc->phi_r_in) && std::isfinite(bc->phi_r_out) && std::isfinite(bc->phi_z0) &&
-          std::isfinite(bc->phi_zL))) {
-        set_error("boundary values must be finite");
-        return nullptr;
-    }
+// Everything after the level-0 mesh is set: device, plane eigenvalues,
+// hierarchy, coarsest inverses, tables and device workspace.  Takes ownership
+// of p (deleted on failure).
+cylpoisson_plan* build_plan(cylpoisson_plan* p) {
+    const int Nr = p->nr, Ntheta = p->nt, Nz = p->nz;
     const long long nodes = (long long)Nr * Ntheta * Nz;
-    if (nodes > (1LL << 40) || Ntheta > 65536) {
-        set_error("grid too large (%lld nodes)", nodes);
-        return nullptr;
-    }
-    cylpoisson_plan* p = new (std::nothrow) cylpoisson_plan();
-    if (!p) {
-        set_error("host allocation failed");
-        return nullptr;
-    }
-    p->nr = Nr;
-    p->nt = Ntheta;
-    p->nz = Nz;
-    p->r_in = r_in;
-    p->r_out = r_out;
-    p->dz = dz;
-    p->dr = (r_out - r_in) / (Nr - 1);
-    p->dtheta = 6.283185307179586476925286766559 / Ntheta;
-    p->bc = *bc;
     if (hipGetDevice(&p->device) != hipSuccess) {
         set_error("no HIP device available");
         delete p;
@@ -483,20 +492,25 @@ cylpoisson_plan* cylpoisson_plan_create(int Nr, int Ntheta, int Nz, double r_in,
             CP_TRY(hipMemset(D.f, 0, n * sizeof(double)));
             CP_TRY(hipMemset(D.r, 0, n * sizeof(double)));
             {
-                // The fused passes use one set of axial coefficients for every
-                // row below spec_lo (the first row whose coefficients differ from
-                // those of row 1; coarsening only makes the last intervals
-                // irregular) and the exact per-row tables from there on.
-                D.spec_lo = H.nz - 1;
-                if (H.nz >= 3) {
-                    D.zc0 = H.zc[1];
-                    D.zs0 = H.zs[1];
-                    D.zn0 = H.zn[1];
-                    for (int k = 1; k + 1 < H.nz; ++k)
-                        if (!(H.zc[k] == D.zc0 && H.zs[k] == D.zs0 && H.zn[k] == D.zn0)) {
-                            D.spec_lo = k;
-                            break;
-                        }
+                // The fused passes use one set of axial coefficients for the
+                // longest run of rows that share them (all but the last rows of
+                // a uniform vertex-centred level, all but the rows next to the
+                // faces of a cell-centred one) and the exact per-row tables
+                // elsewhere.
+                D.reg_lo = D.reg_hi = 1;
+                for (int k = 1; k + 1 < H.nz;) {
+                    int e = k + 1;
+                    while (e + 1 < H.nz && H.zc[e] == H.zc[k] && H.zs[e] == H.zs[k] && H.zn[e] == H.zn[k]) ++e;
+                    if (e - k > D.reg_hi - D.reg_lo) {
+                        D.reg_lo = k;
+                        D.reg_hi = e;
+                    }
+                    k = e;
+                }
+                if (D.reg_hi > D.reg_lo) {
+                    D.zc0 = H.zc[D.reg_lo];
+                    D.zs0 = H.zs[D.reg_lo];
+                    D.zn0 = H.zn[D.reg_lo];
                 }
             }
             double *rw, *re, *rb, *rm, *zc, *zs, *zn;
@@ -582,15 +596,20 @@ cylpoisson_plan* cylpoisson_plan_create(int Nr, int Ntheta, int Nz, double r_in,
             CP_TRY(upload(p, &p->d_tw, tw));
         }
         CP_TRY(upload(p, &p->d_lam, p->lam));
-        std::vector<double> s(Nr, 0.0), inv_s(Nr, 0.0);
-        const HostLevel& H0 = p->hl[0];
-        for (int i = 1; i + 1 < Nr; ++i) {
-            // s_q = r_i dr_i dz_k / eps0 (Eq. mode_rhs), uniform fine spacing
-            s[i] = H0.r[i] * p->dr * p->dz / kEps0;
-            inv_s[i] = 1.0 / s[i];
+        {
+            // s_q = r_i dr_i dz_k / eps0 (Eq. mode_rhs) = rb_i zc_k / eps0 on level 0
+            const HostLevel& H0 = p->hl[0];
+            std::vector<double> s((size_t)Nz * Nr, 0.0), inv_s((size_t)Nz * Nr, 0.0);
+            for (int k = 1; k + 1 < Nz; ++k)
+                for (int i = 1; i + 1 < Nr; ++i) {
+                    const size_t q = (size_t)k * Nr + i;
+                    s[q] = H0.rb[i] * H0.zc[k] / kEps0;
+                    inv_s[q] = 1.0 / s[q];
+                }
+            CP_TRY(upload(p, &p->d_s, s));
+            CP_TRY(upload(p, &p->d_inv_s, inv_s));
+            CP_TRY(upload(p, &p->d_r0, H0.r));
         }
-        CP_TRY(upload(p, &p->d_s, s));
-        CP_TRY(upload(p, &p->d_inv_s, inv_s));
         CP_TRY(upload(p, &p->d_cinv, cinv));
         CP_TRY(dev_alloc(p, &p->d_partial, (size_t)Ntheta * kMaxPartial));
         CP_TRY(dev_alloc(p, &p->d_norms, (size_t)kNormSlots * Ntheta));
@@ -601,7 +620,7 @@ cylpoisson_plan* cylpoisson_plan_create(int Nr, int Ntheta, int Nz, double r_in,
         CP_TRY(dev_alloc(p, &p->d_tmp, (size_t)nodes));
         CP_TRY(hipHostMalloc((void**)&p->h_norms, (size_t)kNormSlots * Ntheta * sizeof(double),
                              hipHostMallocDefault));
-        CP_TRY(dev_alloc(p, &p->d_mask, (size_t)Ntheta));
+        CP_TRY(upload(p, &p->d_mask, std::vector<int>((size_t)Ntheta, 1)));
         CP_TRY(hipHostMalloc((void**)&p->h_mask, (size_t)Ntheta * sizeof(int), hipHostMallocDefault));
         CP_TRY(hipDeviceSynchronize());
     }
@@ -614,6 +633,151 @@ fail:
     delete p;
     (void)hipGetLastError();
     return nullptr;
+}
+
+// Checks shared by the constructors: sizes, boundary values.
+bool check_grid(int Nr, int Ntheta, int Nz, const cylpoisson_bc* bc) {
+    if (Nr < 3 || Nz < 3 || Ntheta < 1) {
+        set_error("need Nr >= 3, Nz >= 3 and Ntheta >= 1 (got %d, %d, %d)", Nr, Nz, Ntheta);
+        return false;
+    }
+    if (!bc) {
+        set_error("bc must not be NULL");
+        return false;
+    }
+    if (!(std::isfinite(bc->phi_r_in) && std::isfinite(bc->phi_r_out) && std::isfinite(bc->phi_z0) &&
+          std::isfinite(bc->phi_zL))) {
+        set_error("boundary values must be finite");
+        return false;
+    }
+    const long long nodes = (long long)Nr * Ntheta * Nz;
+    if (nodes > (1LL << 40) || Ntheta > 65536) {
+        set_error("grid too large (%lld nodes)", nodes);
+        return false;
+    }
+    return true;
+}
+
+cylpoisson_plan* new_plan(int Nr, int Ntheta, int Nz, const cylpoisson_bc* bc) {
+    cylpoisson_plan* p = new (std::nothrow) cylpoisson_plan();
+    if (!p) {
+        set_error("host allocation failed");
+        return nullptr;
+    }
+    p->nr = Nr;
+    p->nt = Ntheta;
+    p->nz = Nz;
+    p->dtheta = 6.283185307179586476925286766559 / Ntheta;
+    p->bc = *bc;
+    return p;
+}
+
+// Nodes and control-volume faces of one direction of an explicit mesh.
+// Vertex layout: `in` holds the n node coordinates, faces half-way between
+// nodes.  Cell layout (App. A): `in` holds the n - 1 faces of n - 2 cells; the
+// nodes are the outer faces (Dirichlet) and the cell centres.
+bool mesh_axis(const double* in, int n, int layout, bool positive, const char* name, std::vector<double>& x,
+               std::vector<double>& lo, std::vector<double>& hi) {
+    const int m = layout == CYLPOISSON_CELL ? n - 1 : n;
+    for (int i = 0; i < m; ++i)
+        if (!std::isfinite(in[i]) || (i > 0 && !(in[i] > in[i - 1]))) {
+            set_error("%s must hold %d finite, strictly increasing values", name, m);
+            return false;
+        }
+    if (positive && !(in[0] > 0.0)) {
+        set_error("%s must start above 0 (the axis is not part of the annulus)", name);
+        return false;
+    }
+    x.assign(n, 0.0);
+    lo.assign(n, 0.0);
+    hi.assign(n, 0.0);
+    if (layout == CYLPOISSON_CELL) {
+        x[0] = in[0];
+        x[n - 1] = in[n - 2];
+        for (int i = 1; i + 1 < n; ++i) {
+            x[i] = 0.5 * (in[i - 1] + in[i]);
+            lo[i] = in[i - 1];
+            hi[i] = in[i];
+        }
+    } else {
+        for (int i = 0; i < n; ++i) x[i] = in[i];
+        for (int i = 1; i + 1 < n; ++i) {
+            lo[i] = 0.5 * (x[i - 1] + x[i]);
+            hi[i] = 0.5 * (x[i] + x[i + 1]);
+        }
+    }
+    for (int i = 1; i < n; ++i)
+        if (!(x[i] > x[i - 1]) || (i + 1 < n && !(lo[i] < x[i] && x[i] < hi[i]))) {
+            set_error("%s: nodes and faces must stay strictly increasing after rounding", name);
+            return false;
+        }
+    return true;
+}
+
+}  // namespace
+}  // namespace cp
+
+extern "C" {
+
+const char* cylpoisson_last_error(void) { return cp::last_error(); }
+
+const char* cylpoisson_status_string(int status) {
+    switch (status) {
+        case CYLPOISSON_OK: return "ok";
+        case CYLPOISSON_NOT_CONVERGED: return "not converged";
+        case CYLPOISSON_EINVAL: return "invalid argument";
+        case CYLPOISSON_ENOMEM: return "out of memory";
+        case CYLPOISSON_EHIP: return "HIP runtime error";
+        case CYLPOISSON_ENONFINITE: return "non-finite input";
+        case CYLPOISSON_EDEVICE: return "pointer is not device memory of the plan's device";
+        default: return "unknown status";
+    }
+}
+
+cylpoisson_plan* cylpoisson_plan_create(int Nr, int Ntheta, int Nz, double r_in, double r_out,
+                                        double dz, const cylpoisson_bc* bc) {
+    set_error("%s", "");
+    if (!check_grid(Nr, Ntheta, Nz, bc)) return nullptr;
+    if (!(std::isfinite(r_in) && std::isfinite(r_out) && std::isfinite(dz)) || !(r_in > 0.0) ||
+        !(r_out > r_in) || !(dz > 0.0)) {
+        set_error("need finite 0 < r_in < r_out and dz > 0");
+        return nullptr;
+    }
+    cylpoisson_plan* p = new_plan(Nr, Ntheta, Nz, bc);
+    if (!p) return nullptr;
+    p->uniform = true;
+    p->layout = CYLPOISSON_VERTEX;
+    p->r_in = r_in;
+    p->r_out = r_out;
+    p->dz = dz;
+    p->dr = (r_out - r_in) / (Nr - 1);
+    return build_plan(p);
+}
+
+cylpoisson_plan* cylpoisson_plan_create_mesh(int Nr, int Ntheta, int Nz, const double* r, const double* z,
+                                             int layout, const cylpoisson_bc* bc) {
+    set_error("%s", "");
+    if (!check_grid(Nr, Ntheta, Nz, bc)) return nullptr;
+    if (!r || !z) {
+        set_error("r and z must not be NULL");
+        return nullptr;
+    }
+    if (layout != CYLPOISSON_VERTEX && layout != CYLPOISSON_CELL) {
+        set_error("layout must be CYLPOISSON_VERTEX (0) or CYLPOISSON_CELL (1), got %d", layout);
+        return nullptr;
+    }
+    cylpoisson_plan* p = new_plan(Nr, Ntheta, Nz, bc);
+    if (!p) return nullptr;
+    p->uniform = false;
+    p->layout = layout;
+    if (!mesh_axis(r, Nr, layout, true, "r", p->xr, p->r_lo, p->r_hi) ||
+        !mesh_axis(z, Nz, layout, false, "z", p->xz, p->z_lo, p->z_hi)) {
+        delete p;
+        return nullptr;
+    }
+    p->r_in = p->xr.front();
+    p->r_out = p->xr.back();
+    return build_plan(p);
 }
 
 void cylpoisson_plan_destroy(cylpoisson_plan* plan) {
@@ -658,7 +822,7 @@ int cylpoisson_plan_set_option(cylpoisson_plan* plan, const char* key, double va
     if (!std::strcmp(key, "masks")) return int_in(0, 1, &plan->opt.masks);
     if (!std::strcmp(key, "graph")) return int_in(0, 1, &plan->opt.graph);
     if (!std::strcmp(key, "krylov")) return int_in(0, 1, &plan->opt.krylov);
-    if (!std::strcmp(key, "krylov_precond")) return int_in(0, 2, &plan->opt.krylov_precond);
+    if (!std::strcmp(key, "krylov_precond")) return int_in(0, 3, &plan->opt.krylov_precond);
     if (!std::strcmp(key, "krylov_restart")) return int_in(1, 16, &plan->opt.krylov_restart);
     if (!std::strcmp(key, "krylov_max")) return int_in(1, 100000, &plan->opt.krylov_max);
     if (!std::strcmp(key, "fallback")) return int_in(0, 1, &plan->opt.fallback);
@@ -741,6 +905,13 @@ int cylpoisson_get_info(const cylpoisson_plan* plan, cylpoisson_info* out) {
     out->bottom_level = plan->bottom_level;
     out->workspace_bytes = plan->workspace_bytes;
     out->device = plan->device;
+    for (int l = 0; l + 1 < out->levels; ++l) {
+        if (l > 0 && l == plan->bottom_level && plan->opt.bottom && plan->opt.fused) break;
+        if (!fused_supported(plan, l)) break;
+        ++out->fused_levels;
+    }
+    out->layout = plan->layout;
+    out->uniform = plan->uniform ? 1 : 0;
     return CYLPOISSON_OK;
 }
 

@@ -305,14 +305,14 @@ hipError_t join_groups(cylpoisson_plan* p, int G, hipStream_t s) {
 }
 
 // Azimuthal transform of node/plane arrays: register FFT where supported,
-// dense DFT product otherwise.  colscale (forward only) multiplies column c by
-// colscale[c % Nr].
+// dense DFT product otherwise.  colscale (forward only) multiplies column
+// c = k Nr + i by colscale[c] (a [Nz][Nr] table).
 hipError_t transform(cylpoisson_plan* p, bool inverse, const double* in, double* out,
                      const double* colscale, hipStream_t s) {
     const long long ncols = (long long)p->nz * p->nr;
     if (p->opt.fft && fft_supported(p->nt))
-        return launch_fft(inverse, p->nt, in, out, ncols, colscale, p->nr, p->d_tw, s);
-    return launch_dft(inverse ? p->d_G : p->d_F, in, out, p->nt, ncols, colscale, p->nr, s);
+        return launch_fft(inverse, p->nt, in, out, ncols, colscale, p->d_tw, s);
+    return launch_dft(inverse ? p->d_G : p->d_F, in, out, p->nt, ncols, colscale, s);
 }
 
 void reset_stats(cylpoisson_plan* p) {
@@ -454,6 +454,11 @@ int run_cycles(cylpoisson_plan* p, double tol, hipStream_t s, bool ring_only, bo
     const int G = groups_active(p);
     const bool graphs = graphs_active(p, G);
     const bool masks = masks_active(p);
+    struct MaskScope {
+        cylpoisson_plan* p;
+        ~MaskScope() { p->mask_live = false; }
+    } mask_scope{p};
+    p->mask_live = masks;
     const double budget = tol * tol * b2 / nt;
     std::vector<double> frozen(nt, -1.0);  // last norm of a frozen plane, -1 while active
     if (masks) {
@@ -774,8 +779,9 @@ int fgmres_restart(cylpoisson_plan* p, double tol2, int maxit, double* res, hipS
 // The learned solve: one plain V-cycle from zero measures the V-cycle's
 // contraction; one FGMRES restart with the network measures the network's
 // contraction per step; the faster one finishes the solve (V-cycles from the
-// current iterate when the network is worse and "fallback" is set).  u holds
-// the Dirichlet rings and a zero interior on entry.
+// current iterate when the network is worse and "fallback" is set).  With a
+// V-cycle as the preconditioner FGMRES runs from the zero iterate unjudged.
+// u holds the Dirichlet rings and a zero interior on entry.
 int run_learned(cylpoisson_plan* p, double tol, hipStream_t s) {
     cylpoisson_stats& st = p->stats;
     const int nt = p->nt;
@@ -792,17 +798,23 @@ int run_learned(cylpoisson_plan* p, double tol, hipStream_t s) {
     st.initial_residual_norm = std::sqrt(b2);
     if (b2 == 0.0) return st.status = CYLPOISSON_OK;
     const double tol2 = tol * tol * b2;
-    // the plain V-cycle's contraction from the zero iterate
-    CP_HIP(vcycle_step(p, s));
-    CP_HIP(residual_norms(p, 1, s));
-    CP_HIP(hipMemcpyAsync(p->h_norms + nt, p->d_norms + nt, nt * sizeof(double), hipMemcpyDeviceToHost, s));
-    CP_HIP(hipStreamSynchronize(s));
-    const double rel1 = std::sqrt(weighted(p, p->h_norms + nt) / b2);
-    st.vcycle_rate = rel1;
-    st.cycles = 1;
-    st.rel_residual = rel1;
-    if (rel1 <= tol) return st.status = CYLPOISSON_OK;
-    // the network's contraction per FGMRES step over one restart
+    // A V-cycle preconditioner is a fixed linear map, so the plain V-cycle
+    // iterates lie in the space FGMRES minimises over: no judging needed.
+    const bool judge = p->opt.krylov_precond != 3;
+    double rel1 = 1.0;
+    if (judge) {
+        // the plain V-cycle's contraction from the zero iterate
+        CP_HIP(vcycle_step(p, s));
+        CP_HIP(residual_norms(p, 1, s));
+        CP_HIP(hipMemcpyAsync(p->h_norms + nt, p->d_norms + nt, nt * sizeof(double), hipMemcpyDeviceToHost, s));
+        CP_HIP(hipStreamSynchronize(s));
+        rel1 = std::sqrt(weighted(p, p->h_norms + nt) / b2);
+        st.vcycle_rate = rel1;
+        st.cycles = 1;
+        st.rel_residual = rel1;
+        if (rel1 <= tol) return st.status = CYLPOISSON_OK;
+    }
+    // the preconditioner's contraction per FGMRES step over one restart
     int err = 0;
     double res = 0.0;
     int k = fgmres_restart(p, tol2, p->opt.krylov_max, &res, s, &err);
@@ -812,7 +824,7 @@ int run_learned(cylpoisson_plan* p, double tol, hipStream_t s) {
     st.learned_rate = k > 0 ? std::pow(rel / rel1, 1.0 / k) : 1.0;
     st.rel_residual = rel;
     if (rel <= tol) return st.status = CYLPOISSON_OK;
-    if (p->opt.fallback && st.learned_rate >= st.vcycle_rate) {
+    if (judge && p->opt.fallback && st.learned_rate >= st.vcycle_rate) {
         st.learned_fallback = 1;
         const int judged = st.krylov_iterations;
         const double vr = st.vcycle_rate, lr = st.learned_rate;
@@ -840,6 +852,8 @@ int run_learned(cylpoisson_plan* p, double tol, hipStream_t s) {
 }  // namespace
 
 hipError_t vcycle_step(cylpoisson_plan* p, hipStream_t s) { return vcycle(p, 0, s, false, -1, nullptr); }
+
+hipError_t vcycle_from_zero(cylpoisson_plan* p, hipStream_t s) { return vcycle(p, 0, s, true, -1, nullptr); }
 
 }  // namespace cp
 

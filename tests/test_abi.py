@@ -66,3 +66,33 @@ def test_null_plan_and_status_strings():
     for code in (P.OK, P.NOT_CONVERGED, P.EINVAL, P.ENOMEM, P.EHIP, P.ENONFINITE, P.EDEVICE):
         assert P.status_string(code) != "unknown status"
     assert P.status_string(42) == "unknown status"
+
+
+@pytest.mark.parametrize("r,z,layout,msg", [
+    ([0.02, 0.03, 0.03, 0.05], [0.0, 0.01, 0.02], P.VERTEX, "increasing"),   # repeated radius
+    ([0.0, 0.01, 0.02], [0.0, 0.01, 0.02], P.VERTEX, "above 0"),              # the axis
+    ([0.02, 0.03, 0.05], [0.0, float("nan"), 0.02], P.VERTEX, "finite"),
+    ([0.02, 0.03, 0.05], [0.02, 0.01, 0.0], P.VERTEX, "increasing"),          # decreasing z
+    ([0.02, 0.05], [0.0, 0.01], P.CELL, "increasing"),                        # wrong count (Python)
+])
+def test_plan_create_mesh_rejects_bad_meshes(r, z, layout, msg):
+    if layout == P.CELL:
+        with pytest.raises(ValueError):
+            P.plan_create_mesh(len(r), 2, len(z) + 1, r, z, layout)
+        return
+    with pytest.raises(P.CylPoissonError) as e:
+        P.plan_create_mesh(len(r), 2, len(z), r, z, layout)
+    assert e.value.status == P.EINVAL
+    assert msg in P.last_error()
+
+
+def test_plan_create_mesh_rejects_null_and_bad_layout():
+    lib = P.library()
+    bc = P.BC(0.0, 0.0, 0.0, 0.0)
+    arr = (ctypes.c_double * 3)(0.02, 0.03, 0.04)
+    assert not lib.cylpoisson_plan_create_mesh(3, 2, 3, None, arr, P.VERTEX, ctypes.byref(bc))
+    assert "NULL" in P.last_error()
+    assert not lib.cylpoisson_plan_create_mesh(3, 2, 3, arr, arr, 7, ctypes.byref(bc))
+    assert "layout" in P.last_error()
+    assert not lib.cylpoisson_plan_create_mesh(3, 2, 3, arr, arr, P.VERTEX, None)
+    assert "bc" in P.last_error()

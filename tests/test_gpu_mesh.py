@@ -1,0 +1,195 @@
+"""Explicit meshes (App. A): cell-centred finite volumes with half-cell
+Dirichlet faces, and vertex- or cell-centred grids with non-uniform r and z
+spacing, solved through the C ABI and compared with the oracle's direct mode
+solves (exact up to rounding) on the same seeded inputs."""
+import numpy as np
+import pytest
+import torch
+
+import workloads as W
+from oracle import fv, solvers
+
+from gpu_util import INTERIOR, dev, host, rel_l2, say
+
+pytestmark = pytest.mark.gpu
+
+EPS = np.finfo(np.float64).eps
+BC = (5.0, -3.0, 1.0, 300.0)
+ST = W.stretched_points
+
+# name -> (layout, r, z, ntheta); r/z are node coordinates (vertex) or cell faces (cell)
+CASES = {
+    # uniform cells, register FFT, several fused chunks per plane and a ragged last chunk
+    "cell_uniform": ("cell", np.linspace(0.02, 0.05, 97), np.linspace(0.0, 0.06, 131), 16),
+    # cells stretched towards the inner wall and the top face, dense DFT path
+    "cell_stretched": ("cell", ST(0.02, 0.05, 80, 1.015), ST(0.0, 0.06, 100, 0.985), 12),
+    # non-uniform vertex-centred nodes
+    "vertex_stretched": ("vertex", ST(0.02, 0.05, 71, 1.02), ST(0.0, 0.05, 90, 1.012), 16),
+    # few cells: the coarsest (direct) level is the whole plane
+    "cell_tiny": ("cell", ST(0.02, 0.05, 9, 1.1), ST(0.0, 0.02, 6, 1.0), 5),
+    # odd counts, one level coarsened in r only (cells about 3:1)
+    "cell_flat": ("cell", np.linspace(0.02, 0.05, 41), np.linspace(0.0, 0.12, 34), 6),
+}
+
+
+@pytest.fixture(scope="module")
+def P():
+    import paper_2609_07172_amd as P
+    P.library()
+    assert torch.cuda.is_available()
+    return P
+
+
+def layout_of(P, name):
+    return P.CELL if name == "cell" else P.VERTEX
+
+
+def oracle_grid(case):
+    layout, r, z, nt = case
+    return fv.Grid.cell_centred(r, z, nt) if layout == "cell" else fv.Grid.vertex(r, z, nt)
+
+
+def plan_for(P, case, **options):
+    layout, r, z, nt = case
+    return P.Plan.from_mesh(r, z, nt, layout_of(P, layout), BC, **options)
+
+
+_REF = {}
+
+
+def reference(name):
+    """Seeded charge on the mesh nodes and the oracle's solution (cached per case)."""
+    if name not in _REF:
+        g = oracle_grid(CASES[name])
+        rho = W.mesh_blob_charge(g.r, g.z, g.ntheta, seed=len(name))
+        _REF[name] = (g, rho, solvers.solve_modes(g, rho, BC))
+    return _REF[name]
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_mesh_solve_matches_oracle(P, name):
+    g, rho, ref = reference(name)
+    say("mesh solve", name, g.shape)
+    plan = plan_for(P, CASES[name])
+    assert plan.shape == g.shape
+    info = plan.info()
+    assert info["layout"] == layout_of(P, CASES[name][0]) and info["uniform"] == 0
+    phi, st = plan.solve(dev(rho), tol=1e-13)
+    say("cycles", st["cycles"])
+    assert st["status"] == P.OK, st
+    # point smoothing is weaker where the cells are stretched (about 30 cycles
+    # at 6:1 spacing ratios, 8 to 12 on uniform cells)
+    assert st["cycles"] <= 36, st["cycles"]
+    got = host(phi)
+    assert rel_l2(got, ref) <= 1e-12, rel_l2(got, ref)
+    # boundary nodes carry the Dirichlet values (axial faces win at the corners)
+    np.testing.assert_allclose(got[:, 1:-1, 0], BC[0], rtol=1e-13, atol=1e-12)
+    np.testing.assert_allclose(got[:, 1:-1, -1], BC[1], rtol=1e-13, atol=1e-12)
+    np.testing.assert_allclose(got[:, 0, :], BC[2], rtol=1e-13, atol=1e-12)
+    np.testing.assert_allclose(got[:, -1, :], BC[3], rtol=1e-13, atol=1e-12)
+
+
+def test_large_meshes_run_fused_passes(P):
+    """Irregular rows next to the faces or everywhere (stretched z) no longer keep
+    a level off the fused passes."""
+    for name in ("cell_uniform", "cell_stretched", "vertex_stretched"):
+        info = plan_for(P, CASES[name]).info()
+        assert info["fused_levels"] >= 1, (name, info)
+
+
+@pytest.mark.parametrize("options", [dict(fused=0), dict(precision=32), dict(masks=1), dict(groups=3),
+                                     dict(graph=1), dict(nu1=1, nu2=3), dict(bottom=0)],
+                         ids=lambda o: ",".join(f"{k}={v}" for k, v in o.items()))
+def test_stretched_cells_every_solver_path(P, options):
+    g, rho, ref = reference("cell_stretched")
+    say("mesh options", options)
+    plan = plan_for(P, CASES["cell_stretched"], **options)
+    phi, st = plan.solve(dev(rho), tol=1e-13)
+    assert st["status"] == P.OK, st
+    assert rel_l2(host(phi), ref) <= 1e-12, rel_l2(host(phi), ref)
+
+
+def test_warm_start_on_a_mesh(P):
+    g, rho, ref = reference("vertex_stretched")
+    say("mesh warm start")
+    plan = plan_for(P, CASES["vertex_stretched"])
+    cold, st0 = plan.solve(dev(rho), tol=1e-13)
+    plan.set_option("warm_start", 1)
+    phi = cold.clone()
+    phi, st1 = plan.solve(dev(rho * 1.001), tol=1e-13, phi=phi)
+    assert st1["status"] == P.OK and st1["cycles"] < st0["cycles"], (st0["cycles"], st1["cycles"])
+    ref2 = solvers.solve_modes(g, rho * 1.001, BC)
+    assert rel_l2(host(phi), ref2) <= 1e-12
+
+
+def test_uniform_mesh_matches_the_uniform_constructor(P):
+    """The explicit-coordinate path on uniform vertex nodes gives the uniform plan's
+    answer (tables differ only by the rounding of the coordinates)."""
+    p = W.SMALL.with_sizes(65, 16, 49)
+    say("uniform via mesh", p.shape)
+    th, z, r = W.node_coordinates(p)
+    rho = dev(W.blob_charge(p, seed=4))
+    a, sa = P.Plan.for_problem(p).solve(rho, tol=1e-13)
+    b, sb = P.Plan.from_mesh(r, z, p.ntheta, P.VERTEX, p.bc).solve(rho, tol=1e-13)
+    assert sa["status"] == sb["status"] == P.OK
+    assert abs(sa["cycles"] - sb["cycles"]) <= 1
+    assert rel_l2(host(b), host(a)) <= 1e-12
+
+
+def test_cell_centred_apply_matches_oracle(P):
+    g, _, _ = reference("cell_stretched")
+    say("mesh apply", g.shape)
+    layout, r, z, nt = CASES["cell_stretched"]
+    phi = np.zeros(g.shape)
+    rng = np.random.Generator(np.random.PCG64(21))
+    phi[INTERIOR] = rng.standard_normal(phi[INTERIOR].shape)
+    phi[:, :, 0], phi[:, :, -1], phi[:, 0, :], phi[:, -1, :] = BC
+    plan = plan_for(P, CASES["cell_stretched"])
+    out = torch.empty_like(dev(phi))
+    P.apply(plan.handle, dev(phi), out)
+    got = host(out)
+    gl = fv.Grid.cell_centred(np.asarray(r, np.longdouble), np.asarray(z, np.longdouble), nt, np.longdouble)
+    ref = fv.charge_from_potential(gl, phi.astype(np.longdouble)).astype(np.float64)
+    # bound: the size of the terms that cancel, |A| |phi| + |b^D| (|phi|), over s
+    a = abs(fv.assemble(g))
+    ab = np.abs(phi)
+    scale = (a @ ab[INTERIOR].ravel() + fv.rhs(g, np.zeros(g.shape), ab).ravel()).reshape(g.interior_shape)
+    scale = scale * fv.EPS0 / g.s_eps0
+    col = scale.max(axis=0)[None] * nt
+    err = np.abs(got[INTERIOR] - ref[INTERIOR])
+    assert (err <= 64 * EPS * col).all(), float((err / col).max() / EPS)
+    assert (got[:, 0, :] == 0).all() and (got[:, :, 0] == 0).all()
+
+
+@pytest.mark.parametrize("name", ["cell_stretched", "vertex_stretched"])
+def test_multigrid_preconditioned_fgmres_on_stretched_meshes(P, name):
+    """One V-cycle as the FGMRES preconditioner: fewer V-cycles in all than the
+    plain iteration where the point smoother is weak, same answer."""
+    g, rho, ref = reference(name)
+    say("mg-fgmres", name)
+    _, s0 = plan_for(P, CASES[name]).solve(dev(rho), tol=1e-13)
+    plan = plan_for(P, CASES[name], krylov=1, krylov_precond=3)
+    phi, st = plan.solve(dev(rho), tol=1e-13)
+    say("plain cycles", s0["cycles"], "fgmres steps", st["krylov_iterations"])
+    assert st["status"] == P.OK and st["learned_fallback"] == 0, st
+    assert st["cycles"] == st["krylov_iterations"]  # one preconditioning V-cycle per step
+    assert rel_l2(host(phi), ref) <= 1e-12
+    assert st["krylov_iterations"] < 0.75 * s0["cycles"], (st["krylov_iterations"], s0["cycles"])
+    # the per-step contraction beats the plain iteration's mean contraction
+    plain_rate = (s0["rel_residual"] / 1.0) ** (1.0 / s0["cycles"])
+    assert st["learned_rate"] < plain_rate, (st["learned_rate"], plain_rate)
+
+
+def test_masks_do_not_leak_into_a_later_fgmres_solve(P):
+    """Planes frozen by a masked solve are not skipped by the V-cycles of a later
+    FGMRES solve on the same plan."""
+    g, rho, ref = reference("cell_uniform")
+    say("masks then fgmres")
+    plan = plan_for(P, CASES["cell_uniform"], masks=1)
+    _, st = plan.solve(dev(rho), tol=1e-13)
+    assert st["status"] == P.OK and st["frozen_planes"] > 0, st
+    plan.set_option("krylov", 1)
+    plan.set_option("krylov_precond", 3)
+    phi, st = plan.solve(dev(rho), tol=1e-13)
+    assert st["status"] == P.OK, st
+    assert rel_l2(host(phi), ref) <= 1e-12

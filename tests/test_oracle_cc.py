@@ -9,17 +9,12 @@ import numpy as np
 import pytest
 import scipy.sparse.linalg as spla
 
+import workloads as W
 from oracle import fv, solvers, spectral
 
+stretched = W.stretched_points
+
 EPS0 = fv.EPS0
-
-
-def stretched(a, b, n, beta):
-    """n + 1 increasing points from a to b, geometrically stretched by beta (1 = uniform)."""
-    if beta == 1.0:
-        return np.linspace(a, b, n + 1)
-    w = beta ** np.arange(n)
-    return a + (b - a) * np.concatenate([[0.0], np.cumsum(w) / w.sum()])
 
 
 def test_half_cell_dirichlet_example(golden_dir):

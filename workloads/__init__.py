@@ -35,6 +35,8 @@ __all__ = [
     "manufactured_potential",
     "blob_charge",
     "random_problems",
+    "stretched_points",
+    "mesh_blob_charge",
 ]
 
 
@@ -172,21 +174,26 @@ def blob_charge(p: Problem, seed: int = 24680) -> np.ndarray:
     white noise of relative amplitude 1e-3 (a particle-noise proxy) is added.
     Boundary nodes are zero (they are not read by the solve).
     """
-    rng = np.random.Generator(np.random.PCG64(seed))
     th, z, r = node_coordinates(p)
     dr = (p.r_out - p.r_in) / (p.nr - 1)
-    dth = 2.0 * math.pi / p.ntheta
+    return _blob_charge(th, z, r, (p.r_in, p.r_out), (0.0, p.length), dr, p.dz, seed)
+
+
+def _blob_charge(th, z, r, r_span, z_span, dr, dz, seed):
+    rng = np.random.Generator(np.random.PCG64(seed))
+    dth = 2.0 * math.pi / len(th)
     T = th[:, None, None]
     Z = z[None, :, None]
     R = r[None, None, :]
-    rho = np.zeros(p.shape)
+    shape = (len(th), len(z), len(r))
+    rho = np.zeros(shape)
     for _ in range(8):
         q = rng.uniform(-1.0, 1.0) * 1e-4
         sr = rng.uniform(2.0, 5.0) * dr
-        sz = rng.uniform(2.0, 5.0) * p.dz
+        sz = rng.uniform(2.0, 5.0) * dz
         st = rng.uniform(2.0, 5.0) * dth
-        rc = rng.uniform(*_inside(p.r_in, p.r_out, 3 * sr))
-        zc = rng.uniform(*_inside(0.0, p.length, 3 * sz))
+        rc = rng.uniform(*_inside(r_span[0], r_span[1], 3 * sr))
+        zc = rng.uniform(*_inside(z_span[0], z_span[1], 3 * sz))
         tc = rng.uniform(0.0, 2.0 * math.pi)
         dt = np.angle(np.exp(1j * (T - tc)))  # periodic distance in (-pi, pi]
         rho += q * np.exp(-0.5 * (((R - rc) / sr) ** 2 + (dt / st) ** 2 + ((Z - zc) / sz) ** 2))
@@ -196,10 +203,33 @@ def blob_charge(p: Problem, seed: int = 24680) -> np.ndarray:
         psi_m = rng.uniform(0.0, 2.0 * math.pi)
         spokes = spokes + eps_m * np.cos(m * T + psi_m)
     rho = rho * spokes
-    rho = rho + 1e-3 * np.abs(rho).max() * rng.standard_normal(p.shape)
+    rho = rho + 1e-3 * np.abs(rho).max() * rng.standard_normal(shape)
     rho[:, :, 0] = rho[:, :, -1] = 0.0
     rho[:, 0, :] = rho[:, -1, :] = 0.0
     return np.ascontiguousarray(rho)
+
+
+def stretched_points(a: float, b: float, n: int, beta: float) -> np.ndarray:
+    """n + 1 increasing points from a to b whose intervals grow geometrically by
+    the factor beta (beta = 1: uniform; beta < 1 refines towards b).  A mesh
+    generator for the non-uniform grids of App. A (boundary-layer refinement)."""
+    if beta == 1.0:
+        return np.linspace(a, b, n + 1)
+    w = beta ** np.arange(n)
+    x = a + (b - a) * np.concatenate([[0.0], np.cumsum(w) / w.sum()])
+    x[-1] = b
+    return x
+
+
+def mesh_blob_charge(r, z, ntheta: int, seed: int = 24680) -> np.ndarray:
+    """``blob_charge`` on explicit node coordinates r (Nr) and z (Nz): widths in
+    units of the median node spacings, centres inside [r[0], r[-1]] x [z[0], z[-1]]."""
+    r = np.asarray(r, dtype=np.float64)
+    z = np.asarray(z, dtype=np.float64)
+    th = 2.0 * math.pi * np.arange(ntheta, dtype=np.float64) / ntheta
+    dr = float(np.median(np.diff(r)))
+    dz = float(np.median(np.diff(z)))
+    return _blob_charge(th, z, r, (float(r[0]), float(r[-1])), (float(z[0]), float(z[-1])), dr, dz, seed)
 
 
 def random_problems(count: int = 16, seed: int = 24680) -> list[Problem]:
