@@ -96,10 +96,10 @@ def traffic_for(kernel: str, launches_bytes: float):
     return float(rec["bytes_per_launch"][kernel])
 
 
-FINE_KERNELS = {  # finest-level pass symbols -> kernel class
-    "k_pass_fine<2, 1, true, true>": "fine_down",
-    "k_pass_fine<2, 1, true, false>": "fine_down",
-    "k_pass_fine<2, 1, false, false>": "fine_up",
+FINE_KERNELS = {  # finest-level FP64 pass symbols -> kernel class
+    "k_pass_fine<double, 2, 1, true, true>": "fine_down",
+    "k_pass_fine<double, 2, 1, true, false>": "fine_down",
+    "k_pass_fine<double, 2, 1, false, false>": "fine_up",
 }
 
 
@@ -297,6 +297,48 @@ def time_batch(args):
     return out
 
 
+def time_meshes(problem, args):
+    """The paper-scale node counts on explicit cell-centred meshes (App. A):
+    uniform cells, and cells stretched geometrically 4:1 towards the inner wall
+    and towards z = 0 (boundary-layer refinement), each solved by plain
+    V-cycles and by V-cycle-preconditioned FGMRES."""
+    import torch
+
+    import paper_2609_07172_amd as P
+    import workloads as W
+
+    nr, nt, nz = problem.nr, problem.ntheta, problem.nz
+    length = problem.length
+    meshes = {
+        "cell_uniform": (np.linspace(problem.r_in, problem.r_out, nr - 1), np.linspace(0.0, length, nz - 1)),
+        "cell_stretched_4to1": (W.stretched_points(problem.r_in, problem.r_out, nr - 2, 4.0 ** (1.0 / (nr - 3))),
+                                W.stretched_points(0.0, length, nz - 2, 0.25 ** (1.0 / (nz - 3)))),
+    }
+    out = {}
+    for name, (rf, zf) in meshes.items():
+        rho = torch.from_numpy(W.mesh_blob_charge(W.cell_centres(rf), W.cell_centres(zf), nt, seed=11)).to("cuda:0")
+        phi = torch.empty_like(rho)
+        rec = {}
+        for label, opts in (("vcycles", {}), ("mg_fgmres", {"krylov": 1, "krylov_precond": 3})):
+            plan = P.Plan.from_mesh(rf, zf, nt, P.CELL, problem.bc, **opts)
+            for _ in range(2):
+                plan.solve(rho, tol=args.tol, phi=phi)
+            torch.cuda.synchronize()
+            steps = max(3, args.steps // 4)
+            t0 = time.perf_counter()
+            for _ in range(steps):
+                _, st = plan.solve(rho, tol=args.tol, phi=phi)
+            torch.cuda.synchronize()
+            ms = (time.perf_counter() - t0) / steps * 1e3
+            rec[label] = {"ms": round(ms, 4), "cycles": st["cycles"], "krylov_steps": st["krylov_iterations"],
+                          "rel_residual": st["rel_residual"], "fused_levels": plan.info()["fused_levels"]}
+            log(f"mesh {name} {label}: {ms:.3f} ms/solve, {st['cycles']} V-cycles, "
+                f"rel residual {st['rel_residual']:.3e}")
+            plan.close()
+        out[name] = rec
+    return out
+
+
 def time_learned(problem, rho_d, args, ref, phit):
     """The learned preconditioner at this size: a network trained on the GPU on
     about 20k pairs from a sequence of charges of this grid (the manufactured
@@ -481,6 +523,7 @@ def main():
         variants["warm_start_sequence"] = time_sequence(problem, rho_d, args)
         variants["batch_uneven"] = time_batch(args)
         variants["learned_preconditioner"] = time_learned(problem, rho_d, args, ref, phit)
+        variants["meshes"] = time_meshes(problem, args)
 
     if args.copy_probe > 0:
         # a plain device copy of known size: the scale for the HBM byte counters

@@ -182,28 +182,59 @@ __global__ void __launch_bounds__(256) k_coarse_solve(LevelView v, const double*
 }
 
 // ------------------------------------------------------------ plane norms
-// partial[p][b] = sum over block b's share of plane p's interior of r^2.
-__global__ void __launch_bounds__(256) k_norm_partial(LevelView v, const double* __restrict__ r,
-                                                      double* __restrict__ partial) {
+// Block b of plane p takes the interior rows k = 1 + b, 1 + b + nb, ... and
+// its threads the columns of each row, so every row is read coalesced and no
+// index is divided.  Fixed-order block reduction into partial[p][b].
+__device__ __forceinline__ void block_sum_store(double s, double* __restrict__ out) {
     __shared__ double red[256];
-    const int p = blockIdx.y;
-    const int ni = v.nr - 2, nk = v.nz - 2;
-    const long long total = (long long)ni * nk;
-    const double* rp = r + (long long)p * v.pstride;
-    double s = 0.0;
-    for (long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x; q < total;
-         q += (long long)gridDim.x * blockDim.x) {
-        const int i = (int)(q % ni) + 1, k = (int)(q / ni) + 1;
-        const double x = rp[(long long)k * v.pitch + i];
-        s = fma(x, x, s);
-    }
     red[threadIdx.x] = s;
     __syncthreads();
     for (int w = 128; w > 0; w >>= 1) {
         if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
         __syncthreads();
     }
-    if (threadIdx.x == 0) partial[(long long)p * kMaxPartial + blockIdx.x] = red[0];
+    if (threadIdx.x == 0) *out = red[0];
+}
+
+// partial[p][b] = sum of x^2 over block b's rows of plane p's interior.
+__global__ void __launch_bounds__(256) k_norm_partial(LevelView v, const double* __restrict__ x,
+                                                      double* __restrict__ partial) {
+    const int p = blockIdx.y;
+    const double* xp = x + (long long)p * v.pstride;
+    double s = 0.0;
+    for (int k = 1 + blockIdx.x; k <= v.nz - 2; k += gridDim.x)
+        for (int i = 1 + threadIdx.x; i <= v.nr - 2; i += blockDim.x) {
+            const double a = xp[(long long)k * v.pitch + i];
+            s = fma(a, a, s);
+        }
+    block_sum_store(s, partial + (long long)p * kMaxPartial + blockIdx.x);
+}
+
+// The same sums for r = f - A_p u with u's interior taken as zero (its ring as
+// given): away from the ring r = f; next to it the point residual with the
+// ring neighbours (the expression every other kernel evaluates).
+__global__ void __launch_bounds__(256) k_rhs_norm_partial(LevelView v, const double* __restrict__ lam,
+                                                          const double* __restrict__ u,
+                                                          const double* __restrict__ f,
+                                                          double* __restrict__ partial) {
+    const int p = blockIdx.y;
+    const long long base = (long long)p * v.pstride;
+    const int ie = v.nr - 2, ke = v.nz - 2;
+    double s = 0.0;
+    for (int k = 1 + blockIdx.x; k <= ke; k += gridDim.x)
+        for (int i = 1 + threadIdx.x; i <= ie; i += blockDim.x) {
+            const long long o = base + (long long)k * v.pitch + i;
+            double r = f[o];
+            if (i == 1 || i == ie || k == 1 || k == ke) {
+                const double uw = i == 1 ? u[o - 1] : 0.0;
+                const double ue = i == ie ? u[o + 1] : 0.0;
+                const double us = k == 1 ? u[o - v.pitch] : 0.0;
+                const double un = k == ke ? u[o + v.pitch] : 0.0;
+                r = residual(0.0, r, uw, ue, us, un, coef_at(v, i, k, lam[p]));
+            }
+            s = fma(r, r, s);
+        }
+    block_sum_store(s, partial + (long long)p * kMaxPartial + blockIdx.x);
 }
 
 // FP64 refinement step of the mixed-precision solve, finest level, with the
@@ -431,11 +462,12 @@ hipError_t launch_coarse_solve(const DeviceLevel& L, int nt, const double* lam, 
     return hipGetLastError();
 }
 
+// Blocks per plane of the norm kernels: one per interior row, at most kMaxPartial.
+static int norm_blocks(const LevelView& v) { return std::max(1, std::min(kMaxPartial, v.nz - 2)); }
+
 hipError_t launch_plane_norms(const DeviceLevel& L, int nt, const double* r, double* partial,
                               double* norms_out, hipStream_t s) {
-    const long long total = (long long)(L.v.nr - 2) * (L.v.nz - 2);
-    int nb = (int)std::min<long long>(kMaxPartial, (total + 255) / 256);
-    if (nb < 1) nb = 1;
+    const int nb = norm_blocks(L.v);
     k_norm_partial<<<dim3(nb, nt), 256, 0, s>>>(L.v, r, partial);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
@@ -511,7 +543,12 @@ hipError_t launch_refine(const DeviceLevel& L, int nt, const double* lam, const 
 
 hipError_t launch_rhs_norms(const DeviceLevel& L, int nt, const double* lam, const double* u,
                             const double* f, double* partial, double* norms_out, hipStream_t s) {
-    return refine_t<kZero, false>(L, nt, lam, u, nullptr, nullptr, f, nullptr, partial, norms_out, s);
+    const int nb = norm_blocks(L.v);
+    k_rhs_norm_partial<<<dim3(nb, nt), 256, 0, s>>>(L.v, lam, u, f, partial);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    k_norm_final<<<(nt + 63) / 64, 64, 0, s>>>(partial, nb, nt, norms_out);
+    return hipGetLastError();
 }
 
 }  // namespace cp

@@ -92,6 +92,28 @@ Axis axis_geometry(const std::vector<int>& pos, const AxisMesh& m, bool level0) 
     return a;
 }
 
+// On an explicit mesh, rows whose neighbour distances and widths agree to
+// within the rounding of the coordinates themselves (2 ulp of the largest
+// coordinate) take the values of the first row of their run, so a mesh that is
+// uniform up to that rounding gets rows with identical tables, which the fused
+// passes treat as one regular band.  The change is no larger than the rounding
+// already carried by differences of the given coordinates.
+void snap_uniform_runs(Axis& a, double xmax) {
+    const double tol = 2.0 * (std::nextafter(xmax, INFINITY) - xmax);
+    const int n = (int)a.x.size();
+    int anchor = 1;
+    for (int i = 2; i + 1 < n; ++i) {
+        if (std::fabs(a.hm[i] - a.hm[anchor]) <= tol && std::fabs(a.hp[i] - a.hp[anchor]) <= tol &&
+            std::fabs(a.width[i] - a.width[anchor]) <= tol) {
+            a.hm[i] = a.hm[anchor];
+            a.hp[i] = a.hp[anchor];
+            a.width[i] = a.width[anchor];
+        } else {
+            anchor = i;
+        }
+    }
+}
+
 // Typical node spacing of a level: the median distance between neighbours.
 double median_gap(const std::vector<int>& pos, const AxisMesh& m) {
     std::vector<double> g;
@@ -281,7 +303,8 @@ void build_levels(cylpoisson_plan* p) {
         H.nz = (int)lz[l].size();
         H.pitch = H.nr;
         const Axis ar = axis_geometry(lr[l], mr, l == 0);
-        const Axis az = axis_geometry(lz[l], mz, l == 0);
+        Axis az = axis_geometry(lz[l], mz, l == 0);
+        if (!p->uniform) snap_uniform_runs(az, std::max(std::fabs(p->xz.front()), std::fabs(p->xz.back())));
         H.r = ar.x;
         H.z = az.x;
         H.rw.assign(H.nr, 0.0);
