@@ -301,7 +301,8 @@ def time_meshes(problem, args):
     """The paper-scale node counts on explicit cell-centred meshes (App. A):
     uniform cells, and cells stretched geometrically 4:1 towards the inner wall
     and towards z = 0 (boundary-layer refinement), each solved by plain
-    V-cycles and by V-cycle-preconditioned FGMRES."""
+    V-cycles, by V-cycle-preconditioned FGMRES and by V-cycles with the
+    alternating zebra line smoother."""
     import torch
 
     import paper_2609_07172_amd as P
@@ -319,7 +320,8 @@ def time_meshes(problem, args):
         rho = torch.from_numpy(W.mesh_blob_charge(W.cell_centres(rf), W.cell_centres(zf), nt, seed=11)).to("cuda:0")
         phi = torch.empty_like(rho)
         rec = {}
-        for label, opts in (("vcycles", {}), ("mg_fgmres", {"krylov": 1, "krylov_precond": 3})):
+        for label, opts in (("vcycles", {}), ("mg_fgmres", {"krylov": 1, "krylov_precond": 3}),
+                            ("alternating_lines", {"smoother": 2})):
             plan = P.Plan.from_mesh(rf, zf, nt, P.CELL, problem.bc, **opts)
             for _ in range(2):
                 plan.solve(rho, tol=args.tol, phi=phi)

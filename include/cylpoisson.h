@@ -175,6 +175,14 @@ void cylpoisson_plan_destroy(cylpoisson_plan* plan);
  *   "timing"         1 = record per-kernel-class device times (cylpoisson_stats)
  *   "bottom"         1 = run the small levels of each plane in one LDS-resident
  *                    kernel (with "fused" = 1; default 1)
+ *   "smoother"       0 = point red-black SOR (default); 1 = zebra line relaxation
+ *                    along r (the interior rows of one parity, then of the other,
+ *                    each solved exactly along r with its neighbour rows fixed);
+ *                    2 = alternating zebra lines, r-lines then z-lines in every
+ *                    sweep, for cells whose aspect ratio varies across the mesh.
+ *                    Lines use no over-relaxation and run one kernel per colour,
+ *                    so 1 and 2 bypass the fused passes and the LDS bottom kernel
+ *                    (and exclude precision 32 and masks, which need them)
  *   "fft"            1 = azimuthal transforms as register FFTs when Ntheta is 16,
  *                    32, 64 or 128; 0 = dense DFT product (default 1)
  *   "precision"      64 = FP64 V-cycles (default); 32 = mixed precision: FP64

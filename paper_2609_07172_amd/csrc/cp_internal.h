@@ -122,6 +122,7 @@ struct Options {
     int krylov_max = 200;    // FGMRES iterations in all
     int fallback = 1;        // 1: V-cycles take over when the network contracts less than a V-cycle
     int inner_cycles = 2;  // FP32 V-cycles per FP64 refinement step
+    int smoother = 0;      // 0: point red-black SOR; 1: r-line zebra; 2: r-line then z-line zebra
 };
 
 }  // namespace cp
@@ -239,6 +240,10 @@ hipError_t launch_plane_norms(const DeviceLevel& L, int nt, const double* r, dou
 hipError_t launch_apply(const DeviceLevel& L, int nt, const double* lam, const double* u,
                         const double* inv_s, double* out, hipStream_t s);
 hipError_t launch_norm_final(const double* partial, int nb, int nt, double* out, hipStream_t s);
+// One colour of zebra line relaxation on u (lines along r when along_r, else
+// along z); `scratch` is a node array of the level whose interior it may overwrite.
+hipError_t launch_line_sweep(const DeviceLevel& L, int nt, const double* lam, double* u, const double* f,
+                             double* scratch, bool along_r, int color, hipStream_t s);
 hipError_t launch_init_ring(const DeviceLevel& L, int nt, const cylpoisson_bc& bc, hipStream_t s);
 hipError_t launch_rhs_norms(const DeviceLevel& L, int nt, const double* lam, const double* u,
                             const double* f, double* partial, double* norms_out, hipStream_t s);
@@ -270,6 +275,8 @@ hipError_t launch_bottom32(cylpoisson_plan* p, hipStream_t s, int p0 = 0, int np
 
 // ---- fused passes (fused.hip) ----
 bool fused_supported(const cylpoisson_plan* p, int l);
+// The LDS bottom kernel serves the small levels (options bottom, fused, point smoother).
+bool bottom_active(const cylpoisson_plan* p);
 hipError_t fused_down(cylpoisson_plan* p, int l, bool zero_u, bool zero_interior, hipStream_t s,
                       int p0 = 0, int np = -1);
 hipError_t fused_up(cylpoisson_plan* p, int l, double* partial, int partial_ld, int* nchunks,

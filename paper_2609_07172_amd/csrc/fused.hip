@@ -5,7 +5,7 @@
 namespace cp {
 
 bool fused_supported(const cylpoisson_plan* p, int l) {
-    if (!p->opt.fused || l + 1 >= (int)p->dl.size()) return false;
+    if (!p->opt.fused || p->opt.smoother != 0 || l + 1 >= (int)p->dl.size()) return false;
     if (p->opt.nu1 > 4 || p->opt.nu2 > 4) return false;
     const Shape sd = pass_shape<double>(p, l, p->opt.nu1, true);
     const Shape su = pass_shape<double>(p, l, p->opt.nu2, false);

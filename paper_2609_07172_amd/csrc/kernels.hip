@@ -9,6 +9,8 @@ namespace cp {
 namespace {
 
 constexpr int kTx = 64, kTy = 4;
+// Lines up to this length are solved by cyclic reduction in one workgroup.
+constexpr int kMaxPcrLine = 1024;
 
 // ---------------------------------------------------------------- DFT (FMA)
 // Y[p][c] = cs(c) * sum_j M[p][j] X[j][c] for c in [0, ncols), p in [0, n).
@@ -97,6 +99,167 @@ __global__ void __launch_bounds__(256) k_rb(LevelView v, const double* __restric
     const long long o = (long long)p * v.pstride + (long long)k * v.pitch + i;
     const Coef c = coef_at(v, i, k, lam[p]);
     u[o] = relax(u[o], f[o], u[o - 1], u[o + 1], u[o - v.pitch], u[o + v.pitch], c, omega);
+}
+
+// ------------------------------------------------------- line relaxation
+// Zebra line relaxation: every interior line of one colour is solved exactly
+// with the lines of the other colour held fixed (line Gauss-Seidel), by the
+// Thomas algorithm, one thread per line.  Along r, line k carries
+//   -G_W u_{i-1} + (D0 + lambda mu) u_i - G_E u_{i+1} = f_i + G_S u_{k-1,i} + G_N u_{k+1,i}
+// (the ring values enter the right-hand side at i = 1 and i = nr - 2); along z
+// the roles of (W, E) and (S, N) swap.  The forward elimination keeps the
+// modified super-diagonal c'_j in `scratch` and the modified right-hand side
+// d'_j in the line's own entries of u (the exact line solve does not read
+// them); back substitution then overwrites them with the solution.
+__global__ void __launch_bounds__(64) k_rline(LevelView v, const double* __restrict__ lam, double* __restrict__ u,
+                                              const double* __restrict__ f, double* __restrict__ scratch,
+                                              int color) {
+    const int k = 1 + color + 2 * (blockIdx.x * blockDim.x + threadIdx.x);
+    const int p = blockIdx.y;
+    if (k > v.nz - 2) return;
+    const double l = lam[p];
+    const long long row = (long long)p * v.pstride + (long long)k * v.pitch;
+    double* ur = u + row;
+    const double* fr = f + row;
+    double* cr = scratch + row;
+    const double* us = ur - v.pitch;
+    const double* un = ur + v.pitch;
+    const int ie = v.nr - 2;
+    double cp = 0.0, dp = 0.0;
+    for (int i = 1; i <= ie; ++i) {
+        const Coef c = coef_at(v, i, k, l);
+        double rhs = fma(c.gn, un[i], fma(c.gs, us[i], fr[i]));
+        if (i == 1) rhs = fma(c.gw, ur[0], rhs);
+        if (i == ie) rhs = fma(c.ge, ur[ie + 1], rhs);
+        const double a = i > 1 ? c.gw : 0.0;  // the sub-diagonal is -a
+        const double inv = 1.0 / fma(a, cp, c.diag);
+        cp = (i < ie ? -c.ge : 0.0) * inv;
+        dp = fma(a, dp, rhs) * inv;
+        cr[i] = cp;
+        ur[i] = dp;
+    }
+    double x = dp;
+    for (int i = ie - 1; i >= 1; --i) {
+        x = fma(-cr[i], x, ur[i]);
+        ur[i] = x;
+    }
+}
+
+__global__ void __launch_bounds__(64) k_zline(LevelView v, const double* __restrict__ lam, double* __restrict__ u,
+                                              const double* __restrict__ f, double* __restrict__ scratch,
+                                              int color) {
+    const int i = 1 + color + 2 * (blockIdx.x * blockDim.x + threadIdx.x);
+    const int p = blockIdx.y;
+    if (i > v.nr - 2) return;
+    const double l = lam[p];
+    const long long col = (long long)p * v.pstride + i;
+    double* uc = u + col;
+    const double* fc = f + col;
+    double* cc = scratch + col;
+    const long long P = v.pitch;
+    const int ke = v.nz - 2;
+    double cp = 0.0, dp = 0.0;
+    for (int k = 1; k <= ke; ++k) {
+        const Coef c = coef_at(v, i, k, l);
+        const long long o = (long long)k * P;
+        double rhs = fma(c.ge, uc[o + 1], fma(c.gw, uc[o - 1], fc[o]));
+        if (k == 1) rhs = fma(c.gs, uc[0], rhs);
+        if (k == ke) rhs = fma(c.gn, uc[o + P], rhs);
+        const double a = k > 1 ? c.gs : 0.0;
+        const double inv = 1.0 / fma(a, cp, c.diag);
+        cp = (k < ke ? -c.gn : 0.0) * inv;
+        dp = fma(a, dp, rhs) * inv;
+        cc[o] = cp;
+        uc[o] = dp;
+    }
+    double x = dp;
+    for (int k = ke - 1; k >= 1; --k) {
+        const long long o = (long long)k * P;
+        x = fma(-cc[o], x, uc[o]);
+        uc[o] = x;
+    }
+}
+
+// The same line solves with one workgroup per line and one thread per
+// unknown, by parallel cyclic reduction in LDS: at stride s = 1, 2, 4, ...
+// every equation eliminates its neighbours s positions away, so after
+// ceil(log2 n) steps each equation holds its own unknown alone.  Each thread
+// keeps its own pivot b and publishes 1/b, so a step costs one division.
+// Lines run along r (ALONG_R, coalesced rows) or along z (one column).
+// Consecutive lines go to one XCD (workgroups are dealt to the 8 XCDs in
+// turn), so lines that share neighbour rows or cache lines share an L2.
+template <bool ALONG_R>
+__global__ void __launch_bounds__(1024) k_line_pcr(LevelView v, const double* __restrict__ lam,
+                                                   double* __restrict__ u, const double* __restrict__ f,
+                                                   int color, int lines) {
+    extern __shared__ double sm[];
+    const int n = ALONG_R ? v.nr - 2 : v.nz - 2;
+    const int per_xcd = (lines + 7) / 8;
+    const int j = (blockIdx.x & 7) * per_xcd + (blockIdx.x >> 3);
+    if (j >= lines) return;  // whole workgroup: before any barrier
+    const int line = 1 + color + 2 * j;
+    const int p = blockIdx.y;
+    const int t = threadIdx.x;
+    const int m = blockDim.x;
+    double* A = sm;
+    double* I = sm + 2 * m;  // 1 / pivot
+    double* C = sm + 4 * m;
+    double* D = sm + 6 * m;
+    const bool act = t < n;
+    const int x = t + 1;
+    const int i = ALONG_R ? x : line, k = ALONG_R ? line : x;
+    const long long o = (long long)p * v.pstride + (long long)k * v.pitch + i;
+    double a = 0.0, b = 1.0, c = 0.0, d = 0.0;
+    if (act) {
+        const Coef cf = coef_at(v, i, k, lam[p]);
+        // neighbours across lines (held fixed) and the ring at the line's ends
+        const double g_lo = ALONG_R ? cf.gw : cf.gs, g_hi = ALONG_R ? cf.ge : cf.gn;
+        const long long step = ALONG_R ? 1 : v.pitch, across = ALONG_R ? v.pitch : 1;
+        const double x_lo = ALONG_R ? cf.gs : cf.gw, x_hi = ALONG_R ? cf.gn : cf.ge;
+        d = fma(x_hi, u[o + across], fma(x_lo, u[o - across], f[o]));
+        if (x == 1) d = fma(g_lo, u[o - step], d);
+        if (x == n) d = fma(g_hi, u[o + step], d);
+        a = x > 1 ? -g_lo : 0.0;
+        c = x < n ? -g_hi : 0.0;
+        b = cf.diag;
+    }
+    int buf = 0;
+    A[t] = a;
+    I[t] = 1.0 / b;
+    C[t] = c;
+    D[t] = d;
+    __syncthreads();
+    for (int st = 1; st < n; st <<= 1) {
+        const double* a0 = A + buf * m;
+        const double* i0 = I + buf * m;
+        const double* c0 = C + buf * m;
+        const double* d0 = D + buf * m;
+        if (act) {
+            const int lo = t - st, hi = t + st;
+            double na = 0.0, nc = 0.0;
+            if (lo >= 0) {
+                const double al = -a * i0[lo];
+                na = al * a0[lo];
+                b = fma(al, c0[lo], b);
+                d = fma(al, d0[lo], d);
+            }
+            if (hi < n) {
+                const double ga = -c * i0[hi];
+                nc = ga * c0[hi];
+                b = fma(ga, a0[hi], b);
+                d = fma(ga, d0[hi], d);
+            }
+            a = na;
+            c = nc;
+        }
+        buf ^= 1;
+        A[buf * m + t] = a;
+        I[buf * m + t] = 1.0 / b;
+        C[buf * m + t] = c;
+        D[buf * m + t] = d;
+        __syncthreads();
+    }
+    if (act) u[o] = d * I[buf * m + t];
 }
 
 // ---------------------------------------------------------------- residual
@@ -435,6 +598,32 @@ hipError_t launch_copy_interior(const DeviceLevel& L, int nt, const double* src,
 hipError_t launch_rb_sweep(const DeviceLevel& L, int nt, const double* lam, double* u,
                            const double* f, int color, double omega, hipStream_t s) {
     k_rb<<<grid_interior(L.v, nt, 2), dim3(kTx, kTy), 0, s>>>(L.v, lam, u, f, color, omega);
+    return hipGetLastError();
+}
+
+hipError_t launch_line_sweep(const DeviceLevel& L, int nt, const double* lam, double* u, const double* f,
+                             double* scratch, bool along_r, int color, hipStream_t s) {
+    const int lines = along_r ? L.v.nz - 2 : L.v.nr - 2;
+    const int mine = (lines - color + 1) / 2;  // lines 1 + color, 3 + color, ...
+    if (mine <= 0) return hipSuccess;
+    const int len = along_r ? L.v.nr - 2 : L.v.nz - 2;
+    if (len <= kMaxPcrLine) {
+        // one workgroup per line: a power of two of threads covering the line
+        int m = 64;
+        while (m < len) m <<= 1;
+        const size_t lds = 8 * (size_t)m * sizeof(double);
+        const unsigned blocks = 8u * (unsigned)((mine + 7) / 8);
+        if (along_r)
+            k_line_pcr<true><<<dim3(blocks, nt), m, lds, s>>>(L.v, lam, u, f, color, mine);
+        else
+            k_line_pcr<false><<<dim3(blocks, nt), m, lds, s>>>(L.v, lam, u, f, color, mine);
+        return hipGetLastError();
+    }
+    const dim3 grid((unsigned)((mine + 63) / 64), nt);
+    if (along_r)
+        k_rline<<<grid, 64, 0, s>>>(L.v, lam, u, f, scratch, color);
+    else
+        k_zline<<<grid, 64, 0, s>>>(L.v, lam, u, f, scratch, color);
     return hipGetLastError();
 }
 

@@ -401,8 +401,12 @@ using namespace cp;
 
 namespace cp {
 
+bool bottom_active(const cylpoisson_plan* p) {
+    return p->opt.bottom && p->opt.fused && p->opt.smoother == 0;
+}
+
 bool mixed_supported(const cylpoisson_plan* p) {
-    if (p->bottom_level < 1 || !p->opt.bottom || !p->opt.fused) return false;
+    if (p->bottom_level < 1 || !bottom_active(p)) return false;
     for (int l = 0; l < p->bottom_level; ++l)
         if (!fused_supported(p, l)) return false;
     return true;
@@ -838,6 +842,7 @@ int cylpoisson_plan_set_option(cylpoisson_plan* plan, const char* key, double va
     if (!std::strcmp(key, "timing")) return int_in(0, 1, &plan->opt.timing);
     if (!std::strcmp(key, "prefetch")) return int_in(1, 4, &plan->opt.prefetch);
     if (!std::strcmp(key, "bottom")) return int_in(0, 1, &plan->opt.bottom);
+    if (!std::strcmp(key, "smoother")) return int_in(0, 2, &plan->opt.smoother);
     if (!std::strcmp(key, "fft")) return int_in(0, 1, &plan->opt.fft);
     if (!std::strcmp(key, "inner_cycles")) return int_in(1, 8, &plan->opt.inner_cycles);
     if (!std::strcmp(key, "groups")) return int_in(1, 8, &plan->opt.groups);
@@ -887,6 +892,7 @@ int cylpoisson_plan_get_option(const cylpoisson_plan* plan, const char* key, dou
                  {"fused", (double)o.fused}, {"chunk_rows", (double)o.chunk_rows},
                  {"chunk_rows_coarse", (double)o.chunk_rows_coarse}, {"prefetch", (double)o.prefetch},
                  {"timing", (double)o.timing}, {"bottom", (double)o.bottom}, {"fft", (double)o.fft},
+                 {"smoother", (double)o.smoother},
                  {"precision", (double)o.precision}, {"inner_cycles", (double)o.inner_cycles},
                  {"groups", (double)o.groups}, {"warm_start", (double)o.warm_start},
                  {"masks", (double)o.masks}, {"graph", (double)o.graph}, {"krylov", (double)o.krylov},
@@ -929,7 +935,7 @@ int cylpoisson_get_info(const cylpoisson_plan* plan, cylpoisson_info* out) {
     out->workspace_bytes = plan->workspace_bytes;
     out->device = plan->device;
     for (int l = 0; l + 1 < out->levels; ++l) {
-        if (l > 0 && l == plan->bottom_level && plan->opt.bottom && plan->opt.fused) break;
+        if (l > 0 && l == plan->bottom_level && bottom_active(plan)) break;
         if (!fused_supported(plan, l)) break;
         ++out->fused_levels;
     }

@@ -141,12 +141,18 @@ hipError_t residual_norms(cylpoisson_plan* p, int slot, hipStream_t s) {
     return launch_plane_norms(L, p->nt, L.r, p->d_partial, p->d_norms + (size_t)slot * p->nt, s);
 }
 
+// `sweeps` smoothing sweeps on a level by the one-kernel-per-colour path: point
+// red-black SOR, or zebra line relaxation (r-lines, then z-lines for the
+// alternating variant) with L.r as the elimination scratch.
 hipError_t smooth(cylpoisson_plan* p, DeviceLevel& L, int sweeps, hipStream_t s) {
     for (int it = 0; it < sweeps; ++it)
-        for (int color = 0; color < 2; ++color) {
-            hipError_t e = launch_rb_sweep(L, p->nt, p->d_lam, L.u, L.f, color, p->opt.omega, s);
-            if (e != hipSuccess) return e;
-        }
+        for (int dir = 0; dir < (p->opt.smoother == 2 ? 2 : 1); ++dir)
+            for (int color = 0; color < 2; ++color) {
+                hipError_t e = p->opt.smoother == 0
+                                   ? launch_rb_sweep(L, p->nt, p->d_lam, L.u, L.f, color, p->opt.omega, s)
+                                   : launch_line_sweep(L, p->nt, p->d_lam, L.u, L.f, L.r, dir == 0, color, s);
+                if (e != hipSuccess) return e;
+            }
     return hipSuccess;
 }
 
@@ -174,7 +180,7 @@ hipError_t vcycle(cylpoisson_plan* p, int l, hipStream_t s, bool zero_top, int s
             e = launch_coarse_solve(L, p->nt, p->d_lam, p->d_cinv, p->coarse_n, L.f, L.u, s);
         return e;
     }
-    if (l > 0 && l == p->bottom_level && p->opt.bottom && p->opt.fused) return launch_bottom(p, s, p0, np);
+    if (l > 0 && l == p->bottom_level && bottom_active(p)) return launch_bottom(p, s, p0, np);
     DeviceLevel& C = p->dl[l + 1];
     if (fused_supported(p, l)) {
         {

@@ -193,3 +193,83 @@ def test_masks_do_not_leak_into_a_later_fgmres_solve(P):
     phi, st = plan.solve(dev(rho), tol=1e-13)
     assert st["status"] == P.OK, st
     assert rel_l2(host(phi), ref) <= 1e-12
+
+
+def test_paper_scale_stretched_cells_sampled_planes(P):
+    """400 x 128 x 512 nodes on cells stretched 4:1 towards the inner wall and
+    z = 0: three Fourier planes of the GPU solution (the GPU's own forward DFT
+    of phi) against the oracle's direct solves of those modes.  Per-plane
+    errors are bounded by the field's (Parseval), so each must be within
+    1e-12 of the interior field norm."""
+    nr, nt, nz = 400, 128, 512
+    rf = W.stretched_points(0.02, 0.05, nr - 2, 4.0 ** (1.0 / (nr - 3)))
+    zf = W.stretched_points(0.0, 0.1, nz - 2, 0.25 ** (1.0 / (nz - 3)))
+    g = fv.Grid.cell_centred(rf, zf, nt)
+    rho = W.mesh_blob_charge(g.r, g.z, nt, seed=3)
+    bc = (0.0, 0.0, 0.0, 300.0)
+    say("paper-scale stretched cells", g.shape)
+    plan = P.Plan.from_mesh(rf, zf, nt, P.CELL, bc)
+    phi_d, st = plan.solve(dev(rho), tol=1e-13)
+    assert st["status"] == P.OK, st
+    planes_d = torch.empty_like(phi_d)
+    P.dft_forward(plan.handle, phi_d, planes_d)
+    got = host(planes_d)
+    phi = host(phi_d)
+    from oracle import spectral
+    b = fv.rhs(g, rho, fv.boundary_values(g, bc))
+    bp = spectral.forward(np.reshape(b, g.interior_shape))
+    lam = spectral.plane_eigenvalues(nt, float(g.dtheta))
+    norm = np.linalg.norm(phi[INTERIOR])
+    for p in (0, 1, 100):  # m = 0 (with the boundary term), cos m = 1, sin m = 37
+        ref = solvers.solve_mode(g, lam[p], bp[p].ravel())
+        err = np.linalg.norm(got[p, 1:-1, 1:-1] - ref) * np.sqrt(nt)
+        say("plane", p, err / norm)
+        assert err <= 1e-12 * norm, (p, err / norm)
+
+
+@pytest.mark.parametrize("smoother", [1, 2])
+@pytest.mark.parametrize("name", ["cell_stretched", "vertex_stretched", "cell_flat", "cell_tiny"])
+def test_line_smoothers_match_oracle(P, name, smoother):
+    """Zebra line relaxation (r-lines; alternating r- and z-lines) reaches the
+    oracle's answer; it runs on the one-kernel-per-colour path."""
+    g, rho, ref = reference(name)
+    say("line smoother", smoother, name)
+    plan = plan_for(P, CASES[name], smoother=smoother)
+    assert plan.info()["fused_levels"] == 0 and plan.get_option("smoother") == smoother
+    phi, st = plan.solve(dev(rho), tol=1e-13)
+    say("cycles", st["cycles"])
+    assert st["status"] == P.OK, st
+    assert rel_l2(host(phi), ref) <= 1e-12, rel_l2(host(phi), ref)
+
+
+@pytest.mark.parametrize("name", ["cell_stretched", "vertex_stretched"])
+def test_alternating_lines_need_fewer_cycles_on_stretched_meshes(P, name):
+    g, rho, ref = reference(name)
+    _, point = plan_for(P, CASES[name]).solve(dev(rho), tol=1e-13)
+    _, lines = plan_for(P, CASES[name], smoother=2).solve(dev(rho), tol=1e-13)
+    say(name, "point", point["cycles"], "alternating lines", lines["cycles"])
+    assert lines["cycles"] < point["cycles"], (lines["cycles"], point["cycles"])
+
+
+def test_line_smoother_on_the_uniform_grid_and_in_fgmres(P):
+    p = W.SMALL
+    rho = W.blob_charge(p, seed=8)
+    ref = solvers.solve_sparse(fv.Grid.of(p), rho, p.bc)
+    say("line smoother uniform")
+    for opts in (dict(smoother=1), dict(smoother=2, krylov=1, krylov_precond=3)):
+        phi, st = P.Plan.for_problem(p, **opts).solve(dev(rho), tol=1e-13)
+        assert st["status"] == P.OK, (opts, st)
+        assert rel_l2(host(phi), ref) <= 1e-12, (opts, rel_l2(host(phi), ref))
+
+
+def test_smoother_option_errors(P):
+    plan = P.Plan.for_problem(W.SMALL)
+    for bad in (-1, 3, 1.5):
+        with pytest.raises(P.CylPoissonError) as e:
+            plan.set_option("smoother", bad)
+        assert e.value.status == P.EINVAL
+    plan.set_option("smoother", 1)
+    plan.set_option("precision", 32)
+    with pytest.raises(P.CylPoissonError) as e:
+        plan.solve(dev(np.zeros(W.SMALL.shape)), tol=1e-12)
+    assert e.value.status == P.EINVAL
