@@ -609,13 +609,18 @@ Shape pass_shape(const cylpoisson_plan* p, int l, int nu, bool down) {
     sh.threads = sh.tn;
     const int rows = L.v.nz - 2;
     int chunk = l == 0 ? p->opt.chunk_rows : p->opt.chunk_rows_coarse;
-    if (chunk <= 0) {
+    if (chunk <= 0 && l == 0) {
         // The finest level is bandwidth-bound: few long chunks (about two
-        // workgroups per compute unit) keep the recomputed halo small.  Coarser
-        // levels are latency-bound: more, shorter chunks.
-        const int want = l == 0 ? 512 : 1024;
-        const int per_plane = std::max(1, want / std::max(1, p->nt));
-        chunk = std::max(l == 0 ? 64 : 32, (rows + per_plane - 1) / per_plane);
+        // workgroups per compute unit) keep the recomputed halo small.
+        const int per_plane = std::max(1, 512 / std::max(1, p->nt));
+        chunk = std::max(64, (rows + per_plane - 1) / per_plane);
+    } else if (chunk <= 0) {
+        // Coarser levels are latency-bound: enough short chunks for about two
+        // waves per SIMD over the chip (2048 waves), at least 8 rows each.
+        const int waves = (sh.threads + 63) / 64;
+        const int per_plane =
+            std::min(kMaxPartial, std::max(1, (2048 + p->nt * waves - 1) / (p->nt * waves)));
+        chunk = std::max(8, (rows + per_plane - 1) / per_plane);
     }
     chunk = std::min(std::max(chunk, 1), std::max(rows, 1));
     sh.chunk = chunk;

@@ -269,7 +269,9 @@ def test_fused_passes_match_per_step_kernels(P, shape):
     ha, hb = host(pa), host(pb)
     assert sa["cycles"] == sb["cycles"] == 6
     assert rel_l2(ha, hb) <= 1e-14, rel_l2(ha, hb)
-    np.testing.assert_allclose(sa["history"][:6], sb["history"][:6], rtol=1e-9)
+    # relative residuals agree to 1e-9, down to the floor of evaluating a
+    # residual in FP64 (about 1e-16 of ||b||; 1e-15 allowed)
+    np.testing.assert_allclose(sa["history"][:6], sb["history"][:6], rtol=1e-9, atol=1e-15)
 
 
 @pytest.mark.parametrize("chunk", [1, 5, 16, 1000])

@@ -37,6 +37,7 @@ __all__ = [
     "random_problems",
     "stretched_points",
     "mesh_blob_charge",
+    "cell_centres",
 ]
 
 
@@ -219,6 +220,13 @@ def stretched_points(a: float, b: float, n: int, beta: float) -> np.ndarray:
     x = a + (b - a) * np.concatenate([[0.0], np.cumsum(w) / w.sum()])
     x[-1] = b
     return x
+
+
+def cell_centres(faces) -> np.ndarray:
+    """Node coordinates of a cell-centred direction with the given faces: the
+    first face, the cell midpoints, the last face (where the Dirichlet values sit)."""
+    f = np.asarray(faces, dtype=np.float64)
+    return np.concatenate([f[:1], 0.5 * (f[:-1] + f[1:]), f[-1:]])
 
 
 def mesh_blob_charge(r, z, ntheta: int, seed: int = 24680) -> np.ndarray:
