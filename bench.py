@@ -408,9 +408,13 @@ def time_learned(problem, rho_d, args, ref, phit):
     torch.cuda.synchronize()
     fwd_ms = e0.elapsed_time(e1) / 5
     flops = 2.0 * npairs * H * Wd * (9 * 4 * 16 + 9 * 16 * 16 + 9 * 16 * 2)
+    # algorithmic HBM bytes: read 4 FP32 inputs, write 2 FP32 outputs per pixel
+    nbytes = 24.0 * npairs * H * Wd
     out["network_forward"] = {"pixels": npairs * H * Wd, "ms": round(fwd_ms, 4),
                               "tflops": round(flops / (fwd_ms * 1e-3) / 1e12, 2),
-                              "mfma_bf16_peak_tflops": 2500.0}
+                              "mfma_bf16_peak_tflops": 2500.0,
+                              "hbm_gbs": round(nbytes / (fwd_ms * 1e-3) / 1e9, 1), "hbm_peak_gbs": HBM_PEAK_GBS,
+                              "roofline_ms": round(max(flops / 2.5e15, nbytes / (HBM_PEAK_GBS * 1e9)) * 1e3, 4)}
     log(f"learned: {out['ms']:.3f} ms/solve, FGMRES rates {rates}, V-cycle {st['vcycle_rate']:.3f}, "
         f"fell back {st['learned_fallback']}; network forward {fwd_ms:.3f} ms")
     for q in (lplan, plan):

@@ -341,7 +341,7 @@ hipError_t learned_precond(cylpoisson_plan* p, const double* v, double* z, hipSt
     k_net_input<<<g, 256, 0, s>>>(lv, p->d_lam, v, p->net_sc, p->net_x, p->nt, p->d_r0,
                                   p->r_out - p->r_in);
     e = hipGetLastError();
-    if (e == hipSuccess) e = net_forward(n, p->net_x, p->net_y, npairs, H, W, s);
+    if (e == hipSuccess) e = net_infer(n, p->net_x, p->net_y, npairs, H, W, s);
     if (e != hipSuccess) return e;
     k_net_output<<<g, 256, 0, s>>>(lv, p->d_lam, p->net_y, p->net_sc, z, p->nt);
     return hipGetLastError();
@@ -455,7 +455,7 @@ int cylpoisson_nn_get_grads(const cylpoisson_nn* nn, float* out, int count) {
 
 int cylpoisson_nn_forward(cylpoisson_nn* nn, const float* x, float* y, int B, int H, int W, void* stream) {
     if (!nn || !x || !y || B < 1 || H < 1 || W < 1) return fail(CYLPOISSON_EINVAL, "invalid network arguments");
-    return hip_status(net_forward(&nn->st, x, y, B, H, W, static_cast<hipStream_t>(stream)), "network forward");
+    return hip_status(net_infer(&nn->st, x, y, B, H, W, static_cast<hipStream_t>(stream)), "network forward");
 }
 
 int cylpoisson_nn_loss_grad(cylpoisson_nn* nn, const float* x, const float* t, int B, int H, int W,

@@ -230,6 +230,106 @@ __global__ void k_pack(const float* __restrict__ w, short* __restrict__ wf, shor
     }
 }
 
+// ---- fused inference: all three layers of one output tile in one workgroup ----
+// The tile's input (halo 3), first activation (halo 2) and second activation
+// (halo 1) stay in LDS as BF16, so every operand of a product is one 8-byte
+// LDS read (channels fastest) and nothing but the input and the output
+// touches HBM.  Activations are rounded to BF16 where they are stored, which
+// is where the per-layer kernels round them (as they enter the next product),
+// and the products run over the same K blocks in the same order, so the
+// result equals theirs.  Pixels outside the image hold zero (zero padding).
+constexpr int kFTH = 16, kFTW = 32;  // output tile: rows x columns
+constexpr int kFS = 20;              // LDS stride of an activation pixel (BF16 values; 40 B, 8-aligned)
+constexpr int kFIH = kFTH + 6, kFIW = kFTW + 6;
+constexpr int kFA1H = kFTH + 4, kFA1W = kFTW + 4;
+constexpr int kFA2H = kFTH + 2, kFA2W = kFTW + 2;
+constexpr size_t kFusedLds =
+    ((size_t)kFIH * kFIW * 4 + (size_t)kFA1H * kFA1W * kFS + (size_t)kFA2H * kFA2W * kFS) * sizeof(short);
+
+// One layer over an OH x OW region whose source region (SS values per pixel)
+// is one pixel larger on every side.  (oy0, ox0): image position of the
+// region's first pixel.  FINAL writes the NOUT valid channels to the image y.
+template <int CIN, int NOUT, bool RELU, bool FINAL, int OH, int OW, int SS>
+__device__ __forceinline__ void fused_layer(const short* __restrict__ src, short* __restrict__ dst,
+                                            const short* __restrict__ wpk, int oy0, int ox0, int H, int W,
+                                            float* __restrict__ yimg) {
+    constexpr int KB = (9 * CIN + 15) / 16;
+    constexpr int SW = OW + 2;
+    constexpr int NPIX = OH * OW, NT = (NPIX + 15) / 16;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    const int row = lane & 15, g = lane >> 4;
+    v4s bw[KB];
+#pragma unroll
+    for (int kb = 0; kb < KB; ++kb)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) bw[kb][j] = wpk[(kb * 16 + g * 4 + j) * 16 + row];
+    for (int tile = wave; tile < NT; tile += nw) {
+        const int q = tile * 16 + row;  // this lane's pixel in the A operand
+        const bool qv = q < NPIX;
+        const int qr = qv ? q / OW : 0, qc = qv ? q % OW : 0;
+        v4f acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int kb = 0; kb < KB; ++kb) {
+            // k = t * CIN + c: 4 taps x 4 channels per block (CIN = 4) or one tap x 16 channels
+            const int t = CIN == 4 ? kb * 4 + g : kb;
+            const int c0 = CIN == 4 ? 0 : g * 4;
+            v4s a = {0, 0, 0, 0};
+            if (qv && t < 9) {
+                int dy, dx;
+                tap_offset(t, &dy, &dx);
+                a = *(const v4s*)(src + ((qr + 1 + dy) * SW + (qc + 1 + dx)) * SS + c0);
+            }
+            acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, bw[kb], acc, 0, 0, 0);
+        }
+        // acc[j] = C[pixel 4 g + j of the tile][channel row]
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int pq = tile * 16 + 4 * g + j;
+            if (pq >= NPIX) continue;
+            const int pr = pq / OW, pc = pq % OW;
+            const int gy = oy0 + pr, gx = ox0 + pc;
+            const bool inside = gy >= 0 && gy < H && gx >= 0 && gx < W;
+            float v = acc[j];
+            if (RELU) v = fmaxf(v, 0.f);
+            if (!FINAL)
+                dst[pq * kFS + row] = inside ? to_bf16(v) : (short)0;
+            else if (row < NOUT && inside)
+                yimg[((long long)gy * W + gx) * NOUT + row] = v;
+        }
+    }
+}
+
+constexpr int kFusedThreads = 1024;  // 16 waves; the LDS (60 KB) allows two workgroups per compute unit
+
+__global__ void __launch_bounds__(kFusedThreads) k_net_fused(const float* __restrict__ x, const short* __restrict__ w0,
+                                                   const short* __restrict__ w1, const short* __restrict__ w2,
+                                                   float* __restrict__ y, int H, int W) {
+    extern __shared__ short sm_net[];
+    short* in = sm_net;
+    short* a1 = in + kFIH * kFIW * 4;
+    short* a2 = a1 + kFA1H * kFA1W * kFS;
+    const int b = blockIdx.y;
+    const int tiles_x = (W + kFTW - 1) / kFTW;
+    const int y0 = (blockIdx.x / tiles_x) * kFTH, x0 = (blockIdx.x % tiles_x) * kFTW;
+    const float* img = x + (long long)b * H * W * 4;
+    for (int q = threadIdx.x; q < kFIH * kFIW; q += blockDim.x) {
+        const int gy = y0 - 3 + q / kFIW, gx = x0 - 3 + q % kFIW;
+        v4s v = {0, 0, 0, 0};
+        if (gy >= 0 && gy < H && gx >= 0 && gx < W) {
+            const float* px = img + ((long long)gy * W + gx) * 4;  // only 4-byte alignment is assumed
+#pragma unroll
+            for (int c = 0; c < 4; ++c) v[c] = to_bf16(px[c]);
+        }
+        *(v4s*)(in + q * 4) = v;
+    }
+    __syncthreads();
+    fused_layer<4, 16, true, false, kFA1H, kFA1W, 4>(in, a1, w0, y0 - 2, x0 - 2, H, W, nullptr);
+    __syncthreads();
+    fused_layer<16, 16, true, false, kFA2H, kFA2W, kFS>(a1, a2, w1, y0 - 1, x0 - 1, H, W, nullptr);
+    __syncthreads();
+    fused_layer<16, 2, false, true, kFTH, kFTW, kFS>(a2, nullptr, w2, y0, x0, H, W, y + (long long)b * H * W * 2);
+}
+
 template <int KIN, int NOUT, bool BWD, bool RELU>
 hipError_t conv_t(const float* src, const short* wpk, float* out, const float* mask, int B, int H, int W,
                   hipStream_t s) {
@@ -296,6 +396,20 @@ hipError_t net_forward(NetState* n, const float* x, float* y, int B, int H, int 
     if (e == hipSuccess) e = conv_t<16, 16, false, true>(n->a1, n->wf[1], n->a2, nullptr, B, H, W, s);
     if (e == hipSuccess) e = conv_t<16, 2, false, false>(n->a2, n->wf[2], y, nullptr, B, H, W, s);
     return e;
+}
+
+hipError_t net_infer(NetState* n, const float* x, float* y, int B, int H, int W, hipStream_t s) {
+    static bool lds_set = false;  // the attribute is per function, once per process
+    if (!lds_set) {
+        hipError_t e = hipFuncSetAttribute((const void*)k_net_fused, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                           (int)kFusedLds);
+        if (e != hipSuccess) return e;
+        lds_set = true;
+    }
+    if (B <= 0 || H <= 0 || W <= 0) return hipSuccess;
+    const unsigned tiles = (unsigned)(((H + kFTH - 1) / kFTH) * ((W + kFTW - 1) / kFTW));
+    k_net_fused<<<dim3(tiles, (unsigned)B), kFusedThreads, kFusedLds, s>>>(x, n->wf[0], n->wf[1], n->wf[2], y, H, W);
+    return hipGetLastError();
 }
 
 hipError_t net_loss_grad(NetState* n, const float* x, const float* t, int B, int H, int W, double* loss,

@@ -34,8 +34,11 @@ size_t net_weight_offset(int layer);
 int net_total_weights();
 hipError_t net_repack(NetState* n, hipStream_t s);
 hipError_t net_reserve(NetState* n, long long pixels);
-// y = net(x) for B images of H x W (x: 4 channels, y: 2 channels)
+// y = net(x) for B images of H x W (x: 4 channels, y: 2 channels), one kernel
+// per layer with the activations kept in n->a1, n->a2 (for back-propagation)
 hipError_t net_forward(NetState* n, const float* x, float* y, int B, int H, int W, hipStream_t s);
+// The same y from one fused kernel (activations in LDS only): inference
+hipError_t net_infer(NetState* n, const float* x, float* y, int B, int H, int W, hipStream_t s);
 // forward, loss on the inner pixels (host value if loss != nullptr) and all weight gradients into dw
 hipError_t net_loss_grad(NetState* n, const float* x, const float* t, int B, int H, int W, double* loss,
                          hipStream_t s);

@@ -53,8 +53,11 @@ def f32(x):
     return torch.from_numpy(np.ascontiguousarray(x, dtype=np.float32)).to("cuda:0")
 
 
-@pytest.mark.parametrize("shape", [(2, 16, 16), (3, 20, 37), (1, 9, 70)])
+@pytest.mark.parametrize("shape", [(2, 16, 16), (3, 20, 37), (1, 9, 70), (1, 1, 1), (2, 5, 3), (1, 17, 65),
+                                   (2, 33, 129), (1, 48, 200)])
 def test_forward_matches_oracle(P, shape):
+    """The fused inference kernel (16 x 64 output tiles, halos in LDS): one
+    pixel, tiles cut by the image edges, several tiles each way."""
     B, H, Wd = shape
     params = nn.init_params(5)
     net = P.Net(seed=1)
