@@ -60,8 +60,12 @@ __device__ void lds_smooth(const BottomLevel& L, T* sm, double lam, int sweeps, 
     }
 }
 
+// One workgroup per plane: 1024 threads (few registers), so the small levels'
+// sweeps take fewer passes between barriers.
+constexpr int kBottomThreads = 1024;
+
 template <typename T>
-__global__ void __launch_bounds__(512) k_bottom(BottomArgs<T> a) {
+__global__ void __launch_bounds__(kBottomThreads) k_bottom(BottomArgs<T> a) {
     extern __shared__ double smem_bottom[];
     T* sm = (T*)smem_bottom;
     const int p = a.p0 + blockIdx.x;
@@ -221,7 +225,7 @@ hipError_t launch_bottom_t(cylpoisson_plan* p, const T* f_in, T* u_out, hipStrea
     a.p0 = p0;
     a.mask = p->mask_live ? p->d_mask : nullptr;
     const size_t bytes = bottom_lds_bytes(p, lb) / sizeof(double) * sizeof(T);
-    k_bottom<T><<<np, 512, bytes, s>>>(a);
+    k_bottom<T><<<np, kBottomThreads, bytes, s>>>(a);
     return hipGetLastError();
 }
 

@@ -334,9 +334,9 @@ void reset_stats(cylpoisson_plan* p) {
 // arguments depend only on the plan, its options and the cycle index (norm
 // slot), so a replay equals the eager launches.  Options that change launch
 // parameters drop the cache.
-bool graphs_active(const cylpoisson_plan* p, int G) {
-    return p->opt.graph && G == 1 && !p->opt.timing && mixed_supported(p);
-}
+// Any V-cycle path can be captured: it launches kernels only (no memset or
+// copy); the per-step path's norms are formed outside the graph.
+bool graphs_active(const cylpoisson_plan* p, int G) { return p->opt.graph && G == 1 && !p->opt.timing; }
 
 hipError_t graph_cycle(cylpoisson_plan* p, hipStream_t s, int c, bool zero_top, NormSlot* ns) {
     const int key = 2 * c + (zero_top ? 1 : 0);

@@ -100,6 +100,22 @@ def test_masks_on_a_full_spectrum_match_the_oracle(P):
 
 
 # -------------------------------------------------------------- graphs
+@pytest.mark.parametrize("options", [dict(fused=0), dict(smoother=2)], ids=["per-step", "lines"])
+def test_graph_replays_on_the_per_step_path(P, options):
+    """The one-kernel-per-step V-cycle (and the line smoothers on it) is captured
+    and replayed too, bitwise equal to eager launches on every replay."""
+    p = W.SMALL.with_sizes(65, 8, 49)
+    eager = P.Plan.for_problem(p, **options)
+    graph = P.Plan.for_problem(p, graph=1, **options)
+    say("graph per-step", options)
+    for seed in (1, 2, 3):
+        r = dev(W.blob_charge(p, seed=seed))
+        a, sa = eager.solve(r, tol=1e-13)
+        b, sb = graph.solve(r, tol=1e-13)
+        assert sa["cycles"] == sb["cycles"] and sb["status"] == P.OK
+        np.testing.assert_array_equal(host(a), host(b))
+
+
 def test_graph_replays_equal_eager_launches(P):
     """Each cycle's graph is captured on the first solve and replayed on later
     ones; every replay (with eager work and synchronisations in between) must
