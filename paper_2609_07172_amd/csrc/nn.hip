@@ -399,14 +399,12 @@ hipError_t net_forward(NetState* n, const float* x, float* y, int B, int H, int 
 }
 
 hipError_t net_infer(NetState* n, const float* x, float* y, int B, int H, int W, hipStream_t s) {
-    static bool lds_set = false;  // the attribute is per function, once per process
-    if (!lds_set) {
-        hipError_t e = hipFuncSetAttribute((const void*)k_net_fused, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                           (int)kFusedLds);
-        if (e != hipSuccess) return e;
-        lds_set = true;
-    }
     if (B <= 0 || H <= 0 || W <= 0) return hipSuccess;
+    // more than the default 64 KB of dynamic LDS: allowed on the current device
+    // at every launch (a host call of a few microseconds)
+    hipError_t e = hipFuncSetAttribute((const void*)k_net_fused, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)kFusedLds);
+    if (e != hipSuccess) return e;
     const unsigned tiles = (unsigned)(((H + kFTH - 1) / kFTH) * ((W + kFTW - 1) / kFTW));
     k_net_fused<<<dim3(tiles, (unsigned)B), kFusedThreads, kFusedLds, s>>>(x, n->wf[0], n->wf[1], n->wf[2], y, H, W);
     return hipGetLastError();

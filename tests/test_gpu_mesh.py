@@ -273,3 +273,23 @@ def test_smoother_option_errors(P):
     with pytest.raises(P.CylPoissonError) as e:
         plan.solve(dev(np.zeros(W.SMALL.shape)), tol=1e-12)
     assert e.value.status == P.EINVAL
+
+
+# near-isotropic cells (dr ~ dz = 3e-5 m) so that FP64 resolves the answer to
+# far below 1e-12; extremely flat cells put the oracle's own residual near 1e-11
+LONG_LINES = {"long-r-lines": W.Problem(1030, 2, 9, 0.02, 0.05, 3e-5, name="long-r"),
+              "long-z-lines": W.Problem(9, 2, 1030, 0.02, 0.02 + 8 * 3e-5, 3e-5, name="long-z")}
+
+
+@pytest.mark.parametrize("name", list(LONG_LINES))
+def test_long_lines_use_the_thomas_sweeps(P, name):
+    """Lines longer than 1024 unknowns (past one workgroup of cyclic reduction)
+    are solved by a Thomas sweep per thread; the result is the oracle's."""
+    p = LONG_LINES[name]
+    rho = W.blob_charge(p, seed=5)
+    ref = solvers.solve_separable(fv.Grid.of(p), rho, p.bc)
+    say("long lines", name, p.shape)
+    for sm in (1, 2):
+        phi, st = P.Plan.for_problem(p, smoother=sm).solve(dev(rho), tol=1e-13)
+        assert st["status"] == P.OK, (sm, st)
+        assert rel_l2(host(phi), ref) <= 1e-12, (sm, rel_l2(host(phi), ref))
