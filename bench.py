@@ -541,6 +541,19 @@ def main():
         torch.cuda.synchronize()
         log(f"copy probe: {args.copy_probe} MiB x 3")
 
+    # practical HBM peak: a plain 1 GiB device-to-device copy (reads and writes 1 GiB)
+    csrc = torch.ones((1 << 30) // 8, dtype=torch.float64, device=dev)
+    cdst = torch.empty_like(csrc)
+    cdst.copy_(csrc)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(5):
+        cdst.copy_(csrc)
+    e1.record()
+    torch.cuda.synchronize()
+    copy_gbs = 2.0 * (1 << 30) * 5 / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del csrc, cdst
+
     b = alg_bytes(info, problem.ntheta)
     up_avg_ms = sums["fine_up"] / max(1, launches["fine_up"])
     down_avg_ms = sums["fine_down"] / max(1, launches["fine_down"])
@@ -581,6 +594,14 @@ def main():
         "ms_without_events": round(ms_plain, 4),
         "ms_min": round(min(per) * 1e3, 4),
         "ms_p50": round(float(np.median(per)) * 1e3, 4),
+        # the whole solve against the algorithmic byte model: 16 B per node and per
+        # unknown for the transforms, 69.3 B per unknown and V-cycle
+        "solve_roofline": {"model_bytes": 16.0 * problem.nodes + 16.0 * unknowns + 69.3 * st["cycles"] * unknowns,
+                           "t_roof_ms": round((16.0 * problem.nodes + 16.0 * unknowns
+                                               + 69.3 * st["cycles"] * unknowns) / (HBM_PEAK_GBS * 1e9) * 1e3, 4),
+                           "frac": round((16.0 * problem.nodes + 16.0 * unknowns + 69.3 * st["cycles"] * unknowns)
+                                         / (HBM_PEAK_GBS * 1e9) / (ms_plain * 1e-3), 4)},
+        "copy_gbs": round(copy_gbs, 1),
         "dof_cycles_per_s": unknowns * st["cycles"] / (ms * 1e-3),
         "poisson_cells_per_s": problem.nodes / (ms * 1e-3),
         "kernel_ms_per_solve": {k: round(v / args.steps, 4) for k, v in sums.items()},

@@ -20,6 +20,7 @@ struct BottomArgs {
     const BottomLevel* lv;  // levels handled here, finest first
     int nlev;
     int off_r;              // LDS offset of the residual scratch (finest level's size)
+    int tab_bytes;          // byte offset of the coefficient tables (doubles) in LDS
     const T* f_in;          // right-hand side of the finest level here (global)
     T* u_out;               // its solution (global, interior written)
     const double* lam;
@@ -33,10 +34,27 @@ struct BottomArgs {
 
 __device__ __forceinline__ int interior(const LevelView& v) { return (v.nr - 2) * (v.nz - 2); }
 
+// A level's coefficient tables as copied into LDS at the start of the kernel.
+struct LdsTables {
+    const double *rw, *re, *rb, *rm, *zc, *zs, *zn;
+};
+
+__device__ __forceinline__ LdsTables lds_tables(const BottomLevel& L, const double* tab) {
+    const double* b = tab + L.off_tab;
+    const int nr = L.v.nr, nz = L.v.nz;
+    return LdsTables{b, b + nr, b + 2 * nr, b + 3 * nr, b + 4 * nr, b + 4 * nr + nz, b + 4 * nr + 2 * nz};
+}
+
+// coef_at from the LDS copy of the tables: the same values, the same expression.
+__device__ __forceinline__ Coef coef_lds(const LdsTables& t, int i, int k, double lam) {
+    return make_coef(t.rw[i], t.re[i], t.rb[i], t.rm[i], t.zc[k], t.zs[k], t.zn[k], lam);
+}
+
 // One red-black colour on level L in LDS.
 template <typename T>
-__device__ void lds_half_sweep(const BottomLevel& L, T* sm, double lam, int color, T omega) {
+__device__ void lds_half_sweep(const BottomLevel& L, T* sm, const double* tab, double lam, int color, T omega) {
     const LevelView& v = L.v;
+    const LdsTables tb = lds_tables(L, tab);
     T* u = sm + L.off_u;
     const T* f = sm + L.off_f;
     const int ni = v.nr - 2, nk = v.nz - 2;
@@ -46,17 +64,17 @@ __device__ void lds_half_sweep(const BottomLevel& L, T* sm, double lam, int colo
         const int i = 2 - (color ^ (k & 1)) + 2 * (q % hw);
         if (i > v.nr - 2) continue;
         const int o = k * v.nr + i;
-        const CoefT<T> c = coef_as<T>(coef_at(v, i, k, lam));
+        const CoefT<T> c = coef_as<T>(coef_lds(tb, i, k, lam));
         u[o] = relax(u[o], f[o], u[o - 1], u[o + 1], u[o - v.nr], u[o + v.nr], c, omega);
     }
     __syncthreads();
 }
 
 template <typename T>
-__device__ void lds_smooth(const BottomLevel& L, T* sm, double lam, int sweeps, T omega) {
+__device__ void lds_smooth(const BottomLevel& L, T* sm, const double* tab, double lam, int sweeps, T omega) {
     for (int s = 0; s < sweeps; ++s) {
-        lds_half_sweep(L, sm, lam, 0, omega);
-        lds_half_sweep(L, sm, lam, 1, omega);
+        lds_half_sweep(L, sm, tab, lam, 0, omega);
+        lds_half_sweep(L, sm, tab, lam, 1, omega);
     }
 }
 
@@ -68,6 +86,7 @@ template <typename T>
 __global__ void __launch_bounds__(kBottomThreads) k_bottom(BottomArgs<T> a) {
     extern __shared__ double smem_bottom[];
     T* sm = (T*)smem_bottom;
+    double* tab = (double*)((char*)smem_bottom + a.tab_bytes);
     const int p = a.p0 + blockIdx.x;
     if (a.mask && a.mask[p] == 0) return;  // whole workgroup, before any barrier
     const double lam = a.lam[p];
@@ -79,6 +98,23 @@ __global__ void __launch_bounds__(kBottomThreads) k_bottom(BottomArgs<T> a) {
         for (int q = threadIdx.x; q < total; q += blockDim.x) sm[q] = T(0);
         const BottomLevel& F = a.lv[0];
         for (int q = threadIdx.x; q < F.v.nr * F.v.nz; q += blockDim.x) sm[a.off_r + q] = T(0);
+        // every level's coefficient tables into LDS (read in every phase below)
+        for (int l = 0; l < a.nlev; ++l) {
+            const BottomLevel& L = a.lv[l];
+            const int nr = L.v.nr, nz = L.v.nz;
+            double* t = tab + L.off_tab;
+            for (int q = threadIdx.x; q < nr; q += blockDim.x) {
+                t[q] = L.v.rw[q];
+                t[nr + q] = L.v.re[q];
+                t[2 * nr + q] = L.v.rb[q];
+                t[3 * nr + q] = L.v.rm[q];
+            }
+            for (int q = threadIdx.x; q < nz; q += blockDim.x) {
+                t[4 * nr + q] = L.v.zc[q];
+                t[4 * nr + nz + q] = L.v.zs[q];
+                t[4 * nr + 2 * nz + q] = L.v.zn[q];
+            }
+        }
     }
     __syncthreads();
     {
@@ -95,7 +131,8 @@ __global__ void __launch_bounds__(kBottomThreads) k_bottom(BottomArgs<T> a) {
     for (int l = 0; l + 1 < a.nlev; ++l) {
         const BottomLevel& L = a.lv[l];
         const BottomLevel& C = a.lv[l + 1];
-        lds_smooth(L, sm, lam, a.nu1, omega);
+        lds_smooth(L, sm, tab, lam, a.nu1, omega);
+        const LdsTables tb = lds_tables(L, tab);
         const LevelView& v = L.v;
         const int ni = v.nr - 2;
         T* r = sm + a.off_r;
@@ -105,7 +142,7 @@ __global__ void __launch_bounds__(kBottomThreads) k_bottom(BottomArgs<T> a) {
             const int i = q % ni + 1, k = q / ni + 1;
             const int o = k * v.nr + i;
             r[o] = residual(u[o], f[o], u[o - 1], u[o + 1], u[o - v.nr], u[o + v.nr],
-                            coef_as<T>(coef_at(v, i, k, lam)));
+                            coef_as<T>(coef_lds(tb, i, k, lam)));
         }
         __syncthreads();
         const int nci = C.v.nr - 2;
@@ -138,7 +175,7 @@ __global__ void __launch_bounds__(kBottomThreads) k_bottom(BottomArgs<T> a) {
             const int i = q % ni + 1, k = q / ni + 1;
             const int o = k * C.v.nr + i;
             tmp[q] = residual(u[o], f[o], u[o - 1], u[o + 1], u[o - C.v.nr], u[o + C.v.nr],
-                              coef_as<T>(coef_at(C.v, i, k, lam)));
+                              coef_as<T>(coef_lds(lds_tables(C, tab), i, k, lam)));
         }
         __syncthreads();
         T* corr = tmp + n;
@@ -171,7 +208,7 @@ __global__ void __launch_bounds__(kBottomThreads) k_bottom(BottomArgs<T> a) {
                                              (T)L.tz.pwl[k], (T)L.tz.pwr[k]);
         }
         __syncthreads();
-        lds_smooth(L, sm, lam, a.nu2, omega);
+        lds_smooth(L, sm, tab, lam, a.nu2, omega);
     }
     {
         const BottomLevel& F = a.lv[0];
@@ -186,15 +223,26 @@ __global__ void __launch_bounds__(kBottomThreads) k_bottom(BottomArgs<T> a) {
 
 }  // namespace
 
-// LDS of the FP64 bottom kernel; the FP32 one has the same layout in floats.
-size_t bottom_lds_bytes(const cylpoisson_plan* p, int lb) {
+// LDS layout of the bottom kernel for value type size vt: every level's
+// iterate and right-hand side and the residual scratch (value type), then
+// (8-byte aligned) every level's coefficient tables (doubles).
+static size_t bottom_tab_offset(const cylpoisson_plan* p, int lb, size_t vt) {
     const int nl = (int)p->hl.size();
     size_t n = 0;
     for (int l = lb; l < nl; ++l) n += 2 * (size_t)p->hl[l].nr * p->hl[l].nz;
     size_t r = (size_t)p->hl[lb].nr * p->hl[lb].nz;
     r = std::max(r, (size_t)2 * p->coarse_n);
-    return (n + r) * sizeof(double);
+    return ((n + r) * vt + 7) & ~(size_t)7;
 }
+
+static size_t bottom_lds_bytes_t(const cylpoisson_plan* p, int lb, size_t vt) {
+    size_t tab = 0;
+    for (int l = lb; l < (int)p->hl.size(); ++l) tab += 4 * (size_t)p->hl[l].nr + 3 * (size_t)p->hl[l].nz;
+    return bottom_tab_offset(p, lb, vt) + tab * sizeof(double);
+}
+
+// LDS of the FP64 bottom kernel (the FP32 one needs less).
+size_t bottom_lds_bytes(const cylpoisson_plan* p, int lb) { return bottom_lds_bytes_t(p, lb, sizeof(double)); }
 
 namespace {
 
@@ -214,6 +262,7 @@ hipError_t launch_bottom_t(cylpoisson_plan* p, const T* f_in, T* u_out, hipStrea
     a.lv = p->d_bottom;
     a.nlev = (int)p->hl.size() - lb;
     a.off_r = p->bottom_off_r;
+    a.tab_bytes = (int)bottom_tab_offset(p, p->bottom_level, sizeof(T));
     a.f_in = f_in;
     a.u_out = u_out;
     a.lam = p->d_lam;
@@ -224,7 +273,7 @@ hipError_t launch_bottom_t(cylpoisson_plan* p, const T* f_in, T* u_out, hipStrea
     a.omega = p->opt.omega;
     a.p0 = p0;
     a.mask = p->mask_live ? p->d_mask : nullptr;
-    const size_t bytes = bottom_lds_bytes(p, lb) / sizeof(double) * sizeof(T);
+    const size_t bytes = bottom_lds_bytes_t(p, lb, sizeof(T));
     k_bottom<T><<<np, kBottomThreads, bytes, s>>>(a);
     return hipGetLastError();
 }
@@ -234,7 +283,7 @@ hipError_t launch_bottom_t(cylpoisson_plan* p, const T* f_in, T* u_out, hipStrea
 hipError_t bottom_prepare(const cylpoisson_plan* p, int lb) {
     const size_t bytes = bottom_lds_bytes(p, lb);
     hipError_t e = bottom_prepare_t<double>(bytes);
-    if (e == hipSuccess) e = bottom_prepare_t<float>(bytes / 2);
+    if (e == hipSuccess) e = bottom_prepare_t<float>(bottom_lds_bytes_t(p, lb, sizeof(float)));
     return e;
 }
 

@@ -86,7 +86,9 @@ struct DeviceLevel32 {
 struct BottomLevel {
     LevelView v;
     Transfer1D tr, tz;
-    int off_u, off_f;
+    int off_u, off_f;  // iterate and right-hand side (value-type elements)
+    int off_tab;       // coefficient tables rw, re, rb, rm (nr each), zc, zs, zn (nz each),
+                       // in doubles from the start of the table region
 };
 
 struct HostLevel {

@@ -592,7 +592,7 @@ cylpoisson_plan* build_plan(cylpoisson_plan* p) {
                 continue;
             }
             std::vector<BottomLevel> bl;
-            int off = 0;
+            int off = 0, tab = 0;
             for (int l = lb; l < nl; ++l) {
                 BottomLevel b{};
                 b.v = p->dl[l].v;
@@ -602,6 +602,8 @@ cylpoisson_plan* build_plan(cylpoisson_plan* p) {
                 off += p->hl[l].nr * p->hl[l].nz;
                 b.off_f = off;
                 off += p->hl[l].nr * p->hl[l].nz;
+                b.off_tab = tab;
+                tab += 4 * p->hl[l].nr + 3 * p->hl[l].nz;
                 bl.push_back(b);
             }
             p->bottom_off_r = off;
