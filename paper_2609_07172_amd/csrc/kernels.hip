@@ -651,12 +651,15 @@ hipError_t launch_coarse_solve(const DeviceLevel& L, int nt, const double* lam, 
     return hipGetLastError();
 }
 
-// Blocks per plane of the norm kernels: one per interior row, at most kMaxPartial.
-static int norm_blocks(const LevelView& v) { return std::max(1, std::min(kMaxPartial, v.nz - 2)); }
+// Blocks per plane of the norm kernels: about 4096 blocks in all (each takes
+// every nb-th interior row), at most one per row and kMaxPartial per plane.
+static int norm_blocks(const LevelView& v, int nt) {
+    return std::max(1, std::min(std::min(kMaxPartial, v.nz - 2), 4096 / std::max(1, nt)));
+}
 
 hipError_t launch_plane_norms(const DeviceLevel& L, int nt, const double* r, double* partial,
                               double* norms_out, hipStream_t s) {
-    const int nb = norm_blocks(L.v);
+    const int nb = norm_blocks(L.v, nt);
     k_norm_partial<<<dim3(nb, nt), 256, 0, s>>>(L.v, r, partial);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
@@ -732,7 +735,7 @@ hipError_t launch_refine(const DeviceLevel& L, int nt, const double* lam, const 
 
 hipError_t launch_rhs_norms(const DeviceLevel& L, int nt, const double* lam, const double* u,
                             const double* f, double* partial, double* norms_out, hipStream_t s) {
-    const int nb = norm_blocks(L.v);
+    const int nb = norm_blocks(L.v, nt);
     k_rhs_norm_partial<<<dim3(nb, nt), 256, 0, s>>>(L.v, lam, u, f, partial);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;

@@ -500,15 +500,19 @@ int run_cycles(cylpoisson_plan* p, double tol, hipStream_t s, bool ring_only, bo
         if (c != next_check && c != maxc) continue;
         CP_HIP(join_groups(p, G, s));
         const int first = last_read + 1;
-        for (int t = first; t <= c; ++t) {
-            if (slots[t].partial_chunks > 0)
-                CP_HIP(hipMemcpyAsync(p->h_slot_partial + (size_t)t * nt * kSlotPartial,
-                                      p->d_slot_partial + (size_t)t * nt * kSlotPartial,
-                                      (size_t)nt * kSlotPartial * sizeof(double),
-                                      hipMemcpyDeviceToHost, s));
-            else
-                CP_HIP(hipMemcpyAsync(p->h_norms + (size_t)t * nt, p->d_norms + (size_t)t * nt,
-                                      (size_t)nt * sizeof(double), hipMemcpyDeviceToHost, s));
+        // one copy per kind of slot for the cycles since the last check (the
+        // slots of consecutive cycles are contiguous; unused ones ride along)
+        {
+            bool any_partial = false, any_norms = false;
+            for (int t = first; t <= c; ++t) (slots[t].partial_chunks > 0 ? any_partial : any_norms) = true;
+            const size_t nslots = (size_t)(c - first + 1);
+            if (any_partial)
+                CP_HIP(hipMemcpyAsync(p->h_slot_partial + (size_t)first * nt * kSlotPartial,
+                                      p->d_slot_partial + (size_t)first * nt * kSlotPartial,
+                                      nslots * nt * kSlotPartial * sizeof(double), hipMemcpyDeviceToHost, s));
+            if (any_norms)
+                CP_HIP(hipMemcpyAsync(p->h_norms + (size_t)first * nt, p->d_norms + (size_t)first * nt,
+                                      nslots * nt * sizeof(double), hipMemcpyDeviceToHost, s));
         }
         CP_HIP(hipStreamSynchronize(s));
         ++st.checks;
