@@ -475,6 +475,24 @@ cylpoisson_plan* build_plan(cylpoisson_plan* p) {
         p->lam[q] = 4.0 / (p->dtheta * p->dtheta) * s * s;
     }
     build_levels(p);
+    // every table entry, and the source scale rb zc / eps0, must be finite:
+    // geometry beyond the double range is rejected here
+    for (const HostLevel& H : p->hl) {
+        bool ok = true;
+        double zmax = 0.0;
+        for (int k = 1; k + 1 < H.nz && ok; ++k) {
+            ok = std::isfinite(H.zc[k]) && std::isfinite(H.zs[k]) && std::isfinite(H.zn[k]);
+            zmax = std::max(zmax, H.zc[k]);
+        }
+        for (int i = 1; i + 1 < H.nr && ok; ++i)
+            ok = std::isfinite(H.rw[i]) && std::isfinite(H.re[i]) && std::isfinite(H.rm[i]) &&
+                 std::isfinite(H.rb[i] * zmax / kEps0);
+        if (!ok) {
+            set_error("grid geometry gives non-finite finite-volume coefficients");
+            delete p;
+            return nullptr;
+        }
+    }
     {
         const HostLevel& Hc = p->hl.back();
         const long long nc = (long long)(Hc.nr - 2) * (Hc.nz - 2);
@@ -736,8 +754,9 @@ bool mesh_axis(const double* in, int n, int layout, bool positive, const char* n
         }
     }
     for (int i = 1; i < n; ++i)
-        if (!(x[i] > x[i - 1]) || (i + 1 < n && !(lo[i] < x[i] && x[i] < hi[i]))) {
-            set_error("%s: nodes and faces must stay strictly increasing after rounding", name);
+        if (!std::isfinite(x[i]) || !std::isfinite(lo[i]) || !std::isfinite(hi[i]) || !(x[i] > x[i - 1]) ||
+            (i + 1 < n && !(lo[i] < x[i] && x[i] < hi[i]))) {
+            set_error("%s: nodes and faces must stay finite and strictly increasing after rounding", name);
             return false;
         }
     return true;

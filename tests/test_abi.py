@@ -73,6 +73,7 @@ def test_null_plan_and_status_strings():
     ([0.0, 0.01, 0.02], [0.0, 0.01, 0.02], P.VERTEX, "above 0"),              # the axis
     ([0.02, 0.03, 0.05], [0.0, float("nan"), 0.02], P.VERTEX, "finite"),
     ([0.02, 0.03, 0.05], [0.02, 0.01, 0.0], P.VERTEX, "increasing"),          # decreasing z
+    ([1.0e308, 1.5e308, 1.7e308], [0.0, 0.01, 0.02], P.VERTEX, "finite"),     # faces overflow
     ([0.02, 0.05], [0.0, 0.01], P.CELL, "increasing"),                        # wrong count (Python)
 ])
 def test_plan_create_mesh_rejects_bad_meshes(r, z, layout, msg):

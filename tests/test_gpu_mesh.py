@@ -293,3 +293,12 @@ def test_long_lines_use_the_thomas_sweeps(P, name):
         phi, st = P.Plan.for_problem(p, smoother=sm).solve(dev(rho), tol=1e-13)
         assert st["status"] == P.OK, (sm, st)
         assert rel_l2(host(phi), ref) <= 1e-12, (sm, rel_l2(host(phi), ref))
+
+
+def test_plans_reject_geometry_beyond_the_double_range(P):
+    """Finite inputs whose finite-volume coefficients overflow are refused."""
+    with pytest.raises(P.CylPoissonError) as e:
+        P.Plan(5, 2, 5, 1.0, 1e300, 1e300)
+    assert e.value.status == P.EINVAL and "non-finite" in P.last_error()
+    with pytest.raises(P.CylPoissonError):
+        P.Plan.from_mesh([1.0, 1e300, 1.5e300], [0.0, 1e300, 1.5e300], 2, P.VERTEX)
