@@ -163,6 +163,8 @@ void cylpoisson_plan_destroy(cylpoisson_plan* plan);
 
 /* Set a solver option.  Keys (value ranges):
  *   "nu1", "nu2"     pre-/post-smoothing sweeps (1 .. 8; default 2, 2)
+ *   "nu1_coarse", "nu2_coarse"  the same on every level below the finest
+ *                    (0 .. 8; 0 = nu1, nu2; default 0, 0)
  *   "omega"          red-black over-relaxation factor (0 < omega < 2; default 1.15)
  *   "max_cycles"     V-cycle limit per solve (1 .. CYLPOISSON_MAX_HISTORY; default 40)
  *   "check_every"    cycles between host convergence checks once the predicted

@@ -268,8 +268,8 @@ hipError_t launch_bottom_t(cylpoisson_plan* p, const T* f_in, T* u_out, hipStrea
     a.lam = p->d_lam;
     a.cinv = p->d_cinv;
     a.ncoarse = p->coarse_n;
-    a.nu1 = p->opt.nu1;
-    a.nu2 = p->opt.nu2;
+    a.nu1 = nu_pre(p, lb);
+    a.nu2 = nu_post(p, lb);
     a.omega = p->opt.omega;
     a.p0 = p0;
     a.mask = p->mask_live ? p->d_mask : nullptr;

@@ -125,6 +125,7 @@ struct Options {
     int fallback = 1;        // 1: V-cycles take over when the network contracts less than a V-cycle
     int inner_cycles = 2;  // FP32 V-cycles per FP64 refinement step
     int smoother = 0;      // 0: point red-black SOR; 1: r-line zebra; 2: r-line then z-line zebra
+    int nu1_coarse = 0, nu2_coarse = 0;  // sweeps on levels >= 1 (0: nu1, nu2)
 };
 
 }  // namespace cp
@@ -207,6 +208,16 @@ struct cylpoisson_plan {
     float* net_sc = nullptr;
     long long net_pixels = 0;
 };
+
+namespace cp {
+// Pre- and post-smoothing sweeps on level l.
+inline int nu_pre(const cylpoisson_plan* p, int l) {
+    return l > 0 && p->opt.nu1_coarse > 0 ? p->opt.nu1_coarse : p->opt.nu1;
+}
+inline int nu_post(const cylpoisson_plan* p, int l) {
+    return l > 0 && p->opt.nu2_coarse > 0 ? p->opt.nu2_coarse : p->opt.nu2;
+}
+}  // namespace cp
 
 namespace cp {
 

@@ -6,9 +6,9 @@ namespace cp {
 
 bool fused_supported(const cylpoisson_plan* p, int l) {
     if (!p->opt.fused || p->opt.smoother != 0 || l + 1 >= (int)p->dl.size()) return false;
-    if (p->opt.nu1 > 4 || p->opt.nu2 > 4) return false;
-    const Shape sd = pass_shape<double>(p, l, p->opt.nu1, true);
-    const Shape su = pass_shape<double>(p, l, p->opt.nu2, false);
+    if (nu_pre(p, l) > 4 || nu_post(p, l) > 4) return false;
+    const Shape sd = pass_shape<double>(p, l, nu_pre(p, l), true);
+    const Shape su = pass_shape<double>(p, l, nu_post(p, l), false);
     // the up pass has thread t carry coarse interior column t + 1: the coarse
     // level must be coarsened in r (a level coarsened in z only is not fused)
     const bool coarse_cols = p->dl[l + 1].v.nr - 2 <= su.threads;
@@ -21,14 +21,14 @@ hipError_t fused_down(cylpoisson_plan* p, int l, bool zero_u, bool zero_interior
     if (np < 0) np = p->nt;
     DeviceLevel& L = p->dl[l];
     DeviceLevel& C = p->dl[l + 1];
-    const Shape sh = pass_shape<double>(p, l, p->opt.nu1, true);
+    const Shape sh = pass_shape<double>(p, l, nu_pre(p, l), true);
     PassArgs<double> a = make_args<double>(p, l, sh, p0, np);
     a.u_in = L.u;
     a.f = L.f;
     a.u_out = L.u2;
     a.fc = C.f;
     a.zero_interior = zero_interior ? 1 : 0;
-    return launch_nu<double>(l == 0, p->opt.nu1, p->opt.prefetch, true, zero_u, a, sh.nchunks * np,
+    return launch_nu<double>(l == 0, nu_pre(p, l), p->opt.prefetch, true, zero_u, a, sh.nchunks * np,
                              sh.threads, sh.lds, s);
 }
 
@@ -41,7 +41,7 @@ hipError_t fused_up(cylpoisson_plan* p, int l, double* partial, int partial_ld, 
     if (np < 0) np = p->nt;
     DeviceLevel& L = p->dl[l];
     DeviceLevel& C = p->dl[l + 1];
-    const Shape sh = pass_shape<double>(p, l, p->opt.nu2, false);
+    const Shape sh = pass_shape<double>(p, l, nu_post(p, l), false);
     PassArgs<double> a = make_args<double>(p, l, sh, p0, np);
     a.u_in = L.u2;
     a.f = L.f;
@@ -50,7 +50,7 @@ hipError_t fused_up(cylpoisson_plan* p, int l, double* partial, int partial_ld, 
     a.partial = partial;
     a.partial_ld = partial_ld;
     if (nchunks) *nchunks = sh.nchunks;
-    return launch_nu<double>(l == 0, p->opt.nu2, p->opt.prefetch, false, false, a, sh.nchunks * np,
+    return launch_nu<double>(l == 0, nu_post(p, l), p->opt.prefetch, false, false, a, sh.nchunks * np,
                              sh.threads, sh.lds, s);
 }
 

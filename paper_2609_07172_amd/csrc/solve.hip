@@ -193,7 +193,7 @@ hipError_t vcycle(cylpoisson_plan* p, int l, hipStream_t s, bool zero_top, int s
             e = vcycle(p, l + 1, s, true, -1, nullptr, p0, np);
         }
         const bool want = l == 0 && slot >= 0;
-        const int nch = fused_chunks(p, l, p->opt.nu2);
+        const int nch = fused_chunks(p, l, nu_post(p, l));
         const bool host_sum = want && nch <= kSlotPartial;
         if (e == hipSuccess) {
             Timed tm(p, l == 0 ? kFineUp : -1, s);
@@ -215,7 +215,7 @@ hipError_t vcycle(cylpoisson_plan* p, int l, hipStream_t s, bool zero_top, int s
     if (l > 0) e = launch_zero_interior(L, p->nt, L.u, s);
     {
         Timed tm(p, l == 0 ? kFineDown : -1, s);
-        if (e == hipSuccess) e = smooth(p, L, p->opt.nu1, s);
+        if (e == hipSuccess) e = smooth(p, L, nu_pre(p, l), s);
         if (e == hipSuccess) e = launch_residual(L, p->nt, p->d_lam, L.u, L.f, L.r, s);
         if (e == hipSuccess) e = launch_restrict(L, C, p->nt, L.r, C.f, s);
     }
@@ -226,7 +226,7 @@ hipError_t vcycle(cylpoisson_plan* p, int l, hipStream_t s, bool zero_top, int s
     {
         Timed tm(p, l == 0 ? kFineUp : -1, s);
         if (e == hipSuccess) e = launch_prolong(L, C, p->nt, C.u, L.u, s);
-        if (e == hipSuccess) e = smooth(p, L, p->opt.nu2, s);
+        if (e == hipSuccess) e = smooth(p, L, nu_post(p, l), s);
     }
     return e;
 }

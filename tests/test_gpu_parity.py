@@ -339,3 +339,19 @@ def test_anisotropic_grids_converge_and_match_the_oracle(P, shape):
     phi, st = P.Plan.for_problem(p).solve(dev(rho), tol=1e-13)
     assert st["status"] == P.OK and st["cycles"] <= 14, st
     assert rel_l2(host(phi), ref) <= 1e-12
+
+
+@pytest.mark.parametrize("nus", [(1, 1), (3, 2), (4, 4)])
+@pytest.mark.parametrize("fused", [1, 0])
+def test_coarse_sweep_counts_reach_the_oracle(P, nus, fused):
+    """nu1_coarse / nu2_coarse change the sweeps below the finest level only (fused
+    passes, per-step kernels and the LDS bottom kernel); the answer is the oracle's."""
+    p = W.BATCHED.with_sizes(97, 8, 129)
+    rho = W.blob_charge(p, seed=31)
+    ref = solvers.solve_separable(fv.Grid.of(p), rho, p.bc)
+    say("coarse sweeps", nus, "fused", fused)
+    plan = P.Plan.for_problem(p, nu1_coarse=nus[0], nu2_coarse=nus[1], fused=fused)
+    assert plan.get_option("nu1_coarse") == nus[0] and plan.get_option("nu2_coarse") == nus[1]
+    phi, st = plan.solve(dev(rho), tol=1e-14)
+    assert st["status"] == P.OK, st
+    assert rel_l2(host(phi), ref) <= 1e-12, rel_l2(host(phi), ref)
