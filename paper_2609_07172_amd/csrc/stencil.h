@@ -7,6 +7,11 @@
 // Row q of A_p (Eq. matrix_free_mode_operator / appendix_matrix_row):
 //   (A_p u)_q = (D0_q + lambda_p mu_q) u_q - G_W u_W - G_E u_E - G_S u_S - G_N u_N
 // with D0_q = G_W + G_E + G_S + G_N (Eq. interior_base_diagonal).
+//
+// Floating-point contraction is off inside every helper and each fused
+// multiply-add is written out, so the compiler cannot fuse a product into a
+// sum differently in different kernels: every kernel that uses these helpers
+// rounds each node's update identically.
 #pragma once
 
 #include "cp_internal.h"
@@ -30,6 +35,7 @@ __device__ __forceinline__ CoefT<T> coef_as(const Coef& c) {
 // D0 + lambda mu (Eqs. interior_base_diagonal, mode_mass_coefficient).
 __device__ __forceinline__ Coef make_coef(double rw, double re, double rb, double rm, double zc,
                                           double zs, double zn, double lambda) {
+#pragma clang fp contract(off)
     Coef c;
     c.gw = rw * zc;
     c.ge = re * zc;
@@ -48,6 +54,7 @@ __device__ __forceinline__ Coef coef_at(const LevelView& v, int i, int k, double
 // Sum of conductance-weighted neighbours, in one fixed order.
 template <typename T>
 __device__ __forceinline__ T neighbour_sum(T uw, T ue, T us, T un, const CoefT<T>& c) {
+#pragma clang fp contract(off)
     T s = c.gw * uw;
     s = fma(c.ge, ue, s);
     s = fma(c.gs, us, s);
@@ -58,33 +65,39 @@ __device__ __forceinline__ T neighbour_sum(T uw, T ue, T us, T un, const CoefT<T
 // (A_p u)_q
 template <typename T>
 __device__ __forceinline__ T apply_row(T uc, T uw, T ue, T us, T un, const CoefT<T>& c) {
+#pragma clang fp contract(off)
     return fma(c.diag, uc, -neighbour_sum(uw, ue, us, un, c));
 }
 
 // f_q - (A_p u)_q
 template <typename T>
 __device__ __forceinline__ T residual(T uc, T f, T uw, T ue, T us, T un, const CoefT<T>& c) {
+#pragma clang fp contract(off)
     return f - apply_row(uc, uw, ue, us, un, c);
 }
 
 // Over-relaxed Gauss-Seidel update of one node:
 //   u <- u + omega ((f + sum G u_nb) / diag - u)
+// with (f + sum) * (1 / diag) - u in one fused multiply-add.
 template <typename T>
 __device__ __forceinline__ T relax(T uc, T f, T uw, T ue, T us, T un, const CoefT<T>& c, T omega) {
-    const T t = (f + neighbour_sum(uw, ue, us, un, c)) * c.invd;
-    return fma(omega, t - uc, uc);
+#pragma clang fp contract(off)
+    const T d = fma(f + neighbour_sum(uw, ue, us, un, c), c.invd, -uc);
+    return fma(omega, d, uc);
 }
 
 // Weighted three-point sum x0 + wm xm + wp xp of the restriction R = P^T,
 // used first along z and then along r.
 template <typename T>
 __device__ __forceinline__ T restrict3(T xm, T x0, T xp, T wm, T wp) {
+#pragma clang fp contract(off)
     return fma(wp, xp, fma(wm, xm, x0));
 }
 
 // Bilinear prolongation value from coarse rows `lo` and `hi` at columns 0 and 1.
 template <typename T>
 __device__ __forceinline__ T prolong2(const T* lo, const T* hi, T wl_r, T wr_r, T wl_z, T wr_z) {
+#pragma clang fp contract(off)
     const T a = fma(wr_r, lo[1], wl_r * lo[0]);
     const T b = fma(wr_r, hi[1], wl_r * hi[0]);
     return fma(wr_z, b, wl_z * a);

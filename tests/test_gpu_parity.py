@@ -257,7 +257,8 @@ def test_paper_scale_matches_separable_oracle(P):
                                    (33, 4, 200)])
 def test_fused_passes_match_per_step_kernels(P, shape):
     """The fused streaming passes run the same red-black schedule and point arithmetic as the
-    one-kernel-per-step path, so the two solutions agree (bitwise where every level is fused)."""
+    one-kernel-per-step path (with contraction pinned in the shared point operations), so the
+    iterates agree bitwise."""
     nr, nt, nz = shape
     p = W.SMALL.with_sizes(nr, nt, nz)
     rho = dev(W.blob_charge(p, seed=nr + nz))
@@ -268,10 +269,10 @@ def test_fused_passes_match_per_step_kernels(P, shape):
     pb, sb = b.solve(rho, tol=1e-30, allow=(P.OK, P.NOT_CONVERGED))
     ha, hb = host(pa), host(pb)
     assert sa["cycles"] == sb["cycles"] == 6
-    assert rel_l2(ha, hb) <= 1e-14, rel_l2(ha, hb)
-    # relative residuals agree to 1e-9, down to the floor of evaluating a
-    # residual in FP64 (about 1e-16 of ||b||; 1e-15 allowed)
-    np.testing.assert_allclose(sa["history"][:6], sb["history"][:6], rtol=1e-9, atol=1e-15)
+    np.testing.assert_array_equal(ha, hb)
+    # the residual norms are summed in another order (per chunk against per
+    # workgroup of the norm kernel): they agree to rounding of the sums
+    np.testing.assert_allclose(sa["history"][:6], sb["history"][:6], rtol=1e-12, atol=1e-15)
 
 
 @pytest.mark.parametrize("chunk", [1, 5, 16, 1000])
@@ -282,9 +283,10 @@ def test_fused_chunking_is_exact(P, chunk):
     say("chunk", chunk)
     ref_plan = P.Plan.for_problem(p, fused=0, max_cycles=3)
     r, _ = ref_plan.solve(rho, tol=1e-30, allow=(P.OK, P.NOT_CONVERGED))
+    r = host(r).copy()
     plan = P.Plan.for_problem(p, chunk_rows=chunk, max_cycles=3)
     x, _ = plan.solve(rho, tol=1e-30, allow=(P.OK, P.NOT_CONVERGED))
-    assert rel_l2(host(x), host(r)) <= 1e-14
+    np.testing.assert_array_equal(host(x), r)
 
 
 @pytest.mark.parametrize("shape", [(129, 8, 129), (65, 5, 97), (401, 4, 65)])
@@ -299,10 +301,12 @@ def test_bottom_kernel_matches_level_by_level(P, shape):
     b = P.Plan.for_problem(p, bottom=0, max_cycles=4)
     assert a.info()["bottom_level"] >= 1
     pa, sa = a.solve(rho, tol=1e-30, allow=(P.OK, P.NOT_CONVERGED))
+    pa = host(pa).copy()
     pb, sb = b.solve(rho, tol=1e-30, allow=(P.OK, P.NOT_CONVERGED))
-    # same point operations, different rounding order (contractions, sum order)
-    # over up to nine levels: a few ulps per cycle
-    assert rel_l2(host(pa), host(pb)) <= 1e-13
+    # the same point operations in the same red-black order, and the same
+    # coarsest product: bitwise
+    np.testing.assert_array_equal(pa, host(pb))
+    assert sa["history"] == sb["history"]
 
 
 # ------------------------------------------------- plane groups on streams
