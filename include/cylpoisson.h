@@ -173,7 +173,7 @@ void cylpoisson_plan_destroy(cylpoisson_plan* plan);
  *                    transfer of a level in one kernel), 0 = one kernel per
  *                    sweep everywhere (default 1)
  *   "chunk_rows"     axial rows per workgroup of the fused passes (0 = automatic)
- *   "prefetch"       rows the fused passes load ahead of the one they consume (1 .. 4; default 1)
+ *   "prefetch"       rows the fused passes load ahead of the one they consume (1 .. 3; default 1)
  *   "timing"         1 = record per-kernel-class device times (cylpoisson_stats)
  *   "bottom"         1 = run the small levels of each plane in one LDS-resident
  *                    kernel (with "fused" = 1; default 1)

@@ -575,7 +575,6 @@ hipError_t launch_nu_pd(bool fine, int pd, bool down, bool zero_u, const PassArg
             case 1: return launch_pd<T, NU, 1>(fine, down, zero_u, a, blocks, threads, lds, s);
             case 2: return launch_pd<T, NU, 2>(fine, down, zero_u, a, blocks, threads, lds, s);
             case 3: return launch_pd<T, NU, 3>(fine, down, zero_u, a, blocks, threads, lds, s);
-            case 4: return launch_pd<T, NU, 4>(fine, down, zero_u, a, blocks, threads, lds, s);
             default: return hipErrorInvalidValue;
         }
     } else {

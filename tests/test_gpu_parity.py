@@ -289,6 +289,27 @@ def test_fused_chunking_is_exact(P, chunk):
     np.testing.assert_array_equal(host(x), r)
 
 
+@pytest.mark.parametrize("pd", [2, 3])
+def test_prefetch_depth_is_exact(P, pd):
+    """Rows loaded further ahead change when values arrive, not what is computed."""
+    p = W.SMALL.with_sizes(257, 8, 193)
+    rho = dev(W.blob_charge(p, seed=pd))
+    say("prefetch", pd)
+    r, sr = P.Plan.for_problem(p, max_cycles=4).solve(rho, tol=1e-30, allow=(P.OK, P.NOT_CONVERGED))
+    r = host(r).copy()
+    x, sx = P.Plan.for_problem(p, prefetch=pd, max_cycles=4).solve(rho, tol=1e-30,
+                                                                   allow=(P.OK, P.NOT_CONVERGED))
+    np.testing.assert_array_equal(host(x), r)
+    assert sx["history"] == sr["history"]
+
+
+def test_prefetch_beyond_three_rows_is_rejected(P):
+    plan = P.Plan.for_problem(W.SMALL)
+    with pytest.raises(P.CylPoissonError):
+        plan.set_option("prefetch", 4)
+    assert plan.get_option("prefetch") == 1
+
+
 @pytest.mark.parametrize("shape", [(129, 8, 129), (65, 5, 97), (401, 4, 65)])
 def test_bottom_kernel_matches_level_by_level(P, shape):
     """The LDS bottom kernel (all small levels of a plane in one workgroup) runs the same
