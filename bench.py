@@ -450,7 +450,7 @@ def main():
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: the solve runs on a single MI355X that owns every "
-              "Fourier plane; multi-GPU runs are not part of this build (use --gpus 1).",
+              "Fourier plane; the library has no multi-GPU path (use --gpus 1).",
               file=sys.stderr)
         sys.exit(2)
 
