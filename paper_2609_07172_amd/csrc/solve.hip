@@ -437,35 +437,44 @@ int run_cycles(cylpoisson_plan* p, double tol, hipStream_t s, bool ring_only, bo
                                         p->d_norms + (size_t)kRhsSlot * nt, s));
         }
     }
-    CP_HIP(hipMemcpyAsync(p->h_norms, p->d_norms, nt * sizeof(double), hipMemcpyDeviceToHost, s));
-    if (warm)
-        CP_HIP(hipMemcpyAsync(p->h_norms + (size_t)kRhsSlot * nt, p->d_norms + (size_t)kRhsSlot * nt,
-                              nt * sizeof(double), hipMemcpyDeviceToHost, s));
-    CP_HIP(hipStreamSynchronize(s));
-    st.checks = 1;
-    double b2 = weighted(p, p->h_norms), r02 = b2;
-    if (warm && !warm_norms(p, &b2, &r02)) return st.status;
-    if (!std::isfinite(b2)) {
-        set_error("right-hand side holds NaN or Inf");
-        st.status = CYLPOISSON_ENONFINITE;
-        return st.status;
-    }
-    st.initial_residual_norm = std::sqrt(b2);
-    if (b2 == 0.0 || std::sqrt(r02 / b2) <= tol) {
-        st.rel_residual = b2 == 0.0 ? 0.0 : std::sqrt(r02 / b2);
-        st.status = CYLPOISSON_OK;
-        return st.status;
+    const bool masks = masks_active(p);
+    // A cold start needs the right-hand side's norms only at the first check
+    // (masks need them before the first cycle, a warm start may already meet
+    // tol): they come back with the first cycles' norms, saving one round
+    // trip to the host.  If they are zero, every node's residual is exactly
+    // zero and the cycles leave the iterate unchanged.
+    const bool defer = !warm && !masks && tol < 1.0;
+    double b2 = 0.0, r02 = 0.0;
+    if (!defer) {
+        CP_HIP(hipMemcpyAsync(p->h_norms, p->d_norms, nt * sizeof(double), hipMemcpyDeviceToHost, s));
+        if (warm)
+            CP_HIP(hipMemcpyAsync(p->h_norms + (size_t)kRhsSlot * nt, p->d_norms + (size_t)kRhsSlot * nt,
+                                  nt * sizeof(double), hipMemcpyDeviceToHost, s));
+        CP_HIP(hipStreamSynchronize(s));
+        st.checks = 1;
+        b2 = r02 = weighted(p, p->h_norms);
+        if (warm && !warm_norms(p, &b2, &r02)) return st.status;
+        if (!std::isfinite(b2)) {
+            set_error("right-hand side holds NaN or Inf");
+            st.status = CYLPOISSON_ENONFINITE;
+            return st.status;
+        }
+        st.initial_residual_norm = std::sqrt(b2);
+        if (b2 == 0.0 || std::sqrt(r02 / b2) <= tol) {
+            st.rel_residual = b2 == 0.0 ? 0.0 : std::sqrt(r02 / b2);
+            st.status = CYLPOISSON_OK;
+            return st.status;
+        }
     }
 
     const int G = groups_active(p);
     const bool graphs = graphs_active(p, G);
-    const bool masks = masks_active(p);
     struct MaskScope {
         cylpoisson_plan* p;
         ~MaskScope() { p->mask_live = false; }
     } mask_scope{p};
     p->mask_live = masks;
-    const double budget = tol * tol * b2 / nt;
+    const double budget = tol * tol * b2 / nt;  // masks only (never deferred)
     std::vector<double> frozen(nt, -1.0);  // last norm of a frozen plane, -1 while active
     if (masks) {
         for (int q = 0; q < nt; ++q) p->h_mask[q] = 1;
@@ -478,7 +487,7 @@ int run_cycles(cylpoisson_plan* p, double tol, hipStream_t s, bool ring_only, bo
     }
     int next_check = std::min(2, maxc);
     int last_read = 0;
-    double prev_rel = std::sqrt(r02 / b2);
+    double prev_rel = defer ? 1.0 : std::sqrt(r02 / b2);
     int status = CYLPOISSON_NOT_CONVERGED;
     int stagnant = 0;
     std::vector<double> plane(nt), last(nt);
@@ -500,22 +509,42 @@ int run_cycles(cylpoisson_plan* p, double tol, hipStream_t s, bool ring_only, bo
         if (c != next_check && c != maxc) continue;
         CP_HIP(join_groups(p, G, s));
         const int first = last_read + 1;
+        const bool rhs_now = defer && last_read == 0;
         // one copy per kind of slot for the cycles since the last check (the
-        // slots of consecutive cycles are contiguous; unused ones ride along)
+        // slots of consecutive cycles are contiguous; unused ones ride along),
+        // the deferred right-hand side norms in slot 0 with them
         {
-            bool any_partial = false, any_norms = false;
+            bool any_partial = false, any_norms = rhs_now;
             for (int t = first; t <= c; ++t) (slots[t].partial_chunks > 0 ? any_partial : any_norms) = true;
             const size_t nslots = (size_t)(c - first + 1);
+            const int nfirst = rhs_now ? 0 : first;
             if (any_partial)
                 CP_HIP(hipMemcpyAsync(p->h_slot_partial + (size_t)first * nt * kSlotPartial,
                                       p->d_slot_partial + (size_t)first * nt * kSlotPartial,
                                       nslots * nt * kSlotPartial * sizeof(double), hipMemcpyDeviceToHost, s));
             if (any_norms)
-                CP_HIP(hipMemcpyAsync(p->h_norms + (size_t)first * nt, p->d_norms + (size_t)first * nt,
-                                      nslots * nt * sizeof(double), hipMemcpyDeviceToHost, s));
+                CP_HIP(hipMemcpyAsync(p->h_norms + (size_t)nfirst * nt, p->d_norms + (size_t)nfirst * nt,
+                                      (size_t)(c - nfirst + 1) * nt * sizeof(double), hipMemcpyDeviceToHost, s));
         }
         CP_HIP(hipStreamSynchronize(s));
         ++st.checks;
+        if (rhs_now) {
+            b2 = weighted(p, p->h_norms);
+            if (!std::isfinite(b2)) {
+                set_error("right-hand side holds NaN or Inf");
+                st.cycles = 0;
+                status = CYLPOISSON_ENONFINITE;
+                break;
+            }
+            st.initial_residual_norm = std::sqrt(b2);
+            if (b2 == 0.0) {
+                // zero residual everywhere: the cycles changed nothing
+                st.cycles = 0;
+                st.rel_residual = 0.0;
+                status = CYLPOISSON_OK;
+                break;
+            }
+        }
         for (int t = first; t <= c; ++t) {
             const double* norms = p->h_norms + (size_t)t * nt;
             if (slots[t].partial_chunks > 0) {

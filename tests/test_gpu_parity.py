@@ -209,6 +209,39 @@ def test_non_finite_rho_is_reported(P):
     assert (host(phi) == 7.0).all()
 
 
+@pytest.mark.parametrize("shape", [(9, 4, 9), (129, 8, 129)])
+def test_zero_problem_needs_no_cycle(P, shape):
+    """rho = 0 with zero face values: the zero field solves it; no cycle is
+    counted and the answer is exactly zero (the right-hand side's norm may come
+    back only with the first cycles' norms, which must not change it)."""
+    import dataclasses
+    p = dataclasses.replace(W.SMALL.with_sizes(*shape), phi_zL=0.0)
+    say("zero problem", shape)
+    plan = P.Plan.for_problem(p)
+    phi = torch.full(p.shape, 7.0, dtype=torch.float64, device="cuda:0")
+    _, st = plan.solve(dev(np.zeros(p.shape)), tol=1e-12, phi=phi)
+    assert st["status"] == P.OK and st["cycles"] == 0 and st["rel_residual"] == 0.0
+    assert st["initial_residual_norm"] == 0.0
+    assert (host(phi) == 0.0).all()
+
+
+@pytest.mark.parametrize("shape", [(129, 8, 129)])
+def test_non_finite_rho_is_reported_on_fused_grids(P, shape):
+    p = W.SMALL.with_sizes(*shape)
+    rho = W.blob_charge(p, 1)
+    rho[5, 60, 70] = np.inf
+    say("inf rho", shape)
+    plan = P.Plan.for_problem(p)
+    phi = torch.full(p.shape, 7.0, dtype=torch.float64, device="cuda:0")
+    with pytest.raises(P.CylPoissonError) as e:
+        plan.solve(dev(rho), phi=phi)
+    assert e.value.status == P.ENONFINITE
+    assert (host(phi) == 7.0).all()
+    # the plan solves the next problem normally
+    phi2, st = plan.solve(dev(W.blob_charge(p, 2)), tol=1e-12)
+    assert st["status"] == P.OK and np.isfinite(host(phi2)).all()
+
+
 def test_not_converged_returns_last_iterate(P):
     p = W.SMALL
     rho = W.blob_charge(p, 2)
