@@ -126,6 +126,7 @@ struct Options {
     int inner_cycles = 2;  // FP32 V-cycles per FP64 refinement step
     int smoother = 0;      // 0: point red-black SOR; 1: r-line zebra; 2: r-line then z-line zebra
     int nu1_coarse = 0, nu2_coarse = 0;  // sweeps on levels >= 1 (0: nu1, nu2)
+    int fmg = 0;           // 1: full-multigrid start before the V-cycles
 };
 
 }  // namespace cp
@@ -244,8 +245,12 @@ hipError_t launch_residual(const DeviceLevel& L, int nt, const double* lam, cons
                            const double* f, double* r, hipStream_t s);
 hipError_t launch_restrict(const DeviceLevel& F, const DeviceLevel& C, int nt, const double* r,
                            double* fc, hipStream_t s);
+// u += P uc on F's interior, or u = P uc when !add
 hipError_t launch_prolong(const DeviceLevel& F, const DeviceLevel& C, int nt, const double* uc,
-                          double* u, hipStream_t s);
+                          double* u, hipStream_t s, bool add = true);
+// fc = P^T b, b the residual of the iterate that is u's ring and zero inside (reads u's ring only)
+hipError_t launch_restrict_rhs(const DeviceLevel& F, const DeviceLevel& C, int nt, const double* lam,
+                               const double* u, const double* f, double* fc, hipStream_t s);
 hipError_t launch_coarse_solve(const DeviceLevel& L, int nt, const double* lam, const double* cinv,
                                int n, const double* f, double* u, hipStream_t s);
 hipError_t launch_plane_norms(const DeviceLevel& L, int nt, const double* r, double* partial,

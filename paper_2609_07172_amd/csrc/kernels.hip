@@ -296,8 +296,52 @@ __global__ void __launch_bounds__(256) k_restrict(LevelView vf, LevelView vc, Tr
         restrict3(col[0], col[1], col[2], tr.rwm[I], tr.rwp[I]);
 }
 
+// f_c = P^T b for the residual b of the iterate that is u's ring and zero
+// inside: the finest right-hand side with its Dirichlet terms, formed node by
+// node as k_rhs_norm_partial forms it (only u's ring is read).
+__global__ void __launch_bounds__(256) k_restrict_rhs(LevelView vf, LevelView vc, Transfer1D tr,
+                                                      Transfer1D tz, const double* __restrict__ lam,
+                                                      const double* __restrict__ u,
+                                                      const double* __restrict__ f,
+                                                      double* __restrict__ fc) {
+    const int I = blockIdx.x * blockDim.x + threadIdx.x + 1;
+    const int K = blockIdx.y * blockDim.y + threadIdx.y + 1;
+    const int p = blockIdx.z;
+    if (I > vc.nr - 2 || K > vc.nz - 2) return;
+    const int fi = tr.cidx[I], fk = tz.cidx[K];
+    const int ie = vf.nr - 2, ke = vf.nz - 2;
+    const long long base = (long long)p * vf.pstride;
+    double b[3][3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            const int i = fi - 1 + d, k = fk - 1 + a;
+            double r = 0.0;  // the faces: b = 0
+            if (i >= 1 && i <= ie && k >= 1 && k <= ke) {
+                const long long o = base + (long long)k * vf.pitch + i;
+                r = f[o];
+                if (i == 1 || i == ie || k == 1 || k == ke) {
+                    const double uw = i == 1 ? u[o - 1] : 0.0;
+                    const double ue = i == ie ? u[o + 1] : 0.0;
+                    const double us = k == 1 ? u[o - vf.pitch] : 0.0;
+                    const double un = k == ke ? u[o + vf.pitch] : 0.0;
+                    r = residual(0.0, r, uw, ue, us, un, coef_at(vf, i, k, lam[p]));
+                }
+            }
+            b[a][d] = r;
+        }
+    const double wzm = tz.rwm[K], wzp = tz.rwp[K];
+    double col[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) col[d] = restrict3(b[0][d], b[1][d], b[2][d], wzm, wzp);
+    fc[(long long)p * vc.pstride + (long long)K * vc.pitch + I] =
+        restrict3(col[0], col[1], col[2], tr.rwm[I], tr.rwp[I]);
+}
+
 // ------------------------------------------------------------ prolongation
-// u_f += P e_c (the coarse ring is zero).
+// u_f += P e_c, or u_f = P e_c on the interior when !ADD (the coarse ring is zero).
+template <bool ADD>
 __global__ void __launch_bounds__(256) k_prolong(LevelView vf, LevelView vc, Transfer1D tr,
                                                  Transfer1D tz, const double* __restrict__ uc,
                                                  double* __restrict__ u) {
@@ -308,7 +352,11 @@ __global__ void __launch_bounds__(256) k_prolong(LevelView vf, LevelView vc, Tra
     const int I = tr.pidx[i], K = tz.pidx[k];
     const double* c0 = uc + (long long)p * vc.pstride + (long long)K * vc.pitch + I;
     const double e = prolong_value(c0, vc.pitch, tr.pwl[i], tr.pwr[i], tz.pwl[k], tz.pwr[k]);
-    u[(long long)p * vf.pstride + (long long)k * vf.pitch + i] += e;
+    double* o = u + (long long)p * vf.pstride + (long long)k * vf.pitch + i;
+    if (ADD)
+        *o += e;
+    else
+        *o = e;
 }
 
 // -------------------------------------------------------- coarsest solve
@@ -640,8 +688,17 @@ hipError_t launch_restrict(const DeviceLevel& F, const DeviceLevel& C, int nt, c
 }
 
 hipError_t launch_prolong(const DeviceLevel& F, const DeviceLevel& C, int nt, const double* uc,
-                          double* u, hipStream_t s) {
-    k_prolong<<<grid_interior(F.v, nt), dim3(kTx, kTy), 0, s>>>(F.v, C.v, F.tr, F.tz, uc, u);
+                          double* u, hipStream_t s, bool add) {
+    if (add)
+        k_prolong<true><<<grid_interior(F.v, nt), dim3(kTx, kTy), 0, s>>>(F.v, C.v, F.tr, F.tz, uc, u);
+    else
+        k_prolong<false><<<grid_interior(F.v, nt), dim3(kTx, kTy), 0, s>>>(F.v, C.v, F.tr, F.tz, uc, u);
+    return hipGetLastError();
+}
+
+hipError_t launch_restrict_rhs(const DeviceLevel& F, const DeviceLevel& C, int nt, const double* lam,
+                               const double* u, const double* f, double* fc, hipStream_t s) {
+    k_restrict_rhs<<<grid_interior(C.v, nt), dim3(kTx, kTy), 0, s>>>(F.v, C.v, F.tr, F.tz, lam, u, f, fc);
     return hipGetLastError();
 }
 

@@ -867,6 +867,7 @@ int cylpoisson_plan_set_option(cylpoisson_plan* plan, const char* key, double va
     if (!std::strcmp(key, "smoother")) return int_in(0, 2, &plan->opt.smoother);
     if (!std::strcmp(key, "nu1_coarse")) return int_in(0, 8, &plan->opt.nu1_coarse);
     if (!std::strcmp(key, "nu2_coarse")) return int_in(0, 8, &plan->opt.nu2_coarse);
+    if (!std::strcmp(key, "fmg")) return int_in(0, 1, &plan->opt.fmg);
     if (!std::strcmp(key, "fft")) return int_in(0, 1, &plan->opt.fft);
     if (!std::strcmp(key, "inner_cycles")) return int_in(1, 8, &plan->opt.inner_cycles);
     if (!std::strcmp(key, "groups")) return int_in(1, 8, &plan->opt.groups);
@@ -917,7 +918,7 @@ int cylpoisson_plan_get_option(const cylpoisson_plan* plan, const char* key, dou
                  {"chunk_rows_coarse", (double)o.chunk_rows_coarse}, {"prefetch", (double)o.prefetch},
                  {"timing", (double)o.timing}, {"bottom", (double)o.bottom}, {"fft", (double)o.fft},
                  {"smoother", (double)o.smoother}, {"nu1_coarse", (double)o.nu1_coarse},
-                 {"nu2_coarse", (double)o.nu2_coarse},
+                 {"nu2_coarse", (double)o.nu2_coarse}, {"fmg", (double)o.fmg},
                  {"precision", (double)o.precision}, {"inner_cycles", (double)o.inner_cycles},
                  {"groups", (double)o.groups}, {"warm_start", (double)o.warm_start},
                  {"masks", (double)o.masks}, {"graph", (double)o.graph}, {"krylov", (double)o.krylov},
