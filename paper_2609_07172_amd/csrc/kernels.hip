@@ -298,7 +298,13 @@ __global__ void __launch_bounds__(256) k_restrict(LevelView vf, LevelView vc, Tr
 
 // f_c = P^T b for the residual b of the iterate that is u's ring and zero
 // inside: the finest right-hand side with its Dirichlet terms, formed node by
-// node as k_rhs_norm_partial forms it (only u's ring is read).
+// node as k_rhs_norm_partial forms it (only u's ring is read).  Only plane 0
+// has a non-zero ring (theta-invariant face values), and with a zero ring the
+// formula gives b = f exactly.  So EDGE = false forms every coarse node of
+// every plane from f alone (face values dropped), and EDGE = true, launched
+// on plane 0 only, redoes the coarse nodes whose 3 x 3 fine stencil reaches a
+// node next to a face, with their Dirichlet terms.
+template <bool EDGE>
 __global__ void __launch_bounds__(256) k_restrict_rhs(LevelView vf, LevelView vc, Transfer1D tr,
                                                       Transfer1D tz, const double* __restrict__ lam,
                                                       const double* __restrict__ u,
@@ -310,27 +316,41 @@ __global__ void __launch_bounds__(256) k_restrict_rhs(LevelView vf, LevelView vc
     if (I > vc.nr - 2 || K > vc.nz - 2) return;
     const int fi = tr.cidx[I], fk = tz.cidx[K];
     const int ie = vf.nr - 2, ke = vf.nz - 2;
+    const bool edge = fi <= 2 || fi >= ie - 1 || fk <= 2 || fk >= ke - 1;
+    if (EDGE && !edge) return;
     const long long base = (long long)p * vf.pstride;
     double b[3][3];
 #pragma unroll
     for (int a = 0; a < 3; ++a)
 #pragma unroll
-        for (int d = 0; d < 3; ++d) {
-            const int i = fi - 1 + d, k = fk - 1 + a;
-            double r = 0.0;  // the faces: b = 0
-            if (i >= 1 && i <= ie && k >= 1 && k <= ke) {
-                const long long o = base + (long long)k * vf.pitch + i;
-                r = f[o];
-                if (i == 1 || i == ie || k == 1 || k == ke) {
+        for (int d = 0; d < 3; ++d) b[a][d] = f[base + (long long)(fk - 1 + a) * vf.pitch + (fi - 1 + d)];
+    if (edge) {
+        // face values dropped
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+                const int i = fi - 1 + d, k = fk - 1 + a;
+                if (i < 1 || i > ie || k < 1 || k > ke) b[a][d] = 0.0;
+            }
+    }
+    if (EDGE) {
+        // the nodes next to a face add their Dirichlet terms
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+                const int i = fi - 1 + d, k = fk - 1 + a;
+                if (i >= 1 && i <= ie && k >= 1 && k <= ke && (i == 1 || i == ie || k == 1 || k == ke)) {
+                    const long long o = base + (long long)k * vf.pitch + i;
                     const double uw = i == 1 ? u[o - 1] : 0.0;
                     const double ue = i == ie ? u[o + 1] : 0.0;
                     const double us = k == 1 ? u[o - vf.pitch] : 0.0;
                     const double un = k == ke ? u[o + vf.pitch] : 0.0;
-                    r = residual(0.0, r, uw, ue, us, un, coef_at(vf, i, k, lam[p]));
+                    b[a][d] = residual(0.0, b[a][d], uw, ue, us, un, coef_at(vf, i, k, lam[p]));
                 }
             }
-            b[a][d] = r;
-        }
+    }
     const double wzm = tz.rwm[K], wzp = tz.rwp[K];
     double col[3];
 #pragma unroll
@@ -698,7 +718,11 @@ hipError_t launch_prolong(const DeviceLevel& F, const DeviceLevel& C, int nt, co
 
 hipError_t launch_restrict_rhs(const DeviceLevel& F, const DeviceLevel& C, int nt, const double* lam,
                                const double* u, const double* f, double* fc, hipStream_t s) {
-    k_restrict_rhs<<<grid_interior(C.v, nt), dim3(kTx, kTy), 0, s>>>(F.v, C.v, F.tr, F.tz, lam, u, f, fc);
+    k_restrict_rhs<false><<<grid_interior(C.v, nt), dim3(kTx, kTy), 0, s>>>(F.v, C.v, F.tr, F.tz, lam, u, f, fc);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    dim3 g0 = grid_interior(C.v, 1);  // plane 0 only: the others have a zero ring
+    k_restrict_rhs<true><<<g0, dim3(kTx, kTy), 0, s>>>(F.v, C.v, F.tr, F.tz, lam, u, f, fc);
     return hipGetLastError();
 }
 
