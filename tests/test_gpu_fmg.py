@@ -80,3 +80,24 @@ def test_fmg_zero_problem_needs_no_cycle(P):
     _, st = plan.solve(dev(np.zeros(p.shape)), tol=1e-12, phi=phi)
     assert st["status"] == P.OK and st["cycles"] == 0
     assert (host(phi) == 0.0).all()
+
+
+def test_fmg_with_masks_meets_the_oracle(P):
+    """Planes frozen at the first check keep their full-multigrid iterate."""
+    p = W.SMALL.with_sizes(257, 16, 257)
+    rho = W.blob_charge(p, seed=12)
+    ref = solvers.solve_separable(fv.Grid.of(p), rho, p.bc)
+    say("fmg masks")
+    plan = P.Plan.for_problem(p, fmg=1, masks=1)
+    phi, st = plan.solve(dev(rho), tol=1e-13)
+    assert st["status"] == P.OK, st
+    assert rel_l2(host(phi), ref) <= 1e-12
+
+
+def test_fmg_option_range(P):
+    plan = P.Plan.for_problem(W.SMALL)
+    for bad in (-1, 2, 0.5):
+        with pytest.raises(P.CylPoissonError):
+            plan.set_option("fmg", bad)
+    plan.set_option("fmg", 1)
+    assert plan.get_option("fmg") == 1
