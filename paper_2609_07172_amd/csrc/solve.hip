@@ -431,7 +431,9 @@ int run_cycles(cylpoisson_plan* p, double tol, hipStream_t s, bool ring_only, bo
     {
         Timed tm(p, kOther, s);
         DeviceLevel& L = p->dl[0];
-        if (ring_only || fmg) {
+        if (fmg) {
+            // the right-hand side norms are in slot 0 already (launched with the start)
+        } else if (ring_only) {
             CP_HIP(launch_rhs_norms(L, nt, p->d_lam, L.u, L.f, p->d_partial, p->d_norms, s));
         } else {
             CP_HIP(residual_norms(p, 0, s));
@@ -988,7 +990,16 @@ int cylpoisson_solve(cylpoisson_plan* p, const double* rho, double* phi, double 
         Timed tm(p, kOther, s);
         if (fmg) {
             CP_HIP(launch_init_ring(L, p->nt, p->bc, s));
+            // the right-hand side norms read f and u's ring only, which the
+            // start does not write: they run beside its latency-bound coarse
+            // levels on a second stream, joined before the first cycle
+            CP_HIP(ensure_groups(p, 2));
+            CP_HIP(hipEventRecord(p->gevents[0], s));
+            CP_HIP(hipStreamWaitEvent(p->gstreams[0], p->gevents[0], 0));
+            CP_HIP(launch_rhs_norms(L, p->nt, p->d_lam, L.u, L.f, p->d_partial, p->d_norms, p->gstreams[0]));
+            CP_HIP(hipEventRecord(p->gevents[1], p->gstreams[0]));
             CP_HIP(fmg_start(p, s));
+            CP_HIP(hipStreamWaitEvent(s, p->gevents[1], 0));
         } else if (warm) {
             // the planes of the given phi, with the Dirichlet rings rewritten
             CP_HIP(transform(p, false, phi, L.u, nullptr, s));
