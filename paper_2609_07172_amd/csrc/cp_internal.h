@@ -300,6 +300,10 @@ hipError_t fused_down(cylpoisson_plan* p, int l, bool zero_u, bool zero_interior
 hipError_t fused_up(cylpoisson_plan* p, int l, double* partial, int partial_ld, int* nchunks,
                     hipStream_t s, int p0 = 0, int np = -1);
 int fused_chunks(const cylpoisson_plan* p, int l, int nu);
+// The finest down pass whose input interior is zero plus the prolongated
+// level-1 iterate (first cycle after a full-multigrid start); when it applies.
+bool fused_down_pro_ok(const cylpoisson_plan* p);
+hipError_t fused_down_pro(cylpoisson_plan* p, hipStream_t s, int p0 = 0, int np = -1);
 // FP32 passes on the dl32 buffers (mixed precision), no residual norms.
 hipError_t fused_down32(cylpoisson_plan* p, int l, bool zero_u, hipStream_t s, int p0 = 0,
                         int np = -1);

@@ -32,6 +32,31 @@ hipError_t fused_down(cylpoisson_plan* p, int l, bool zero_u, bool zero_interior
                              sh.threads, sh.lds, s);
 }
 
+// The first finest down pass after a full-multigrid start with the start's
+// finest interpolation folded in (k_pass_fine_pro): FP64, two pre-sweeps and
+// one row of prefetch (the tuned finest pass), fused finest level.
+bool fused_down_pro_ok(const cylpoisson_plan* p) {
+    if (!fused_supported(p, 0) || nu_pre(p, 0) != 2 || pass_prefetch<double>(2, p->opt.prefetch) != 1)
+        return false;
+    return pass_shape<double>(p, 0, 2, true, true).lds <= 64 * 1024;
+}
+
+hipError_t fused_down_pro(cylpoisson_plan* p, hipStream_t s, int p0, int np) {
+    if (np < 0) np = p->nt;
+    DeviceLevel& L = p->dl[0];
+    DeviceLevel& C = p->dl[1];
+    const Shape sh = pass_shape<double>(p, 0, 2, true, true);
+    PassArgs<double> a = make_args<double>(p, 0, sh, p0, np);
+    a.u_in = L.u;  // its ring; the interior is zero plus the prolongated C.u
+    a.f = L.f;
+    a.u_out = L.u2;
+    a.fc = C.f;
+    a.ec = C.u;
+    a.zero_interior = 1;
+    k_pass_fine_pro<double, 2, 1><<<sh.nchunks * np, sh.threads, sh.lds, s>>>(a);
+    return hipGetLastError();
+}
+
 int fused_chunks(const cylpoisson_plan* p, int l, int nu) {
     return pass_shape<double>(p, l, nu, false).nchunks;
 }

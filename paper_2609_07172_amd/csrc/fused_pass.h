@@ -70,8 +70,14 @@ struct PassArgs {
     int xcd_major;       // map consecutive chunks of a plane to one XCD
 };
 
-template <typename T, int NU, int PD, bool DOWN, bool ZERO_U>
+// PRO (down passes only): the input's interior is taken as zero plus the
+// prolongated coarse answer ec, formed as rows are consumed (the start of the
+// first cycle after a full-multigrid guess, which then is never written).
+template <typename T, int NU, int PD, bool DOWN, bool ZERO_U, bool PRO = false>
 struct Pass {
+    static_assert(!PRO || DOWN, "PRO is a down-pass mode");
+    // the pass prolongates a coarse correction into its input rows
+    static constexpr bool XP = !DOWN || PRO;
     // Register history: rows x+PD (prefetch) down to x-2NU-2.  Q is even and
     // the first row s is even, so slot J holds rows of one parity and the
     // colour of each column in every half-sweep is known at compile time.
@@ -129,7 +135,7 @@ struct Pass {
         off += (size_t)4 * (a.tn + 1) * sizeof(T);
         off = (off + 7) & ~(size_t)7;
         tab = (double*)(smem + off);
-        off += (size_t)7 * rows * sizeof(double);
+        off += (size_t)(PRO ? 10 : 7) * rows * sizeof(double);
         cringp = (T*)(smem + off);
     }
 
@@ -142,6 +148,10 @@ struct Pass {
     __device__ __forceinline__ double* rowzs() { return tables() + 4 * rows; }
     __device__ __forceinline__ double* rowzn() { return tables() + 5 * rows; }
     __device__ __forceinline__ int* rowk() { return (int*)(tables() + 6 * rows); }
+    // prolongation row tables: the up pass's own, a PRO pass's extra three
+    __device__ __forceinline__ int* pk() { return PRO ? (int*)(tables() + 7 * rows) : rowk(); }
+    __device__ __forceinline__ double* pw0() { return PRO ? tables() + 8 * rows : roww0(); }
+    __device__ __forceinline__ double* pw1() { return PRO ? tables() + 9 * rows : roww1(); }
     __device__ __forceinline__ T* cring() { return cringp; }
     __device__ __forceinline__ T* crow(int K) { return cring() + (K & (kCRing - 1)) * a.vc.nr; }
 
@@ -201,7 +211,8 @@ struct Pass {
             wm2 = (T)(I2 >= 0 ? a.tr.rwm[I2] : 0.0);
             wp2 = (T)(I2 >= 0 ? a.tr.rwp[I2] : 0.0);
             for (int i = t; i < 4 * (a.tn + 1); i += blockDim.x) Vrow(0, 0)[i] = T(0);
-        } else {
+        }
+        if (XP) {
             cK = -1;
             cnext = 0;
             P1 = act1 ? a.tr.pidx[c1] : 0;
@@ -232,18 +243,24 @@ struct Pass {
             rowk()[x - s] = k;
             roww0()[x - s] = w0;
             roww1()[x - s] = w1;
+            if (PRO) {
+                const bool in = interior_row(x);
+                pk()[x - s] = in ? a.tz.pidx[x] : -1;
+                pw0()[x - s] = in ? a.tz.pwl[x] : 0.0;
+                pw1()[x - s] = in ? a.tz.pwr[x] : 0.0;
+            }
             rowzc()[x - s] = v.zc[x];
             rowzs()[x - s] = v.zs[x];
             rowzn()[x - s] = v.zn[x];
         }
-        if (!DOWN) {
+        if (XP) {
             // coarse rows needed by the rows consumed in the first PD + 1 steps
             lds_barrier();
             int klo = a.vc.nz, khi = -1;
             for (int x = s; x <= min(lend, s + PD); ++x)
                 if (interior_row(x)) {
-                    klo = min(klo, rowk()[x - s]);
-                    khi = max(khi, rowk()[x - s] + 1);
+                    klo = min(klo, pk()[x - s]);
+                    khi = max(khi, pk()[x - s] + 1);
                 }
             for (int q = t; q < kCRing; q += blockDim.x) {
                 cring()[q * a.vc.nr] = T(0);
@@ -261,7 +278,7 @@ struct Pass {
         return a.ec + (long long)p * a.vc.pstride + (long long)K * a.vc.pitch;
     }
     __device__ __forceinline__ int coarse_hi(int x) {
-        return (x >= s && x <= lend && interior_row(x)) ? rowk()[x - s] + 1 : -1;
+        return (x >= s && x <= lend && interior_row(x)) ? pk()[x - s] + 1 : -1;
     }
     // Once per step: store the coarse row that arrived and request the next one
     // if the row consumed PD + 1 steps from now needs it.  Thread t carries
@@ -305,9 +322,9 @@ struct Pass {
         }
         ff[J][0] = (in && act1) ? ff[J][0] : T(0);
         ff[J][1] = (in && act2) ? ff[J][1] : T(0);
-        if (!DOWN && in) {
-            const int K = rowk()[x - s];
-            const T wl = (T)roww0()[x - s], wr = (T)roww1()[x - s];
+        if (XP && in) {
+            const int K = pk()[x - s];
+            const T wl = (T)pw0()[x - s], wr = (T)pw1()[x - s];
             const T* lo = crow(K);
             const T* hi = crow(K + 1);
             const T e1 = prolong2(lo + P1, hi + P1, pl1, pr1, wl, wr);
@@ -396,7 +413,7 @@ struct Pass {
         constexpr int sr = (J - 2 * NU - 1 + 4 * Q) % Q;
         const T rnw = Bl[sr], rne = Ar[sr];
         if (DOWN && pendK >= 0) finish_restriction();
-        if (!DOWN) coarse_stream(x + PD + 1);
+        if (XP) coarse_stream(x + PD + 1);
         issue(x + PD, (J + PD) % Q);
         if (!CHK || x <= lend) consume<J, !CHK>(x);
         const int ylo = max(1, s + 1), yhi = min(a.v.nz - 2, lend - 1);
@@ -539,6 +556,15 @@ __global__ void __launch_bounds__(512) k_pass_fine(PassArgs<T> a) {
     pass.run();
 }
 
+// The finest down pass of the first cycle after a full-multigrid start: the
+// interior of the input is zero plus the prolongated level-1 answer.
+template <typename T, int NU, int PD>
+__global__ void __launch_bounds__(512) k_pass_fine_pro(PassArgs<T> a) {
+    extern __shared__ double smem[];
+    Pass<T, NU, PD, true, false, true> pass(a, (char*)smem);
+    pass.run();
+}
+
 
 // ---- host side: launch dispatch, launch shape and arguments ----
 
@@ -601,7 +627,7 @@ struct Shape {
 };
 
 template <typename T>
-Shape pass_shape(const cylpoisson_plan* p, int l, int nu, bool down) {
+Shape pass_shape(const cylpoisson_plan* p, int l, int nu, bool down, bool pro = false) {
     const DeviceLevel& L = p->dl[l];
     Shape sh;
     sh.tn = L.v.nr / 2;  // column pairs covering columns 1 .. nr-1
@@ -631,8 +657,8 @@ Shape pass_shape(const cylpoisson_plan* p, int l, int nu, bool down) {
     const size_t trows = (size_t)(chunk + 4 * nu + 6);
     size_t off = (2 * (sh.tn + 1) * qs + 4 * (sh.tn + 1)) * sizeof(T);
     off = (off + 7) & ~(size_t)7;
-    off += 7 * trows * sizeof(double);
-    if (!down) off += (size_t)(pd == 1 ? 4 : 8) * p->dl[l + 1].v.nr * sizeof(T);
+    off += (size_t)(pro ? 10 : 7) * trows * sizeof(double);
+    if (!down || pro) off += (size_t)(pd == 1 ? 4 : 8) * p->dl[l + 1].v.nr * sizeof(T);
     sh.lds = std::max(off, (size_t)sh.threads * sizeof(double));  // final block reduction
     return sh;
 }

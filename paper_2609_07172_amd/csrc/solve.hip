@@ -170,7 +170,7 @@ struct NormSlot {
 // Planes p0 .. p0 + np - 1 (all when np < 0); a partial range needs the fused
 // passes down to the bottom kernel (groups_active).
 hipError_t vcycle(cylpoisson_plan* p, int l, hipStream_t s, bool zero_top, int slot, NormSlot* ns,
-                  int p0 = 0, int np = -1) {
+                  int p0 = 0, int np = -1, bool pro = false) {
     const int nl = (int)p->dl.size();
     DeviceLevel& L = p->dl[l];
     hipError_t e = hipSuccess;
@@ -185,8 +185,10 @@ hipError_t vcycle(cylpoisson_plan* p, int l, hipStream_t s, bool zero_top, int s
     if (fused_supported(p, l)) {
         {
             Timed tm(p, l == 0 ? kFineDown : -1, s);
-            // coarser levels start from a zero iterate with a zero ring
-            e = fused_down(p, l, l > 0, l == 0 && zero_top, s, p0, np);
+            // coarser levels start from a zero iterate with a zero ring; `pro`:
+            // the finest interior is the prolongated full-multigrid answer
+            e = l == 0 && pro ? fused_down_pro(p, s, p0, np)
+                              : fused_down(p, l, l > 0, l == 0 && zero_top, s, p0, np);
         }
         if (e == hipSuccess) {
             Timed tm(p, l == 0 ? kCoarse : -1, s);
@@ -422,7 +424,7 @@ bool warm_norms(cylpoisson_plan* p, double* b2, double* r02) {
 // always measured against the right-hand side b (the residual of the zero
 // interior).
 int run_cycles(cylpoisson_plan* p, double tol, hipStream_t s, bool ring_only, bool warm = false,
-               bool fmg = false) {
+               bool fmg = false, bool fmg_pro = false) {
     cylpoisson_stats& st = p->stats;
     const int nt = p->nt;
     const int maxc = p->opt.max_cycles;
@@ -503,7 +505,8 @@ int run_cycles(cylpoisson_plan* p, double tol, hipStream_t s, bool ring_only, bo
             for (int g = 0; g < G; ++g) {
                 int p0, np;
                 group_range(p, G, g, &p0, &np);
-                CP_HIP(vcycle(p, 0, group_stream(p, g, s), c == 1 && ring_only, c, &slots[c], p0, np));
+                CP_HIP(vcycle(p, 0, group_stream(p, g, s), c == 1 && ring_only, c, &slots[c], p0, np,
+                              c == 1 && fmg_pro));
             }
         }
         if (slots[c].partial_chunks < 0) {
@@ -913,7 +916,7 @@ bool fmg_active(const cylpoisson_plan* p) {
 // Dirichlet ring, already set, is kept).  A V-cycle on every level between
 // gives the same start at 400 x 128 x 512 (first-cycle residual 8.6e-4
 // against 8.7e-4) for 0.1 ms more.
-hipError_t fmg_start(cylpoisson_plan* p, hipStream_t s) {
+hipError_t fmg_start(cylpoisson_plan* p, hipStream_t s, bool keep_top) {
     const int nt = p->nt, lb = p->bottom_level;
     DeviceLevel& L0 = p->dl[0];
     hipError_t e = launch_restrict_rhs(L0, p->dl[1], nt, p->d_lam, L0.u, L0.f, p->dl[1].f, s);
@@ -928,7 +931,8 @@ hipError_t fmg_start(cylpoisson_plan* p, hipStream_t s) {
         if (e == hipSuccess) e = vcycle(p, l + 1, s, true, -1, nullptr);
         if (e == hipSuccess) e = fused_up(p, l, nullptr, kMaxPartial, nullptr, s);
     }
-    if (e == hipSuccess) e = launch_prolong(L0, p->dl[1], nt, p->dl[1].u, L0.u, s, false);
+    // keep_top: the first finest down pass forms this interpolation itself
+    if (e == hipSuccess && !keep_top) e = launch_prolong(L0, p->dl[1], nt, p->dl[1].u, L0.u, s, false);
     return e;
 }
 
@@ -985,6 +989,10 @@ int cylpoisson_solve(cylpoisson_plan* p, const double* rho, double* phi, double 
     // mixed-precision refinement writes the zero interior itself).
     const bool warm = p->opt.warm_start != 0 && !learned;
     const bool fmg = !warm && !learned && !mixed && fmg_active(p);
+    // the first down pass folds in the start's finest interpolation, except
+    // with masks (a plane frozen before the first cycle keeps the start) and
+    // graphs (the captured first cycle is the plain one)
+    const bool fmg_pro = fmg && fused_down_pro_ok(p) && !masks_active(p) && !graphs_active(p, groups_active(p));
     const bool ring_only = !warm && !learned && !fmg && (mixed || fused_supported(p, 0));
     {
         Timed tm(p, kOther, s);
@@ -998,7 +1006,7 @@ int cylpoisson_solve(cylpoisson_plan* p, const double* rho, double* phi, double 
             CP_HIP(hipStreamWaitEvent(p->gstreams[0], p->gevents[0], 0));
             CP_HIP(launch_rhs_norms(L, p->nt, p->d_lam, L.u, L.f, p->d_partial, p->d_norms, p->gstreams[0]));
             CP_HIP(hipEventRecord(p->gevents[1], p->gstreams[0]));
-            CP_HIP(fmg_start(p, s));
+            CP_HIP(fmg_start(p, s, fmg_pro));
             CP_HIP(hipStreamWaitEvent(s, p->gevents[1], 0));
         } else if (warm) {
             // the planes of the given phi, with the Dirichlet rings rewritten
@@ -1014,7 +1022,7 @@ int cylpoisson_solve(cylpoisson_plan* p, const double* rho, double* phi, double 
     double* result = L.u;
     const int status = learned ? run_learned(p, tol, s)
                        : mixed ? run_mixed(p, tol, s, &result, warm)
-                               : run_cycles(p, tol, s, ring_only, warm, fmg);
+                               : run_cycles(p, tol, s, ring_only, warm, fmg, fmg_pro);
     if (status == CYLPOISSON_OK || status == CYLPOISSON_NOT_CONVERGED) {
         Timed tm(p, kDftInv, s);
         CP_HIP(transform(p, true, result, phi, nullptr, s));
