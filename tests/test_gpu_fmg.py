@@ -27,7 +27,11 @@ def P():
 
 
 @pytest.mark.parametrize("prob", [W.SMALL.with_sizes(257, 8, 257), W.BATCHED, W.HIGH_SHIFT,
-                                  W.SMALL.with_sizes(401, 4, 513)], ids=lambda p: f"{p.nr}x{p.ntheta}x{p.nz}")
+                                  W.SMALL.with_sizes(401, 4, 513),
+                                  # uneven shapes: odd counts, other bottom levels and coarsenings
+                                  W.SMALL.with_sizes(217, 6, 94), W.SMALL.with_sizes(105, 5, 344),
+                                  W.SMALL.with_sizes(384, 4, 411), W.SMALL.with_sizes(76, 7, 259)],
+                         ids=lambda p: f"{p.nr}x{p.ntheta}x{p.nz}")
 def test_fmg_solve_matches_oracle(P, prob):
     rho = W.blob_charge(prob, seed=prob.nr)
     ref = solvers.solve_separable(fv.Grid.of(prob), rho, prob.bc)
