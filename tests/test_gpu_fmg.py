@@ -105,3 +105,17 @@ def test_fmg_option_range(P):
             plan.set_option("fmg", bad)
     plan.set_option("fmg", 1)
     assert plan.get_option("fmg") == 1
+
+
+def test_fmg_fused_interpolation_is_exact(P):
+    """With one row of prefetch the first finest down pass forms its start as
+    it streams; with two it reads it from a written copy.  Prefetch changes no
+    arithmetic, so the two solves agree bitwise."""
+    p = W.SMALL.with_sizes(401, 5, 513)
+    rho = dev(W.blob_charge(p, seed=21))
+    say("fmg fused interpolation")
+    a, sa = P.Plan.for_problem(p, fmg=1).solve(rho, tol=1e-14)
+    a = host(a).copy()
+    b, sb = P.Plan.for_problem(p, fmg=1, prefetch=2).solve(rho, tol=1e-14)
+    np.testing.assert_array_equal(host(b), a)
+    assert sa["history"] == sb["history"]
