@@ -900,8 +900,9 @@ int run_learned(cylpoisson_plan* p, double tol, hipStream_t s) {
 
 hipError_t vcycle_step(cylpoisson_plan* p, hipStream_t s) { return vcycle(p, 0, s, false, -1, nullptr); }
 
-// Full-multigrid start (option "fmg"): every fused level down to the bottom
-// kernel's, the plain point smoother, FP64.
+// Whether the full-multigrid start applies: option "fmg" set, the LDS bottom
+// kernel serving the levels from some level 1 or deeper, and fused passes on
+// every level above it (so the point smoother on FP64 levels).
 bool fmg_active(const cylpoisson_plan* p) {
     if (!p->opt.fmg || !bottom_active(p) || p->bottom_level < 1) return false;
     for (int l = 0; l < p->bottom_level; ++l)
@@ -916,7 +917,7 @@ bool fmg_active(const cylpoisson_plan* p) {
 // Dirichlet ring, already set, is kept).  A V-cycle on every level between
 // gives the same start at 400 x 128 x 512 (first-cycle residual 8.6e-4
 // against 8.7e-4) for 0.1 ms more.
-hipError_t fmg_start(cylpoisson_plan* p, hipStream_t s, bool keep_top) {
+hipError_t fmg_start(cylpoisson_plan* p, hipStream_t s, bool fused_top) {
     const int nt = p->nt, lb = p->bottom_level;
     DeviceLevel& L0 = p->dl[0];
     hipError_t e = launch_restrict_rhs(L0, p->dl[1], nt, p->d_lam, L0.u, L0.f, p->dl[1].f, s);
@@ -931,8 +932,9 @@ hipError_t fmg_start(cylpoisson_plan* p, hipStream_t s, bool keep_top) {
         if (e == hipSuccess) e = vcycle(p, l + 1, s, true, -1, nullptr);
         if (e == hipSuccess) e = fused_up(p, l, nullptr, kMaxPartial, nullptr, s);
     }
-    // keep_top: the first finest down pass forms this interpolation itself
-    if (e == hipSuccess && !keep_top) e = launch_prolong(L0, p->dl[1], nt, p->dl[1].u, L0.u, s, false);
+    // fused_top: the first finest down pass forms this interpolation itself,
+    // so the finest start is not written here
+    if (e == hipSuccess && !fused_top) e = launch_prolong(L0, p->dl[1], nt, p->dl[1].u, L0.u, s, false);
     return e;
 }
 
