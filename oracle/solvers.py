@@ -108,7 +108,9 @@ def solve_separable(grid: fv.Grid, rho, bc=None, phi_boundary=None, workers=None
     The azimuthal part is ``mu_i lambda_m`` (Eq. (discrete_azimuthal_eigenvalue)).
     What remains for each (m, p) is a symmetric tridiagonal system in r,
     solved with ``scipy.linalg.solve_banded``-equivalent Thomas elimination
-    vectorised over all (m, p).
+    vectorised over all (m, p).  Runs in ``grid.dtype``: an extended-precision
+    grid (``numpy.longdouble``, scipy's transforms keep it) gives the exact
+    discrete solution of an FP64 ``rho`` far below the FP64 rounding floor.
     """
     if not getattr(grid, "uniform", True):
         raise ValueError("the separable solver needs the uniform vertex-centred grid")
@@ -118,18 +120,20 @@ def solve_separable(grid: fv.Grid, rho, bc=None, phi_boundary=None, workers=None
     if not (np.array_equal(grid.G_zm, np.broadcast_to(gz, grid.G_zm.shape))
             and np.array_equal(grid.G_zm, grid.G_zp)):
         raise ValueError("separable solve needs k-independent axial conductances")
+    t = grid.dtype
     bh = scipy.fft.rfft(b, axis=0, workers=workers)  # (nm, nz, nr) complex
     bh = scipy.fft.dst(bh, type=1, axis=1, workers=workers)
     nm = bh.shape[0]
-    lam = discrete_eigenvalue(np.arange(nm), nt, float(grid.dtheta))  # (nm,)
-    p = np.arange(1, nz + 1)
-    sig = 4.0 * np.sin(np.pi * p / (2.0 * (nz + 1))) ** 2  # (nz,)
+    lam = discrete_eigenvalue(np.arange(nm), nt, grid.dtheta, dtype=t)  # (nm,)
+    p = np.arange(1, nz + 1, dtype=t)
+    pi = t(2) * np.arccos(t(0))
+    sig = t(4) * np.sin(pi * p / (t(2) * t(nz + 1))) ** 2  # (nz,)
     gw = grid.G_rm[0]  # (nr,)
     ge = grid.G_rp[0]
     mu = grid.mu[0]
     diag = (gw + ge)[None, None, :] + gz[None, None, :] * sig[None, :, None] + mu[None, None, :] * lam[:, None, None]
     # Thomas elimination along r: sub-diagonal -gw[i] (to i-1), super-diagonal -ge[i] (to i+1)
-    cp = np.empty(diag.shape)
+    cp = np.empty(diag.shape, dtype=diag.dtype)
     dp = np.empty(bh.shape, dtype=bh.dtype)
     cp[..., 0] = -ge[0] / diag[..., 0]
     dp[..., 0] = bh[..., 0] / diag[..., 0]

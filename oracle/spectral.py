@@ -32,10 +32,14 @@ def plane_is_sine(ntheta: int) -> np.ndarray:
     return np.arange(ntheta) >= nc
 
 
-def discrete_eigenvalue(m, ntheta: int, dtheta: float):
-    """``lambda_m = (4/dtheta^2) sin^2(pi m / N)``, Eq. (discrete_azimuthal_eigenvalue)."""
-    m = np.asarray(m, dtype=np.float64)
-    return 4.0 / (dtheta * dtheta) * np.sin(np.pi * m / ntheta) ** 2
+def discrete_eigenvalue(m, ntheta: int, dtheta, dtype=np.float64):
+    """``lambda_m = (4/dtheta^2) sin^2(pi m / N)``, Eq. (discrete_azimuthal_eigenvalue),
+    evaluated in ``dtype`` (``numpy.longdouble`` for extended precision)."""
+    t = dtype
+    m = np.asarray(m, dtype=t)
+    pi = t(2) * np.arccos(t(0))
+    dtheta = t(dtheta)
+    return t(4) / (dtheta * dtheta) * np.sin(pi * m / t(ntheta)) ** 2
 
 
 def plane_eigenvalues(ntheta: int, dtheta: float) -> np.ndarray:

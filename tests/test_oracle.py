@@ -236,6 +236,51 @@ def test_separable_matches_sparse_direct(prob):
                solvers.solve_sparse(g, rho, prob.bc)[INTERIOR]) < 1e-13
 
 
+@pytest.mark.slow
+def test_separable_matches_sparse_direct_on_the_127k_proxy():
+    """The separable solver, the reference for the large grids, against SuperLU
+    on the undecomposed 3-D system at 63 x 32 x 63 interior nodes (127,008
+    unknowns, the largest size sparse LU finishes in about a minute)."""
+    p = W.BATCHED.with_sizes(65, 32, 65)
+    g = fv.Grid.of(p)
+    rho = W.blob_charge(p, seed=24680)
+    sep = solvers.solve_separable(g, rho, p.bc)
+    ref = solvers.solve_sparse(g, rho, p.bc)
+    assert rel(sep[INTERIOR], ref[INTERIOR]) < 1e-13
+    assert np.abs(sep - ref).max() < 1e-13 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("prob", [W.SMALL.with_sizes(17, 8, 19), W.HIGH_SHIFT.with_sizes(17, 7, 13)])
+def test_extended_precision_separable_is_exact(prob):
+    """Run in extended precision, the separable solver leaves a relative residual
+    of the assembled cell balances (evaluated by apply_full in extended
+    precision, code the solver does not use) at the extended-precision level,
+    and agrees with the FP64 sparse direct solve to FP64 rounding."""
+    gl = fv.Grid.of(prob, np.longdouble)
+    rho = W.blob_charge(prob, seed=8)
+    ex = solvers.solve_separable(gl, rho, prob.bc)
+    assert ex.dtype == np.longdouble
+    eps_ld = float(np.finfo(np.longdouble).eps)
+    assert solvers.residual_norm(gl, ex, rho, prob.bc) < 1e3 * eps_ld
+    ref = solvers.solve_sparse(fv.Grid.of(prob), rho, prob.bc)
+    assert rel(ex.astype(np.float64)[INTERIOR], ref[INTERIOR]) < 1e-14
+    # the FP64 run of the same solver is not that exact: its residual is at FP64 level
+    f64 = solvers.solve_separable(fv.Grid.of(prob), rho, prob.bc)
+    assert solvers.residual_norm(gl, f64, rho, prob.bc) > 1e2 * eps_ld
+
+
+@pytest.mark.parametrize("n", [1, 2, 5, 16, 128])
+def test_extended_precision_eigenvalue_matches_fp64(n):
+    """Eq. discrete_azimuthal_eigenvalue in extended precision agrees with FP64 to rounding."""
+    dth = 2.0 * math.pi / n
+    m = np.arange(n)
+    ld = spectral.discrete_eigenvalue(m, n, np.longdouble(2) * np.arccos(np.longdouble(-1)) / n,
+                                      dtype=np.longdouble)
+    assert ld.dtype == np.longdouble
+    np.testing.assert_allclose(ld.astype(np.float64), spectral.discrete_eigenvalue(m, n, dth),
+                               rtol=1e-14, atol=1e-14 * float(ld.max() if n > 1 else 1.0))
+
+
 @pytest.mark.parametrize("shape", [(7, 6, 6), (6, 5, 7), (5, 2, 5), (5, 1, 4)])
 def test_mode_decomposition_is_exact(shape):
     """Sec. 3.1-3.2: DFT in theta, the 2-D systems (A_0 + lambda_m M) u = s rho^ + b^D delta_{m0}
