@@ -132,7 +132,8 @@ typedef struct {
  * Ntheta >= 1, 0 < r_in < r_out, dz > 0 and finite boundary values.  Builds
  * the multigrid hierarchy and its coefficient tables on the host, allocates
  * the device workspace on the current HIP device and uploads the tables.
- * Returns NULL on error (see cylpoisson_last_error; EINVAL or ENOMEM). */
+ * Returns NULL on error (cylpoisson_last_status: EINVAL, ENOMEM or EHIP;
+ * cylpoisson_last_error describes it). */
 cylpoisson_plan* cylpoisson_plan_create(int Nr, int Ntheta, int Nz, double r_in, double r_out,
                                         double dz, const cylpoisson_bc* bc);
 
@@ -154,7 +155,7 @@ cylpoisson_plan* cylpoisson_plan_create(int Nr, int Ntheta, int Nz, double r_in,
  * coarsened direction and rediscretise with faces half-way between their
  * nodes; grid transfers interpolate linearly in the coordinates, and a
  * direction is coarsened alone while the median spacings differ more than
- * 2:1.  Returns NULL on error (EINVAL or ENOMEM, see cylpoisson_last_error). */
+ * 2:1.  Returns NULL on error (cylpoisson_last_status: EINVAL, ENOMEM or EHIP). */
 cylpoisson_plan* cylpoisson_plan_create_mesh(int Nr, int Ntheta, int Nz, const double* r, const double* z,
                                              int layout, const cylpoisson_bc* bc);
 
@@ -366,6 +367,13 @@ int cylpoisson_plan_set_net(cylpoisson_plan* plan, cylpoisson_nn* nn);
 
 /* Thread-local message describing the last failure in this thread ("" if none). */
 const char* cylpoisson_last_error(void);
+
+/* Status of the last cylpoisson_plan_create or cylpoisson_plan_create_mesh in
+ * this thread: OK after a plan was returned; after NULL, EINVAL (arguments or
+ * geometry rejected), ENOMEM (a host or device allocation failed, e.g. a
+ * workspace larger than the device memory) or EHIP (another HIP failure).
+ * Every allocation of a failed creation is released. */
+int cylpoisson_last_status(void);
 
 /* Static description of a status code. */
 const char* cylpoisson_status_string(int status);

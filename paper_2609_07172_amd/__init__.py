@@ -20,7 +20,7 @@ __all__ = [
     "OK", "NOT_CONVERGED", "EINVAL", "ENOMEM", "EHIP", "ENONFINITE", "EDEVICE",
     "CylPoissonError", "library", "library_path", "plan_create", "plan_destroy",
     "plan_set_option", "solve", "solve_planes", "apply", "dft_forward", "dft_inverse",
-    "get_stats", "get_info", "last_error", "status_string", "Plan", "EXPORTED_SYMBOLS",
+    "get_stats", "get_info", "last_error", "last_status", "status_string", "Plan", "EXPORTED_SYMBOLS",
     "plan_get_option", "autotune", "solve_batch", "solve_plans", "Net", "plan_create_mesh",
     "VERTEX", "CELL",
 ]
@@ -37,7 +37,7 @@ EXPORTED_SYMBOLS = (
     "cylpoisson_plan_set_option",
     "cylpoisson_solve", "cylpoisson_get_stats", "cylpoisson_get_info", "cylpoisson_apply",
     "cylpoisson_dft_forward", "cylpoisson_dft_inverse", "cylpoisson_solve_planes",
-    "cylpoisson_last_error", "cylpoisson_status_string", "cylpoisson_plan_get_option",
+    "cylpoisson_last_error", "cylpoisson_last_status", "cylpoisson_status_string", "cylpoisson_plan_get_option",
     "cylpoisson_autotune", "cylpoisson_solve_batch", "cylpoisson_nn_create", "cylpoisson_nn_destroy",
     "cylpoisson_nn_weight_count", "cylpoisson_nn_get_weights", "cylpoisson_nn_set_weights",
     "cylpoisson_nn_get_grads", "cylpoisson_nn_forward", "cylpoisson_nn_loss_grad", "cylpoisson_nn_adam_step",
@@ -163,6 +163,8 @@ def library() -> ctypes.CDLL:
     L.cylpoisson_get_info.argtypes = [vp, ctypes.POINTER(Info)]
     L.cylpoisson_last_error.restype = ctypes.c_char_p
     L.cylpoisson_last_error.argtypes = []
+    L.cylpoisson_last_status.restype = i
+    L.cylpoisson_last_status.argtypes = []
     L.cylpoisson_status_string.restype = ctypes.c_char_p
     L.cylpoisson_status_string.argtypes = [i]
     _lib = L
@@ -171,6 +173,11 @@ def library() -> ctypes.CDLL:
 
 def last_error() -> str:
     return library().cylpoisson_last_error().decode()
+
+
+def last_status() -> int:
+    """``cylpoisson_last_status``: why the last plan creation in this thread failed."""
+    return int(library().cylpoisson_last_status())
 
 
 def status_string(status: int) -> str:
@@ -207,7 +214,7 @@ def plan_create(nr, ntheta, nz, r_in, r_out, dz, bc=(0.0, 0.0, 0.0, 0.0)) -> int
     h = library().cylpoisson_plan_create(int(nr), int(ntheta), int(nz), float(r_in),
                                          float(r_out), float(dz), ctypes.byref(b))
     if not h:
-        raise CylPoissonError(EINVAL, last_error())
+        raise CylPoissonError(last_status(), last_error())
     return h
 
 
@@ -226,7 +233,7 @@ def plan_create_mesh(nr, ntheta, nz, r, z, layout=VERTEX, bc=(0.0, 0.0, 0.0, 0.0
     h = library().cylpoisson_plan_create_mesh(int(nr), int(ntheta), int(nz), ra, za, int(layout),
                                               ctypes.byref(b))
     if not h:
-        raise CylPoissonError(EINVAL, last_error())
+        raise CylPoissonError(last_status(), last_error())
     return h
 
 

@@ -228,8 +228,9 @@ constexpr int kSlotPartial = 64;  // per-slot partial sums kept for the host (ch
 // right-hand-side slot of warm starts
 constexpr int kNormSlots = CYLPOISSON_MAX_HISTORY + 3;
 
-// Error reporting (thread-local message).
+// Error reporting (thread-local message; the status of a failed creation).
 void set_error(const char* fmt, ...);
+void set_status(int status);
 
 // ---- kernel launchers (kernels.hip) ----
 hipError_t launch_dft(const double* M, const double* X, double* Y, int n, long long ncols,

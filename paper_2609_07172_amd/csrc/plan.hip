@@ -26,6 +26,10 @@ void set_error(const char* fmt, ...) {
 
 const char* last_error() { return g_err; }
 
+// Status of the last failed plan or network creation in this thread.
+thread_local int g_status = CYLPOISSON_OK;
+void set_status(int status) { g_status = status; }
+
 namespace {
 
 // Keep every other node counted from the first one and always keep the last
@@ -463,6 +467,7 @@ cylpoisson_plan* build_plan(cylpoisson_plan* p) {
     const long long nodes = (long long)Nr * Ntheta * Nz;
     if (hipGetDevice(&p->device) != hipSuccess) {
         set_error("no HIP device available");
+        set_status(CYLPOISSON_EHIP);
         delete p;
         return nullptr;
     }
@@ -676,6 +681,7 @@ cylpoisson_plan* build_plan(cylpoisson_plan* p) {
     return p;
 fail:
     set_error("device allocation or upload failed: %s", hipGetErrorString(e));
+    set_status(e == hipErrorOutOfMemory ? CYLPOISSON_ENOMEM : CYLPOISSON_EHIP);
     free_plan(p);
     delete p;
     (void)hipGetLastError();
@@ -709,6 +715,7 @@ cylpoisson_plan* new_plan(int Nr, int Ntheta, int Nz, const cylpoisson_bc* bc) {
     cylpoisson_plan* p = new (std::nothrow) cylpoisson_plan();
     if (!p) {
         set_error("host allocation failed");
+        set_status(CYLPOISSON_ENOMEM);
         return nullptr;
     }
     p->nr = Nr;
@@ -769,6 +776,8 @@ extern "C" {
 
 const char* cylpoisson_last_error(void) { return cp::last_error(); }
 
+int cylpoisson_last_status(void) { return cp::g_status; }
+
 const char* cylpoisson_status_string(int status) {
     switch (status) {
         case CYLPOISSON_OK: return "ok";
@@ -782,9 +791,9 @@ const char* cylpoisson_status_string(int status) {
     }
 }
 
-cylpoisson_plan* cylpoisson_plan_create(int Nr, int Ntheta, int Nz, double r_in, double r_out,
-                                        double dz, const cylpoisson_bc* bc) {
-    set_error("%s", "");
+namespace {
+cylpoisson_plan* create_uniform(int Nr, int Ntheta, int Nz, double r_in, double r_out, double dz,
+                                const cylpoisson_bc* bc) {
     if (!check_grid(Nr, Ntheta, Nz, bc)) return nullptr;
     if (!(std::isfinite(r_in) && std::isfinite(r_out) && std::isfinite(dz)) || !(r_in > 0.0) ||
         !(r_out > r_in) || !(dz > 0.0)) {
@@ -802,9 +811,8 @@ cylpoisson_plan* cylpoisson_plan_create(int Nr, int Ntheta, int Nz, double r_in,
     return build_plan(p);
 }
 
-cylpoisson_plan* cylpoisson_plan_create_mesh(int Nr, int Ntheta, int Nz, const double* r, const double* z,
-                                             int layout, const cylpoisson_bc* bc) {
-    set_error("%s", "");
+cylpoisson_plan* create_mesh(int Nr, int Ntheta, int Nz, const double* r, const double* z, int layout,
+                             const cylpoisson_bc* bc) {
     if (!check_grid(Nr, Ntheta, Nz, bc)) return nullptr;
     if (!r || !z) {
         set_error("r and z must not be NULL");
@@ -826,6 +834,27 @@ cylpoisson_plan* cylpoisson_plan_create_mesh(int Nr, int Ntheta, int Nz, const d
     p->r_in = p->xr.front();
     p->r_out = p->xr.back();
     return build_plan(p);
+}
+
+// A NULL result whose cause set no status failed validation.
+cylpoisson_plan* finish_create(cylpoisson_plan* p) {
+    if (!p && cp::g_status == CYLPOISSON_OK) cp::set_status(CYLPOISSON_EINVAL);
+    return p;
+}
+}  // namespace
+
+cylpoisson_plan* cylpoisson_plan_create(int Nr, int Ntheta, int Nz, double r_in, double r_out,
+                                        double dz, const cylpoisson_bc* bc) {
+    set_error("%s", "");
+    cp::set_status(CYLPOISSON_OK);
+    return finish_create(create_uniform(Nr, Ntheta, Nz, r_in, r_out, dz, bc));
+}
+
+cylpoisson_plan* cylpoisson_plan_create_mesh(int Nr, int Ntheta, int Nz, const double* r, const double* z,
+                                             int layout, const cylpoisson_bc* bc) {
+    set_error("%s", "");
+    cp::set_status(CYLPOISSON_OK);
+    return finish_create(create_mesh(Nr, Ntheta, Nz, r, z, layout, bc));
 }
 
 void cylpoisson_plan_destroy(cylpoisson_plan* plan) {

@@ -484,9 +484,11 @@ int run_cycles(cylpoisson_plan* p, double tol, hipStream_t s, bool ring_only, bo
     const double budget = tol * tol * b2 / nt;  // masks only (never deferred)
     std::vector<double> frozen(nt, -1.0);  // last norm of a frozen plane, -1 while active
     if (masks) {
+        // every plane takes the first cycle: a ring-only or full-multigrid start
+        // writes a plane's interior only there, and a frozen plane's norm must be
+        // that of the iterate it keeps
         for (int q = 0; q < nt; ++q) p->h_mask[q] = 1;
         CP_HIP(hipMemcpyAsync(p->d_mask, p->h_mask, nt * sizeof(int), hipMemcpyHostToDevice, s));
-        CP_HIP(update_masks(p, p->h_norms, budget, frozen, s));
     }
     if (G > 1) {
         CP_HIP(ensure_groups(p, G));
@@ -992,9 +994,9 @@ int cylpoisson_solve(cylpoisson_plan* p, const double* rho, double* phi, double 
     const bool warm = p->opt.warm_start != 0 && !learned;
     const bool fmg = !warm && !learned && !mixed && fmg_active(p);
     // the first down pass folds in the start's finest interpolation, except
-    // with masks (a plane frozen before the first cycle keeps the start) and
-    // graphs (the captured first cycle is the plain one)
-    const bool fmg_pro = fmg && fused_down_pro_ok(p) && !masks_active(p) && !graphs_active(p, groups_active(p));
+    // with graphs (the captured first cycle is the plain one); masks freeze no
+    // plane before the first cycle
+    const bool fmg_pro = fmg && fused_down_pro_ok(p) && !graphs_active(p, groups_active(p));
     const bool ring_only = !warm && !learned && !fmg && (mixed || fused_supported(p, 0));
     {
         Timed tm(p, kOther, s);
@@ -1025,6 +1027,13 @@ int cylpoisson_solve(cylpoisson_plan* p, const double* rho, double* phi, double 
     const int status = learned ? run_learned(p, tol, s)
                        : mixed ? run_mixed(p, tol, s, &result, warm)
                                : run_cycles(p, tol, s, ring_only, warm, fmg, fmg_pro);
+    if ((status == CYLPOISSON_OK || status == CYLPOISSON_NOT_CONVERGED) && p->stats.cycles == 0 &&
+        (ring_only || fmg)) {
+        // no cycle ran (a right-hand side that is zero, or tol >= 1): the answer
+        // is the zero interior whose residual was measured, which a ring-only
+        // start never wrote and a full-multigrid start overwrote with its guess
+        CP_HIP(launch_zero_interior(L, p->nt, L.u, s));
+    }
     if (status == CYLPOISSON_OK || status == CYLPOISSON_NOT_CONVERGED) {
         Timed tm(p, kDftInv, s);
         CP_HIP(transform(p, true, result, phi, nullptr, s));

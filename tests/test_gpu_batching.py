@@ -10,7 +10,7 @@ import torch
 import workloads as W
 from oracle import fv, solvers
 
-from gpu_util import dev, host, rel_l2, say
+from gpu_util import INTERIOR as INNER, dev, host, rel_l2, say
 
 pytestmark = pytest.mark.gpu
 
@@ -97,6 +97,48 @@ def test_masks_on_a_full_spectrum_match_the_oracle(P):
     phi, st = P.Plan.for_problem(p, masks=1).solve(dev(rho), tol=1e-14)
     assert st["status"] == P.OK and st["rel_residual"] <= 1e-14, st
     assert rel_l2(host(phi), ref) <= 1e-12
+
+
+@pytest.mark.parametrize("fmg", [0, 1])
+def test_masks_after_another_solve_keep_no_stale_plane(P, fmg):
+    """A masked plan solves a full-spectrum charge, then the m <= 3 manufactured
+    charge: the planes whose right-hand side is at rounding level now must hold
+    this solve's answer, not the interior the previous solve left behind."""
+    p = W.SMALL.with_sizes(129, 32, 129)
+    phit, rho = manufactured(p)
+    ref = solvers.solve_separable(fv.Grid.of(p), rho, p.bc)
+    say("masks stale planes, fmg", fmg)
+    plan = P.Plan.for_problem(p, masks=1, fmg=fmg)
+    _, st0 = plan.solve(dev(W.blob_charge(p, seed=3)), tol=1e-14)
+    assert st0["status"] == P.OK, st0
+    phi, st = plan.solve(dev(rho), tol=1e-14)
+    assert st["status"] == P.OK and st["frozen_planes"] >= 32 - 7, st
+    got = host(phi)
+    assert rel_l2(got, ref) <= 1e-12
+    # planes m >= 4 carry rounding only: phi's azimuthal spectrum above m = 3
+    # is at the oracle's level, not that of the blob charge's answer
+    spec = np.abs(np.fft.rfft(got[INNER] - ref[INNER], axis=0)).max()
+    assert spec <= 1e-10 * np.abs(ref).max(), spec
+
+
+@pytest.mark.parametrize("options", [{}, {"fmg": 1}, {"masks": 1}, {"fmg": 1, "masks": 1}],
+                         ids=["zero", "fmg", "masks", "fmg+masks"])
+def test_tolerance_above_one_returns_the_zero_interior(P, options):
+    """tol >= 1 is met by the zero interior before any cycle: the answer is that
+    iterate (Dirichlet values on the boundary nodes, zero inside), whatever the
+    plan's previous solve left in its buffers."""
+    p = W.SMALL.with_sizes(129, 8, 129)
+    plan = P.Plan.for_problem(p, **options)
+    say("tol >= 1", options)
+    plan.solve(dev(W.blob_charge(p, seed=3)), tol=1e-13)
+    phi, st = plan.solve(dev(W.blob_charge(p, seed=4)), tol=1.0)
+    assert st["status"] == P.OK and st["cycles"] == 0, st
+    got = host(phi)
+    assert (got[INNER] == 0.0).all()
+    np.testing.assert_array_equal(got[:, 0, :], p.phi_z0)
+    np.testing.assert_array_equal(got[:, -1, :], p.phi_zL)
+    np.testing.assert_array_equal(got[:, 1:-1, 0], p.phi_r_in)
+    np.testing.assert_array_equal(got[:, 1:-1, -1], p.phi_r_out)
 
 
 # -------------------------------------------------------------- graphs

@@ -295,6 +295,37 @@ def test_long_lines_use_the_thomas_sweeps(P, name):
         assert rel_l2(host(phi), ref) <= 1e-12, (sm, rel_l2(host(phi), ref))
 
 
+# flat cells (34:1 and 1:34): FP64 cannot represent the answer to a 1e-13
+# residual here (the exact solution rounded to FP64 leaves 1.8e-13 on the
+# r-line grid), so the tolerance is derived from that floor
+FLAT_LINES = {"long-r-lines-flat": W.Problem(1030, 2, 9, 0.02, 0.05, 1e-3, name="long-r-flat"),
+              "long-z-lines-flat": W.Problem(9, 2, 1030, 0.02, 0.02 + 8e-3, 3e-5, name="long-z-flat")}
+
+
+@pytest.mark.parametrize("name", list(FLAT_LINES))
+def test_long_lines_on_flat_cells_reach_the_fp64_floor(P, name):
+    """The Thomas-sweep line smoothers on lines longer than 1024 with flat cells.
+    The tolerance is 10 times the relative residual of the exact discrete
+    solution (the oracle's separable solve in extended precision) rounded to
+    FP64, the smallest residual any FP64 answer can have; the answer must then
+    lie within 1e-12 of the exact one, or within 30 times the oracle's own FP64
+    error if that is larger."""
+    p = FLAT_LINES[name]
+    rho = W.blob_charge(p, seed=5)
+    gl = fv.Grid.of(p, np.longdouble)
+    exact = solvers.solve_separable(gl, rho, p.bc)
+    floor = solvers.residual_norm(gl, exact.astype(np.float64), rho, p.bc)
+    exact = exact.astype(np.float64)
+    err64 = rel_l2(solvers.solve_separable(fv.Grid.of(p), rho, p.bc), exact)
+    tol = 10.0 * max(floor, 1e-16)
+    bound = max(1e-12, 30.0 * err64)
+    say("flat long lines", name, p.shape, "tol", tol, "bound", bound)
+    for sm in (1, 2):
+        phi, st = P.Plan.for_problem(p, smoother=sm).solve(dev(rho), tol=tol)
+        assert st["status"] == P.OK, (sm, st)
+        assert rel_l2(host(phi), exact) <= bound, (sm, rel_l2(host(phi), exact))
+
+
 def test_plans_reject_geometry_beyond_the_double_range(P):
     """Finite inputs whose finite-volume coefficients overflow are refused."""
     with pytest.raises(P.CylPoissonError) as e:

@@ -253,6 +253,44 @@ def test_not_converged_returns_last_iterate(P):
     check_boundary(host(phi), p)
 
 
+def test_tolerance_below_the_floor_stops_on_stagnation(P):
+    """A tolerance no FP64 iteration can reach: the cycles stop once the residual
+    falls less than 0.6-fold over three checks, with NOT_CONVERGED, the
+    stagnation message and an answer at the oracle's floor."""
+    p = W.SMALL
+    _, rho = manufactured(p)
+    ref = solvers.solve_sparse(fv.Grid.of(p), rho, p.bc)
+    say("stagnation tol 1e-22")
+    plan = P.Plan.for_problem(p)
+    phi, st = plan.solve(dev(rho), tol=1e-22, allow=(P.OK, P.NOT_CONVERGED))
+    assert st["status"] == P.NOT_CONVERGED, st
+    assert "stagnated" in P.last_error(), P.last_error()
+    assert st["cycles"] < plan.get_option("max_cycles"), st
+    assert st["rel_residual"] < 1e-14, st
+    assert rel_l2(host(phi), ref) <= 1e-12
+    check_boundary(host(phi), p)
+
+
+def test_oversized_plan_reports_enomem_and_releases_its_memory(P):
+    """A workspace larger than the device's memory (16001 x 256 x 16385 nodes:
+    537 GB per node array) fails with ENOMEM, frees what it took, and a normal
+    plan created after it still solves."""
+    torch.cuda.synchronize()
+    free0 = torch.cuda.mem_get_info()[0]
+    say("oversized plan")
+    with pytest.raises(P.CylPoissonError) as e:
+        P.Plan(16001, 256, 16385, 0.02, 0.05, 0.05 / 16384, (0.0, 0.0, 0.0, 300.0))
+    assert e.value.status == P.ENOMEM, (e.value.status, str(e.value))
+    assert P.last_status() == P.ENOMEM
+    torch.cuda.synchronize()
+    assert torch.cuda.mem_get_info()[0] >= free0 - (64 << 20)
+    p = W.SMALL
+    _, rho = manufactured(p)
+    phi, st = P.Plan.for_problem(p).solve(dev(rho), tol=1e-14)
+    assert st["status"] == P.OK and P.last_status() == P.OK
+    assert rel_l2(host(phi), solvers.solve_sparse(fv.Grid.of(p), rho, p.bc)) <= 1e-12
+
+
 def test_host_pointer_is_rejected(P):
     p = W.SMALL.with_sizes(5, 2, 5)
     plan = P.Plan.for_problem(p)
