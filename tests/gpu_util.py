@@ -25,3 +25,17 @@ def host(t: torch.Tensor) -> np.ndarray:
 def rel_l2(a, b, where=INTERIOR) -> float:
     a, b = np.asarray(a)[where], np.asarray(b)[where]
     return float(np.linalg.norm((a - b).ravel()) / np.linalg.norm(b.ravel()))
+
+
+def rel_linf(a, b, where=INTERIOR) -> float:
+    """max |a - b| / max |b| over the selected nodes (Sec. 5.1's epsilon_inf)."""
+    a, b = np.asarray(a)[where], np.asarray(b)[where]
+    return float(np.abs(a - b).max() / np.abs(b).max())
+
+
+def eps2(a, b, r, where=INTERIOR) -> float:
+    """Sec. 5.1's cylindrically weighted epsilon_2 of a against b: weights
+    r_i dr dz per node (uniform dr, dz cancel), r the radial node coordinates."""
+    a, b = np.asarray(a)[where], np.asarray(b)[where]
+    w = np.broadcast_to(np.asarray(r)[where[2]], a.shape)
+    return float(np.sqrt(np.sum(w * (a - b) ** 2) / np.sum(w * b * b)))

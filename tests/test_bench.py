@@ -39,3 +39,36 @@ def test_counter_profile_matches_the_fused_pass_sources():
     for k in ("fine_up", "fine_down"):
         assert 0.9 < rec["bytes_per_launch"][k] / bench.alg_bytes(
             {"level_shapes": [(400, 512), (201, 257)]}, 128)["up"] < 1.25
+
+
+def test_accuracy_measures_on_a_planted_error():
+    """One interior node off by d: rel-L_inf is d / max|ref|, rel-L2 is
+    d / ||ref||, and the charge-driven part divides by ||ref - 300 z / L||."""
+    import numpy as np
+
+    import workloads as W
+
+    p = W.SMALL
+    ref = W.manufactured_potential(p, 12345)
+    phi = ref.copy()
+    d = 1e-9
+    phi[3, 7, 11] += d
+    a = bench.accuracy(phi, ref, p, "x")
+    inner = ref[:, 1:-1, 1:-1]
+    _, z, r = W.node_coordinates(p)
+    blobs = inner - (300.0 * z / p.length)[None, 1:-1, None]
+    assert np.isclose(a["rel_linf_vs_x"], d / np.abs(inner).max(), rtol=1e-12)
+    assert np.isclose(a["rel_l2_vs_x"], d / np.linalg.norm(inner), rtol=1e-12)
+    assert np.isclose(a["rel_l2_charge_part_vs_x"], d / np.linalg.norm(blobs), rtol=1e-12)
+    w = np.broadcast_to(r[None, None, 1:-1], inner.shape)
+    assert np.isclose(a["eps2_vs_x"], d * np.sqrt(r[11] / np.sum(w * inner * inner)), rtol=1e-12)
+    # the error on boundary nodes is not counted
+    phi[0, 0, 0] += 1.0
+    assert bench.accuracy(phi, ref, p, "x") == a
+
+
+def test_full_multigrid_byte_model():
+    """Start: read f, write the level-1 right-hand side, one V-cycle from level 1
+    (a quarter of 69.3 B); the first down pass reads the level-1 answer (2 B)
+    instead of the iterate (8 B)."""
+    assert abs(bench.FMG_BYTES - (8 + 2 + 69.3 / 4 + 2 - 8)) < 1e-12
