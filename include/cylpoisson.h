@@ -282,6 +282,23 @@ int cylpoisson_solve_batch(cylpoisson_plan* const* plans, const double* const* r
 int cylpoisson_solve(cylpoisson_plan* plan, const double* rho, double* phi, double tol,
                      void* stream);
 
+/* The solve of cylpoisson_solve for callers that cannot allocate device
+ * memory (serving loops, harnesses that forbid hipMalloc).  Same arguments,
+ * statuses and results as cylpoisson_solve (bit for bit), but the work arrays
+ * of the V-cycles -- every level's iterates, right-hand side and residual, the
+ * residual-norm partials -- live in a static device array of the library
+ * (64 MiB per device, held from the first use of the library on a device
+ * until the process ends) instead of the plan's workspace.  The call
+ * allocates nothing and creates no stream, event or graph: the options
+ * "timing", "groups" and "graph" are ignored for it.  It needs "precision" 64
+ * and "krylov" 0, and a plan whose work arrays fit in 64 MiB (about 1.4
+ * million unknowns, e.g. 129 x 64 x 129); otherwise EINVAL before any device
+ * work.  All calls on one device share its array and each first clears the
+ * part it uses (with a kernel on `stream`): calls that overlap on one device
+ * race, so issue them on one stream or one after another. */
+int cylpoisson_solve_static(cylpoisson_plan* plan, const double* rho, double* phi, double tol,
+                            void* stream);
+
 /* Statistics of the last solve (or plane solve).  Returns OK or EINVAL. */
 int cylpoisson_get_stats(const cylpoisson_plan* plan, cylpoisson_stats* out);
 

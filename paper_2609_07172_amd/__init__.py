@@ -20,7 +20,7 @@ __all__ = [
     "OK", "NOT_CONVERGED", "EINVAL", "ENOMEM", "EHIP", "ENONFINITE", "EDEVICE",
     "CylPoissonError", "library", "library_path", "plan_create", "plan_destroy",
     "plan_set_option", "solve", "solve_planes", "apply", "dft_forward", "dft_inverse",
-    "get_stats", "get_info", "last_error", "last_status", "status_string", "Plan", "EXPORTED_SYMBOLS",
+    "get_stats", "get_info", "last_error", "last_status", "solve_static", "status_string", "Plan", "EXPORTED_SYMBOLS",
     "plan_get_option", "autotune", "solve_batch", "solve_plans", "Net", "plan_create_mesh",
     "VERTEX", "CELL",
 ]
@@ -35,7 +35,7 @@ KERNEL_CLASSES = ("dft_forward", "dft_inverse", "fine_down", "fine_up", "coarse_
 EXPORTED_SYMBOLS = (
     "cylpoisson_plan_create", "cylpoisson_plan_create_mesh", "cylpoisson_plan_destroy",
     "cylpoisson_plan_set_option",
-    "cylpoisson_solve", "cylpoisson_get_stats", "cylpoisson_get_info", "cylpoisson_apply",
+    "cylpoisson_solve", "cylpoisson_solve_static", "cylpoisson_get_stats", "cylpoisson_get_info", "cylpoisson_apply",
     "cylpoisson_dft_forward", "cylpoisson_dft_inverse", "cylpoisson_solve_planes",
     "cylpoisson_last_error", "cylpoisson_last_status", "cylpoisson_status_string", "cylpoisson_plan_get_option",
     "cylpoisson_autotune", "cylpoisson_solve_batch", "cylpoisson_nn_create", "cylpoisson_nn_destroy",
@@ -120,7 +120,7 @@ def library() -> ctypes.CDLL:
     L.cylpoisson_plan_destroy.argtypes = [vp]
     L.cylpoisson_plan_set_option.restype = i
     L.cylpoisson_plan_set_option.argtypes = [vp, ctypes.c_char_p, d]
-    for name in ("cylpoisson_solve", "cylpoisson_solve_planes"):
+    for name in ("cylpoisson_solve", "cylpoisson_solve_static", "cylpoisson_solve_planes"):
         getattr(L, name).restype = i
         getattr(L, name).argtypes = [vp, vp, vp, d, vp]
     for name in ("cylpoisson_apply", "cylpoisson_dft_forward", "cylpoisson_dft_inverse"):
@@ -274,6 +274,12 @@ def solve(plan, rho, phi, tol=1e-12, stream=None, allow=(OK,)) -> int:
                                              _stream(stream)), allow)
 
 
+def solve_static(plan, rho, phi, tol=1e-12, stream=None, allow=(OK,)) -> int:
+    """``cylpoisson_solve_static``: the solve on the library's static device scratch."""
+    return _check(library().cylpoisson_solve_static(plan, _ptr(rho), _ptr(phi), float(tol),
+                                                    _stream(stream)), allow)
+
+
 def solve_planes(plan, b, u, tol=1e-12, stream=None, allow=(OK,)) -> int:
     return _check(library().cylpoisson_solve_planes(plan, _ptr(b), _ptr(u), float(tol),
                                                     _stream(stream)), allow)
@@ -349,6 +355,15 @@ class Plan:
         if phi is None:
             phi = torch.empty_like(rho)
         solve(self.handle, rho, phi, tol, stream, allow)
+        return phi, get_stats(self.handle)
+
+    def solve_static(self, rho, tol=1e-12, phi=None, stream=None, allow=(OK,)):
+        """The same solve on the library's static device scratch (no allocation
+        by the library; a phi of None is allocated here by torch)."""
+        self._check_shape(rho, *(() if phi is None else (phi,)))
+        if phi is None:
+            phi = torch.empty_like(rho)
+        solve_static(self.handle, rho, phi, tol, stream, allow)
         return phi, get_stats(self.handle)
 
     def info(self) -> dict:

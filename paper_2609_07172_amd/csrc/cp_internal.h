@@ -149,6 +149,9 @@ struct cylpoisson_plan {
     // the kernels read d_mask only while a masked V-cycle iteration keeps it
     // current (set for the duration of run_cycles with masks active)
     bool mask_live = false;
+    // set for the duration of a cylpoisson_solve_static call: its work arrays
+    // live in the library's static scratch and it creates no stream or event
+    bool static_call = false;
     cp::Options opt;
 
     std::vector<cp::HostLevel> hl;

@@ -3,8 +3,16 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 
 #include "cp_internal.h"
+
+// Work arrays of cylpoisson_solve_static: 64 MiB per device, held from the
+// moment the library's code object is loaded on a device until the process
+// ends.  Host code uses the address hipGetSymbolAddress gives for the current
+// device, never this name.
+constexpr size_t kScratchBytes = size_t(64) << 20;
+static __device__ __align__(256) double scratch[kScratchBytes / sizeof(double)];
 
 namespace cp {
 
@@ -942,13 +950,9 @@ hipError_t fmg_start(cylpoisson_plan* p, hipStream_t s, bool fused_top) {
 
 hipError_t vcycle_from_zero(cylpoisson_plan* p, hipStream_t s) { return vcycle(p, 0, s, true, -1, nullptr); }
 
-}  // namespace cp
+namespace {
 
-using namespace cp;
-
-extern "C" {
-
-int cylpoisson_solve(cylpoisson_plan* p, const double* rho, double* phi, double tol, void* stream) {
+int solve_impl(cylpoisson_plan* p, const double* rho, double* phi, double tol, void* stream) {
     if (!p) {
         set_error("plan must not be NULL");
         return CYLPOISSON_EINVAL;
@@ -1000,7 +1004,12 @@ int cylpoisson_solve(cylpoisson_plan* p, const double* rho, double* phi, double 
     const bool ring_only = !warm && !learned && !fmg && (mixed || fused_supported(p, 0));
     {
         Timed tm(p, kOther, s);
-        if (fmg) {
+        if (fmg && p->static_call) {
+            // no second stream: the norms go first on the caller's
+            CP_HIP(launch_init_ring(L, p->nt, p->bc, s));
+            CP_HIP(launch_rhs_norms(L, p->nt, p->d_lam, L.u, L.f, p->d_partial, p->d_norms, s));
+            CP_HIP(fmg_start(p, s, fmg_pro));
+        } else if (fmg) {
             CP_HIP(launch_init_ring(L, p->nt, p->bc, s));
             // the right-hand side norms read f and u's ring only, which the
             // start does not write: they run beside its latency-bound coarse
@@ -1042,6 +1051,120 @@ int cylpoisson_solve(cylpoisson_plan* p, const double* rho, double* phi, double 
         CP_HIP(hipStreamSynchronize(s));
         collect_timing(p);
     }
+    return status;
+}
+
+// ---- the solve on the library's static scratch ----
+// The work arrays of every level (u, u2, f, r), the norm partials and the
+// per-cycle norms live in one file-scope device array instead of the plan's
+// workspace, so a call allocates nothing.  Each device holds its own copy;
+// host code reaches it only through the address hipGetSymbolAddress returns
+// for that device (the array's name is a host-side stand-in).
+std::mutex g_scratch_mutex;
+std::vector<double*> g_scratch_addr;  // per device ordinal, nullptr until looked up
+
+// The scratch address on `device` (current), looked up once per device.
+hipError_t scratch_address(int device, double** out) {
+    std::lock_guard<std::mutex> lock(g_scratch_mutex);
+    if ((int)g_scratch_addr.size() <= device) g_scratch_addr.resize(device + 1, nullptr);
+    if (!g_scratch_addr[device]) {
+        double* ptr = nullptr;
+        hipError_t e = hipGetSymbolAddress((void**)&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_scratch_addr[device] = ptr;
+    }
+    *out = g_scratch_addr[device];
+    return hipSuccess;
+}
+
+// Bytes of the static scratch a plan's solve needs (regions 256-byte aligned);
+// with `base` set, also points the plan's work arrays into it.
+size_t carve_scratch(cylpoisson_plan* p, double* base) {
+    size_t off = 0;
+    auto take = [&](double** slot, size_t count) {
+        if (base) *slot = base + off / sizeof(double);
+        off += (count * sizeof(double) + 255) & ~size_t(255);
+    };
+    for (DeviceLevel& L : p->dl) {
+        const size_t n = (size_t)p->nt * L.v.pstride;
+        take(&L.u, n);
+        take(&L.u2, n);
+        take(&L.f, n);
+        take(&L.r, n);
+    }
+    take(&p->d_partial, (size_t)p->nt * kMaxPartial);
+    take(&p->d_norms, (size_t)kNormSlots * p->nt);
+    take(&p->d_slot_partial, (size_t)kNormSlots * p->nt * kSlotPartial);
+    return off;
+}
+
+}  // namespace
+
+}  // namespace cp
+
+using namespace cp;
+
+extern "C" {
+
+int cylpoisson_solve(cylpoisson_plan* p, const double* rho, double* phi, double tol, void* stream) {
+    return solve_impl(p, rho, phi, tol, stream);
+}
+
+int cylpoisson_solve_static(cylpoisson_plan* p, const double* rho, double* phi, double tol, void* stream) {
+    if (!p) {
+        set_error("plan must not be NULL");
+        return CYLPOISSON_EINVAL;
+    }
+    if (!(tol > 0.0) || !std::isfinite(tol)) {
+        set_error("tol must be a positive finite number");
+        return CYLPOISSON_EINVAL;
+    }
+    if (p->opt.precision != 64 || p->opt.krylov != 0) {
+        set_error("cylpoisson_solve_static runs the FP64 V-cycles only (precision 64, krylov 0)");
+        return p->stats.status = CYLPOISSON_EINVAL;
+    }
+    const size_t need = carve_scratch(p, nullptr);
+    if (need > kScratchBytes) {
+        set_error("cylpoisson_solve_static: this plan's work arrays need %zu bytes; the static scratch "
+                  "holds %zu", need, kScratchBytes);
+        return p->stats.status = CYLPOISSON_EINVAL;
+    }
+    DeviceGuard g(p->device);
+    const size_t bytes = node_bytes(p);
+    int st = check_device_range(p, rho, bytes, "rho");
+    if (st == CYLPOISSON_OK) st = check_device_range(p, phi, bytes, "phi");
+    if (st != CYLPOISSON_OK) return p->stats.status = st;
+    double* base = nullptr;
+    CP_HIP(scratch_address(p->device, &base));
+    // the plan's own work arrays and the options that would create streams,
+    // events or graphs, restored on return (none changes the arithmetic)
+    std::vector<DeviceLevel> levels = p->dl;
+    double* const partial = p->d_partial;
+    double* const norms = p->d_norms;
+    double* const slot_partial = p->d_slot_partial;
+    const Options opt = p->opt;
+    carve_scratch(p, base);
+    p->opt.timing = 0;
+    p->opt.groups = 1;
+    p->opt.graph = 0;
+    p->static_call = true;
+    // the scratch keeps the last call's contents: start from the state of a
+    // new plan's workspace (all zero), with a fill kernel on the stream
+    hipError_t e = launch_zero(base, (long long)(need / sizeof(double)), static_cast<hipStream_t>(stream));
+    int status;
+    if (e != hipSuccess) {
+        set_error("clearing the static scratch failed: %s", hipGetErrorString(e));
+        (void)hipGetLastError();
+        status = p->stats.status = CYLPOISSON_EHIP;
+    } else {
+        status = solve_impl(p, rho, phi, tol, stream);
+    }
+    p->dl = levels;
+    p->d_partial = partial;
+    p->d_norms = norms;
+    p->d_slot_partial = slot_partial;
+    p->opt = opt;
+    p->static_call = false;
     return status;
 }
 
