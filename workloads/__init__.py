@@ -38,6 +38,8 @@ __all__ = [
     "stretched_points",
     "mesh_blob_charge",
     "cell_centres",
+    "blob_field",
+    "sequence_plan",
 ]
 
 
@@ -115,6 +117,51 @@ def _boundary_faces(p: Problem, phi: np.ndarray) -> np.ndarray:
     return phi
 
 
+def _blob_draws(p: Problem, seed: int):
+    """The seeded draws of manufactured_potential, in its order."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    w = p.r_out - p.r_in
+    length = p.length
+    h1 = w / 32.0
+    blobs = []
+    for _ in range(4):
+        a = rng.uniform(-1.0, 1.0)
+        rb = rng.uniform(p.r_in + 0.2 * w, p.r_out - 0.2 * w)
+        zb = rng.uniform(0.2 * length, 0.8 * length)
+        sig = rng.uniform(2.0, 5.0) * h1
+        cd = rng.uniform(-1.0, 1.0, size=6)
+        blobs.append((a, rb, zb, sig, cd))
+    return blobs
+
+
+def _add_blobs(p: Problem, seed: int, dtype, out: np.ndarray) -> np.ndarray:
+    """out + sum_b a_b g_b(r, z) [1 + sum_m (c_bm cos m theta + d_bm sin m theta)]
+    at every node, the blobs added to ``out`` one after another."""
+    th, z, r = (np.asarray(c, dtype=dtype) for c in node_coordinates(p))
+    T = th[:, None, None]
+    Z = z[None, :, None]
+    R = r[None, None, :]
+    for a, rb, zb, sig, cd in _blob_draws(p, seed):
+        g = np.exp(-((R - dtype(rb)) ** 2 + (Z - dtype(zb)) ** 2) / dtype(2.0 * sig * sig))
+        ang = np.ones_like(T)
+        for m in range(1, 4):
+            ang = ang + dtype(cd[2 * m - 2]) * np.cos(m * T) + dtype(cd[2 * m - 1]) * np.sin(m * T)
+        out = out + dtype(a) * g * ang
+    return out
+
+
+def blob_field(p: Problem, seed: int) -> np.ndarray:
+    """The blob part of ``manufactured_potential(p, seed)`` (no axial background)
+    on the interior nodes, zero on the boundary nodes, scaled to unit RMS over
+    the interior: one seeded drift direction of a time sequence whose exact
+    answers stay known (the potential moves by multiples of such fields)."""
+    f = _add_blobs(p, seed, np.float64, np.zeros(p.shape))
+    f[:, 0, :] = f[:, -1, :] = 0.0
+    f[:, :, 0] = f[:, :, -1] = 0.0
+    f /= np.sqrt(np.mean(f[:, 1:-1, 1:-1] ** 2))
+    return np.ascontiguousarray(f)
+
+
 def manufactured_potential(p: Problem, seed: int = 12345, dtype=np.float64) -> np.ndarray:
     """A seeded smooth potential phi_true at every node (volts).
 
@@ -129,30 +176,10 @@ def manufactured_potential(p: Problem, seed: int = 12345, dtype=np.float64) -> n
 
     ``dtype`` may be ``numpy.longdouble`` to evaluate in extended precision.
     """
-    rng = np.random.Generator(np.random.PCG64(seed))
-    w = p.r_out - p.r_in
-    length = p.length
-    h1 = w / 32.0
-    blobs = []
-    for _ in range(4):
-        a = rng.uniform(-1.0, 1.0)
-        rb = rng.uniform(p.r_in + 0.2 * w, p.r_out - 0.2 * w)
-        zb = rng.uniform(0.2 * length, 0.8 * length)
-        sig = rng.uniform(2.0, 5.0) * h1
-        cd = rng.uniform(-1.0, 1.0, size=6)
-        blobs.append((a, rb, zb, sig, cd))
-    th, z, r = (np.asarray(c, dtype=dtype) for c in node_coordinates(p))
-    T = th[:, None, None]
+    _, z, _ = (np.asarray(c, dtype=dtype) for c in node_coordinates(p))
     Z = z[None, :, None]
-    R = r[None, None, :]
-    phi = np.zeros(p.shape, dtype=dtype) + dtype(p.phi_zL) * Z / dtype(length)
-    for a, rb, zb, sig, cd in blobs:
-        g = np.exp(-((R - dtype(rb)) ** 2 + (Z - dtype(zb)) ** 2) / dtype(2.0 * sig * sig))
-        ang = np.ones_like(T)
-        for m in range(1, 4):
-            ang = ang + dtype(cd[2 * m - 2]) * np.cos(m * T) + dtype(cd[2 * m - 1]) * np.sin(m * T)
-        phi = phi + dtype(a) * g * ang
-    return _boundary_faces(p, phi)
+    phi = np.zeros(p.shape, dtype=dtype) + dtype(p.phi_zL) * Z / dtype(p.length)
+    return _boundary_faces(p, _add_blobs(p, seed, dtype, phi))
 
 
 def _inside(lo: float, hi: float, margin: float) -> tuple[float, float]:
@@ -273,6 +300,14 @@ def drift_fields(p: Problem, count: int = 8, seed: int = 97531) -> list[np.ndarr
         f[:, 0, :] = f[:, -1, :] = 0.0
         out.append(np.ascontiguousarray(f))
     return out
+
+
+def sequence_plan(steps: int = 200, fields: int = 8, seed: int = 97531) -> tuple[np.ndarray, np.ndarray]:
+    """Which of ``fields`` seeded blob fields (seeds seed .. seed + fields - 1)
+    drifts the potential at each step of a time sequence, and with which sign:
+    step t adds sign[t] * 0.01 * rms(blob part of phi_true) * blob_field(seed + k[t])."""
+    rng = np.random.Generator(np.random.PCG64(seed + 2))
+    return rng.integers(0, fields, size=steps), rng.choice(np.array([-1.0, 1.0]), size=steps)
 
 
 def drift_signs(steps: int = 200, seed: int = 97531) -> np.ndarray:
