@@ -154,7 +154,10 @@ def alg_bytes(info, nt):
     up = 24 * n0 + 8 * n1
     # down pass: read u (8, skipped on the first cycle), f (8); write u (8), coarse f (8)
     down = 24 * n0 + 8 * n1
-    return {"n0": n0, "n1": n1, "up": up, "down": down, "down_first": down - 8 * n0}
+    # merged pass (up pass of one cycle, down pass of the next): read u, f, the
+    # coarse correction; write u and the coarse right-hand side
+    merged = 24 * n0 + 16 * n1
+    return {"n0": n0, "n1": n1, "up": up, "down": down, "down_first": down - 8 * n0, "merged": merged}
 
 
 def traffic_for(kernel: str, launches_bytes: float):
@@ -177,6 +180,8 @@ FINE_KERNELS = {  # finest-level FP64 pass symbols -> kernel class
     "k_pass_fine<double, 2, 1, false, false>": "fine_up",
     # the first down pass after the full-multigrid start (forms the start itself)
     "k_pass_fine_pro<double, 2, 1>": "fine_down_pro",
+    # the up pass of one cycle and the down pass of the next
+    "k_pass_merge<double, 4, 1>": "fine_merged",
 }
 
 
@@ -706,20 +711,32 @@ def main():
         # the first down pass forms the full-multigrid start from the level-1
         # answer (8 B per level-1 unknown) instead of reading an iterate
         b["down_first"] = b["down"] - 8 * b["n0"] + 8 * b["n1"]
-    up_avg_ms = sums["fine_up"] / max(1, launches["fine_up"])
-    down_avg_ms = sums["fine_down"] / max(1, launches["fine_down"])
-    dominant = "fine_up" if sums["fine_up"] >= sums["fine_down"] else "fine_down"
-    if dominant == "fine_up":
-        bytes_launch, avg_ms = b["up"], up_avg_ms
-    else:
-        c = st["cycles"]
-        bytes_launch, avg_ms = (b["down"] * (c - 1) + b["down_first"]) / c, down_avg_ms
+    # algorithmic bytes per launch of each finest-level pass class: the first
+    # down pass of a solve reads no iterate (or the level-1 answer after the
+    # full-multigrid start), the later ones (after a check) read it
+    nd = launches.get("fine_down", 0) / args.steps
+    first_down = b["down_first"]
+    per_launch = {"fine_up": b["up"], "fine_merged": b["merged"],
+                  "fine_down": (first_down + b["down"] * max(0.0, nd - 1)) / max(nd, 1.0)}
+    fine = {}
+    for cls, nbytes in per_launch.items():
+        if launches.get(cls, 0) == 0:
+            continue
+        avg = sums[cls] / launches[cls]
+        gbs = nbytes / (avg * 1e-3) / 1e9
+        fine[cls] = {"bytes_per_launch": nbytes, "avg_launch_ms": round(avg, 5), "launches_per_solve":
+                     launches[cls] / args.steps, "gbs": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4)}
+    dominant = max(fine, key=lambda k: sums[k])
+    bytes_launch, avg_ms = fine[dominant]["bytes_per_launch"], fine[dominant]["avg_launch_ms"]
     achieved = bytes_launch / (avg_ms * 1e-3) / 1e9
     traffic = traffic_for(dominant, bytes_launch)
 
     unknowns = problem.unknowns
+    # each merged pass moves 24 B per finest unknown less than the up and down
+    # passes it replaces (u and f read once, u written once)
+    merges = launches.get("fine_merged", 0) / args.steps
     model_bytes = (16.0 * problem.nodes + 16.0 * unknowns + 69.3 * st["cycles"] * unknowns
-                   + (FMG_BYTES * unknowns if fmg else 0.0))
+                   + (FMG_BYTES * unknowns if fmg else 0.0) - 24.0 * merges * unknowns)
     out = {
         "metric": METRIC,
         "value": round(ms, 4),
@@ -741,6 +758,7 @@ def main():
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": traffic, "bytes_per_launch": bytes_launch,
                      "avg_launch_ms": round(avg_ms, 5)},
+        "fine_passes": fine,
         "cpu_baseline": cpu,
         "cycles": st["cycles"],
         "rel_residual": st["rel_residual"],
@@ -748,9 +766,9 @@ def main():
         "ms_min": round(min(per) * 1e3, 4),
         "ms_p50": round(float(np.median(per)) * 1e3, 4),
         # the whole solve against the algorithmic byte model: 16 B per node and per
-        # unknown for the transforms, 69.3 B per unknown and V-cycle, and for the
-        # full-multigrid start 37.3 B per unknown (restrict f, write the finest
-        # iterate, one V-cycle from level 1 down)
+        # unknown for the transforms, 69.3 B per unknown and V-cycle, less 24 B
+        # per unknown and merged pass, and for the full-multigrid start FMG_BYTES
+        # per unknown (restrict f, one V-cycle from level 1 down)
         "solve_roofline": {"model_bytes": model_bytes,
                            "t_roof_ms": round(model_bytes / (HBM_PEAK_GBS * 1e9) * 1e3, 4),
                            "frac": round(model_bytes / (HBM_PEAK_GBS * 1e9) / (ms_plain * 1e-3), 4)},

@@ -61,7 +61,7 @@ extern "C" {
 
 #define CYLPOISSON_MAX_HISTORY 64
 #define CYLPOISSON_MAX_LEVELS 24
-#define CYLPOISSON_KERNEL_CLASSES 6
+#define CYLPOISSON_KERNEL_CLASSES 7
 
 typedef struct cylpoisson_plan cylpoisson_plan; /* opaque */
 typedef struct cylpoisson_nn cylpoisson_nn;     /* opaque: the learned preconditioner's network */
@@ -80,7 +80,8 @@ typedef struct {
     int n_history;       /* entries of rel_residual_history that are set */
     double rel_residual; /* final relative residual (definition below) */
     double initial_residual_norm; /* ||b|| in finite-volume scaling */
-    /* relative residual after cycle c (index c - 1); NaN where not evaluated.
+    /* relative residual after cycle c (index c - 1); NaN where not evaluated
+     * (cycles that end in a merged finest pass, option "merge").
      * Relative residual = sqrt(sum_p w_p ||r_p||^2 / sum_p w_p ||b_p||^2) over
      * interior nodes, with the Parseval weights w_p = 1 for m = 0 and m = N/2,
      * 2 otherwise, i.e. the 2-norm of the 3-D residual relative to that of the
@@ -92,7 +93,9 @@ typedef struct {
      * down pass (smoothing, residual, restriction), 3 finest-level up pass
      * (prolongation, smoothing, residual norm), 4 all coarser levels (one
      * interval per cycle), 5 other work (initialisation, norm reductions, the
-     * FP64 refinement steps of a mixed-precision solve). */
+     * FP64 refinement steps of a mixed-precision solve), 6 finest-level merged
+     * pass (the up pass of one cycle and the down pass of the next, option
+     * "merge"). */
     int kernel_launches[CYLPOISSON_KERNEL_CLASSES];
     double kernel_ms[CYLPOISSON_KERNEL_CLASSES];
     /* Mixed precision ("precision" = 32): FP64 refinement steps after the
@@ -234,6 +237,16 @@ void cylpoisson_plan_destroy(cylpoisson_plan* plan);
  *                    to 1e-14 from zero).  FP64 with the fused passes and the
  *                    LDS bottom kernel; ignored otherwise, and with
  *                    "warm_start", "precision" 32 or "krylov" (default 0)
+ *   "merge"          1 = a cycle after which no convergence check follows ends in
+ *                    one finest-level pass that does its up pass and the next
+ *                    cycle's down pass (prolongation, nu2 + nu1 sweeps, residual,
+ *                    restriction) with the node arithmetic of the two passes, so
+ *                    iterates and answers are bitwise those of separate passes;
+ *                    such a cycle's residual norm is not formed (NaN in the
+ *                    history).  Applies with the fused passes on the finest level,
+ *                    nu1 = nu2 = 2, at most 512 radial nodes, one plane group and
+ *                    no graphs (default 1)
+ *   "merge_prefetch" rows the merged pass loads ahead of the one it consumes (1 .. 2; default 1)
  *   "graph"          1 = each V-cycle is captured once into a HIP graph and replayed
  *                    (single plane group, "timing" 0; default 0).  Setting any
  *                    option releases the captured graphs

@@ -30,7 +30,7 @@ EINVAL, ENOMEM, EHIP, ENONFINITE, EDEVICE = -1, -2, -3, -4, -5
 VERTEX, CELL = 0, 1  # mesh layouts of cylpoisson_plan_create_mesh
 MAX_HISTORY = 64
 MAX_LEVELS = 24
-KERNEL_CLASSES = ("dft_forward", "dft_inverse", "fine_down", "fine_up", "coarse_levels", "other")
+KERNEL_CLASSES = ("dft_forward", "dft_inverse", "fine_down", "fine_up", "coarse_levels", "other", "fine_merged")
 
 EXPORTED_SYMBOLS = (
     "cylpoisson_plan_create", "cylpoisson_plan_create_mesh", "cylpoisson_plan_destroy",

@@ -127,6 +127,9 @@ struct Options {
     int smoother = 0;      // 0: point red-black SOR; 1: r-line zebra; 2: r-line then z-line zebra
     int nu1_coarse = 0, nu2_coarse = 0;  // sweeps on levels >= 1 (0: nu1, nu2)
     int fmg = 0;           // 1: full-multigrid start before the V-cycles
+    int merge = 1;         // 1: merged finest pass between cycles without a convergence check
+    int merge_prefetch = 1;  // rows the merged finest pass loads ahead (1 or 2)
+    int chunk_rows_merge = 0;  // axial rows per workgroup of the merged pass (0 = automatic)
 };
 
 }  // namespace cp
@@ -149,10 +152,11 @@ struct cylpoisson_plan {
     // the kernels read d_mask only while a masked V-cycle iteration keeps it
     // current (set for the duration of run_cycles with masks active)
     bool mask_live = false;
-    // set for the duration of a cylpoisson_solve_static call: its work arrays
-    // live in the library's static scratch and it creates no stream or event
-    bool static_call = false;
     cp::Options opt;
+    // cycles and tol of the last solve that converged (0: none since the
+    // options last changed): the first convergence check of the next solve
+    int last_cycles = 0;
+    double last_tol = 0.0;
 
     std::vector<cp::HostLevel> hl;
     std::vector<cp::DeviceLevel> dl;
@@ -252,9 +256,11 @@ hipError_t launch_restrict(const DeviceLevel& F, const DeviceLevel& C, int nt, c
 // u += P uc on F's interior, or u = P uc when !add
 hipError_t launch_prolong(const DeviceLevel& F, const DeviceLevel& C, int nt, const double* uc,
                           double* u, hipStream_t s, bool add = true);
-// fc = P^T b, b the residual of the iterate that is u's ring and zero inside (reads u's ring only)
-hipError_t launch_restrict_rhs(const DeviceLevel& F, const DeviceLevel& C, int nt, const double* lam,
-                               const double* u, const double* f, double* fc, hipStream_t s);
+// fc = P^T b, b the residual of the iterate that is u's ring and zero inside
+// (reads u's ring only), and the per-plane sums of b^2 into norms_out
+hipError_t launch_restrict_rhs_norms(const DeviceLevel& F, const DeviceLevel& C, int nt, const double* lam,
+                                     const double* u, const double* f, double* fc, double* partial,
+                                     double* norms_out, hipStream_t s);
 hipError_t launch_coarse_solve(const DeviceLevel& L, int nt, const double* lam, const double* cinv,
                                int n, const double* f, double* u, hipStream_t s);
 hipError_t launch_plane_norms(const DeviceLevel& L, int nt, const double* r, double* partial,
@@ -308,6 +314,11 @@ int fused_chunks(const cylpoisson_plan* p, int l, int nu);
 // level-1 iterate (first cycle after a full-multigrid start); when it applies.
 bool fused_down_pro_ok(const cylpoisson_plan* p);
 hipError_t fused_down_pro(cylpoisson_plan* p, hipStream_t s, int p0 = 0, int np = -1);
+// The merged finest pass: the up pass of one cycle (u2 + P C.u, nu2 sweeps)
+// and the down pass of the next (nu1 sweeps, residual, C.f = P^T r), writing
+// the iterate to u (the caller then swaps u and u2).
+bool fused_merge_ok(const cylpoisson_plan* p);
+hipError_t fused_merge(cylpoisson_plan* p, hipStream_t s);
 // FP32 passes on the dl32 buffers (mixed precision), no residual norms.
 hipError_t fused_down32(cylpoisson_plan* p, int l, bool zero_u, hipStream_t s, int p0 = 0,
                         int np = -1);

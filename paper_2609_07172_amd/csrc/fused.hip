@@ -57,6 +57,44 @@ hipError_t fused_down_pro(cylpoisson_plan* p, hipStream_t s, int p0, int np) {
     return hipGetLastError();
 }
 
+// The merged finest pass (k_pass_merge): FP64, two sweeps before and after
+// the finest coarse-grid correction (four in a row), one or two rows of
+// prefetch, at most 256 threads, fused passes on the finest level.
+bool fused_merge_ok(const cylpoisson_plan* p) {
+    if (!p->opt.merge || !fused_supported(p, 0) || nu_pre(p, 0) != 2 || nu_post(p, 0) != 2) return false;
+    const Shape sh = pass_shape<double>(p, 0, 4, true, true, true);
+    return sh.threads <= 256 && sh.lds <= 160 * 1024 && sh.nchunks <= kMaxPartial;
+}
+
+template <int PD>
+hipError_t launch_merge(const PassArgs<double>& a, int blocks, int threads, size_t lds, hipStream_t s) {
+    // more than the default 64 KiB of dynamic LDS: allowed on the current
+    // device at every launch (a host call of a few microseconds)
+    if (lds > 64 * 1024) {
+        const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_pass_merge<double, 4, PD>),
+                                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+    }
+    k_pass_merge<double, 4, PD><<<blocks, threads, lds, s>>>(a);
+    return hipGetLastError();
+}
+
+hipError_t fused_merge(cylpoisson_plan* p, hipStream_t s) {
+    DeviceLevel& L = p->dl[0];
+    DeviceLevel& C = p->dl[1];
+    const Shape sh = pass_shape<double>(p, 0, 4, true, true, true);
+    PassArgs<double> a = make_args<double>(p, 0, sh, 0, p->nt);
+    a.u_in = L.u2;  // the last down pass's iterate, plus the prolongated C.u
+    a.f = L.f;
+    a.u_out = L.u;
+    a.fc = C.f;
+    a.ec = C.u;
+    a.zero_interior = 0;
+    const int blocks = sh.nchunks * p->nt;
+    return p->opt.merge_prefetch == 2 ? launch_merge<2>(a, blocks, sh.threads, sh.lds, s)
+                                      : launch_merge<1>(a, blocks, sh.threads, sh.lds, s);
+}
+
 int fused_chunks(const cylpoisson_plan* p, int l, int nu) {
     return pass_shape<double>(p, l, nu, false).nchunks;
 }

@@ -565,6 +565,20 @@ __global__ void __launch_bounds__(512) k_pass_fine_pro(PassArgs<T> a) {
     pass.run();
 }
 
+// The finest level's up pass of one V-cycle and down pass of the next in one
+// stream of rows: the coarse correction is prolongated into the input as rows
+// are consumed, then nu2 + nu1 sweeps run back to back (the red-black order of
+// the two passes), then the residual and its restriction.  The node
+// arithmetic is that of the two passes, so the iterate and the coarse
+// right-hand side are bitwise theirs; the residual norm between the passes is
+// not formed.  It keeps more rows in flight than the separate passes and runs
+// one wave per SIMD (up to 256 threads per workgroup, no scratch).
+template <typename T, int NU, int PD>
+__global__ void __launch_bounds__(256) k_pass_merge(PassArgs<T> a) {
+    extern __shared__ double smem[];
+    Pass<T, NU, PD, true, false, true> pass(a, (char*)smem);
+    pass.run();
+}
 
 // ---- host side: launch dispatch, launch shape and arguments ----
 
@@ -626,15 +640,22 @@ struct Shape {
     size_t lds;
 };
 
+// Launch shape of a pass.  `merge`: the merged finest pass (nu = nu2 + nu1
+// sweeps, pro tables, prefetch pd_merge rows), one workgroup per compute unit.
 template <typename T>
-Shape pass_shape(const cylpoisson_plan* p, int l, int nu, bool down, bool pro = false) {
+Shape pass_shape(const cylpoisson_plan* p, int l, int nu, bool down, bool pro = false, bool merge = false) {
     const DeviceLevel& L = p->dl[l];
     Shape sh;
     sh.tn = L.v.nr / 2;  // column pairs covering columns 1 .. nr-1
     sh.threads = sh.tn;
     const int rows = L.v.nz - 2;
     int chunk = l == 0 ? p->opt.chunk_rows : p->opt.chunk_rows_coarse;
-    if (chunk <= 0 && l == 0) {
+    if (merge) {
+        // one wave per SIMD: about one workgroup per compute unit, long chunks
+        const int per_plane = std::max(1, 256 / std::max(1, p->nt));
+        chunk = p->opt.chunk_rows_merge > 0 ? p->opt.chunk_rows_merge
+                                            : std::max(64, (rows + per_plane - 1) / per_plane);
+    } else if (chunk <= 0 && l == 0) {
         // The finest level is bandwidth-bound: few long chunks (about two
         // workgroups per compute unit) keep the recomputed halo small.
         const int per_plane = std::max(1, 512 / std::max(1, p->nt));
@@ -651,7 +672,7 @@ Shape pass_shape(const cylpoisson_plan* p, int l, int nu, bool down, bool pro = 
     sh.chunk = chunk;
     sh.nchunks = (rows + chunk - 1) / chunk;
     sh.blocks = sh.nchunks * p->nt;
-    const int pd = pass_prefetch<T>(nu, p->opt.prefetch);
+    const int pd = merge ? p->opt.merge_prefetch : pass_prefetch<T>(nu, p->opt.prefetch);
     const int q0 = 2 * nu + 3 + pd;
     const size_t qs = (size_t)((q0 & 1) ? q0 + 1 : q0) + 1;
     const size_t trows = (size_t)(chunk + 4 * nu + 6);

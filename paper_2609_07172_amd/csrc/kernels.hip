@@ -296,69 +296,6 @@ __global__ void __launch_bounds__(256) k_restrict(LevelView vf, LevelView vc, Tr
         restrict3(col[0], col[1], col[2], tr.rwm[I], tr.rwp[I]);
 }
 
-// f_c = P^T b for the residual b of the iterate that is u's ring and zero
-// inside: the finest right-hand side with its Dirichlet terms, formed node by
-// node as k_rhs_norm_partial forms it (only u's ring is read).  Only plane 0
-// has a non-zero ring (theta-invariant face values), and with a zero ring the
-// formula gives b = f exactly.  So EDGE = false forms every coarse node of
-// every plane from f alone (face values dropped), and EDGE = true, launched
-// on plane 0 only, redoes the coarse nodes whose 3 x 3 fine stencil reaches a
-// node next to a face, with their Dirichlet terms.
-template <bool EDGE>
-__global__ void __launch_bounds__(256) k_restrict_rhs(LevelView vf, LevelView vc, Transfer1D tr,
-                                                      Transfer1D tz, const double* __restrict__ lam,
-                                                      const double* __restrict__ u,
-                                                      const double* __restrict__ f,
-                                                      double* __restrict__ fc) {
-    const int I = blockIdx.x * blockDim.x + threadIdx.x + 1;
-    const int K = blockIdx.y * blockDim.y + threadIdx.y + 1;
-    const int p = blockIdx.z;
-    if (I > vc.nr - 2 || K > vc.nz - 2) return;
-    const int fi = tr.cidx[I], fk = tz.cidx[K];
-    const int ie = vf.nr - 2, ke = vf.nz - 2;
-    const bool edge = fi <= 2 || fi >= ie - 1 || fk <= 2 || fk >= ke - 1;
-    if (EDGE && !edge) return;
-    const long long base = (long long)p * vf.pstride;
-    double b[3][3];
-#pragma unroll
-    for (int a = 0; a < 3; ++a)
-#pragma unroll
-        for (int d = 0; d < 3; ++d) b[a][d] = f[base + (long long)(fk - 1 + a) * vf.pitch + (fi - 1 + d)];
-    if (edge) {
-        // face values dropped
-#pragma unroll
-        for (int a = 0; a < 3; ++a)
-#pragma unroll
-            for (int d = 0; d < 3; ++d) {
-                const int i = fi - 1 + d, k = fk - 1 + a;
-                if (i < 1 || i > ie || k < 1 || k > ke) b[a][d] = 0.0;
-            }
-    }
-    if (EDGE) {
-        // the nodes next to a face add their Dirichlet terms
-#pragma unroll
-        for (int a = 0; a < 3; ++a)
-#pragma unroll
-            for (int d = 0; d < 3; ++d) {
-                const int i = fi - 1 + d, k = fk - 1 + a;
-                if (i >= 1 && i <= ie && k >= 1 && k <= ke && (i == 1 || i == ie || k == 1 || k == ke)) {
-                    const long long o = base + (long long)k * vf.pitch + i;
-                    const double uw = i == 1 ? u[o - 1] : 0.0;
-                    const double ue = i == ie ? u[o + 1] : 0.0;
-                    const double us = k == 1 ? u[o - vf.pitch] : 0.0;
-                    const double un = k == ke ? u[o + vf.pitch] : 0.0;
-                    b[a][d] = residual(0.0, b[a][d], uw, ue, us, un, coef_at(vf, i, k, lam[p]));
-                }
-            }
-    }
-    const double wzm = tz.rwm[K], wzp = tz.rwp[K];
-    double col[3];
-#pragma unroll
-    for (int d = 0; d < 3; ++d) col[d] = restrict3(b[0][d], b[1][d], b[2][d], wzm, wzp);
-    fc[(long long)p * vc.pstride + (long long)K * vc.pitch + I] =
-        restrict3(col[0], col[1], col[2], tr.rwm[I], tr.rwp[I]);
-}
-
 // ------------------------------------------------------------ prolongation
 // u_f += P e_c, or u_f = P e_c on the interior when !ADD (the coarse ring is zero).
 template <bool ADD>
@@ -466,6 +403,198 @@ __global__ void __launch_bounds__(256) k_rhs_norm_partial(LevelView v, const dou
             s = fma(r, r, s);
         }
     block_sum_store(s, partial + (long long)p * kMaxPartial + blockIdx.x);
+}
+
+// f_c = P^T b for the residual b of the iterate that is u's ring and zero
+// inside (the finest right-hand side with its Dirichlet terms), and the
+// per-plane sums of b^2 over the fine interior, in one pass over f.
+//
+// Only plane 0 has a non-zero ring (theta-invariant face values); with a zero
+// ring the point residual next to a face is f exactly, so b = f on every node
+// of every other plane and away from the faces on plane 0.  The main kernel
+// therefore reads f alone: a block takes up to 256 coarse columns I0 .. I1 and
+// the coarse rows [Ka, Kb), and marches down the fine rows that feed them.
+// Each fine row of the columns cidx[I0] - 1 .. cidx[I1] + 1 is loaded
+// coalesced, two rows ahead and without branches, into a double-buffered LDS
+// row, and thread t (coarse column I0 + t) keeps the last three rows of its
+// fine columns cidx[I] - 1 .. cidx[I] + 1 in registers.  Each coarse node is
+// the vertical three-point sum of each column, then the horizontal one (the
+// order of every other restriction).  For the norm every fine node is counted
+// once, by the thread that loads it, in the block that owns it: the fine
+// columns (cidx[I0 - 1], cidx[I1]] (the last block up to the face) and the
+// fine rows (cidx_z[Ka - 1], cidx_z[Kb - 1]] likewise; fixed-order block sums
+// go to partial[p][chunk * gridDim.y + y].  On plane 0 the nodes next to a
+// face are left out of the sums: k_face_rhs_norm adds them, and
+// k_restrict_rhs_edge redoes the coarse nodes whose stencil reaches them.
+constexpr int kRowSpan = 3 * 256;  // fine columns of one block's row, at most 2 * 256 + 1
+
+// Workgroup barrier that orders LDS accesses only: global loads issued before
+// it stay in flight (__syncthreads would wait for them).
+__device__ __forceinline__ void lds_only_barrier() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+__global__ void __launch_bounds__(256) k_restrict_rhs_norm(LevelView vf, LevelView vc, Transfer1D tr,
+                                                           Transfer1D tz, const double* __restrict__ f,
+                                                           double* __restrict__ fc,
+                                                           double* __restrict__ partial, int chunk_rows) {
+    __shared__ double row[2][kRowSpan];
+    const int p = blockIdx.z;
+    const int t = threadIdx.x;
+    const int I0 = 256 * blockIdx.y + 1;
+    const int I1 = min(vc.nr - 2, I0 + 255);
+    const int I = I0 + t;
+    const bool act = I <= I1;
+    const int ie = vf.nr - 2, ke = vf.nz - 2;
+    const int Ka = 1 + blockIdx.x * chunk_rows;
+    const int Kb = min(vc.nz - 1, Ka + chunk_rows);
+    const double* fp = f + (long long)p * vf.pstride;
+    // the block's fine columns and the ones whose nodes it counts
+    const int c_lo = tr.cidx[I0] - 1, c_hi = tr.cidx[I1] + 1;
+    const int own_c_lo = tr.cidx[I0 - 1] + 1;
+    const int own_c_hi = I1 == vc.nr - 2 ? ie : tr.cidx[I1];
+    const int ka = tz.cidx[Ka] - 1, kb = tz.cidx[Kb - 1] + 1;
+    const int own_r_lo = tz.cidx[Ka - 1] + 1;
+    const int own_r_hi = Kb - 1 == vc.nz - 2 ? ke : tz.cidx[Kb - 1];
+    const int fo = act ? tr.cidx[I] - 1 - c_lo : 0;  // this column's first fine column in the LDS row
+    const double wrm = act ? tr.rwm[I] : 0.0, wrp = act ? tr.rwp[I] : 0.0;
+    // this thread's loaded columns c_lo + t + 256 q: in range, interior, counted
+    bool in_c[3], own_c[3];
+    int cc[3];
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+        const int c = c_lo + t + 256 * q;
+        in_c[q] = c <= c_hi && c >= 1 && c <= ie;
+        own_c[q] = c <= c_hi && c >= own_c_lo && c <= own_c_hi && !(p == 0 && (c == 1 || c == ie));
+        cc[q] = min(max(c, 1), ie);
+    }
+    // every load is issued from a valid address (row and column clamped);
+    // face rows and columns are zeroed when the row is used
+    auto fetch = [&](int k, double* v) {
+        const long long o = (long long)min(max(k, 1), ke) * vf.pitch;
+#pragma unroll
+        for (int q = 0; q < 3; ++q) v[q] = fp[o + cc[q]];
+    };
+    double next[3], next2[3];
+    fetch(ka, next);
+    fetch(ka + 1, next2);
+    double w[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};  // rows k-2, k-1, k; this column's three fine columns
+    double s = 0.0;
+    int K = Ka;
+    for (int k = ka; k <= kb; ++k) {
+        double* buf = row[k & 1];
+        const bool in_r = k >= 1 && k <= ke;
+        const bool own_r = k >= own_r_lo && k <= own_r_hi && !(p == 0 && (k == 1 || k == ke));
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+            const double b = in_r && in_c[q] ? next[q] : 0.0;
+            if (q < 2 || t + 512 <= c_hi - c_lo) buf[t + 256 * q] = b;
+            if (own_r && own_c[q]) s = fma(b, b, s);
+            next[q] = next2[q];
+        }
+        fetch(k + 2, next2);
+        // the row is complete; the other buffer was last read before this barrier
+        lds_only_barrier();
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            w[0][d] = w[1][d];
+            w[1][d] = w[2][d];
+            w[2][d] = act ? buf[fo + d] : 0.0;
+        }
+        while (K < Kb && tz.cidx[K] + 1 == k) {
+            const double wzm = tz.rwm[K], wzp = tz.rwp[K];
+            double col[3];
+#pragma unroll
+            for (int d = 0; d < 3; ++d) col[d] = restrict3(w[0][d], w[1][d], w[2][d], wzm, wzp);
+            if (act) fc[(long long)p * vc.pstride + (long long)K * vc.pitch + I] = restrict3(col[0], col[1], col[2], wrm, wrp);
+            ++K;
+        }
+    }
+    block_sum_store(s, partial + (long long)p * kMaxPartial + blockIdx.x * gridDim.y + blockIdx.y);
+}
+
+// b at fine node (i, k) of plane 0 next to a face: the point residual of the
+// zero interior with u's ring neighbours.
+__device__ __forceinline__ double face_rhs(const LevelView& vf, const double* __restrict__ lam,
+                                           const double* __restrict__ u, const double* __restrict__ f,
+                                           int i, int k) {
+    const int ie = vf.nr - 2, ke = vf.nz - 2;
+    const long long o = (long long)k * vf.pitch + i;
+    const double uw = i == 1 ? u[o - 1] : 0.0;
+    const double ue = i == ie ? u[o + 1] : 0.0;
+    const double us = k == 1 ? u[o - vf.pitch] : 0.0;
+    const double un = k == ke ? u[o + vf.pitch] : 0.0;
+    return residual(0.0, f[o], uw, ue, us, un, coef_at(vf, i, k, lam[0]));
+}
+
+// Plane 0: the coarse nodes whose 3 x 3 fine stencil reaches a node next to a
+// face, redone with that node's Dirichlet terms (b as every other kernel forms
+// it), one thread per coarse node.
+__global__ void __launch_bounds__(256) k_restrict_rhs_edge(LevelView vf, LevelView vc, Transfer1D tr,
+                                                           Transfer1D tz, const double* __restrict__ lam,
+                                                           const double* __restrict__ u,
+                                                           const double* __restrict__ f,
+                                                           double* __restrict__ fc) {
+    const int I = blockIdx.x * blockDim.x + threadIdx.x + 1;
+    const int K = blockIdx.y * blockDim.y + threadIdx.y + 1;
+    if (I > vc.nr - 2 || K > vc.nz - 2) return;
+    const int fi = tr.cidx[I], fk = tz.cidx[K];
+    const int ie = vf.nr - 2, ke = vf.nz - 2;
+    if (!(fi <= 2 || fi >= ie - 1 || fk <= 2 || fk >= ke - 1)) return;
+    double b[3][3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            const int i = fi - 1 + d, k = fk - 1 + a;
+            if (i < 1 || i > ie || k < 1 || k > ke)
+                b[a][d] = 0.0;
+            else if (i == 1 || i == ie || k == 1 || k == ke)
+                b[a][d] = face_rhs(vf, lam, u, f, i, k);
+            else
+                b[a][d] = f[(long long)k * vf.pitch + i];
+        }
+    const double wzm = tz.rwm[K], wzp = tz.rwp[K];
+    double col[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) col[d] = restrict3(b[0][d], b[1][d], b[2][d], wzm, wzp);
+    fc[(long long)K * vc.pitch + I] = restrict3(col[0], col[1], col[2], tr.rwm[I], tr.rwp[I]);
+}
+
+// Plane 0: the sum of b^2 over the nodes next to a face (rows 1 and ke, then
+// columns 1 and ie of the rows between), added to the first partial sum of
+// plane 0 (one block, fixed order).
+__global__ void __launch_bounds__(256) k_face_rhs_norm(LevelView vf, const double* __restrict__ lam,
+                                                       const double* __restrict__ u,
+                                                       const double* __restrict__ f,
+                                                       double* __restrict__ partial) {
+    const int ie = vf.nr - 2, ke = vf.nz - 2;
+    const int nrow = ke > 1 ? 2 * ie : ie;           // rows 1 and ke (one row when ke == 1)
+    const int ncol = ke > 2 ? (ie > 1 ? 2 : 1) * (ke - 2) : 0;  // columns 1 and ie of rows 2 .. ke - 1
+    double s = 0.0;
+    for (int q = threadIdx.x; q < nrow + ncol; q += blockDim.x) {
+        int i, k;
+        if (q < nrow) {
+            i = 1 + q % ie;
+            k = q < ie ? 1 : ke;
+        } else {
+            const int r = q - nrow;
+            k = 2 + r % (ke - 2);
+            i = r < ke - 2 ? 1 : ie;
+        }
+        const double b = face_rhs(vf, lam, u, f, i, k);
+        s = fma(b, b, s);
+    }
+    __shared__ double red[256];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) partial[0] += red[0];
 }
 
 // FP64 refinement step of the mixed-precision solve, finest level, with the
@@ -716,13 +845,28 @@ hipError_t launch_prolong(const DeviceLevel& F, const DeviceLevel& C, int nt, co
     return hipGetLastError();
 }
 
-hipError_t launch_restrict_rhs(const DeviceLevel& F, const DeviceLevel& C, int nt, const double* lam,
-                               const double* u, const double* f, double* fc, hipStream_t s) {
-    k_restrict_rhs<false><<<grid_interior(C.v, nt), dim3(kTx, kTy), 0, s>>>(F.v, C.v, F.tr, F.tz, lam, u, f, fc);
+hipError_t launch_restrict_rhs_norms(const DeviceLevel& F, const DeviceLevel& C, int nt, const double* lam,
+                                     const double* u, const double* f, double* fc, double* partial,
+                                     double* norms_out, hipStream_t s) {
+    // blocks of 256 coarse columns times chunks of coarse rows: about 2048
+    // blocks in all, at most kMaxPartial per plane
+    const int rows = C.v.nz - 2;
+    const int ncg = (C.v.nr - 2 + 255) / 256;
+    if (rows < 1 || ncg > kMaxPartial) return hipErrorInvalidValue;
+    int nch = std::max(1, std::min(std::min(kMaxPartial / ncg, rows), (2048 + nt * ncg - 1) / (nt * ncg)));
+    const int chunk = (rows + nch - 1) / nch;
+    nch = (rows + chunk - 1) / chunk;
+    k_restrict_rhs_norm<<<dim3(nch, ncg, nt), 256, 0, s>>>(F.v, C.v, F.tr, F.tz, f, fc, partial, chunk);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    dim3 g0 = grid_interior(C.v, 1);  // plane 0 only: the others have a zero ring
-    k_restrict_rhs<true><<<g0, dim3(kTx, kTy), 0, s>>>(F.v, C.v, F.tr, F.tz, lam, u, f, fc);
+    // plane 0's nodes next to a face, with their Dirichlet terms
+    k_restrict_rhs_edge<<<grid_interior(C.v, 1), dim3(kTx, kTy), 0, s>>>(F.v, C.v, F.tr, F.tz, lam, u, f, fc);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    k_face_rhs_norm<<<1, 256, 0, s>>>(F.v, lam, u, f, partial);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    k_norm_final<<<(nt + 63) / 64, 64, 0, s>>>(partial, nch * ncg, nt, norms_out);
     return hipGetLastError();
 }
 

@@ -874,6 +874,9 @@ int cylpoisson_plan_set_option(cylpoisson_plan* plan, const char* key, double va
     }
     // captured graphs hold launch parameters that options change
     cp::drop_graphs(plan);
+    // the next solve's first check no longer follows the last solve's cycle
+    // count (timing changes no arithmetic)
+    if (std::strcmp(key, "timing")) plan->last_cycles = 0;
     auto int_in = [&](int lo, int hi, int* dst) {
         if (!(value >= lo && value <= hi) || value != std::floor(value)) {
             set_error("option %s must be an integer in [%d, %d]", key, lo, hi);
@@ -897,6 +900,9 @@ int cylpoisson_plan_set_option(cylpoisson_plan* plan, const char* key, double va
     if (!std::strcmp(key, "nu1_coarse")) return int_in(0, 8, &plan->opt.nu1_coarse);
     if (!std::strcmp(key, "nu2_coarse")) return int_in(0, 8, &plan->opt.nu2_coarse);
     if (!std::strcmp(key, "fmg")) return int_in(0, 1, &plan->opt.fmg);
+    if (!std::strcmp(key, "merge")) return int_in(0, 1, &plan->opt.merge);
+    if (!std::strcmp(key, "merge_prefetch")) return int_in(1, 2, &plan->opt.merge_prefetch);
+    if (!std::strcmp(key, "chunk_rows_merge")) return int_in(0, 1 << 20, &plan->opt.chunk_rows_merge);
     if (!std::strcmp(key, "fft")) return int_in(0, 1, &plan->opt.fft);
     if (!std::strcmp(key, "inner_cycles")) return int_in(1, 8, &plan->opt.inner_cycles);
     if (!std::strcmp(key, "groups")) return int_in(1, 8, &plan->opt.groups);
@@ -952,7 +958,9 @@ int cylpoisson_plan_get_option(const cylpoisson_plan* plan, const char* key, dou
                  {"groups", (double)o.groups}, {"warm_start", (double)o.warm_start},
                  {"masks", (double)o.masks}, {"graph", (double)o.graph}, {"krylov", (double)o.krylov},
                  {"krylov_precond", (double)o.krylov_precond}, {"krylov_restart", (double)o.krylov_restart},
-                 {"krylov_max", (double)o.krylov_max}, {"fallback", (double)o.fallback}};
+                 {"krylov_max", (double)o.krylov_max}, {"fallback", (double)o.fallback},
+                 {"merge", (double)o.merge}, {"merge_prefetch", (double)o.merge_prefetch},
+                 {"chunk_rows_merge", (double)o.chunk_rows_merge}};
     for (const auto& t : table)
         if (!std::strcmp(key, t.name)) {
             *value = t.v;

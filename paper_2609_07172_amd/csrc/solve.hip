@@ -124,7 +124,7 @@ class Timed {
     int idx_ = -1;
 };
 
-enum { kDftFwd = 0, kDftInv = 1, kFineDown = 2, kFineUp = 3, kCoarse = 4, kOther = 5 };
+enum { kDftFwd = 0, kDftInv = 1, kFineDown = 2, kFineUp = 3, kCoarse = 4, kOther = 5, kFineMerged = 6 };
 
 // After the stream has drained: fold the recorded event pairs into the stats.
 void collect_timing(cylpoisson_plan* p) {
@@ -170,6 +170,71 @@ hipError_t smooth(cylpoisson_plan* p, DeviceLevel& L, int sweeps, hipStream_t s)
 struct NormSlot {
     int partial_chunks = -1;  // -1: not produced by the cycle
 };
+// partial_chunks of a cycle that ended in a merged finest pass: its norms are not formed
+constexpr int kNoNorms = -2;
+
+hipError_t vcycle(cylpoisson_plan* p, int l, hipStream_t s, bool zero_top, int slot, NormSlot* ns,
+                  int p0 = 0, int np = -1, bool pro = false);
+
+// The finest level's parts of a V-cycle on the fused passes (planes p0 ..
+// p0 + np - 1).  Down: the down pass (from a zero interior on the first
+// cycle, or forming the full-multigrid start when `pro`) and the whole V-cycle
+// below it.
+hipError_t cycle_down(cylpoisson_plan* p, hipStream_t s, bool zero_top, bool pro, int p0 = 0, int np = -1) {
+    hipError_t e;
+    {
+        Timed tm(p, kFineDown, s);
+        e = pro ? fused_down_pro(p, s, p0, np) : fused_down(p, 0, false, zero_top, s, p0, np);
+    }
+    if (e == hipSuccess) {
+        Timed tm(p, kCoarse, s);
+        e = vcycle(p, 1, s, true, -1, nullptr, p0, np);
+    }
+    return e;
+}
+
+// Up: the up pass, with the squared residual norms of cycle `slot` when
+// slot >= 0 (recorded in *ns).
+hipError_t cycle_up(cylpoisson_plan* p, hipStream_t s, int slot, NormSlot* ns, int p0 = 0, int np = -1) {
+    const bool want = slot >= 0;
+    const int nch = fused_chunks(p, 0, nu_post(p, 0));
+    const bool host_sum = want && nch <= kSlotPartial;
+    hipError_t e;
+    {
+        Timed tm(p, kFineUp, s);
+        double* part = host_sum ? p->d_slot_partial + (size_t)slot * p->nt * kSlotPartial
+                                : (want ? p->d_partial : nullptr);
+        e = fused_up(p, 0, part, host_sum ? kSlotPartial : kMaxPartial, nullptr, s, p0, np);
+    }
+    if (e == hipSuccess && want) {
+        if (host_sum) {
+            ns->partial_chunks = nch;
+        } else {
+            Timed tm(p, kOther, s);
+            e = launch_norm_final(p->d_partial, nch, p->nt, p->d_norms + (size_t)slot * p->nt, s);
+            if (e == hipSuccess) ns->partial_chunks = 0;
+        }
+    }
+    return e;
+}
+
+// Merged: the up pass of this cycle and the down pass of the next in one
+// pass (no norms), then the whole V-cycle below the finest level of the next
+// cycle.  The pass writes the iterate to u; swapping u and u2 keeps "the down
+// pass's iterate is in u2, the up pass's in u".
+hipError_t cycle_merge(cylpoisson_plan* p, hipStream_t s) {
+    hipError_t e;
+    {
+        Timed tm(p, kFineMerged, s);
+        e = fused_merge(p, s);
+    }
+    std::swap(p->dl[0].u, p->dl[0].u2);
+    if (e == hipSuccess) {
+        Timed tm(p, kCoarse, s);
+        e = vcycle(p, 1, s, true, -1, nullptr);
+    }
+    return e;
+}
 
 // One V-cycle from level l.  On levels l > 0 the iterate starts at zero; on
 // level 0 `zero_top` says its interior is still to be treated as zero (first
@@ -178,7 +243,7 @@ struct NormSlot {
 // Planes p0 .. p0 + np - 1 (all when np < 0); a partial range needs the fused
 // passes down to the bottom kernel (groups_active).
 hipError_t vcycle(cylpoisson_plan* p, int l, hipStream_t s, bool zero_top, int slot, NormSlot* ns,
-                  int p0 = 0, int np = -1, bool pro = false) {
+                  int p0, int np, bool pro) {
     const int nl = (int)p->dl.size();
     DeviceLevel& L = p->dl[l];
     hipError_t e = hipSuccess;
@@ -190,36 +255,16 @@ hipError_t vcycle(cylpoisson_plan* p, int l, hipStream_t s, bool zero_top, int s
     }
     if (l > 0 && l == p->bottom_level && bottom_active(p)) return launch_bottom(p, s, p0, np);
     DeviceLevel& C = p->dl[l + 1];
+    if (l == 0 && fused_supported(p, 0)) {
+        hipError_t e = cycle_down(p, s, zero_top, pro, p0, np);
+        if (e == hipSuccess) e = cycle_up(p, s, slot, ns, p0, np);
+        return e;
+    }
     if (fused_supported(p, l)) {
-        {
-            Timed tm(p, l == 0 ? kFineDown : -1, s);
-            // coarser levels start from a zero iterate with a zero ring; `pro`:
-            // the finest interior is the prolongated full-multigrid answer
-            e = l == 0 && pro ? fused_down_pro(p, s, p0, np)
-                              : fused_down(p, l, l > 0, l == 0 && zero_top, s, p0, np);
-        }
-        if (e == hipSuccess) {
-            Timed tm(p, l == 0 ? kCoarse : -1, s);
-            e = vcycle(p, l + 1, s, true, -1, nullptr, p0, np);
-        }
-        const bool want = l == 0 && slot >= 0;
-        const int nch = fused_chunks(p, l, nu_post(p, l));
-        const bool host_sum = want && nch <= kSlotPartial;
-        if (e == hipSuccess) {
-            Timed tm(p, l == 0 ? kFineUp : -1, s);
-            double* part = host_sum ? p->d_slot_partial + (size_t)slot * p->nt * kSlotPartial
-                                    : (want ? p->d_partial : nullptr);
-            e = fused_up(p, l, part, host_sum ? kSlotPartial : kMaxPartial, nullptr, s, p0, np);
-        }
-        if (e == hipSuccess && want) {
-            if (host_sum) {
-                ns->partial_chunks = nch;
-            } else {
-                Timed tm(p, kOther, s);
-                e = launch_norm_final(p->d_partial, nch, p->nt, p->d_norms + (size_t)slot * p->nt, s);
-                if (e == hipSuccess) ns->partial_chunks = 0;
-            }
-        }
+        // coarser levels start from a zero iterate with a zero ring
+        e = fused_down(p, l, true, false, s, p0, np);
+        if (e == hipSuccess) e = vcycle(p, l + 1, s, true, -1, nullptr, p0, np);
+        if (e == hipSuccess) e = fused_up(p, l, nullptr, kMaxPartial, nullptr, s, p0, np);
         return e;
     }
     if (l > 0) e = launch_zero_interior(L, p->nt, L.u, s);
@@ -502,15 +547,37 @@ int run_cycles(cylpoisson_plan* p, double tol, hipStream_t s, bool ring_only, bo
         CP_HIP(ensure_groups(p, G));
         CP_HIP(fork_groups(p, G, s));
     }
+    // The first check comes after cycle 2, or (without masks, which freeze
+    // planes only at checks) at the cycle count with which the plan's last
+    // solve to the same tol converged: a solve of a similar problem then needs
+    // one host round trip, and the cycles before it can end in merged passes.
     int next_check = std::min(2, maxc);
+    if (!masks && p->last_cycles > 0 && p->last_tol == tol) next_check = std::min(p->last_cycles, maxc);
+    p->last_cycles = 0;
     int last_read = 0;
-    double prev_rel = defer ? 1.0 : std::sqrt(r02 / b2);
+    // relative residual at the last check (the starting iterate's at first)
+    double rel_last = defer ? 1.0 : std::sqrt(r02 / b2);
     int status = CYLPOISSON_NOT_CONVERGED;
     int stagnant = 0;
     std::vector<double> plane(nt), last(nt);
+    // A cycle after which the host does not check ends in the merged finest
+    // pass, which also runs the next cycle's finest down pass (and everything
+    // below it): `pending` then says the next cycle only needs its up pass.
+    const bool merging = !graphs && G == 1 && fused_supported(p, 0) && fused_merge_ok(p);
+    bool pending = false;
     for (int c = 1; c <= maxc; ++c) {
         if (graphs) {
             CP_HIP(graph_cycle(p, s, c, c == 1 && ring_only, &slots[c]));
+        } else if (merging) {
+            if (!pending) CP_HIP(cycle_down(p, s, c == 1 && ring_only, c == 1 && fmg_pro));
+            if (c == next_check || c == maxc) {
+                CP_HIP(cycle_up(p, s, c, &slots[c]));
+                pending = false;
+            } else {
+                CP_HIP(cycle_merge(p, s));
+                slots[c].partial_chunks = kNoNorms;
+                pending = true;
+            }
         } else {
             for (int g = 0; g < G; ++g) {
                 int p0, np;
@@ -519,7 +586,7 @@ int run_cycles(cylpoisson_plan* p, double tol, hipStream_t s, bool ring_only, bo
                               c == 1 && fmg_pro));
             }
         }
-        if (slots[c].partial_chunks < 0) {
+        if (slots[c].partial_chunks == -1) {
             CP_HIP(residual_norms(p, c, s));
             slots[c].partial_chunks = 0;
         }
@@ -533,7 +600,8 @@ int run_cycles(cylpoisson_plan* p, double tol, hipStream_t s, bool ring_only, bo
         // the deferred right-hand side norms in slot 0 with them
         {
             bool any_partial = false, any_norms = rhs_now;
-            for (int t = first; t <= c; ++t) (slots[t].partial_chunks > 0 ? any_partial : any_norms) = true;
+            for (int t = first; t <= c; ++t)
+                if (slots[t].partial_chunks != kNoNorms) (slots[t].partial_chunks > 0 ? any_partial : any_norms) = true;
             const size_t nslots = (size_t)(c - first + 1);
             const int nfirst = rhs_now ? 0 : first;
             if (any_partial)
@@ -564,6 +632,7 @@ int run_cycles(cylpoisson_plan* p, double tol, hipStream_t s, bool ring_only, bo
             }
         }
         for (int t = first; t <= c; ++t) {
+            if (slots[t].partial_chunks == kNoNorms) continue;  // history stays NaN
             const double* norms = p->h_norms + (size_t)t * nt;
             if (slots[t].partial_chunks > 0) {
                 // per-plane sums of the chunk partials, in chunk order
@@ -601,9 +670,12 @@ int run_cycles(cylpoisson_plan* p, double tol, hipStream_t s, bool ring_only, bo
             status = CYLPOISSON_OK;
             break;
         }
-        // predict the cycle count from the last contraction factor
-        const double prev = c >= 2 ? st.rel_residual_history[c - 2] : prev_rel;
-        const double rate = std::isfinite(prev) && prev > 0.0 ? rel / prev : 1.0;
+        // predict the cycle count from the mean contraction factor per cycle
+        // since the last check (the same rule whether or not the cycles between
+        // formed their norms, so merged and separate passes check alike)
+        const int tp = first - 1;
+        const double rate = std::isfinite(rel_last) && rel_last > 0.0 ? std::pow(rel / rel_last, 1.0 / (c - tp)) : 1.0;
+        rel_last = rel;
         stagnant = rate > 0.6 ? stagnant + 1 : 0;
         if (stagnant >= 3) {
             set_error("residual stagnated at %.3e (tolerance %.3e)", rel, tol);
@@ -617,7 +689,6 @@ int run_cycles(cylpoisson_plan* p, double tol, hipStream_t s, bool ring_only, bo
             step = 1;
         }
         next_check = std::min(maxc, c + step);
-        prev_rel = rel;
         if (masks) {
             CP_HIP(update_masks(p, last.data(), budget, frozen, s));
             if (G > 1) CP_HIP(fork_groups(p, G, s));
@@ -627,6 +698,10 @@ int run_cycles(cylpoisson_plan* p, double tol, hipStream_t s, bool ring_only, bo
     if (status == CYLPOISSON_NOT_CONVERGED && st.cycles >= maxc)
         set_error("tolerance %.3e not reached in %d cycles (relative residual %.3e)", tol, maxc,
                   st.rel_residual);
+    if (status == CYLPOISSON_OK && st.cycles > 0) {
+        p->last_cycles = st.cycles;
+        p->last_tol = tol;
+    }
     return status;
 }
 
@@ -921,7 +996,8 @@ bool fmg_active(const cylpoisson_plan* p) {
 }
 
 // The finest right-hand side (with the Dirichlet terms of u's ring)
-// restricted to every level and one V-cycle of the bottom kernel from zero;
+// restricted to every level (the first restriction also leaves the right-hand
+// side's per-plane norms in slot 0) and one V-cycle of the bottom kernel from zero;
 // that answer is interpolated up to level 1, which takes one V-cycle from it,
 // and the finest interior becomes the interpolated level-1 answer (u's
 // Dirichlet ring, already set, is kept).  A V-cycle on every level between
@@ -930,7 +1006,8 @@ bool fmg_active(const cylpoisson_plan* p) {
 hipError_t fmg_start(cylpoisson_plan* p, hipStream_t s, bool fused_top) {
     const int nt = p->nt, lb = p->bottom_level;
     DeviceLevel& L0 = p->dl[0];
-    hipError_t e = launch_restrict_rhs(L0, p->dl[1], nt, p->d_lam, L0.u, L0.f, p->dl[1].f, s);
+    hipError_t e = launch_restrict_rhs_norms(L0, p->dl[1], nt, p->d_lam, L0.u, L0.f, p->dl[1].f,
+                                             p->d_partial, p->d_norms, s);
     for (int l = 1; l < lb && e == hipSuccess; ++l)
         e = launch_restrict(p->dl[l], p->dl[l + 1], nt, p->dl[l].f, p->dl[l + 1].f, s);
     if (e == hipSuccess) e = launch_bottom(p, s);
@@ -1004,23 +1081,11 @@ int solve_impl(cylpoisson_plan* p, const double* rho, double* phi, double tol, v
     const bool ring_only = !warm && !learned && !fmg && (mixed || fused_supported(p, 0));
     {
         Timed tm(p, kOther, s);
-        if (fmg && p->static_call) {
-            // no second stream: the norms go first on the caller's
+        if (fmg) {
+            // the start's restriction of the finest right-hand side also forms
+            // that right-hand side's norms (slot 0), in the same pass over f
             CP_HIP(launch_init_ring(L, p->nt, p->bc, s));
-            CP_HIP(launch_rhs_norms(L, p->nt, p->d_lam, L.u, L.f, p->d_partial, p->d_norms, s));
             CP_HIP(fmg_start(p, s, fmg_pro));
-        } else if (fmg) {
-            CP_HIP(launch_init_ring(L, p->nt, p->bc, s));
-            // the right-hand side norms read f and u's ring only, which the
-            // start does not write: they run beside its latency-bound coarse
-            // levels on a second stream, joined before the first cycle
-            CP_HIP(ensure_groups(p, 2));
-            CP_HIP(hipEventRecord(p->gevents[0], s));
-            CP_HIP(hipStreamWaitEvent(p->gstreams[0], p->gevents[0], 0));
-            CP_HIP(launch_rhs_norms(L, p->nt, p->d_lam, L.u, L.f, p->d_partial, p->d_norms, p->gstreams[0]));
-            CP_HIP(hipEventRecord(p->gevents[1], p->gstreams[0]));
-            CP_HIP(fmg_start(p, s, fmg_pro));
-            CP_HIP(hipStreamWaitEvent(s, p->gevents[1], 0));
         } else if (warm) {
             // the planes of the given phi, with the Dirichlet rings rewritten
             CP_HIP(transform(p, false, phi, L.u, nullptr, s));
@@ -1032,10 +1097,11 @@ int solve_impl(cylpoisson_plan* p, const double* rho, double* phi, double tol, v
             CP_HIP(launch_copy_ring(L, p->nt, L.u, L.u2, s));
         }
     }
-    double* result = L.u;
+    double* result = nullptr;
     const int status = learned ? run_learned(p, tol, s)
                        : mixed ? run_mixed(p, tol, s, &result, warm)
                                : run_cycles(p, tol, s, ring_only, warm, fmg, fmg_pro);
+    if (!mixed) result = L.u;  // merged finest passes swap u and u2
     if ((status == CYLPOISSON_OK || status == CYLPOISSON_NOT_CONVERGED) && p->stats.cycles == 0 &&
         (ring_only || fmg)) {
         // no cycle ran (a right-hand side that is zero, or tol >= 1): the answer
@@ -1147,7 +1213,6 @@ int cylpoisson_solve_static(cylpoisson_plan* p, const double* rho, double* phi, 
     p->opt.timing = 0;
     p->opt.groups = 1;
     p->opt.graph = 0;
-    p->static_call = true;
     // the scratch keeps the last call's contents: start from the state of a
     // new plan's workspace (all zero), with a fill kernel on the stream
     hipError_t e = launch_zero(base, (long long)(need / sizeof(double)), static_cast<hipStream_t>(stream));
@@ -1164,7 +1229,6 @@ int cylpoisson_solve_static(cylpoisson_plan* p, const double* rho, double* phi, 
     p->d_norms = norms;
     p->d_slot_partial = slot_partial;
     p->opt = opt;
-    p->static_call = false;
     return status;
 }
 

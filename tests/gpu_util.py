@@ -39,3 +39,9 @@ def eps2(a, b, r, where=INTERIOR) -> float:
     a, b = np.asarray(a)[where], np.asarray(b)[where]
     w = np.broadcast_to(np.asarray(r)[where[2]], a.shape)
     return float(np.sqrt(np.sum(w * (a - b) ** 2) / np.sum(w * b * b)))
+
+
+def histories_agree(ha, hb) -> bool:
+    """Residual histories of two solves agree at every cycle both evaluated
+    (a cycle that ends in a merged finest pass has no norm: None) and in length."""
+    return len(ha) == len(hb) and all(a == b for a, b in zip(ha, hb) if a is not None and b is not None)

@@ -13,7 +13,7 @@ import torch
 import workloads as W
 from oracle import fv, solvers
 
-from gpu_util import dev, host, rel_l2, say
+from gpu_util import dev, histories_agree, host, rel_l2, say
 
 pytestmark = pytest.mark.gpu
 
@@ -73,7 +73,7 @@ def test_fmg_is_bitwise_under_groups_and_graphs(P, options):
     for _ in range(3):  # graph replays after the first capture
         b, sb = plan.solve(rho, tol=1e-14)
         np.testing.assert_array_equal(host(b), a)
-        assert sb["history"] == sa["history"]
+        assert histories_agree(sb["history"], sa["history"])
 
 
 def test_fmg_zero_problem_needs_no_cycle(P):

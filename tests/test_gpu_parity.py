@@ -16,7 +16,7 @@ import torch
 import workloads as W
 from oracle import fv, solvers, spectral
 
-from gpu_util import INTERIOR, dev, host, rel_l2, say
+from gpu_util import INTERIOR, dev, histories_agree, host, rel_l2, say
 
 pytestmark = pytest.mark.gpu
 
@@ -343,7 +343,9 @@ def test_fused_passes_match_per_step_kernels(P, shape):
     np.testing.assert_array_equal(ha, hb)
     # the residual norms are summed in another order (per chunk against per
     # workgroup of the norm kernel): they agree to rounding of the sums
-    np.testing.assert_allclose(sa["history"][:6], sb["history"][:6], rtol=1e-12, atol=1e-15)
+    both = [(x, y) for x, y in zip(sa["history"][:6], sb["history"][:6]) if x is not None and y is not None]
+    assert both
+    np.testing.assert_allclose([x for x, _ in both], [y for _, y in both], rtol=1e-12, atol=1e-15)
 
 
 @pytest.mark.parametrize("chunk", [1, 5, 16, 1000])
@@ -419,7 +421,7 @@ def test_plane_groups_are_bitwise_identical(P, groups, precision):
     a = host(a).copy()
     b, sb = grouped.solve(rho, tol=1e-14)
     np.testing.assert_array_equal(a, host(b))
-    assert sa["cycles"] == sb["cycles"] and sa["history"] == sb["history"]
+    assert sa["cycles"] == sb["cycles"] and histories_agree(sa["history"], sb["history"])
 
 
 # ------------------------------------------------ anisotropic cells
@@ -451,3 +453,50 @@ def test_coarse_sweep_counts_reach_the_oracle(P, nus, fused):
     phi, st = plan.solve(dev(rho), tol=1e-14)
     assert st["status"] == P.OK, st
     assert rel_l2(host(phi), ref) <= 1e-12, rel_l2(host(phi), ref)
+
+
+# ------------------------------------------- merged finest pass (option merge)
+@pytest.mark.parametrize("shape,options", [((400, 16, 512), {}), ((129, 8, 129), {}), ((201, 5, 97), {}),
+                                           ((257, 8, 257), {"fmg": 1}), ((129, 8, 129), {"merge_prefetch": 2})],
+                         ids=["400x16x512", "129x8x129", "201x5x97", "fmg-257", "prefetch2"])
+def test_merged_finest_passes_equal_the_separate_passes(P, shape, options):
+    """A cycle without a check ends in one finest pass doing its up pass and the
+    next cycle's down pass, with the node arithmetic of the two: iterates and
+    answers are bitwise those of separate passes.  A fixed check schedule
+    (tol 1e-30: checks after cycles 2 and 7) merges the boundaries after
+    cycles 1, 3, 4, 5 and 6."""
+    nr, nt, nz = shape
+    p = W.SMALL.with_sizes(nr, nt, nz)
+    rho = dev(W.blob_charge(p, seed=nr + nt))
+    say("merged passes", shape, options)
+    a = P.Plan.for_problem(p, merge=1, max_cycles=7, timing=1, **options)
+    b = P.Plan.for_problem(p, merge=0, max_cycles=7, **options)
+    pa, sa = a.solve(rho, tol=1e-30, allow=(P.OK, P.NOT_CONVERGED))
+    pa = host(pa).copy()
+    pb, sb = b.solve(rho, tol=1e-30, allow=(P.OK, P.NOT_CONVERGED))
+    np.testing.assert_array_equal(pa, host(pb))
+    assert sa["cycles"] == sb["cycles"] == 7
+    assert sa["kernel_launches"]["fine_merged"] == 5, sa["kernel_launches"]
+    assert [h is None for h in sa["history"]] == [True, False, True, True, True, True, False]
+    assert histories_agree(sa["history"], sb["history"])
+
+
+def test_first_check_follows_the_last_converged_solve(P):
+    """A repeated solve to the same tol checks first at the cycle count the last
+    one needed: fewer host round trips, the same answer."""
+    p = W.BATCHED
+    rho = dev(W.blob_charge(p, seed=5))
+    plan = P.Plan.for_problem(p, fmg=1)
+    say("first check from history")
+    a, sa = plan.solve(rho, tol=1e-13)
+    a = host(a).copy()
+    b, sb = plan.solve(rho, tol=1e-13)
+    assert sa["status"] == sb["status"] == P.OK
+    assert sb["cycles"] == sa["cycles"] and sb["checks"] < sa["checks"], (sa, sb)
+    np.testing.assert_array_equal(a, host(b))
+    # another tolerance, or a changed option, starts from the default schedule again
+    _, sc = plan.solve(rho, tol=1e-12)
+    assert sc["status"] == P.OK
+    plan.set_option("nu1", 2)
+    _, sd = plan.solve(rho, tol=1e-13)
+    assert sd["checks"] == sa["checks"]

@@ -13,7 +13,7 @@ import torch
 import workloads as W
 from oracle import fv, solvers
 
-from gpu_util import dev, host, rel_l2, say
+from gpu_util import dev, histories_agree, host, rel_l2, say
 
 pytestmark = pytest.mark.gpu
 
@@ -39,7 +39,7 @@ def test_static_scratch_solve_equals_the_plan_solve(P, fmg):
         b, sb = plan.solve_static(r, tol=1e-13)
         b = host(b)
         assert sa["status"] == P.OK and sb["status"] == P.OK, (sa, sb)
-        assert sa["cycles"] == sb["cycles"] and sa["history"] == sb["history"]
+        assert sa["cycles"] == sb["cycles"] and histories_agree(sa["history"], sb["history"])
         np.testing.assert_array_equal(a, b)
         assert rel_l2(b, ref) <= 1e-12
         # the plan's own solve still works after the static one
