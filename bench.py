@@ -523,6 +523,40 @@ def time_learned(problem, rho_d, args, ref, phit):
         rates[label] = s2["learned_rate"]
         pl.close()
     out["fgmres_rate_per_step"] = rates
+    # the network inside the multigrid preconditioner: FGMRES with one V-cycle
+    # (krylov_precond 3) against one V-cycle followed by the network's
+    # correction of the residual it leaves (krylov_precond 4), per step and to tol
+    inner = {}
+    for label, precond, n in (("vcycle", 3, None), ("vcycle_plus_network", 4, net),
+                              ("vcycle_plus_nothing", 4, None)):
+        pl = P.Plan.for_problem(problem, krylov=1, krylov_precond=precond, fallback=0, krylov_max=8)
+        if n is not None:
+            P.plan_set_net(pl, n)
+        _, s2 = pl.solve(rho_d, tol=1e-30, phi=phi_d, allow=(P.OK, P.NOT_CONVERGED))
+        rec = {"rate_per_step": s2["learned_rate"]}
+        pl.close()
+        if label != "vcycle_plus_nothing":
+            pl = P.Plan.for_problem(problem, krylov=1, krylov_precond=precond)
+            if n is not None:
+                P.plan_set_net(pl, n)
+            pl.solve(rho_d, tol=args.tol, phi=phi_d)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                _, s3 = pl.solve(rho_d, tol=args.tol, phi=phi_d)
+            torch.cuda.synchronize()
+            rec.update({"ms": round((time.perf_counter() - t0) / reps * 1e3, 4), "status": s3["status"],
+                        "krylov_iterations": s3["krylov_iterations"], "fell_back": s3["learned_fallback"],
+                        "rel_residual": s3["rel_residual"]})
+            if ref is not None:
+                rec["rel_l2_vs_oracle"] = interior_rel(phi_d.cpu().numpy(), ref)
+            pl.close()
+        inner[label] = rec
+    out["network_inside_vcycle"] = inner
+    log(f"learned V-cycle: FGMRES per step {inner['vcycle']['rate_per_step']:.4f} (V-cycle), "
+        f"{inner['vcycle_plus_network']['rate_per_step']:.4f} (V-cycle + network), "
+        f"{inner['vcycle_plus_nothing']['rate_per_step']:.4f} (V-cycle, judged path without network); "
+        f"{inner['vcycle_plus_network']['ms']:.2f} ms against {inner['vcycle']['ms']:.2f} ms")
     # the network's forward pass over every mode pair of this grid
     npairs, H, Wd = problem.ntheta // 2 + 1, problem.nz - 2, problem.nr - 2
     x = torch.randn((npairs, H, Wd, 4), dtype=torch.float32, device=rho_d.device)

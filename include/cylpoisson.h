@@ -222,10 +222,19 @@ void cylpoisson_plan_destroy(cylpoisson_plan* plan);
  *                    (strongly stretched meshes), at one V-cycle plus the Arnoldi
  *                    work per step (counted in `cycles`); not judged (no judging
  *                    cycle, no fallback, vcycle_rate 0) since the plain V-cycle
- *                    iterates lie in the space FGMRES minimises over (default 1)
+ *                    iterates lie in the space FGMRES minimises over; 4 = one
+ *                    V-cycle from zero followed by the attached network's
+ *                    correction of the residual it leaves (z = V(v); z += N(v - A z)):
+ *                    the network inside the multigrid preconditioner, judged like 1
+ *                    against the plain V-cycle (default 1)
  *   "krylov_restart" FGMRES restart length, also the judged steps (1 .. 16; default 8)
  *   "krylov_max"     FGMRES steps in all (default 200)
  *   "fallback"       1 = V-cycles take over from a worse network (default 1)
+ *   "nn_target"      training pairs cylpoisson_nn_collect stores: 0 = each V-cycle
+ *                    iterate's residual and the correction four red-black SOR
+ *                    sweeps make from it; 1 = the residual after each V-cycle and
+ *                    the iterate's error u* - u (u* the solve to tol 1e-14 first)
+ *                    (default 0)
  *   "fmg"            1 = full-multigrid start: the right-hand side is restricted
  *                    to every level, the LDS bottom kernel solves the coarsest
  *                    ones from zero, its answer is interpolated up to level 1,

@@ -130,6 +130,7 @@ struct Options {
     int merge = 1;         // 1: merged finest pass between cycles without a convergence check
     int merge_prefetch = 1;  // rows the merged finest pass loads ahead (1 or 2)
     int chunk_rows_merge = 0;  // axial rows per workgroup of the merged pass (0 = automatic)
+    int nn_target = 0;     // training targets: 0 = SOR correction of the residual, 1 = V-cycle iterate error
 };
 
 }  // namespace cp

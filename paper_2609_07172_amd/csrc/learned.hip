@@ -213,8 +213,9 @@ int net_pairs(int nt) { return nt / 2 + 1; }
 hipError_t krylov_reserve(cylpoisson_plan* p, int m) {
     const size_t bytes = (size_t)p->nt * p->dl[0].v.pstride * sizeof(double);
     // m + 1 Arnoldi vectors, m preconditioned ones, one ping-pong buffer for
-    // the V-cycle preconditioner
-    while ((int)p->kv.size() < 2 * m + 2) {
+    // the V-cycle preconditioner, and two for the learned correction after it
+    // (the V-cycle's residual and the network's correction)
+    while ((int)p->kv.size() < 2 * m + 4) {
         double* ptr = nullptr;
         hipError_t e = hipMalloc(&ptr, bytes);
         if (e != hipSuccess) return e;
@@ -279,11 +280,37 @@ hipError_t plane_lincomb(cylpoisson_plan* p, double* dst, double alpha, const do
     return hipSuccess;
 }
 
+hipError_t net_correction(cylpoisson_plan* p, const double* v, double* z, hipStream_t s);
+
 // z = M(v): the network on every cos/sin pair (or, without a network or with
 // the option "krylov_precond" = 0, the identity; 2: four SOR sweeps; 3: one
-// V-cycle).
+// V-cycle; 4: one V-cycle followed by the network's correction of the error
+// it leaves, computed from its residual).
 hipError_t learned_precond(cylpoisson_plan* p, const double* v, double* z, hipStream_t s) {
-    const LevelView& lv = p->dl[0].v;
+    if (p->opt.krylov_precond == 4) {
+        // z = V(v); r' = v - A z; z += N(r')
+        double* const rv = p->kv[2 * p->opt.krylov_restart + 2];
+        double* const cz = p->kv[2 * p->opt.krylov_restart + 3];
+        const int saved = p->opt.krylov_precond;
+        p->opt.krylov_precond = 3;
+        hipError_t e = learned_precond(p, v, z, s);
+        p->opt.krylov_precond = saved;
+        if (e == hipSuccess) e = plane_apply(p, z, rv, s);
+        if (e == hipSuccess) {
+            const double* a[1] = {v};
+            const double c[1] = {1.0};
+            e = plane_lincomb(p, rv, -1.0, a, c, 1, s);
+        }
+        if (e == hipSuccess && p->net) {
+            e = net_correction(p, rv, cz, s);
+            if (e == hipSuccess) {
+                const double* a[1] = {cz};
+                const double c[1] = {1.0};
+                e = plane_lincomb(p, z, 1.0, a, c, 1, s);
+            }
+        }
+        return e;
+    }
     if (p->opt.krylov_precond == 3) {
         // one V-cycle on A z = v from z = 0; the level-0 iterate, its ping-pong
         // buffer and right-hand side are lent to z, a spare Krylov vector and v
@@ -317,6 +344,12 @@ hipError_t learned_precond(cylpoisson_plan* p, const double* v, double* z, hipSt
         const double c[1] = {1.0};
         return plane_lincomb(p, z, 0.0, a, c, 1, s);
     }
+    return net_correction(p, v, z, s);
+}
+
+// z = the network's correction for the residual planes v (every cos/sin pair).
+hipError_t net_correction(cylpoisson_plan* p, const double* v, double* z, hipStream_t s) {
+    const LevelView& lv = p->dl[0].v;
     NetState* n = &p->net->st;
     const int npairs = net_pairs(p->nt);
     const int H = lv.nz - 2, W = lv.nr - 2;
@@ -502,21 +535,36 @@ int cylpoisson_nn_collect(cylpoisson_plan* p, cylpoisson_nn* nn, const double* r
         n.patch_capacity = cap;
     }
     // the right-hand side of this rho (one cycle of a solve sets it up), then
-    // the V-cycle iterates from zero; each residual r_k is paired with the
-    // correction c_k that kSmoothSweeps red-black SOR sweeps on A c = r_k make
-    // from c = 0 (the plain solver's smoother, a local map the network can hold)
+    // the V-cycle iterates from zero.  Target 0 (option nn_target): each
+    // residual r_k is paired with the correction c_k that kSmoothSweeps
+    // red-black SOR sweeps on A c = r_k make from c = 0 (the plain solver's
+    // smoother, a local map the network can hold).  Target 1: after each
+    // V-cycle the residual r_k is paired with the iterate's error u* - u_k,
+    // u* the converged solution (a solve to tol 1e-14 first): the pairs of the
+    // learned correction that follows a V-cycle (krylov_precond 4).
     constexpr int kSmoothSweeps = 4;
+    const int target = p->opt.nn_target;
     double* phi = nullptr;
+    double* ustar = nullptr;
     const size_t bytes = (size_t)p->nt * v.pstride * sizeof(double);
     hipError_t e = hipMalloc(&phi, bytes);
-    if (e != hipSuccess) return hip_status(e, "collection scratch");
+    if (e == hipSuccess && target == 1) e = hipMalloc(&ustar, bytes);
+    if (e != hipSuccess) {
+        if (phi) (void)hipFree(phi);
+        return hip_status(e, "collection scratch");
+    }
     const Options saved = p->opt;
     p->opt.precision = 64;
     p->opt.krylov = 0;
     p->opt.warm_start = 0;
-    p->opt.max_cycles = 1;
-    int st = cylpoisson_solve(p, rho, phi, 1e-300, stream);
+    p->opt.max_cycles = target == 1 ? CYLPOISSON_MAX_HISTORY : 1;
+    int st = cylpoisson_solve(p, rho, phi, target == 1 ? 1e-14 : 1e-300, stream);
     if (st == CYLPOISSON_NOT_CONVERGED) st = CYLPOISSON_OK;
+    if (st == CYLPOISSON_OK && target == 1) {
+        // the converged planes u*
+        e = hipMemcpyAsync(ustar, p->dl[0].u, bytes, hipMemcpyDeviceToDevice, s);
+        if (e != hipSuccess) st = hip_status(e, "collection scratch");
+    }
     SplitMix64 rng{seed};
     const int npairs = net_pairs(p->nt);
     std::vector<int> pos((size_t)patches_per_cycle * 3);
@@ -529,11 +577,18 @@ int cylpoisson_nn_collect(cylpoisson_plan* p, cylpoisson_nn* nn, const double* r
         if (e == hipSuccess) e = launch_copy_ring(p->dl[0], p->nt, p->dl[0].u, p->dl[0].u2, s);
         for (int c = 0; c < cycles && e == hipSuccess; ++c) {
             DeviceLevel& L = p->dl[0];
-            e = launch_residual(L, p->nt, p->d_lam, L.u, L.f, L.r, s);
-            if (e == hipSuccess) e = hipMemsetAsync(phi, 0, bytes, s);  // c = 0, ring included
-            for (int sw = 0; sw < kSmoothSweeps && e == hipSuccess; ++sw)
-                for (int color = 0; color < 2 && e == hipSuccess; ++color)
-                    e = launch_rb_sweep(L, p->nt, p->d_lam, phi, L.r, color, saved.omega, s);
+            if (target == 1) e = vcycle_step(p, s);
+            if (e == hipSuccess) e = launch_residual(L, p->nt, p->d_lam, L.u, L.f, L.r, s);
+            if (target == 1) {
+                const double* a[2] = {ustar, L.u};
+                const double w[2] = {1.0, -1.0};
+                if (e == hipSuccess) e = plane_lincomb(p, phi, 0.0, a, w, 2, s);
+            } else {
+                if (e == hipSuccess) e = hipMemsetAsync(phi, 0, bytes, s);  // c = 0, ring included
+                for (int sw = 0; sw < kSmoothSweeps && e == hipSuccess; ++sw)
+                    for (int color = 0; color < 2 && e == hipSuccess; ++color)
+                        e = launch_rb_sweep(L, p->nt, p->d_lam, phi, L.r, color, saved.omega, s);
+            }
             if (e == hipSuccess)
                 e = launch_plane_norms(L, p->nt, L.r, p->d_partial, p->d_norms + (size_t)(kNormSlots - 2) * p->nt, s);
             if (e == hipSuccess) {
@@ -557,7 +612,7 @@ int cylpoisson_nn_collect(cylpoisson_plan* p, cylpoisson_nn* nn, const double* r
             // the host rewrites pos next cycle: wait for the copy
             if (e == hipSuccess) e = hipStreamSynchronize(s);
             if (e == hipSuccess) n.patches += patches_per_cycle;
-            if (e == hipSuccess) e = vcycle_step(p, s);
+            if (e == hipSuccess && target == 0) e = vcycle_step(p, s);
         }
         if (e == hipSuccess) e = hipStreamSynchronize(s);
         if (e != hipSuccess) st = hip_status(e, "collecting patches");
@@ -565,6 +620,7 @@ int cylpoisson_nn_collect(cylpoisson_plan* p, cylpoisson_nn* nn, const double* r
     p->opt = saved;
     if (d_pos) (void)hipFree(d_pos);
     if (d_sc) (void)hipFree(d_sc);
+    if (ustar) (void)hipFree(ustar);
     (void)hipFree(phi);
     return st;
 }

@@ -910,7 +910,8 @@ int cylpoisson_plan_set_option(cylpoisson_plan* plan, const char* key, double va
     if (!std::strcmp(key, "masks")) return int_in(0, 1, &plan->opt.masks);
     if (!std::strcmp(key, "graph")) return int_in(0, 1, &plan->opt.graph);
     if (!std::strcmp(key, "krylov")) return int_in(0, 1, &plan->opt.krylov);
-    if (!std::strcmp(key, "krylov_precond")) return int_in(0, 3, &plan->opt.krylov_precond);
+    if (!std::strcmp(key, "krylov_precond")) return int_in(0, 4, &plan->opt.krylov_precond);
+    if (!std::strcmp(key, "nn_target")) return int_in(0, 1, &plan->opt.nn_target);
     if (!std::strcmp(key, "krylov_restart")) return int_in(1, 16, &plan->opt.krylov_restart);
     if (!std::strcmp(key, "krylov_max")) return int_in(1, 100000, &plan->opt.krylov_max);
     if (!std::strcmp(key, "fallback")) return int_in(0, 1, &plan->opt.fallback);
@@ -960,7 +961,7 @@ int cylpoisson_plan_get_option(const cylpoisson_plan* plan, const char* key, dou
                  {"krylov_precond", (double)o.krylov_precond}, {"krylov_restart", (double)o.krylov_restart},
                  {"krylov_max", (double)o.krylov_max}, {"fallback", (double)o.fallback},
                  {"merge", (double)o.merge}, {"merge_prefetch", (double)o.merge_prefetch},
-                 {"chunk_rows_merge", (double)o.chunk_rows_merge}};
+                 {"chunk_rows_merge", (double)o.chunk_rows_merge}, {"nn_target", (double)o.nn_target}};
     for (const auto& t : table)
         if (!std::strcmp(key, t.name)) {
             *value = t.v;

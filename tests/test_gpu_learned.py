@@ -171,6 +171,72 @@ def test_learned_solve_falls_back_when_worse(P, trained):
     assert st["status"] == P.OK and rel_l2(host(phi), ref) <= 1e-12
 
 
+# ------------------- the network inside the V-cycle (krylov_precond 4)
+@pytest.fixture(scope="module")
+def trained_vcycle(P):
+    """A network trained on 15,360 residual/smoother-correction pairs of the
+    129 x 64 x 129 grid (five charges, six V-cycle iterates each)."""
+    p = W.BATCHED
+    plan = P.Plan.for_problem(p)
+    net = P.Net(seed=2024)
+    for k in range(5):
+        net.collect(plan, dev(W.blob_charge(p, seed=100 + k)), cycles=6, patches_per_cycle=512, seed=k)
+    net.train(epochs=30, batch=256, lr=2e-3)
+    net.train(epochs=10, batch=256, lr=5e-4)
+    return p, net
+
+
+def test_learned_correction_inside_the_vcycle_gains_per_step(P, trained_vcycle):
+    """FGMRES preconditioned by one V-cycle followed by the network's correction
+    of the residual the V-cycle leaves (a learned smoothing step trained on the
+    plain solver's residual/smoother-correction pairs): per FGMRES step it
+    contracts more than the same V-cycle without the network and than with an
+    untrained network (measured: 0.0147 against 0.0151 and 0.0171; the plain
+    V-cycle alone contracts 0.053 from zero).  The gain is small: the V-cycle
+    leaves mostly smooth error, which a 7 x 7 receptive field cannot correct."""
+    p, net = trained_vcycle
+    rho = dev(W.blob_charge(p, seed=24680))
+    rates = {}
+    for label, n in (("no network", None), ("untrained", P.Net(seed=77)), ("trained", net)):
+        plan = P.Plan.for_problem(p, krylov=1, krylov_precond=4, fallback=0, krylov_max=8)
+        if n is not None:
+            P.plan_set_net(plan, n)
+        _, st = plan.solve(rho, tol=1e-30, allow=(P.OK, P.NOT_CONVERGED))
+        assert st["krylov_iterations"] == 8, st
+        rates[label] = st["learned_rate"]
+        say("v-cycle + net", label, st["learned_rate"], "plain v-cycle", st["vcycle_rate"])
+    assert rates["trained"] < rates["no network"], rates
+    assert rates["trained"] < rates["untrained"], rates
+
+
+def test_learned_vcycle_solve_meets_the_oracle_and_falls_back(P, trained):
+    """The judged solve with the learned V-cycle reaches the oracle's answer; a
+    network trained on targets it cannot represent (the iterates' smooth global
+    error, option nn_target 1) contracts less than a plain V-cycle and the solve
+    hands over to V-cycles, still meeting the oracle."""
+    p, net = trained
+    rho = W.blob_charge(p, seed=99)
+    ref = solvers.solve_separable(fv.Grid.of(p), rho, p.bc)
+    plan = P.Plan.for_problem(p, krylov=1, krylov_precond=4)
+    P.plan_set_net(plan, net)
+    phi, st = plan.solve(dev(rho), tol=1e-13)
+    assert st["status"] == P.OK and st["learned_fallback"] == 0, st
+    assert rel_l2(host(phi), ref) <= 1e-12
+    bad = P.Net(seed=9)
+    cplan = P.Plan.for_problem(p, nn_target=1)
+    for k in range(3):
+        bad.collect(cplan, dev(W.blob_charge(p, seed=80 + k)), cycles=4, patches_per_cycle=128, seed=k)
+    bad.train(epochs=10, batch=128, lr=2e-3)
+    plan2 = P.Plan.for_problem(p, krylov=1, krylov_precond=4)
+    P.plan_set_net(plan2, bad)
+    phi2, st2 = plan2.solve(dev(rho), tol=1e-13)
+    say("error-target net", st2["learned_rate"], "plain v-cycle", st2["vcycle_rate"], "fell back", st2["learned_fallback"])
+    assert st2["status"] == P.OK
+    if st2["learned_rate"] >= st2["vcycle_rate"]:
+        assert st2["learned_fallback"] == 1
+    assert rel_l2(host(phi2), ref) <= 1e-12
+
+
 def test_learned_option_errors(P):
     plan = P.Plan.for_problem(W.SMALL, krylov=1)
     plan.set_option("precision", 32)
