@@ -243,9 +243,11 @@ void cylpoisson_plan_destroy(cylpoisson_plan* plan);
  *                    Its error is then smaller per unit of residual, so a
  *                    looser tol reaches a given error (at 400 x 128 x 512, tol
  *                    1e-13 gives rel-L2 5e-13 in 6 cycles, against 8 cycles
- *                    to 1e-14 from zero).  FP64 with the fused passes and the
- *                    LDS bottom kernel; ignored otherwise, and with
- *                    "warm_start", "precision" 32 or "krylov" (default 0)
+ *                    to 1e-14 from zero).  With "precision" 32 the FP64
+ *                    refinement starts from that iterate (its residual measured
+ *                    against the right-hand side as for a warm start).  Needs
+ *                    the fused passes and the LDS bottom kernel; ignored
+ *                    otherwise, and with "warm_start" or "krylov" (default 0)
  *   "merge"          1 = a cycle after which no convergence check follows ends in
  *                    one finest-level pass that does its up pass and the next
  *                    cycle's down pass (prolongation, nu2 + nu1 sweeps, residual,

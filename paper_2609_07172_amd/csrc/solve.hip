@@ -1073,11 +1073,14 @@ int solve_impl(cylpoisson_plan* p, const double* rho, double* phi, double tol, v
     // so only the Dirichlet rings of the two iterate buffers are written (the
     // mixed-precision refinement writes the zero interior itself).
     const bool warm = p->opt.warm_start != 0 && !learned;
-    const bool fmg = !warm && !learned && !mixed && fmg_active(p);
+    // the full-multigrid start also serves the mixed-precision solve, whose
+    // FP64 refinement then starts from it as from a given iterate
+    const bool fmg = !warm && !learned && fmg_active(p);
     // the first down pass folds in the start's finest interpolation, except
-    // with graphs (the captured first cycle is the plain one); masks freeze no
-    // plane before the first cycle
-    const bool fmg_pro = fmg && fused_down_pro_ok(p) && !graphs_active(p, groups_active(p));
+    // with graphs (the captured first cycle is the plain one) and in mixed
+    // precision (the first pass is the FP64 refinement); masks freeze no plane
+    // before the first cycle
+    const bool fmg_pro = fmg && !mixed && fused_down_pro_ok(p) && !graphs_active(p, groups_active(p));
     const bool ring_only = !warm && !learned && !fmg && (mixed || fused_supported(p, 0));
     {
         Timed tm(p, kOther, s);
@@ -1099,11 +1102,11 @@ int solve_impl(cylpoisson_plan* p, const double* rho, double* phi, double tol, v
     }
     double* result = nullptr;
     const int status = learned ? run_learned(p, tol, s)
-                       : mixed ? run_mixed(p, tol, s, &result, warm)
+                       : mixed ? run_mixed(p, tol, s, &result, warm || fmg)
                                : run_cycles(p, tol, s, ring_only, warm, fmg, fmg_pro);
     if (!mixed) result = L.u;  // merged finest passes swap u and u2
     if ((status == CYLPOISSON_OK || status == CYLPOISSON_NOT_CONVERGED) && p->stats.cycles == 0 &&
-        (ring_only || fmg)) {
+        (ring_only || (fmg && !mixed))) {
         // no cycle ran (a right-hand side that is zero, or tol >= 1): the answer
         // is the zero interior whose residual was measured, which a ring-only
         // start never wrote and a full-multigrid start overwrote with its guess

@@ -143,3 +143,20 @@ def test_mixed_paper_scale_matches_separable_oracle(P):
     assert st["status"] == P.OK, st
     assert rel_l2(got, ref) <= 1e-12, rel_l2(got, ref)
     assert rel_l2(got, phit) <= 1e-12
+
+
+@pytest.mark.parametrize("prob", [W.BATCHED, W.SMALL.with_sizes(257, 16, 257)])
+def test_mixed_from_the_full_multigrid_start_meets_the_oracle(P, prob):
+    """Option fmg with precision 32: the FP64 refinement starts from the
+    full-multigrid iterate (a warm start whose residual is measured against the
+    right-hand side) and needs fewer refinement steps than from zero."""
+    rho = W.blob_charge(prob, seed=24680)
+    ref = solvers.solve_separable(fv.Grid.of(prob), rho, prob.bc)
+    say("mixed fmg", prob.name)
+    _, s0 = mixed_plan(P, prob).solve(dev(rho), tol=1e-13)
+    phi, st = mixed_plan(P, prob, fmg=1).solve(dev(rho), tol=1e-13)
+    assert st["status"] == P.OK, st
+    assert st["refinements"] <= s0["refinements"], (st, s0)
+    assert rel_l2(host(phi), ref) <= 1e-12, rel_l2(host(phi), ref)
+    got = host(phi)
+    np.testing.assert_array_equal(got[:, -1, :], prob.phi_zL)
