@@ -299,10 +299,14 @@ struct Pass {
     // Loads of row x into slot j: every lane loads from a clamped, valid address
     // and consume() keeps what is needed, so several rows stay in flight.
     __device__ __forceinline__ void issue(int x, int j) {
-        const long long o = (long long)min(x, lend) * a.v.pitch;
+        const int xr = min(x, lend);
+        const long long o = (long long)xr * a.v.pitch;
         if (!ZERO_U) {
-            uu[j][0] = urow[o + k1];
-            uu[j][1] = urow[o + k2];
+            // a zero interior is not read: its lanes load the row's ring value
+            // instead (one cache line per row), which consume() discards
+            const bool skip = DOWN && a.zero_interior && interior_row(xr);
+            uu[j][0] = urow[o + (skip && act1 ? 0 : k1)];
+            uu[j][1] = urow[o + (skip && act2 ? 0 : k2)];
         }
         ff[j][0] = frow[o + k1];
         ff[j][1] = frow[o + k2];

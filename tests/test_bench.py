@@ -28,6 +28,9 @@ def test_fine_pass_bytes_at_400x128x512():
     assert b["up"] == 675_517_440
     assert b["down"] == b["up"]
     assert b["down_first"] == b["down"] - 8 * 25_981_440
+    # merged pass: read u and f, write u; read the coarse correction and write
+    # the coarse right-hand side (8 B each per level-1 unknown)
+    assert b["merged"] == 24 * 25_981_440 + 16 * 128 * 199 * 255
 
 
 def test_counter_profile_matches_the_fused_pass_sources():
@@ -35,10 +38,10 @@ def test_counter_profile_matches_the_fused_pass_sources():
     assert rec["source_hash"] == bench.source_hash(), (
         "profiles/traffic.json was taken on other fused-pass sources: retake the FETCH_SIZE and "
         "WRITE_SIZE profiles and ingest them with bench.py --ingest-counters")
-    assert {"fine_up", "fine_down"} <= set(rec["bytes_per_launch"])
-    for k in ("fine_up", "fine_down"):
-        assert 0.9 < rec["bytes_per_launch"][k] / bench.alg_bytes(
-            {"level_shapes": [(400, 512), (201, 257)]}, 128)["up"] < 1.25
+    assert {"fine_up", "fine_down", "fine_merged"} <= set(rec["bytes_per_launch"])
+    alg = bench.alg_bytes({"level_shapes": [(400, 512), (201, 257)]}, 128)
+    for k, model in (("fine_up", "up"), ("fine_down", "down"), ("fine_merged", "merged")):
+        assert 0.9 < rec["bytes_per_launch"][k] / alg[model] < 1.25
 
 
 def test_accuracy_measures_on_a_planted_error():
