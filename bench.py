@@ -304,7 +304,8 @@ def time_sequence(problem, rho0_d, args, seq, phit, steps=200):
     SEQ_FIELDS seeded unit-RMS blob fields (workloads.sequence_plan), so the
     charge moves by the same multiple of that field's charge (formed by the
     oracle) and the exact answer of every step is known.  Each step is solved
-    to tol from zero (cold) or from the previous answer (warm start); the timed
+    to tol from the full-multigrid start (cold) or from the previous answer
+    (warm start); the timed
     loop includes the charge update on the device.  An untimed replay then
     checks every step's answer against its exact potential.  Without the CPU
     leg (no oracle), the drift is a smooth seeded charge field instead and only
@@ -329,7 +330,7 @@ def time_sequence(problem, rho0_d, args, seq, phit, steps=200):
         kind = "rho drift: 0.01 max|rho0| x smooth seeded field per step (no exact answers)"
     out = {"steps": steps, "tol": tol, "drift": kind, "fields": SEQ_FIELDS}
     for label, warm in (("cold", 0), ("warm", 1)):
-        plan = P.Plan.for_problem(problem, warm_start=warm)
+        plan = P.Plan.for_problem(problem, warm_start=warm, fmg=1)  # fmg: cold starts only
         rho = rho0_d.clone()
         phi = torch.zeros_like(rho)
         allow = (P.OK, P.NOT_CONVERGED)

@@ -158,6 +158,8 @@ struct cylpoisson_plan {
     // options last changed): the first convergence check of the next solve
     int last_cycles = 0;
     double last_tol = 0.0;
+    int last_kind = 0;       // 0 zero start, 1 full-multigrid start, 2 warm start
+    double last_rate = -1.0; // mean contraction per cycle of a measured start
 
     std::vector<cp::HostLevel> hl;
     std::vector<cp::DeviceLevel> dl;

@@ -548,11 +548,28 @@ int run_cycles(cylpoisson_plan* p, double tol, hipStream_t s, bool ring_only, bo
         CP_HIP(fork_groups(p, G, s));
     }
     // The first check comes after cycle 2, or (without masks, which freeze
-    // planes only at checks) at the cycle count with which the plan's last
-    // solve to the same tol converged: a solve of a similar problem then needs
-    // one host round trip, and the cycles before it can end in merged passes.
+    // planes only at checks) where the plan's last converged solve to the same
+    // tol predicts: a solve of a similar problem then needs one host round
+    // trip, and the cycles before it can end in merged passes.  A start whose
+    // residual is known (a warm start) takes the last solve's mean contraction
+    // factor per cycle from its own starting residual to tol; a cold start
+    // (residual unknown until the first check) takes the last cycle count of a
+    // solve that started the same way (zero or full-multigrid).  A prediction
+    // that comes early costs one more check, never more cycles; the factor's
+    // prediction is capped at the last solve's cycle count, because a solve
+    // whose last cycles reach the rounding floor of the residual measures a
+    // slower mean factor than its cycles had, and would predict ever more.
+    const int kind = warm ? 2 : fmg ? 1 : 0;
     int next_check = std::min(2, maxc);
-    if (!masks && p->last_cycles > 0 && p->last_tol == tol) next_check = std::min(p->last_cycles, maxc);
+    if (!masks && p->last_cycles > 0 && p->last_tol == tol) {
+        const double rel0 = std::sqrt(r02 / b2);
+        if (!defer && p->last_rate > 0.0 && p->last_rate < 0.9 && rel0 > tol) {
+            const double need = std::ceil(std::log(tol / rel0) / std::log(p->last_rate) - 1e-9);
+            next_check = std::max(1, std::min({(int)need, p->last_cycles, maxc}));
+        } else if (defer && p->last_kind == kind) {
+            next_check = std::min(p->last_cycles, maxc);
+        }
+    }
     p->last_cycles = 0;
     int last_read = 0;
     // relative residual at the last check (the starting iterate's at first)
@@ -701,6 +718,14 @@ int run_cycles(cylpoisson_plan* p, double tol, hipStream_t s, bool ring_only, bo
     if (status == CYLPOISSON_OK && st.cycles > 0) {
         p->last_cycles = st.cycles;
         p->last_tol = tol;
+        p->last_kind = kind;
+        // mean contraction factor per cycle from a measured start that was
+        // already close (-1 otherwise: the first cycles from a far start
+        // contract less than later ones, and would predict too many)
+        const double rel0 = defer || b2 <= 0.0 ? 0.0 : std::sqrt(r02 / b2);
+        p->last_rate = rel0 > 0.0 && rel0 < 0.5 && st.rel_residual > 0.0
+                           ? std::pow(st.rel_residual / rel0, 1.0 / st.cycles)
+                           : -1.0;
     }
     return status;
 }

@@ -500,3 +500,36 @@ def test_first_check_follows_the_last_converged_solve(P):
     plan.set_option("nu1", 2)
     _, sd = plan.solve(rho, tol=1e-13)
     assert sd["checks"] == sa["checks"]
+
+
+def test_warm_first_check_not_from_a_cold_solve(P):
+    """Warm starts close to the answer predict their first check from the last
+    warm solve's contraction factor, never from a solve that started far away:
+    a small drift of the charge then needs fewer cycles than the solve from
+    zero."""
+    p = W.BATCHED
+    rho = W.blob_charge(p, seed=5)
+    drift = W.drift_fields(p, count=2, seed=11)
+    amp = 1e-3 * float(np.abs(rho).max())
+    plan = P.Plan.for_problem(p, warm_start=1)
+    phi = dev(np.zeros(p.shape))
+    say("warm first check")
+    _, s0 = plan.solve(dev(rho), tol=1e-13, phi=phi)
+    stats = []
+    for k in range(8):
+        rho = rho + amp * drift[k % 2]
+        _, st = plan.solve(dev(rho), tol=1e-13, phi=phi)
+        assert st["status"] == P.OK, st
+        stats.append(st)
+    assert all(st["cycles"] < s0["cycles"] for st in stats), (s0, stats)
+    # the starting residual's read-back, then at most one check before the
+    # predicted one (the factor varies a little from step to step)
+    assert all(st["checks"] <= 3 for st in stats), stats
+    # cycles between checks end in merged passes and form no norms: the first
+    # formed norm is the first check, never later than the last solve's count
+    # (a solve ending on the rounding floor must not push the next one on)
+    for prev, st in zip(stats, stats[1:]):
+        first = next(i for i, h in enumerate(st["history"]) if h is not None) + 1
+        assert first <= prev["cycles"], (prev, st)
+    ref = solvers.solve_separable(fv.Grid.of(p), rho, p.bc)
+    assert rel_l2(host(phi), ref) < 1e-12
