@@ -129,6 +129,8 @@ typedef struct {
                          * kernel run one kernel per sweep) */
     int layout;         /* CYLPOISSON_VERTEX or CYLPOISSON_CELL */
     int uniform;        /* 1 = built by cylpoisson_plan_create (uniform vertex-centred mesh) */
+    int direct_level;   /* level solved exactly by the separable solve, where the V-cycle
+                         * stops under option "direct" = 1; -1 if none */
 } cylpoisson_info;
 
 /* Create a plan for an Nr x Ntheta x Nz grid.  Requires Nr >= 3, Nz >= 3,
@@ -258,6 +260,15 @@ void cylpoisson_plan_destroy(cylpoisson_plan* plan);
  *                    nu1 = nu2 = 2, at most 512 radial nodes, one plane group and
  *                    no graphs (default 1)
  *   "merge_prefetch" rows the merged pass loads ahead of the one it consumes (1 .. 2; default 1)
+ *   "direct"         1 = the V-cycle stops at the plan's direct level (cylpoisson_info
+ *                    direct_level: the first level from 1 on with at most 128 interior
+ *                    axial and 256 interior radial nodes) and solves it exactly on every
+ *                    plane: the axial generalised eigenvectors of the level's separable
+ *                    operator (formed when the plan is built), one radial tridiagonal
+ *                    solve per eigenvector, and the inverse transform.  Used by every
+ *                    FP64 V-cycle, the full-multigrid start included; the FP32 inner
+ *                    cycles of "precision" 32 keep the bottom kernel.  Ignored where no
+ *                    level qualifies (default 0)
  *   "graph"          1 = each V-cycle is captured once into a HIP graph and replayed
  *                    (single plane group, "timing" 0; default 0).  Setting any
  *                    option releases the captured graphs

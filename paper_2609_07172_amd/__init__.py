@@ -83,14 +83,16 @@ class Info(ctypes.Structure):
                 ("level_nz", ctypes.c_int * MAX_LEVELS), ("coarse_unknowns", ctypes.c_int),
                 ("bottom_level", ctypes.c_int),
                 ("workspace_bytes", ctypes.c_longlong), ("device", ctypes.c_int),
-                ("fused_levels", ctypes.c_int), ("layout", ctypes.c_int), ("uniform", ctypes.c_int)]
+                ("fused_levels", ctypes.c_int), ("layout", ctypes.c_int), ("uniform", ctypes.c_int),
+                ("direct_level", ctypes.c_int)]
 
     def as_dict(self) -> dict:
         return {"nr": self.nr, "ntheta": self.ntheta, "nz": self.nz, "levels": self.levels,
                 "level_shapes": [(self.level_nr[i], self.level_nz[i]) for i in range(self.levels)],
                 "coarse_unknowns": self.coarse_unknowns, "bottom_level": self.bottom_level,
                 "workspace_bytes": self.workspace_bytes, "device": self.device,
-                "fused_levels": self.fused_levels, "layout": self.layout, "uniform": self.uniform}
+                "fused_levels": self.fused_levels, "layout": self.layout, "uniform": self.uniform,
+                "direct_level": self.direct_level}
 
 
 class CylPoissonError(RuntimeError):

@@ -634,6 +634,21 @@ cylpoisson_plan* build_plan(cylpoisson_plan* p) {
             p->bottom_level = lb;
             break;
         }
+        // the exact separable solve: the first level from 1 on small enough for
+        // it, at or above the bottom kernel's first level (the V-cycle stops there)
+        for (int l = 1; l < nl; ++l) {
+            if (p->bottom_level >= 1 && l > p->bottom_level) break;
+            if (!direct_level_ok(p->hl[l])) continue;
+            std::vector<double> V, VT, fac;
+            std::vector<int> set;
+            direct_tables(p->hl[l], p->lam, V, VT, fac, set);
+            CP_TRY(upload(p, &p->d_dir_V, V));
+            CP_TRY(upload(p, &p->d_dir_VT, VT));
+            CP_TRY(upload(p, &p->d_dir_fac, fac));
+            CP_TRY(upload(p, &p->d_dir_set, set));
+            p->direct_level = l;
+            break;
+        }
         std::vector<double> F, G;
         dft_matrices(Ntheta, F, G);
         CP_TRY(upload(p, &p->d_F, F));
@@ -912,6 +927,7 @@ int cylpoisson_plan_set_option(cylpoisson_plan* plan, const char* key, double va
     if (!std::strcmp(key, "krylov")) return int_in(0, 1, &plan->opt.krylov);
     if (!std::strcmp(key, "krylov_precond")) return int_in(0, 4, &plan->opt.krylov_precond);
     if (!std::strcmp(key, "nn_target")) return int_in(0, 1, &plan->opt.nn_target);
+    if (!std::strcmp(key, "direct")) return int_in(0, 1, &plan->opt.direct);
     if (!std::strcmp(key, "krylov_restart")) return int_in(1, 16, &plan->opt.krylov_restart);
     if (!std::strcmp(key, "krylov_max")) return int_in(1, 100000, &plan->opt.krylov_max);
     if (!std::strcmp(key, "fallback")) return int_in(0, 1, &plan->opt.fallback);
@@ -961,7 +977,8 @@ int cylpoisson_plan_get_option(const cylpoisson_plan* plan, const char* key, dou
                  {"krylov_precond", (double)o.krylov_precond}, {"krylov_restart", (double)o.krylov_restart},
                  {"krylov_max", (double)o.krylov_max}, {"fallback", (double)o.fallback},
                  {"merge", (double)o.merge}, {"merge_prefetch", (double)o.merge_prefetch},
-                 {"chunk_rows_merge", (double)o.chunk_rows_merge}, {"nn_target", (double)o.nn_target}};
+                 {"chunk_rows_merge", (double)o.chunk_rows_merge}, {"nn_target", (double)o.nn_target},
+                 {"direct", (double)o.direct}};
     for (const auto& t : table)
         if (!std::strcmp(key, t.name)) {
             *value = t.v;
@@ -999,12 +1016,14 @@ int cylpoisson_get_info(const cylpoisson_plan* plan, cylpoisson_info* out) {
     out->workspace_bytes = plan->workspace_bytes;
     out->device = plan->device;
     for (int l = 0; l + 1 < out->levels; ++l) {
+        if (l > 0 && l == plan->direct_level && direct_active(plan)) break;
         if (l > 0 && l == plan->bottom_level && bottom_active(plan)) break;
         if (!fused_supported(plan, l)) break;
         ++out->fused_levels;
     }
     out->layout = plan->layout;
     out->uniform = plan->uniform ? 1 : 0;
+    out->direct_level = plan->direct_level;
     return CYLPOISSON_OK;
 }
 

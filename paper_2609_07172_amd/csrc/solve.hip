@@ -247,6 +247,7 @@ hipError_t vcycle(cylpoisson_plan* p, int l, hipStream_t s, bool zero_top, int s
     const int nl = (int)p->dl.size();
     DeviceLevel& L = p->dl[l];
     hipError_t e = hipSuccess;
+    if (l > 0 && l == p->direct_level && direct_active(p)) return launch_direct(p, s, p0, np);
     if (l == nl - 1) {
         if (l > 0) e = launch_zero_interior(L, p->nt, L.u, s);
         if (e == hipSuccess)
@@ -1010,32 +1011,43 @@ int run_learned(cylpoisson_plan* p, double tol, hipStream_t s) {
 
 hipError_t vcycle_step(cylpoisson_plan* p, hipStream_t s) { return vcycle(p, 0, s, false, -1, nullptr); }
 
-// Whether the full-multigrid start applies: option "fmg" set, the LDS bottom
-// kernel serving the levels from some level 1 or deeper, and fused passes on
-// every level above it (so the point smoother on FP64 levels).
+// The level where the V-cycle stops: the direct level (exact separable
+// solve) when that applies, else the LDS bottom kernel's first level; -1 if
+// neither serves a level from 1 on.
+int stop_level(const cylpoisson_plan* p) {
+    if (direct_active(p)) return p->direct_level;
+    if (bottom_active(p) && p->bottom_level >= 1) return p->bottom_level;
+    return -1;
+}
+
+// Whether the full-multigrid start applies: option "fmg" set, the V-cycle
+// stopping at some level 1 or deeper (direct solve or LDS bottom kernel), and
+// fused passes on every level above it (so the point smoother on FP64 levels).
 bool fmg_active(const cylpoisson_plan* p) {
-    if (!p->opt.fmg || !bottom_active(p) || p->bottom_level < 1) return false;
-    for (int l = 0; l < p->bottom_level; ++l)
+    const int lc = stop_level(p);
+    if (!p->opt.fmg || lc < 1) return false;
+    for (int l = 0; l < lc; ++l)
         if (!fused_supported(p, l)) return false;
     return true;
 }
 
 // The finest right-hand side (with the Dirichlet terms of u's ring)
-// restricted to every level (the first restriction also leaves the right-hand
-// side's per-plane norms in slot 0) and one V-cycle of the bottom kernel from zero;
-// that answer is interpolated up to level 1, which takes one V-cycle from it,
-// and the finest interior becomes the interpolated level-1 answer (u's
-// Dirichlet ring, already set, is kept).  A V-cycle on every level between
-// gives the same start at 400 x 128 x 512 (first-cycle residual 8.6e-4
-// against 8.7e-4) for 0.1 ms more.
+// restricted down to the level where the V-cycle stops (the first restriction
+// also leaves the right-hand side's per-plane norms in slot 0), solved there
+// (exactly by the direct solve, or by one V-cycle of the bottom kernel from
+// zero); that answer is interpolated up to level 1, which takes one V-cycle
+// from it, and the finest interior becomes the interpolated level-1 answer
+// (u's Dirichlet ring, already set, is kept).  A V-cycle on every level
+// between gives the same start at 400 x 128 x 512 (first-cycle residual
+// 8.6e-4 against 8.7e-4) for 0.1 ms more.
 hipError_t fmg_start(cylpoisson_plan* p, hipStream_t s, bool fused_top) {
-    const int nt = p->nt, lb = p->bottom_level;
+    const int nt = p->nt, lb = stop_level(p);
     DeviceLevel& L0 = p->dl[0];
     hipError_t e = launch_restrict_rhs_norms(L0, p->dl[1], nt, p->d_lam, L0.u, L0.f, p->dl[1].f,
                                              p->d_partial, p->d_norms, s);
     for (int l = 1; l < lb && e == hipSuccess; ++l)
         e = launch_restrict(p->dl[l], p->dl[l + 1], nt, p->dl[l].f, p->dl[l + 1].f, s);
-    if (e == hipSuccess) e = launch_bottom(p, s);
+    if (e == hipSuccess) e = direct_active(p) ? launch_direct(p, s) : launch_bottom(p, s);
     for (int l = lb - 1; l >= 1 && e == hipSuccess; --l) {
         DeviceLevel& L = p->dl[l];
         e = launch_prolong(L, p->dl[l + 1], nt, p->dl[l + 1].u, L.u, s, false);

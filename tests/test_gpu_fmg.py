@@ -1,5 +1,6 @@
 """The full-multigrid start (option "fmg"): the right-hand side restricted to
-every level, the bottom kernel from zero, one V-cycle per level on the way up
+the level where the V-cycle stops, solved there (exactly, or by the bottom
+kernel from zero), one V-cycle per level on the way up
 from the interpolated coarser answer, then V-cycles on the finest level from
 the interpolated level-1 answer.  It changes the starting iterate only, so the
 solve must still meet the oracle, take no more cycles than the zero start, and
@@ -32,12 +33,13 @@ def P():
                                   W.SMALL.with_sizes(217, 6, 94), W.SMALL.with_sizes(105, 5, 344),
                                   W.SMALL.with_sizes(384, 4, 411), W.SMALL.with_sizes(76, 7, 259)],
                          ids=lambda p: f"{p.nr}x{p.ntheta}x{p.nz}")
-def test_fmg_solve_matches_oracle(P, prob):
+@pytest.mark.parametrize("direct", [1, 0])
+def test_fmg_solve_matches_oracle(P, prob, direct):
     rho = W.blob_charge(prob, seed=prob.nr)
     ref = solvers.solve_separable(fv.Grid.of(prob), rho, prob.bc)
-    say("fmg", prob.nr, prob.ntheta, prob.nz)
-    zero = P.Plan.for_problem(prob)
-    plan = P.Plan.for_problem(prob, fmg=1)
+    say("fmg", prob.nr, prob.ntheta, prob.nz, "direct", direct)
+    zero = P.Plan.for_problem(prob, direct=direct)
+    plan = P.Plan.for_problem(prob, fmg=1, direct=direct)
     _, s0 = zero.solve(dev(rho), tol=1e-14)
     phi, st = plan.solve(dev(rho), tol=1e-14)
     got = host(phi)

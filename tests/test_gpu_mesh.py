@@ -183,7 +183,11 @@ def test_multigrid_preconditioned_fgmres_on_stretched_meshes(P, name):
 def test_masks_do_not_leak_into_a_later_fgmres_solve(P):
     """Planes frozen by a masked solve are not skipped by the V-cycles of a later
     FGMRES solve on the same plan."""
-    g, rho, ref = reference("cell_uniform")
+    g, rho, _ = reference("cell_uniform")
+    # an axisymmetric charge: every plane but plane 0 starts within its share of
+    # the tolerance and freezes at the first check
+    rho = np.ascontiguousarray(np.broadcast_to(rho.mean(axis=0, keepdims=True), rho.shape))
+    ref = solvers.solve_modes(g, rho, BC)
     say("masks then fgmres")
     plan = plan_for(P, CASES["cell_uniform"], masks=1)
     _, st = plan.solve(dev(rho), tol=1e-13)

@@ -324,18 +324,19 @@ def test_paper_scale_matches_separable_oracle(P):
 
 
 # -------------------------------------------------- fused vs per-step path
+@pytest.mark.parametrize("direct", [0, 1])
 @pytest.mark.parametrize("shape", [(33, 16, 33), (40, 8, 37), (129, 8, 129), (26, 3, 71), (129, 4, 33),
                                    (33, 4, 200)])
-def test_fused_passes_match_per_step_kernels(P, shape):
+def test_fused_passes_match_per_step_kernels(P, shape, direct):
     """The fused streaming passes run the same red-black schedule and point arithmetic as the
     one-kernel-per-step path (with contraction pinned in the shared point operations), so the
-    iterates agree bitwise."""
+    iterates agree bitwise; with the exact coarse-level solve both paths stop there."""
     nr, nt, nz = shape
     p = W.SMALL.with_sizes(nr, nt, nz)
     rho = dev(W.blob_charge(p, seed=nr + nz))
-    say("fused-vs-step", shape)
-    a = P.Plan.for_problem(p, fused=1, max_cycles=6)
-    b = P.Plan.for_problem(p, fused=0, max_cycles=6)
+    say("fused-vs-step", shape, "direct", direct)
+    a = P.Plan.for_problem(p, fused=1, max_cycles=6, direct=direct)
+    b = P.Plan.for_problem(p, fused=0, max_cycles=6, direct=direct)
     pa, sa = a.solve(rho, tol=1e-30, allow=(P.OK, P.NOT_CONVERGED))
     pb, sb = b.solve(rho, tol=1e-30, allow=(P.OK, P.NOT_CONVERGED))
     ha, hb = host(pa), host(pb)
@@ -391,8 +392,9 @@ def test_bottom_kernel_matches_level_by_level(P, shape):
     p = W.SMALL.with_sizes(nr, nt, nz)
     rho = dev(W.blob_charge(p, seed=nt))
     say("bottom", shape)
-    a = P.Plan.for_problem(p, bottom=1, max_cycles=4)
-    b = P.Plan.for_problem(p, bottom=0, max_cycles=4)
+    # the V-cycle must reach the bottom kernel's levels: no exact solve above them
+    a = P.Plan.for_problem(p, bottom=1, max_cycles=4, direct=0)
+    b = P.Plan.for_problem(p, bottom=0, max_cycles=4, direct=0)
     assert a.info()["bottom_level"] >= 1
     pa, sa = a.solve(rho, tol=1e-30, allow=(P.OK, P.NOT_CONVERGED))
     pa = host(pa).copy()
@@ -533,3 +535,58 @@ def test_warm_first_check_not_from_a_cold_solve(P):
         assert first <= prev["cycles"], (prev, st)
     ref = solvers.solve_separable(fv.Grid.of(p), rho, p.bc)
     assert rel_l2(host(phi), ref) < 1e-12
+
+
+# ------------------------------------------- exact solve of a coarse level
+@pytest.mark.parametrize("prob,tol", [(W.SMALL, 1e-14), (W.BATCHED, 1e-14), (W.HIGH_SHIFT, 1e-14),
+                                      (W.SMALL.with_sizes(400, 8, 512), 1e-14),
+                                      (W.SMALL.with_sizes(217, 6, 94), 1e-14),
+                                      (W.SMALL.with_sizes(65, 5, 401), 1e-14),
+                                      # cells 20:1, coarsened in r only: the residual's FP64
+                                      # floor is 5e-14 with or without the exact solve
+                                      (W.SMALL.with_sizes(401, 4, 65), 1e-13)],
+                         ids=lambda x: f"{x.nr}x{x.ntheta}x{x.nz}" if hasattr(x, "nr") else str(x))
+def test_direct_coarse_solve_matches_oracle(P, prob, tol):
+    """The V-cycle stopping at a level solved exactly (axial eigenvectors, radial
+    tridiagonal solves) meets the oracle, converges at least as fast per cycle as
+    the V-cycle through every level (its coarse correction is exact rather than
+    one V-cycle's), and contracts like a two- or three-grid method."""
+    rho = W.blob_charge(prob, seed=prob.nz)
+    ref = solvers.solve_separable(fv.Grid.of(prob), rho, prob.bc)
+    say("direct", prob.nr, prob.ntheta, prob.nz)
+    a = P.Plan.for_problem(prob, direct=1)
+    b = P.Plan.for_problem(prob, direct=0)
+    assert a.info()["direct_level"] >= 1, a.info()
+    pa, sa = a.solve(dev(rho), tol=tol)
+    pa = host(pa).copy()
+    pb, sb = b.solve(dev(rho), tol=tol)
+    assert sa["status"] == sb["status"] == P.OK, (sa, sb)
+    assert rel_l2(pa, ref) <= 1e-12, rel_l2(pa, ref)
+    assert rel_l2(host(pb), ref) <= 1e-12
+    assert sa["cycles"] <= sb["cycles"], (sa["cycles"], sb["cycles"])
+
+    def rate(st):
+        # mean contraction per cycle from the first formed norm to the last
+        h = [(i + 1, x) for i, x in enumerate(st["history"]) if x is not None]
+        (c0, r0), (c1, r1) = h[0], h[-1]
+        return (r1 / r0) ** (1.0 / (c1 - c0)) if c1 > c0 else 0.0
+
+    # a broken coarse solve would leave the V-cycle contracting by 0.5 or worse
+    assert rate(sa) < 0.1, sa["history"]
+
+
+def test_direct_level_choice(P):
+    """The exact solve takes the first level from 1 on with at most 128 interior
+    axial and 256 interior radial nodes; with option direct = 0 (the default)
+    the V-cycle goes down to the bottom kernel."""
+    info = P.Plan.for_problem(W.PAPER_SCALE).info()
+    assert info["direct_level"] == 2, info  # (400, 512) -> (201, 257) -> (101, 129)
+    shapes = info["level_shapes"]
+    assert shapes[2][1] - 2 <= 128 < shapes[1][1] - 2
+    info = P.Plan.for_problem(W.BATCHED).info()
+    assert info["direct_level"] == 1, info
+    plan = P.Plan.for_problem(W.BATCHED)
+    assert plan.get_option("direct") == 0  # off by default: measured slower at 400 x 128 x 512
+    on = P.Plan.for_problem(W.BATCHED, direct=1)
+    # the V-cycle stops at the direct level: fewer levels run fused passes
+    assert on.info()["fused_levels"] <= plan.info()["fused_levels"]
