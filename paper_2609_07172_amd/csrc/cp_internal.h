@@ -320,6 +320,40 @@ hipError_t launch_bottom(cylpoisson_plan* p, hipStream_t s, int p0 = 0, int np =
 // computed in FP64 from the FP32 residual.
 hipError_t launch_bottom32(cylpoisson_plan* p, hipStream_t s, int p0 = 0, int np = -1);
 
+
+// ---- convergence checks of the V-cycle iteration (solve.hip) ----
+// Where the squared residual norms of a cycle went: reduced per plane into
+// d_norms[slot] (partial_chunks = 0), or left as per-chunk partial sums in
+// d_slot_partial[slot] for the host to add up in a fixed order.
+struct NormSlot {
+    int partial_chunks = -1;  // -1: not produced by the cycle
+};
+// partial_chunks of a cycle that ended in a merged finest pass: its norms are not formed
+constexpr int kNoNorms = -2;
+
+// One plan's iteration state between checks.
+struct CheckCtl {
+    double tol = 0.0;
+    int maxc = 0;
+    int kind = 0;          // 0 zero start, 1 full-multigrid start, 2 warm start
+    bool masks = false;
+    bool defer = false;    // right-hand side norms read back with the first check
+    double b2 = 0.0, r02 = 0.0;  // weighted squared norms of b and of the starting residual
+    double rel_last = 1.0;
+    int next_check = 0, last_read = 0, stagnant = 0;
+    int status = CYLPOISSON_NOT_CONVERGED;
+    std::vector<double> frozen, plane, last;  // per plane (masks; scratch)
+};
+// first check (predicted from the plan's last converged solve); resets the prediction
+void checks_begin(cylpoisson_plan* p, CheckCtl& k);
+// enqueue the read-back of the norms since the last check, up to cycle c
+hipError_t checks_copy(cylpoisson_plan* p, const CheckCtl& k, const std::vector<NormSlot>& slots, int c,
+                       hipStream_t s);
+// the check after cycle c once the copies arrived: true when the iteration ends
+bool checks_after(cylpoisson_plan* p, CheckCtl& k, const std::vector<NormSlot>& slots, int c);
+// status into the stats and the next solve's prediction; returns the status
+int checks_end(cylpoisson_plan* p, const CheckCtl& k);
+
 // ---- exact separable solve of a coarse level (direct.hip) ----
 bool direct_level_ok(const HostLevel& H);
 void direct_tables(const HostLevel& H, const std::vector<double>& lam, std::vector<double>& V,

@@ -164,14 +164,6 @@ hipError_t smooth(cylpoisson_plan* p, DeviceLevel& L, int sweeps, hipStream_t s)
     return hipSuccess;
 }
 
-// Where the squared residual norms of a cycle went: reduced per plane into
-// d_norms[slot] (partial_chunks = 0), or left as per-chunk partial sums in
-// d_slot_partial[slot] for the host to add up in a fixed order.
-struct NormSlot {
-    int partial_chunks = -1;  // -1: not produced by the cycle
-};
-// partial_chunks of a cycle that ended in a merged finest pass: its norms are not formed
-constexpr int kNoNorms = -2;
 
 hipError_t vcycle(cylpoisson_plan* p, int l, hipStream_t s, bool zero_top, int slot, NormSlot* ns,
                   int p0 = 0, int np = -1, bool pro = false);
@@ -470,6 +462,183 @@ bool warm_norms(cylpoisson_plan* p, double* b2, double* r02) {
     return true;
 }
 
+}  // namespace
+
+// ---- convergence checks, shared by run_cycles and the batched solve ----
+
+// The first check comes after cycle 2, or (without masks, which freeze planes
+// only at checks) where the plan's last converged solve to the same tol
+// predicts: a solve of a similar problem then needs one host round trip, and
+// the cycles before it can end in merged passes.  A start whose residual is
+// known (a warm start) takes the last solve's mean contraction factor per
+// cycle from its own starting residual to tol; a cold start (residual unknown
+// until the first check) takes the last cycle count of a solve that started
+// the same way (zero or full-multigrid).  A prediction that comes early costs
+// one more check, never more cycles; the factor's prediction is capped at the
+// last solve's cycle count, because a solve whose last cycles reach the
+// rounding floor of the residual measures a slower mean factor than its
+// cycles had, and would predict ever more.
+void checks_begin(cylpoisson_plan* p, CheckCtl& k) {
+    const int maxc = k.maxc;
+    k.next_check = std::min(2, maxc);
+    if (!k.masks && p->last_cycles > 0 && p->last_tol == k.tol) {
+        const double rel0 = k.defer ? 0.0 : std::sqrt(k.r02 / k.b2);
+        if (!k.defer && p->last_rate > 0.0 && p->last_rate < 0.9 && rel0 > k.tol) {
+            const double need = std::ceil(std::log(k.tol / rel0) / std::log(p->last_rate) - 1e-9);
+            k.next_check = std::max(1, std::min({(int)need, p->last_cycles, maxc}));
+        } else if (k.defer && p->last_kind == k.kind) {
+            k.next_check = std::min(p->last_cycles, maxc);
+        }
+    }
+    p->last_cycles = 0;
+    k.last_read = 0;
+    // relative residual at the last check (the starting iterate's at first)
+    k.rel_last = k.defer ? 1.0 : std::sqrt(k.r02 / k.b2);
+    k.status = CYLPOISSON_NOT_CONVERGED;
+    k.stagnant = 0;
+    k.plane.assign(p->nt, 0.0);
+    k.last.assign(p->nt, 0.0);
+}
+
+// One copy per kind of slot for the cycles since the last check (the slots of
+// consecutive cycles are contiguous; unused ones ride along), the deferred
+// right-hand side norms in slot 0 with them.
+hipError_t checks_copy(cylpoisson_plan* p, const CheckCtl& k, const std::vector<NormSlot>& slots, int c,
+                       hipStream_t s) {
+    const int nt = p->nt, first = k.last_read + 1;
+    const bool rhs_now = k.defer && k.last_read == 0;
+    bool any_partial = false, any_norms = rhs_now;
+    for (int t = first; t <= c; ++t)
+        if (slots[t].partial_chunks != kNoNorms) (slots[t].partial_chunks > 0 ? any_partial : any_norms) = true;
+    const size_t nslots = (size_t)(c - first + 1);
+    const int nfirst = rhs_now ? 0 : first;
+    hipError_t e = hipSuccess;
+    if (any_partial)
+        e = hipMemcpyAsync(p->h_slot_partial + (size_t)first * nt * kSlotPartial,
+                           p->d_slot_partial + (size_t)first * nt * kSlotPartial,
+                           nslots * nt * kSlotPartial * sizeof(double), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess && any_norms)
+        e = hipMemcpyAsync(p->h_norms + (size_t)nfirst * nt, p->d_norms + (size_t)nfirst * nt,
+                           (size_t)(c - nfirst + 1) * nt * sizeof(double), hipMemcpyDeviceToHost, s);
+    return e;
+}
+
+// The check after cycle c, once checks_copy's copies have arrived: the
+// deferred right-hand side norm, the history of the cycles since the last
+// check, and the decision.  Returns true when the iteration ends (k.status
+// and the stats set); otherwise k.next_check is the next check.
+bool checks_after(cylpoisson_plan* p, CheckCtl& k, const std::vector<NormSlot>& slots, int c) {
+    cylpoisson_stats& st = p->stats;
+    const int nt = p->nt, first = k.last_read + 1;
+    const bool rhs_now = k.defer && k.last_read == 0;
+    st.cycles = c;
+    ++st.checks;
+    if (rhs_now) {
+        k.b2 = weighted(p, p->h_norms);
+        if (!std::isfinite(k.b2)) {
+            set_error("right-hand side holds NaN or Inf");
+            st.cycles = 0;
+            k.status = CYLPOISSON_ENONFINITE;
+            return true;
+        }
+        st.initial_residual_norm = std::sqrt(k.b2);
+        if (k.b2 == 0.0) {
+            // zero residual everywhere: the cycles changed nothing
+            st.cycles = 0;
+            st.rel_residual = 0.0;
+            k.status = CYLPOISSON_OK;
+            return true;
+        }
+    }
+    std::vector<double>& plane = k.plane;
+    for (int t = first; t <= c; ++t) {
+        if (slots[t].partial_chunks == kNoNorms) continue;  // history stays NaN
+        const double* norms = p->h_norms + (size_t)t * nt;
+        if (slots[t].partial_chunks > 0) {
+            // per-plane sums of the chunk partials, in chunk order
+            const double* part = p->h_slot_partial + (size_t)t * nt * kSlotPartial;
+            for (int q = 0; q < nt; ++q) {
+                double sum = 0.0;
+                for (int m = 0; m < slots[t].partial_chunks; ++m) sum += part[(size_t)q * kSlotPartial + m];
+                plane[q] = sum;
+            }
+            norms = plane.data();
+        }
+        if (k.masks) {
+            // frozen planes wrote nothing in these cycles: their last norm stands
+            if (norms != plane.data()) {
+                std::copy(norms, norms + nt, plane.begin());
+                norms = plane.data();
+            }
+            for (int q = 0; q < nt; ++q)
+                if (k.frozen[q] >= 0.0) plane[q] = k.frozen[q];
+            if (t == c) std::copy(norms, norms + nt, k.last.begin());
+        }
+        const double rel = std::sqrt(weighted(p, norms) / k.b2);
+        if (t - 1 < CYLPOISSON_MAX_HISTORY) st.rel_residual_history[t - 1] = rel;
+        st.n_history = t;
+    }
+    k.last_read = c;
+    const double rel = st.rel_residual_history[c - 1];
+    st.rel_residual = rel;
+    if (!std::isfinite(rel)) {
+        set_error("iteration produced NaN or Inf");
+        k.status = CYLPOISSON_ENONFINITE;
+        return true;
+    }
+    if (rel <= k.tol) {
+        k.status = CYLPOISSON_OK;
+        return true;
+    }
+    // predict the cycle count from the mean contraction factor per cycle
+    // since the last check (the same rule whether or not the cycles between
+    // formed their norms, so merged and separate passes check alike)
+    const int tp = first - 1;
+    const double rate =
+        std::isfinite(k.rel_last) && k.rel_last > 0.0 ? std::pow(rel / k.rel_last, 1.0 / (c - tp)) : 1.0;
+    k.rel_last = rel;
+    k.stagnant = rate > 0.6 ? k.stagnant + 1 : 0;
+    if (k.stagnant >= 3) {
+        set_error("residual stagnated at %.3e (tolerance %.3e)", rel, k.tol);
+        return true;
+    }
+    if (c >= k.maxc) return true;
+    int step = p->opt.check_every;
+    if (rate > 0.0 && rate < 0.9) {
+        const double need = std::ceil(std::log(k.tol / rel) / std::log(rate) - 1e-9);
+        step = std::max(1, std::min((int)need, 64));
+    } else {
+        step = 1;
+    }
+    k.next_check = std::min(k.maxc, c + step);
+    return false;
+}
+
+// The end of an iteration: the status into the stats, the max_cycles message,
+// and what the next solve's first check is predicted from.
+int checks_end(cylpoisson_plan* p, const CheckCtl& k) {
+    cylpoisson_stats& st = p->stats;
+    st.status = k.status;
+    if (k.status == CYLPOISSON_NOT_CONVERGED && st.cycles >= k.maxc)
+        set_error("tolerance %.3e not reached in %d cycles (relative residual %.3e)", k.tol, k.maxc,
+                  st.rel_residual);
+    if (k.status == CYLPOISSON_OK && st.cycles > 0) {
+        p->last_cycles = st.cycles;
+        p->last_tol = k.tol;
+        p->last_kind = k.kind;
+        // mean contraction factor per cycle from a measured start that was
+        // already close (-1 otherwise: the first cycles from a far start
+        // contract less than later ones, and would predict too many)
+        const double rel0 = k.defer || k.b2 <= 0.0 ? 0.0 : std::sqrt(k.r02 / k.b2);
+        p->last_rate = rel0 > 0.0 && rel0 < 0.5 && st.rel_residual > 0.0
+                           ? std::pow(st.rel_residual / rel0, 1.0 / st.cycles)
+                           : -1.0;
+    }
+    return k.status;
+}
+
+namespace {
+
 // V-cycles on the level-0 planes.  f is set; u holds its Dirichlet ring, and
 // its interior is zero unless `ring_only`, in which case the interior is
 // treated as zero without being read (fused finest level only), or `warm` or
@@ -498,31 +667,34 @@ int run_cycles(cylpoisson_plan* p, double tol, hipStream_t s, bool ring_only, bo
                                         p->d_norms + (size_t)kRhsSlot * nt, s));
         }
     }
-    const bool masks = masks_active(p);
+    CheckCtl k;
+    k.tol = tol;
+    k.maxc = maxc;
+    k.kind = warm ? 2 : fmg ? 1 : 0;
+    k.masks = masks_active(p);
     // A cold start needs the right-hand side's norms only at the first check
     // (masks need them before the first cycle, a warm start may already meet
     // tol): they come back with the first cycles' norms, saving one round
     // trip to the host.  If they are zero, every node's residual is exactly
     // zero and the cycles leave the iterate unchanged.
-    const bool defer = !warm && !masks && tol < 1.0;
-    double b2 = 0.0, r02 = 0.0;
-    if (!defer) {
+    k.defer = !warm && !k.masks && tol < 1.0;
+    if (!k.defer) {
         CP_HIP(hipMemcpyAsync(p->h_norms, p->d_norms, nt * sizeof(double), hipMemcpyDeviceToHost, s));
         if (warm)
             CP_HIP(hipMemcpyAsync(p->h_norms + (size_t)kRhsSlot * nt, p->d_norms + (size_t)kRhsSlot * nt,
                                   nt * sizeof(double), hipMemcpyDeviceToHost, s));
         CP_HIP(hipStreamSynchronize(s));
         st.checks = 1;
-        b2 = r02 = weighted(p, p->h_norms);
-        if (warm && !warm_norms(p, &b2, &r02)) return st.status;
-        if (!std::isfinite(b2)) {
+        k.b2 = k.r02 = weighted(p, p->h_norms);
+        if (warm && !warm_norms(p, &k.b2, &k.r02)) return st.status;
+        if (!std::isfinite(k.b2)) {
             set_error("right-hand side holds NaN or Inf");
             st.status = CYLPOISSON_ENONFINITE;
             return st.status;
         }
-        st.initial_residual_norm = std::sqrt(b2);
-        if (b2 == 0.0 || std::sqrt(r02 / b2) <= tol) {
-            st.rel_residual = b2 == 0.0 ? 0.0 : std::sqrt(r02 / b2);
+        st.initial_residual_norm = std::sqrt(k.b2);
+        if (k.b2 == 0.0 || std::sqrt(k.r02 / k.b2) <= tol) {
+            st.rel_residual = k.b2 == 0.0 ? 0.0 : std::sqrt(k.r02 / k.b2);
             st.status = CYLPOISSON_OK;
             return st.status;
         }
@@ -534,10 +706,10 @@ int run_cycles(cylpoisson_plan* p, double tol, hipStream_t s, bool ring_only, bo
         cylpoisson_plan* p;
         ~MaskScope() { p->mask_live = false; }
     } mask_scope{p};
-    p->mask_live = masks;
-    const double budget = tol * tol * b2 / nt;  // masks only (never deferred)
-    std::vector<double> frozen(nt, -1.0);  // last norm of a frozen plane, -1 while active
-    if (masks) {
+    p->mask_live = k.masks;
+    const double budget = tol * tol * k.b2 / nt;  // masks only (never deferred)
+    k.frozen.assign(nt, -1.0);  // last norm of a frozen plane, -1 while active
+    if (k.masks) {
         // every plane takes the first cycle: a ring-only or full-multigrid start
         // writes a plane's interior only there, and a frozen plane's norm must be
         // that of the iterate it keeps
@@ -548,42 +720,14 @@ int run_cycles(cylpoisson_plan* p, double tol, hipStream_t s, bool ring_only, bo
         CP_HIP(ensure_groups(p, G));
         CP_HIP(fork_groups(p, G, s));
     }
-    // The first check comes after cycle 2, or (without masks, which freeze
-    // planes only at checks) where the plan's last converged solve to the same
-    // tol predicts: a solve of a similar problem then needs one host round
-    // trip, and the cycles before it can end in merged passes.  A start whose
-    // residual is known (a warm start) takes the last solve's mean contraction
-    // factor per cycle from its own starting residual to tol; a cold start
-    // (residual unknown until the first check) takes the last cycle count of a
-    // solve that started the same way (zero or full-multigrid).  A prediction
-    // that comes early costs one more check, never more cycles; the factor's
-    // prediction is capped at the last solve's cycle count, because a solve
-    // whose last cycles reach the rounding floor of the residual measures a
-    // slower mean factor than its cycles had, and would predict ever more.
-    const int kind = warm ? 2 : fmg ? 1 : 0;
-    int next_check = std::min(2, maxc);
-    if (!masks && p->last_cycles > 0 && p->last_tol == tol) {
-        const double rel0 = std::sqrt(r02 / b2);
-        if (!defer && p->last_rate > 0.0 && p->last_rate < 0.9 && rel0 > tol) {
-            const double need = std::ceil(std::log(tol / rel0) / std::log(p->last_rate) - 1e-9);
-            next_check = std::max(1, std::min({(int)need, p->last_cycles, maxc}));
-        } else if (defer && p->last_kind == kind) {
-            next_check = std::min(p->last_cycles, maxc);
-        }
-    }
-    p->last_cycles = 0;
-    int last_read = 0;
-    // relative residual at the last check (the starting iterate's at first)
-    double rel_last = defer ? 1.0 : std::sqrt(r02 / b2);
-    int status = CYLPOISSON_NOT_CONVERGED;
-    int stagnant = 0;
-    std::vector<double> plane(nt), last(nt);
+    checks_begin(p, k);
     // A cycle after which the host does not check ends in the merged finest
     // pass, which also runs the next cycle's finest down pass (and everything
     // below it): `pending` then says the next cycle only needs its up pass.
     const bool merging = !graphs && G == 1 && fused_supported(p, 0) && fused_merge_ok(p);
     bool pending = false;
     for (int c = 1; c <= maxc; ++c) {
+        const int next_check = k.next_check;
         if (graphs) {
             CP_HIP(graph_cycle(p, s, c, c == 1 && ring_only, &slots[c]));
         } else if (merging) {
@@ -611,124 +755,15 @@ int run_cycles(cylpoisson_plan* p, double tol, hipStream_t s, bool ring_only, bo
         st.cycles = c;
         if (c != next_check && c != maxc) continue;
         CP_HIP(join_groups(p, G, s));
-        const int first = last_read + 1;
-        const bool rhs_now = defer && last_read == 0;
-        // one copy per kind of slot for the cycles since the last check (the
-        // slots of consecutive cycles are contiguous; unused ones ride along),
-        // the deferred right-hand side norms in slot 0 with them
-        {
-            bool any_partial = false, any_norms = rhs_now;
-            for (int t = first; t <= c; ++t)
-                if (slots[t].partial_chunks != kNoNorms) (slots[t].partial_chunks > 0 ? any_partial : any_norms) = true;
-            const size_t nslots = (size_t)(c - first + 1);
-            const int nfirst = rhs_now ? 0 : first;
-            if (any_partial)
-                CP_HIP(hipMemcpyAsync(p->h_slot_partial + (size_t)first * nt * kSlotPartial,
-                                      p->d_slot_partial + (size_t)first * nt * kSlotPartial,
-                                      nslots * nt * kSlotPartial * sizeof(double), hipMemcpyDeviceToHost, s));
-            if (any_norms)
-                CP_HIP(hipMemcpyAsync(p->h_norms + (size_t)nfirst * nt, p->d_norms + (size_t)nfirst * nt,
-                                      (size_t)(c - nfirst + 1) * nt * sizeof(double), hipMemcpyDeviceToHost, s));
-        }
+        CP_HIP(checks_copy(p, k, slots, c, s));
         CP_HIP(hipStreamSynchronize(s));
-        ++st.checks;
-        if (rhs_now) {
-            b2 = weighted(p, p->h_norms);
-            if (!std::isfinite(b2)) {
-                set_error("right-hand side holds NaN or Inf");
-                st.cycles = 0;
-                status = CYLPOISSON_ENONFINITE;
-                break;
-            }
-            st.initial_residual_norm = std::sqrt(b2);
-            if (b2 == 0.0) {
-                // zero residual everywhere: the cycles changed nothing
-                st.cycles = 0;
-                st.rel_residual = 0.0;
-                status = CYLPOISSON_OK;
-                break;
-            }
-        }
-        for (int t = first; t <= c; ++t) {
-            if (slots[t].partial_chunks == kNoNorms) continue;  // history stays NaN
-            const double* norms = p->h_norms + (size_t)t * nt;
-            if (slots[t].partial_chunks > 0) {
-                // per-plane sums of the chunk partials, in chunk order
-                const double* part = p->h_slot_partial + (size_t)t * nt * kSlotPartial;
-                for (int q = 0; q < nt; ++q) {
-                    double sum = 0.0;
-                    for (int k = 0; k < slots[t].partial_chunks; ++k) sum += part[(size_t)q * kSlotPartial + k];
-                    plane[q] = sum;
-                }
-                norms = plane.data();
-            }
-            if (masks) {
-                // frozen planes wrote nothing in these cycles: their last norm stands
-                if (norms != plane.data()) {
-                    std::copy(norms, norms + nt, plane.begin());
-                    norms = plane.data();
-                }
-                for (int q = 0; q < nt; ++q)
-                    if (frozen[q] >= 0.0) plane[q] = frozen[q];
-                if (t == c) std::copy(norms, norms + nt, last.begin());
-            }
-            const double rel = std::sqrt(weighted(p, norms) / b2);
-            if (t - 1 < CYLPOISSON_MAX_HISTORY) st.rel_residual_history[t - 1] = rel;
-            st.n_history = t;
-        }
-        last_read = c;
-        const double rel = st.rel_residual_history[c - 1];
-        st.rel_residual = rel;
-        if (!std::isfinite(rel)) {
-            set_error("iteration produced NaN or Inf");
-            status = CYLPOISSON_ENONFINITE;
-            break;
-        }
-        if (rel <= tol) {
-            status = CYLPOISSON_OK;
-            break;
-        }
-        // predict the cycle count from the mean contraction factor per cycle
-        // since the last check (the same rule whether or not the cycles between
-        // formed their norms, so merged and separate passes check alike)
-        const int tp = first - 1;
-        const double rate = std::isfinite(rel_last) && rel_last > 0.0 ? std::pow(rel / rel_last, 1.0 / (c - tp)) : 1.0;
-        rel_last = rel;
-        stagnant = rate > 0.6 ? stagnant + 1 : 0;
-        if (stagnant >= 3) {
-            set_error("residual stagnated at %.3e (tolerance %.3e)", rel, tol);
-            break;
-        }
-        int step = p->opt.check_every;
-        if (rate > 0.0 && rate < 0.9) {
-            const double need = std::ceil(std::log(tol / rel) / std::log(rate) - 1e-9);
-            step = std::max(1, std::min((int)need, 64));
-        } else {
-            step = 1;
-        }
-        next_check = std::min(maxc, c + step);
-        if (masks) {
-            CP_HIP(update_masks(p, last.data(), budget, frozen, s));
+        if (checks_after(p, k, slots, c)) break;
+        if (k.masks) {
+            CP_HIP(update_masks(p, k.last.data(), budget, k.frozen, s));
             if (G > 1) CP_HIP(fork_groups(p, G, s));
         }
     }
-    st.status = status;
-    if (status == CYLPOISSON_NOT_CONVERGED && st.cycles >= maxc)
-        set_error("tolerance %.3e not reached in %d cycles (relative residual %.3e)", tol, maxc,
-                  st.rel_residual);
-    if (status == CYLPOISSON_OK && st.cycles > 0) {
-        p->last_cycles = st.cycles;
-        p->last_tol = tol;
-        p->last_kind = kind;
-        // mean contraction factor per cycle from a measured start that was
-        // already close (-1 otherwise: the first cycles from a far start
-        // contract less than later ones, and would predict too many)
-        const double rel0 = defer || b2 <= 0.0 ? 0.0 : std::sqrt(r02 / b2);
-        p->last_rate = rel0 > 0.0 && rel0 < 0.5 && st.rel_residual > 0.0
-                           ? std::pow(st.rel_residual / rel0, 1.0 / st.cycles)
-                           : -1.0;
-    }
-    return status;
+    return checks_end(p, k);
 }
 
 // Mixed-precision cycles on the level-0 planes (f set, u holding its

@@ -211,6 +211,66 @@ def test_batch_of_uneven_problems_matches_each_oracle(P):
         np.testing.assert_array_equal(host(alone), host(phi))
 
 
+@pytest.mark.skip(reason="the shared-launch batch (one launch per pass over all problems) aborted the process in its first GPU run; the cause was not found and the path was taken out")
+@pytest.mark.parametrize("fmg", [0, 1])
+def test_lockstep_batch_is_bitwise_the_lone_solves(P, fmg):
+    """The batch's V-cycles run in shared launches (one per pass over all
+    problems; uneven widths, depths and bottom levels): every problem runs the
+    cycles it would alone, with the same node arithmetic, so its answer, cycle
+    count and checked residuals are those of its lone solve, and of the batch
+    on separate streams."""
+    probs = [W.SMALL.with_sizes(nr, nt, nz) for nr, nt, nz in
+             [(65, 32, 97), (33, 16, 33), (97, 8, 65), (40, 12, 71), (257, 8, 129), (17, 64, 129), (129, 3, 257)]]
+    rhos = [dev(W.blob_charge(q, seed=300 + i)) for i, q in enumerate(probs)]
+    say("lockstep batch, fmg", fmg)
+    lock = [P.Plan.for_problem(q, fmg=fmg, batch_lockstep=1) for q in probs]
+    streams = [P.Plan.for_problem(q, fmg=fmg, batch_lockstep=0) for q in probs]
+    alone = [P.Plan.for_problem(q, fmg=fmg) for q in probs]
+    for rep in range(2):  # the second batch checks first where the first one converged
+        a, sa = P.solve_plans(lock, rhos, tol=1e-14)
+        a = [host(x).copy() for x in a]
+        b, sb = P.solve_plans(streams, rhos, tol=1e-14)
+        # cells more than 2:1 coarsen one direction only and run some levels on
+        # per-step kernels: those problems run on streams of their own
+        assert sum(x["lockstep"] for x in sa) >= 4, [x["lockstep"] for x in sa]
+        assert not any(x["lockstep"] for x in sb)
+        for i, (plan, r) in enumerate(zip(alone, rhos)):
+            c, sc = plan.solve(r, tol=1e-14)
+            np.testing.assert_array_equal(a[i], host(c))
+            np.testing.assert_array_equal(a[i], host(b[i]))
+            assert sa[i]["status"] == sc["status"] == P.OK
+            assert sa[i]["cycles"] == sc["cycles"] == sb[i]["cycles"], (i, sa[i], sc)
+            assert histories_agree(sa[i]["history"], sc["history"])
+            ref = solvers.solve_separable(fv.Grid.of(probs[i]), W.blob_charge(probs[i], seed=300 + i),
+                                          probs[i].bc) if rep == 0 else None
+            if ref is not None:
+                assert rel_l2(a[i], ref) <= 1e-12
+
+
+@pytest.mark.skip(reason="the shared-launch batch (one launch per pass over all problems) aborted the process in its first GPU run; the cause was not found and the path was taken out")
+def test_lockstep_batch_with_a_zero_problem_and_a_cycle_limit(P):
+    """Problems that end at once (zero right-hand side, grounded boundary) or
+    at their cycle limit leave the shared launches while the others go on."""
+    import dataclasses
+    grounded = dataclasses.replace(W.SMALL.with_sizes(65, 8, 65), phi_zL=0.0)
+    probs = [W.BATCHED, grounded, W.SMALL.with_sizes(97, 4, 129)]
+    rhos = [dev(W.blob_charge(W.BATCHED, seed=7)), torch.zeros(grounded.shape, dtype=torch.float64, device="cuda"),
+            dev(W.blob_charge(probs[2], seed=8))]
+    plans = [P.Plan.for_problem(probs[0], batch_lockstep=1), P.Plan.for_problem(probs[1], batch_lockstep=1),
+             P.Plan.for_problem(probs[2], max_cycles=2, batch_lockstep=1)]
+    say("lockstep batch with a zero problem")
+    phis = [torch.full_like(r, 7.0) for r in rhos]
+    status, sts = P.solve_batch([p.handle for p in plans], rhos, phis, tol=1e-13, allow=(P.OK, P.NOT_CONVERGED))
+    assert status == P.NOT_CONVERGED and sts == [P.OK, P.OK, P.NOT_CONVERGED], sts
+    assert all(p.stats()["lockstep"] == 1 for p in plans)
+    assert plans[1].stats()["cycles"] == 0 and plans[2].stats()["cycles"] == 2
+    assert float(phis[1].abs().max()) == 0.0
+    ref = solvers.solve_separable(fv.Grid.of(W.BATCHED), W.blob_charge(W.BATCHED, seed=7), W.BATCHED.bc)
+    assert rel_l2(host(phis[0]), ref) <= 1e-12
+    alone, _ = P.Plan.for_problem(probs[2], max_cycles=2).solve(rhos[2], tol=1e-13, allow=(P.OK, P.NOT_CONVERGED))
+    np.testing.assert_array_equal(host(alone), host(phis[2]))
+
+
 def test_batch_reports_each_status(P):
     p = W.SMALL
     rho = dev(W.blob_charge(p, seed=1))
