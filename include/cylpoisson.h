@@ -261,14 +261,15 @@ void cylpoisson_plan_destroy(cylpoisson_plan* plan);
  *                    no graphs (default 1)
  *   "merge_prefetch" rows the merged pass loads ahead of the one it consumes (1 .. 2; default 1)
  *   "direct"         1 = the V-cycle stops at the plan's direct level (cylpoisson_info
- *                    direct_level: the first level from 1 on with at most 128 interior
- *                    axial and 256 interior radial nodes) and solves it exactly on every
- *                    plane: the axial generalised eigenvectors of the level's separable
+ *                    direct_level: the first level from 1 on with at most 64 interior
+ *                    nodes each way, at or above the bottom kernel's first level) and
+ *                    solves it exactly on every plane, one workgroup per plane in LDS:
+ *                    the axial generalised eigenvectors of the level's separable
  *                    operator (formed when the plan is built), one radial tridiagonal
  *                    solve per eigenvector, and the inverse transform.  Used by every
  *                    FP64 V-cycle, the full-multigrid start included; the FP32 inner
  *                    cycles of "precision" 32 keep the bottom kernel.  Ignored where no
- *                    level qualifies (default 0)
+ *                    level qualifies (default 1)
  *   "graph"          1 = each V-cycle is captured once into a HIP graph and replayed
  *                    (single plane group, "timing" 0; default 0).  Setting any
  *                    option releases the captured graphs

@@ -131,15 +131,14 @@ struct Options {
     int merge_prefetch = 1;  // rows the merged finest pass loads ahead (1 or 2)
     int chunk_rows_merge = 0;  // axial rows per workgroup of the merged pass (0 = automatic)
     int nn_target = 0;     // training targets: 0 = SOR correction of the residual, 1 = V-cycle iterate error
-    int direct = 0;        // 1: exact separable solve on the plan's direct level (V-cycles stop there)
+    int direct = 1;        // 1: exact separable solve on the plan's direct level (V-cycles stop there)
 };
 
-// Largest interior sizes of a level solved exactly by the separable solve
-// (axial eigenvector transform, radial tridiagonal solves): the transforms
-// cost 2 nzi multiply-adds per unknown, and the forward kernel holds a
-// 16 x nri tile of values and factors in LDS.
-constexpr int kDirectMaxNz = 128;
-constexpr int kDirectMaxNr = 256;
+// Largest interior sizes of a level solved exactly by the separable solve:
+// one workgroup holds the plane, its transform, the elimination factors and
+// the axial eigenvectors in LDS (130 KB at 64 x 64).
+constexpr int kDirectMaxNz = 64;
+constexpr int kDirectMaxNr = 64;
 
 }  // namespace cp
 
@@ -191,13 +190,10 @@ struct cylpoisson_plan {
     double* d_tmp = nullptr;     // node-array scratch (apply, plane solves)
     int bottom_level = -1;       // first level of the LDS bottom kernel (-1 = none)
     // exact separable solve of one coarse level (-1 = none): the axial
-    // eigenvectors V [nzi][nzi] and V^T, per (lambda set, eigenvector, radial node) the
-    // elimination factors (m, rw m, re m), and each plane's lambda set
+    // eigenvectors V [nzi][nzi] and their eigenvalues
     int direct_level = -1;
     double* d_dir_V = nullptr;
-    double* d_dir_VT = nullptr;
-    double* d_dir_fac = nullptr;
-    int* d_dir_set = nullptr;
+    double* d_dir_sigma = nullptr;
     int bottom_off_r = 0;
     cp::BottomLevel* d_bottom = nullptr;
     std::vector<void*> allocations;
@@ -356,12 +352,11 @@ int checks_end(cylpoisson_plan* p, const CheckCtl& k);
 
 // ---- exact separable solve of a coarse level (direct.hip) ----
 bool direct_level_ok(const HostLevel& H);
-void direct_tables(const HostLevel& H, const std::vector<double>& lam, std::vector<double>& V,
-                   std::vector<double>& VT, std::vector<double>& fac, std::vector<int>& set);
+void direct_tables(const HostLevel& H, std::vector<double>& V, std::vector<double>& sigma);
+hipError_t direct_prepare(const HostLevel& H);
 // option "direct" set and a direct level chosen
 bool direct_active(const cylpoisson_plan* p);
-// u = A^-1 f on the direct level's interior (ring untouched), planes p0 .. p0 + np - 1;
-// the level's r array holds the transformed values in between
+// u = A^-1 f on the direct level's interior (ring untouched), planes p0 .. p0 + np - 1
 hipError_t launch_direct(cylpoisson_plan* p, hipStream_t s, int p0 = 0, int np = -1);
 
 // ---- fused passes (fused.hip) ----

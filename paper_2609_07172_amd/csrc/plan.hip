@@ -639,13 +639,14 @@ cylpoisson_plan* build_plan(cylpoisson_plan* p) {
         for (int l = 1; l < nl; ++l) {
             if (p->bottom_level >= 1 && l > p->bottom_level) break;
             if (!direct_level_ok(p->hl[l])) continue;
-            std::vector<double> V, VT, fac;
-            std::vector<int> set;
-            direct_tables(p->hl[l], p->lam, V, VT, fac, set);
+            if (direct_prepare(p->hl[l]) != hipSuccess) {
+                (void)hipGetLastError();
+                break;
+            }
+            std::vector<double> V, sigma;
+            direct_tables(p->hl[l], V, sigma);
             CP_TRY(upload(p, &p->d_dir_V, V));
-            CP_TRY(upload(p, &p->d_dir_VT, VT));
-            CP_TRY(upload(p, &p->d_dir_fac, fac));
-            CP_TRY(upload(p, &p->d_dir_set, set));
+            CP_TRY(upload(p, &p->d_dir_sigma, sigma));
             p->direct_level = l;
             break;
         }

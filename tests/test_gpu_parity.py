@@ -556,11 +556,14 @@ def test_direct_coarse_solve_matches_oracle(P, prob, tol):
     say("direct", prob.nr, prob.ntheta, prob.nz)
     a = P.Plan.for_problem(prob, direct=1)
     b = P.Plan.for_problem(prob, direct=0)
-    assert a.info()["direct_level"] >= 1, a.info()
     pa, sa = a.solve(dev(rho), tol=tol)
     pa = host(pa).copy()
     pb, sb = b.solve(dev(rho), tol=tol)
     assert sa["status"] == sb["status"] == P.OK, (sa, sb)
+    if a.info()["direct_level"] < 1:
+        # no level small enough at or above the bottom kernel's: the option is ignored
+        np.testing.assert_array_equal(pa, host(pb))
+        return
     assert rel_l2(pa, ref) <= 1e-12, rel_l2(pa, ref)
     assert rel_l2(host(pb), ref) <= 1e-12
     assert sa["cycles"] <= sb["cycles"], (sa["cycles"], sb["cycles"])
@@ -576,17 +579,17 @@ def test_direct_coarse_solve_matches_oracle(P, prob, tol):
 
 
 def test_direct_level_choice(P):
-    """The exact solve takes the first level from 1 on with at most 128 interior
-    axial and 256 interior radial nodes; with option direct = 0 (the default)
-    the V-cycle goes down to the bottom kernel."""
+    """The exact solve takes the first level from 1 on with at most 64 interior
+    nodes each way (one workgroup's LDS holds the plane and its transforms);
+    with option direct = 0 the V-cycle goes down to the bottom kernel."""
     info = P.Plan.for_problem(W.PAPER_SCALE).info()
-    assert info["direct_level"] == 2, info  # (400, 512) -> (201, 257) -> (101, 129)
+    assert info["direct_level"] == 3, info  # (400, 512) -> (201, 257) -> (101, 129) -> (51, 65)
     shapes = info["level_shapes"]
-    assert shapes[2][1] - 2 <= 128 < shapes[1][1] - 2
+    assert shapes[3][1] - 2 <= 64 < shapes[2][1] - 2 and shapes[3][0] - 2 <= 64
     info = P.Plan.for_problem(W.BATCHED).info()
     assert info["direct_level"] == 1, info
-    plan = P.Plan.for_problem(W.BATCHED)
-    assert plan.get_option("direct") == 0  # off by default: measured slower at 400 x 128 x 512
-    on = P.Plan.for_problem(W.BATCHED, direct=1)
-    # the V-cycle stops at the direct level: fewer levels run fused passes
+    plan = P.Plan.for_problem(W.BATCHED, direct=0)
+    on = P.Plan.for_problem(W.BATCHED)
+    assert on.get_option("direct") == 1  # on by default
+    # the V-cycle stops at the direct level: no more levels run fused passes
     assert on.info()["fused_levels"] <= plan.info()["fused_levels"]
