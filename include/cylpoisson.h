@@ -130,7 +130,7 @@ typedef struct {
     int layout;         /* CYLPOISSON_VERTEX or CYLPOISSON_CELL */
     int uniform;        /* 1 = built by cylpoisson_plan_create (uniform vertex-centred mesh) */
     int direct_level;   /* level solved exactly by the separable solve, where the V-cycle
-                         * stops under option "direct" = 1; -1 if none */
+                         * stops under the current option "direct"; -1 if none or off */
 } cylpoisson_info;
 
 /* Create a plan for an Nr x Ntheta x Nz grid.  Requires Nr >= 3, Nz >= 3,
@@ -260,16 +260,21 @@ void cylpoisson_plan_destroy(cylpoisson_plan* plan);
  *                    nu1 = nu2 = 2, at most 512 radial nodes, one plane group and
  *                    no graphs (default 1)
  *   "merge_prefetch" rows the merged pass loads ahead of the one it consumes (1 .. 2; default 1)
- *   "direct"         1 = the V-cycle stops at the plan's direct level (cylpoisson_info
- *                    direct_level: the first level from 1 on with at most 64 interior
- *                    nodes each way, at or above the bottom kernel's first level) and
- *                    solves it exactly on every plane, one workgroup per plane in LDS:
- *                    the axial generalised eigenvectors of the level's separable
- *                    operator (formed when the plan is built), one radial tridiagonal
- *                    solve per eigenvector, and the inverse transform.  Used by every
- *                    FP64 V-cycle, the full-multigrid start included; the FP32 inner
- *                    cycles of "precision" 32 keep the bottom kernel.  Ignored where no
- *                    level qualifies (default 1)
+ *   "direct"         exact solve of a coarse level (Sec. 3.3 solves the coarsest one
+ *                    directly): the V-cycle stops at that level and solves it on every
+ *                    plane with the axial generalised eigenvectors of the level's
+ *                    separable operator (formed when the plan is built), one radial
+ *                    tridiagonal solve per eigenvector, and the inverse transform.
+ *                    1 = the first level from 1 on, at or above the bottom kernel's
+ *                    first level, with at most 128 interior nodes each way; a level
+ *                    above 64 nodes in either direction runs two kernels with FP64
+ *                    matrix-core transforms and two workgroups per plane, using the
+ *                    level's residual array as scratch.  2 = the first such level with
+ *                    at most 64 each way, one workgroup per plane with everything in
+ *                    LDS.  0 = off: the V-cycle goes down to the bottom kernel.  Used
+ *                    by every FP64 V-cycle, the full-multigrid start included; the
+ *                    FP32 inner cycles of "precision" 32 keep the bottom kernel.
+ *                    Ignored where no level qualifies (0 .. 2; default 1)
  *   "graph"          1 = each V-cycle is captured once into a HIP graph and replayed
  *                    (single plane group, "timing" 0; default 0).  Setting any
  *                    option releases the captured graphs

@@ -131,14 +131,31 @@ struct Options {
     int merge_prefetch = 1;  // rows the merged finest pass loads ahead (1 or 2)
     int chunk_rows_merge = 0;  // axial rows per workgroup of the merged pass (0 = automatic)
     int nn_target = 0;     // training targets: 0 = SOR correction of the residual, 1 = V-cycle iterate error
-    int direct = 1;        // 1: exact separable solve on the plan's direct level (V-cycles stop there)
+    int direct = 1;        // exact separable solve of a coarse level, where the V-cycles stop:
+                           // 0 off; 1 the first level with <= 128 interior nodes each way;
+                           // 2 the first with <= 64 each way (one workgroup per plane)
 };
 
-// Largest interior sizes of a level solved exactly by the separable solve:
-// one workgroup holds the plane, its transform, the elimination factors and
-// the axial eigenvectors in LDS (130 KB at 64 x 64).
+// Largest interior sizes of a level solved exactly by the separable solve
+// in one workgroup per plane: it holds the plane, its transform, the
+// elimination factors and the axial eigenvectors in LDS (130 KB at 64 x 64).
 constexpr int kDirectMaxNz = 64;
 constexpr int kDirectMaxNr = 64;
+// Largest interior size each way of the two-kernel form (FP64 matrix-core
+// products; two workgroups per plane, each with half the eigenvectors).
+constexpr int kDirectBigMax = 128;
+
+// One level chosen for the exact separable solve, with its axial eigenvector
+// tables on the device.
+struct DirectLevel {
+    int level = -1;           // -1: none
+    bool big = false;         // a side above 64 interior nodes: the two-kernel form
+    double* V = nullptr;      // one workgroup per plane: V [nzi][nzi]; two-kernel form: [128][128], zero padded
+    double* VT = nullptr;     // two-kernel form: V^T [128][128], zero padded
+    double* M = nullptr;      // two-kernel form: per plane [128][128] elimination factors,
+                              // M[i * 128 + j] = m_i of eigenvector j, zero padded
+    double* sigma = nullptr;  // [nzi] axial eigenvalues
+};
 
 }  // namespace cp
 
@@ -189,11 +206,9 @@ struct cylpoisson_plan {
     double* h_norms = nullptr;   // pinned host copy
     double* d_tmp = nullptr;     // node-array scratch (apply, plane solves)
     int bottom_level = -1;       // first level of the LDS bottom kernel (-1 = none)
-    // exact separable solve of one coarse level (-1 = none): the axial
-    // eigenvectors V [nzi][nzi] and their eigenvalues
-    int direct_level = -1;
-    double* d_dir_V = nullptr;
-    double* d_dir_sigma = nullptr;
+    // exact separable solve of a coarse level: [0] the level option direct = 1
+    // takes, [1] the level direct = 2 takes (the same one when it is small enough)
+    cp::DirectLevel dir[2];
     int bottom_off_r = 0;
     cp::BottomLevel* d_bottom = nullptr;
     std::vector<void*> allocations;
@@ -351,10 +366,14 @@ bool checks_after(cylpoisson_plan* p, CheckCtl& k, const std::vector<NormSlot>& 
 int checks_end(cylpoisson_plan* p, const CheckCtl& k);
 
 // ---- exact separable solve of a coarse level (direct.hip) ----
-bool direct_level_ok(const HostLevel& H);
+// a level the solve can take with at most `max_nodes` interior nodes each way
+bool direct_level_ok(const HostLevel& H, int max_nodes);
+// the level's tables: V [nzi][nzi] row-major, eigenvalues [nzi]
 void direct_tables(const HostLevel& H, std::vector<double>& V, std::vector<double>& sigma);
-hipError_t direct_prepare(const HostLevel& H);
-// option "direct" set and a direct level chosen
+// the kernels' LDS limits for a level of this size (once, when a plan is built)
+hipError_t direct_prepare(const HostLevel& H, bool big);
+// the level the option "direct" selects (-1 when off or none)
+int direct_level(const cylpoisson_plan* p);
 bool direct_active(const cylpoisson_plan* p);
 // u = A^-1 f on the direct level's interior (ring untouched), planes p0 .. p0 + np - 1
 hipError_t launch_direct(cylpoisson_plan* p, hipStream_t s, int p0 = 0, int np = -1);

@@ -13,12 +13,15 @@
 // host when the plan is built), A_p u = f becomes, for each axial eigenvector
 // j, one tridiagonal system along r:
 //   (T_r(lambda_p) + sigma_j R_b) w_j = (V^T f)_j,   u = V w.
-// Each plane is solved exactly (up to rounding) by one workgroup with the
-// whole plane, V and the tables in LDS (k_direct): the axial transform, one
-// elimination per eigenvector (its factors formed as it goes), and the
-// inverse transform written to the level's interior.  The coarse correction
-// of a V-cycle has a zero Dirichlet ring, so only interior values enter and
-// only interior values are written.
+// Up to 64 interior nodes each way, each plane is solved exactly (up to
+// rounding) by one workgroup with the whole plane, V and the tables in LDS
+// (k_direct): the axial transform, one elimination per eigenvector (its
+// factors formed as it goes), and the inverse transform written to the
+// level's interior.  Up to 128 each way, two kernels with FP64 matrix-core
+// products and two workgroups per plane do the same (k_direct_fwd,
+// k_direct_inv; see below).  The coarse correction of a V-cycle has a zero
+// Dirichlet ring, so only interior values enter and only interior values are
+// written.
 
 #include "cp_internal.h"
 
@@ -190,6 +193,281 @@ __global__ __launch_bounds__(kDirThreads) void k_direct(DirectArgs a) {
     }
 }
 
+// ---- two-kernel form: up to 128 interior nodes each way ----
+//
+// Both transforms are dense contractions over 128-point axes, done on the
+// FP64 matrix cores (v_mfma_f64_16x16x4f64: D += A B with A 16 x 4, B 4 x 16;
+// lane l holds A[l % 16][l / 16], B[l / 16][l % 16] and D[l / 16 + 4q][l % 16],
+// q < 4; checked on the device).  Workgroup (h, plane) owns eigenvectors 64h .. 64h + 63 in the first
+// kernel and axial rows 64h .. 64h + 63 in the second, so 128 planes fill 256
+// compute units; wave w owns radial columns 16w .. 16w + 15, whose values it
+// keeps in registers for every k-step, while the eigenvector half sits in LDS.
+//   k_direct_fwd: g = V^T f for its eigenvectors, then one more wave
+//     eliminates and back-substitutes each eigenvector's system with the
+//     elimination factors m_i formed when the plan is built (per plane and
+//     eigenvector: the factor chain is a division per step, and on the FP64
+//     pipe the matrix products share it would run after them, not beside
+//     them), and the workgroup writes w [nzi][nri] to the level's r array
+//     (free at the level where the V-cycle stops).
+//   k_direct_inv: u = V w for its rows, into the level's interior.
+// Padded rows and columns of V (beyond nzi) are zero, and so are the
+// operands loaded beyond the level, so the padding adds nothing.
+
+typedef double dbl4 __attribute__((ext_vector_type(4)));
+
+constexpr int kBigHalf = 64;                                  // eigenvectors / rows per workgroup
+constexpr int kBigSteps = kDirectBigMax / 4;                  // k-steps of one product
+constexpr int kBigWaves = kDirectBigMax / 16;                 // product waves (16 radial columns each)
+constexpr int kBigFwdThreads = (kBigWaves + 1) * 64;          // + the elimination wave
+constexpr int kBigInvThreads = kBigWaves * 64;
+constexpr int kBigLdg = kDirectBigMax + 1;                    // LDS pitch of g's rows (odd)
+constexpr int kBigV = kDirectBigMax * kBigHalf;               // one half of V (or V^T) in LDS
+constexpr int kBigVG = kBigV > kBigHalf * kBigLdg ? kBigV : kBigHalf * kBigLdg;
+constexpr int kBigFwdLds = kBigVG + kDirectBigMax * kBigHalf + 2 * kDirectBigMax;
+constexpr int kBigInvLds = kBigV;
+constexpr int kBigChain = 8;                                  // chain steps per block of LDS loads
+
+struct BigArgs {
+    LevelView v;
+    const double* f;      // right-hand side (the level's f)
+    double* u;            // answer (the level's u; its ring stays zero)
+    double* w;            // the level's r array: per plane w [nzi][nri] between the kernels
+    const double* V;      // [128][128], V[k * 128 + j], zero padded
+    const double* VT;     // [128][128], VT[j * 128 + k], zero padded
+    const double* M;      // per plane [128][128]: M[i * 128 + j] = m_i of eigenvector j, zero padded
+    const int* mask;      // per plane: 0 = frozen, or nullptr
+    int p0, np;           // planes p0 .. p0 + np - 1
+};
+
+// Halves of padded 128 x 128 tables, dst[q] = src[(q / 64) * 128 + col0 + q % 64]
+// for q < lim (lim <= 128 * 64: whole rows of the half), in two steps so that
+// other loads can be issued between them: the loads into registers, then the
+// stores to LDS.  Indices past lim are clamped to its last element, which
+// those threads then store again with its own value, so no store needs a branch.
+template <int T, int NT>
+struct HalfStage {
+    static constexpr int N = (kBigV + T - 1) / T;
+    double x[NT][N];
+    __device__ __forceinline__ void load(const double* const (&src)[NT], const int (&lim)[NT], int col0, int t) {
+#pragma unroll
+        for (int u = 0; u < N; ++u)
+#pragma unroll
+            for (int b = 0; b < NT; ++b) {
+                const int q = min(u * T + t, lim[b] - 1);
+                x[b][u] = src[b][(q >> 6) * kDirectBigMax + col0 + (q & 63)];
+            }
+    }
+    __device__ __forceinline__ void store(double* const (&dst)[NT], const int (&lim)[NT], int t) const {
+#pragma unroll
+        for (int u = 0; u < N; ++u)
+#pragma unroll
+            for (int b = 0; b < NT; ++b) dst[b][min(u * T + t, lim[b] - 1)] = x[b][u];
+    }
+};
+
+// Workgroup -> (half, plane) of the two-kernel form.  With two halves, the
+// halves of one plane are 8 workgroups apart: workgroups are dealt to the 8
+// XCDs in turn, so both run on one XCD and the second finds the plane's input
+// in that XCD's L2.  False for the padding workgroups of the last group.
+__device__ __forceinline__ bool big_block(int halves, int np, int* h, int* p) {
+    const int id = blockIdx.x;
+    if (halves == 1) {
+        *h = 0;
+        *p = id;
+    } else {
+        *h = (id >> 3) & 1;
+        *p = (id >> 4) * 8 + (id & 7);
+    }
+    return *p < np;
+}
+__host__ inline int big_blocks(int halves, int np) { return halves == 1 ? np : 16 * ((np + 7) / 8); }
+
+// Transform and eliminations.  Waves 0 .. ceil(nri / 16) - 1 form g = V^T f
+// for their radial columns; then wave kBigWaves runs the eliminations,
+//   d_i = m_i g_i + (rw_i m_i) d_{i-1},  w_i = d_i + (re_i m_i) w_{i+1}
+// (one fused multiply-add per step on each chain), loading its operands from
+// LDS kBigChain steps at a time (each step otherwise waits for its loads).
+// Factor rows past nri are zero, so the steps past the last node give zeros
+// that are never read.
+__global__ __launch_bounds__(kBigFwdThreads) void k_direct_fwd(BigArgs a) {
+    extern __shared__ double smem[];
+    const LevelView v = a.v;
+    const int nzi = v.nz - 2, nri = v.nr - 2;
+    int h, pl;
+    if (!big_block((nzi + kBigHalf - 1) / kBigHalf, a.np, &h, &pl)) return;  // whole workgroup
+    const int plane = a.p0 + pl;
+    if (a.mask && a.mask[plane] == 0) return;  // whole workgroup, before any barrier
+    const int nrt = (nri + 15) / 16;
+    const int t = threadIdx.x, wave = t >> 6, l = t & 63;
+    const int j0 = h * kBigHalf, nj = min(kBigHalf, nzi - j0);
+    const int ks = (nzi + 3) / 4;
+    double* VG = smem;  // V's half [k][64], later g [64][kBigLdg]
+    double* M = VG + kBigVG;  // factors [i][64]
+    double* rw = M + kDirectBigMax * kBigHalf;
+    double* re = rw + kDirectBigMax;
+    // V's half whole (the products read rows up to 4 ceil(nzi / 4) - 1); the
+    // factors' rows the eliminations' blocks reach (rows past nri are zero)
+    HalfStage<kBigFwdThreads, 2> stage;
+    const int lim[2] = {kBigV, min(kDirectBigMax, (nri + kBigChain - 1) / kBigChain * kBigChain) * kBigHalf};
+    {
+        const double* const src[2] = {a.V, a.M + (size_t)plane * kDirectBigMax * kDirectBigMax};
+        stage.load(src, lim, j0, t);
+    }
+    // this wave's columns of f (the products' B operands); values outside the
+    // level are zero (exec-masked loads into zeroed registers)
+    double fb[kBigSteps];
+    {
+        const double* f = a.f + (size_t)plane * v.pstride + v.pitch + 1;  // interior (0, 0)
+        const int r = 16 * wave + (l & 15);
+        const bool col = wave < nrt && r < nri;
+#pragma unroll
+        for (int s = 0; s < kBigSteps; ++s) {
+            const int k = 4 * s + (l >> 4);
+            fb[s] = col && k < nzi ? f[k * v.pitch + r] : 0.0;
+        }
+    }
+    if (t < kDirectBigMax) {
+        const bool in = t < nri;
+        rw[t] = in ? v.rw[t + 1] : 0.0;
+        re[t] = in ? v.re[t + 1] : 0.0;
+    }
+    {
+        double* const dst[2] = {VG, M};
+        stage.store(dst, lim, t);
+    }
+    __syncthreads();
+    dbl4 acc[4];
+    if (wave < nrt) {
+        // g[j][r] = sum_k V[k][j0 + j] f[k][r] for this wave's 16 columns, 4 tiles of 16 eigenvectors
+#pragma unroll
+        for (int jt = 0; jt < 4; ++jt) acc[jt] = dbl4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int s = 0; s < kBigSteps; ++s) {
+            if (s < ks) {
+                const double* vrow = VG + (4 * s + (l >> 4)) * kBigHalf + (l & 15);
+#pragma unroll
+                for (int jt = 0; jt < 4; ++jt)
+                    acc[jt] = __builtin_amdgcn_mfma_f64_16x16x4f64(vrow[16 * jt], fb[s], acc[jt], 0, 0, 0);
+            }
+        }
+    }
+    __syncthreads();  // every wave's reads of V are done before g overwrites it
+    if (wave < nrt) {
+#pragma unroll
+        for (int jt = 0; jt < 4; ++jt)
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+                VG[(16 * jt + (l >> 4) + 4 * q) * kBigLdg + 16 * wave + (l & 15)] = acc[jt][q];
+    }
+    __syncthreads();
+    if (wave == kBigWaves && l < nj) {
+        double* g = VG + l * kBigLdg;
+        double d = 0.0;
+        for (int i0 = 0; i0 < nri; i0 += kBigChain) {
+            double gv[kBigChain], qv[kBigChain];
+#pragma unroll
+            for (int u = 0; u < kBigChain; ++u) {
+                const double m = M[(i0 + u) * kBigHalf + l];
+                gv[u] = g[i0 + u] * m;
+                qv[u] = rw[i0 + u] * m;
+            }
+#pragma unroll
+            for (int u = 0; u < kBigChain; ++u) {
+                d = fma(qv[u], d, gv[u]);
+                gv[u] = d;
+            }
+#pragma unroll
+            for (int u = 0; u < kBigChain; ++u) g[i0 + u] = gv[u];
+        }
+        double w = 0.0;
+        for (int top = nri - 1; top >= 0; top -= kBigChain) {
+            double gv[kBigChain], cv[kBigChain];
+#pragma unroll
+            for (int u = 0; u < kBigChain; ++u) {
+                const int i = max(top - u, 0);
+                gv[u] = g[i];
+                cv[u] = re[i] * M[i * kBigHalf + l];
+            }
+#pragma unroll
+            for (int u = 0; u < kBigChain; ++u) {
+                w = fma(cv[u], w, gv[u]);
+                gv[u] = w;
+            }
+#pragma unroll
+            for (int u = 0; u < kBigChain; ++u)
+                if (top - u >= 0) g[top - u] = gv[u];
+        }
+    }
+    __syncthreads();
+    double* wout = a.w + (size_t)plane * v.pstride + (size_t)j0 * nri;
+    for (int q = t; q < nj * nri; q += kBigFwdThreads) {
+        const int j = q / nri, i = q - j * nri;
+        wout[q] = VG[j * kBigLdg + i];
+    }
+}
+
+// Inverse transform: waves 0 .. ceil(nri / 16) - 1 form u = V w for their
+// radial columns and this workgroup's 64 axial rows.
+__global__ __launch_bounds__(kBigInvThreads) void k_direct_inv(BigArgs a) {
+    extern __shared__ double smem[];
+    const LevelView v = a.v;
+    const int nzi = v.nz - 2, nri = v.nr - 2;
+    int h, pl;
+    if (!big_block((nzi + kBigHalf - 1) / kBigHalf, a.np, &h, &pl)) return;  // whole workgroup
+    const int plane = a.p0 + pl;
+    if (a.mask && a.mask[plane] == 0) return;
+    const int nrt = (nri + 15) / 16;
+    const int t = threadIdx.x, wave = t >> 6, l = t & 63;
+    const int k0 = h * kBigHalf, ks = (nzi + 3) / 4;
+    const int r = 16 * wave + (l & 15);
+    HalfStage<kBigInvThreads, 1> stage;
+    const int lim[1] = {kBigV};
+    {
+        const double* const src[1] = {a.VT};  // V^T's half [j][64]
+        stage.load(src, lim, k0, t);
+    }
+    // this wave's columns of w (the product's B operands)
+    double wb[kBigSteps];
+    {
+        const double* w = a.w + (size_t)plane * v.pstride;
+        const bool col = wave < nrt && r < nri;
+#pragma unroll
+        for (int s = 0; s < kBigSteps; ++s) {
+            const int j = 4 * s + (l >> 4);
+            wb[s] = col && j < nzi ? w[j * nri + r] : 0.0;
+        }
+    }
+    {
+        double* const dst[1] = {smem};
+        stage.store(dst, lim, t);
+    }
+    __syncthreads();
+    if (wave >= nrt) return;  // after the only barrier
+    // u[k0 + k][r] = sum_j V[k0 + k][j] w[j][r], 4 tiles of 16 rows
+    dbl4 acc[4];
+#pragma unroll
+    for (int kt = 0; kt < 4; ++kt) acc[kt] = dbl4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int s = 0; s < kBigSteps; ++s) {
+        if (s < ks) {
+            const double* vrow = smem + (4 * s + (l >> 4)) * kBigHalf + (l & 15);
+#pragma unroll
+            for (int kt = 0; kt < 4; ++kt)
+                acc[kt] = __builtin_amdgcn_mfma_f64_16x16x4f64(vrow[16 * kt], wb[s], acc[kt], 0, 0, 0);
+        }
+    }
+    double* u = a.u + (size_t)plane * v.pstride + v.pitch + 1;
+    if (r < nri) {
+#pragma unroll
+        for (int kt = 0; kt < 4; ++kt)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int k = k0 + 16 * kt + (l >> 4) + 4 * q;
+                if (k < nzi) u[(size_t)k * v.pitch + r] = acc[kt][q];
+            }
+    }
+}
+
 // Eigenvalues and orthonormal eigenvectors of the symmetric n x n matrix S
 // (row-major, overwritten) by cyclic Jacobi rotations: Q[k * n + j] is
 // component k of eigenvector j, sig[j] its eigenvalue.
@@ -236,9 +514,9 @@ void jacobi_eigen(int n, std::vector<double>& S, std::vector<double>& Q, std::ve
 
 }  // namespace
 
-bool direct_level_ok(const HostLevel& H) {
+bool direct_level_ok(const HostLevel& H, int max_nodes) {
     const int nzi = H.nz - 2, nri = H.nr - 2;
-    if (nzi < 1 || nri < 1 || nzi > kDirectMaxNz || nri > kDirectMaxNr) return false;
+    if (nzi < 1 || nri < 1 || nzi > max_nodes || nri > max_nodes) return false;
     for (int k = 1; k <= nzi; ++k) {
         if (!(H.zc[k] > 0.0)) return false;
         // the axial operator must be symmetric for the eigenvector transform
@@ -271,29 +549,61 @@ void direct_tables(const HostLevel& H, std::vector<double>& V, std::vector<doubl
         for (int j = 0; j < nzi; ++j) V[(size_t)k * nzi + j] = Q[(size_t)k * nzi + j] / std::sqrt(H.zc[k + 1]);
 }
 
-bool direct_active(const cylpoisson_plan* p) { return p->opt.direct && p->direct_level > 0; }
+int direct_level(const cylpoisson_plan* p) {
+    if (p->opt.direct == 1) return p->dir[0].level;
+    if (p->opt.direct == 2) return p->dir[1].level;
+    return -1;
+}
+
+bool direct_active(const cylpoisson_plan* p) { return direct_level(p) > 0; }
 
 hipError_t launch_direct(cylpoisson_plan* p, hipStream_t s, int p0, int np) {
-    const int l = p->direct_level;
-    DeviceLevel& L = p->dl[l];
+    const DirectLevel& d = p->dir[p->opt.direct == 2 ? 1 : 0];
+    DeviceLevel& L = p->dl[d.level];
     if (np < 0) np = p->nt - p0;
-    DirectArgs a{};
+    if (np <= 0) return hipSuccess;
+    const int nzi = L.v.nz - 2, nri = L.v.nr - 2;
+    if (!d.big) {
+        DirectArgs a{};
+        a.v = L.v;
+        a.f = L.f;
+        a.u = L.u;
+        a.V = d.V;
+        a.sigma = d.sigma;
+        a.lam = p->d_lam;
+        a.mask = p->mask_live ? p->d_mask : nullptr;
+        a.p0 = p0;
+        const size_t lds = sizeof(double) * dir_lds_doubles(nzi, nri);
+        k_direct<<<np, kDirThreads, lds, s>>>(a);
+        return hipGetLastError();
+    }
+    BigArgs a{};
     a.v = L.v;
     a.f = L.f;
     a.u = L.u;
-    a.V = p->d_dir_V;
-    a.sigma = p->d_dir_sigma;
-    a.lam = p->d_lam;
+    a.w = L.r;
+    a.V = d.V;
+    a.VT = d.VT;
+    a.M = d.M;
     a.mask = p->mask_live ? p->d_mask : nullptr;
     a.p0 = p0;
-    const size_t lds = sizeof(double) * dir_lds_doubles(L.v.nz - 2, L.v.nr - 2);
-    k_direct<<<np, kDirThreads, lds, s>>>(a);
+    a.np = np;
+    const int blocks = big_blocks((nzi + kBigHalf - 1) / kBigHalf, np);
+    k_direct_fwd<<<blocks, kBigFwdThreads, sizeof(double) * kBigFwdLds, s>>>(a);
+    k_direct_inv<<<blocks, kBigInvThreads, sizeof(double) * kBigInvLds, s>>>(a);
     return hipGetLastError();
 }
 
-// The kernel's LDS (up to 130 KB) beyond the default 64 KiB, allowed once
-// when a plan is built (a launch under graph capture then needs no host call).
-hipError_t direct_prepare(const HostLevel& H) {
+// The kernels' LDS beyond the default 64 KiB (up to 130 KB for one workgroup
+// per plane, 133 KB for the transform kernel of the two-kernel form), allowed
+// once when a plan is built (a launch under graph capture then needs no host call).
+hipError_t direct_prepare(const HostLevel& H, bool big) {
+    if (big) {
+        static_assert(sizeof(double) * kBigFwdLds <= 160 * 1024, "LDS of k_direct_fwd");
+        static_assert(sizeof(double) * kBigInvLds <= 64 * 1024, "LDS of k_direct_inv");
+        return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_direct_fwd),
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    }
     const size_t lds = sizeof(double) * dir_lds_doubles(H.nz - 2, H.nr - 2);
     if (lds <= 64 * 1024) return hipSuccess;
     return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_direct), hipFuncAttributeMaxDynamicSharedMemorySize,

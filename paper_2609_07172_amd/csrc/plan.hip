@@ -635,20 +635,60 @@ cylpoisson_plan* build_plan(cylpoisson_plan* p) {
             break;
         }
         // the exact separable solve: the first level from 1 on small enough for
-        // it, at or above the bottom kernel's first level (the V-cycle stops there)
-        for (int l = 1; l < nl; ++l) {
+        // each form, at or above the bottom kernel's first level (the V-cycle
+        // stops there); [0] up to 128 interior nodes each way, [1] up to 64
+        for (int l = 1; l < nl && (p->dir[0].level < 0 || p->dir[1].level < 0); ++l) {
             if (p->bottom_level >= 1 && l > p->bottom_level) break;
-            if (!direct_level_ok(p->hl[l])) continue;
-            if (direct_prepare(p->hl[l]) != hipSuccess) {
-                (void)hipGetLastError();
-                break;
+            const HostLevel& H = p->hl[l];
+            const bool fits = direct_level_ok(H, kDirectBigMax);
+            const bool small = fits && H.nz - 2 <= kDirectMaxNz && H.nr - 2 <= kDirectMaxNr;
+            for (int which = 0; which < 2; ++which) {
+                DirectLevel& d = p->dir[which];
+                if (d.level >= 0 || !(which == 0 ? fits : small)) continue;
+                if (which == 1 && p->dir[0].level == l) {
+                    d = p->dir[0];  // the same level, in one workgroup per plane
+                    continue;
+                }
+                if (direct_prepare(H, !small) != hipSuccess) {
+                    (void)hipGetLastError();
+                    continue;
+                }
+                std::vector<double> V, sigma;
+                direct_tables(H, V, sigma);
+                d.big = !small;
+                if (d.big) {
+                    // zero-padded [128][128] copies of V and V^T
+                    const int n = H.nz - 2, m = kDirectBigMax;
+                    std::vector<double> Vp((size_t)m * m, 0.0), VTp((size_t)m * m, 0.0);
+                    for (int k = 0; k < n; ++k)
+                        for (int j = 0; j < n; ++j) {
+                            Vp[(size_t)k * m + j] = V[(size_t)k * n + j];
+                            VTp[(size_t)j * m + k] = V[(size_t)k * n + j];
+                        }
+                    CP_TRY(upload(p, &d.V, Vp));
+                    CP_TRY(upload(p, &d.VT, VTp));
+                    // elimination factors of (T_r(lambda_p) + sigma_j R_b) w = g along r:
+                    // m_i = 1 / (b_i - rw_i c_{i-1}), c_i = re_i m_i, per plane and eigenvector
+                    const int nri = H.nr - 2;
+                    std::vector<double> Mf((size_t)p->nt * m * m, 0.0);
+                    for (int q = 0; q < p->nt; ++q)
+                        for (int j = 0; j < n; ++j) {
+                            double c = 0.0;
+                            for (int i = 0; i < nri; ++i) {
+                                const int I = i + 1;
+                                const double b = H.rw[I] + H.re[I] + p->lam[q] * H.rm[I] + sigma[j] * H.rb[I];
+                                const double mi = 1.0 / (b - H.rw[I] * c);
+                                c = H.re[I] * mi;
+                                Mf[((size_t)q * m + i) * m + j] = mi;
+                            }
+                        }
+                    CP_TRY(upload(p, &d.M, Mf));
+                } else {
+                    CP_TRY(upload(p, &d.V, V));
+                }
+                CP_TRY(upload(p, &d.sigma, sigma));
+                d.level = l;
             }
-            std::vector<double> V, sigma;
-            direct_tables(p->hl[l], V, sigma);
-            CP_TRY(upload(p, &p->d_dir_V, V));
-            CP_TRY(upload(p, &p->d_dir_sigma, sigma));
-            p->direct_level = l;
-            break;
         }
         std::vector<double> F, G;
         dft_matrices(Ntheta, F, G);
@@ -928,7 +968,7 @@ int cylpoisson_plan_set_option(cylpoisson_plan* plan, const char* key, double va
     if (!std::strcmp(key, "krylov")) return int_in(0, 1, &plan->opt.krylov);
     if (!std::strcmp(key, "krylov_precond")) return int_in(0, 4, &plan->opt.krylov_precond);
     if (!std::strcmp(key, "nn_target")) return int_in(0, 1, &plan->opt.nn_target);
-    if (!std::strcmp(key, "direct")) return int_in(0, 1, &plan->opt.direct);
+    if (!std::strcmp(key, "direct")) return int_in(0, 2, &plan->opt.direct);
     if (!std::strcmp(key, "krylov_restart")) return int_in(1, 16, &plan->opt.krylov_restart);
     if (!std::strcmp(key, "krylov_max")) return int_in(1, 100000, &plan->opt.krylov_max);
     if (!std::strcmp(key, "fallback")) return int_in(0, 1, &plan->opt.fallback);
@@ -1017,14 +1057,14 @@ int cylpoisson_get_info(const cylpoisson_plan* plan, cylpoisson_info* out) {
     out->workspace_bytes = plan->workspace_bytes;
     out->device = plan->device;
     for (int l = 0; l + 1 < out->levels; ++l) {
-        if (l > 0 && l == plan->direct_level && direct_active(plan)) break;
+        if (l > 0 && l == direct_level(plan)) break;
         if (l > 0 && l == plan->bottom_level && bottom_active(plan)) break;
         if (!fused_supported(plan, l)) break;
         ++out->fused_levels;
     }
     out->layout = plan->layout;
     out->uniform = plan->uniform ? 1 : 0;
-    out->direct_level = plan->direct_level;
+    out->direct_level = direct_level(plan);
     return CYLPOISSON_OK;
 }
 

@@ -239,7 +239,7 @@ hipError_t vcycle(cylpoisson_plan* p, int l, hipStream_t s, bool zero_top, int s
     const int nl = (int)p->dl.size();
     DeviceLevel& L = p->dl[l];
     hipError_t e = hipSuccess;
-    if (l > 0 && l == p->direct_level && direct_active(p)) return launch_direct(p, s, p0, np);
+    if (l > 0 && l == direct_level(p)) return launch_direct(p, s, p0, np);
     if (l == nl - 1) {
         if (l > 0) e = launch_zero_interior(L, p->nt, L.u, s);
         if (e == hipSuccess)
@@ -1050,7 +1050,7 @@ hipError_t vcycle_step(cylpoisson_plan* p, hipStream_t s) { return vcycle(p, 0, 
 // solve) when that applies, else the LDS bottom kernel's first level; -1 if
 // neither serves a level from 1 on.
 int stop_level(const cylpoisson_plan* p) {
-    if (direct_active(p)) return p->direct_level;
+    if (direct_active(p)) return direct_level(p);
     if (bottom_active(p) && p->bottom_level >= 1) return p->bottom_level;
     return -1;
 }

@@ -33,7 +33,7 @@ def P():
                                   W.SMALL.with_sizes(217, 6, 94), W.SMALL.with_sizes(105, 5, 344),
                                   W.SMALL.with_sizes(384, 4, 411), W.SMALL.with_sizes(76, 7, 259)],
                          ids=lambda p: f"{p.nr}x{p.ntheta}x{p.nz}")
-@pytest.mark.parametrize("direct", [1, 0])
+@pytest.mark.parametrize("direct", [1, 2, 0])
 def test_fmg_solve_matches_oracle(P, prob, direct):
     rho = W.blob_charge(prob, seed=prob.nr)
     ref = solvers.solve_separable(fv.Grid.of(prob), rho, prob.bc)

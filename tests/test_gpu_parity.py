@@ -324,9 +324,9 @@ def test_paper_scale_matches_separable_oracle(P):
 
 
 # -------------------------------------------------- fused vs per-step path
-@pytest.mark.parametrize("direct", [0, 1])
+@pytest.mark.parametrize("direct", [0, 1, 2])
 @pytest.mark.parametrize("shape", [(33, 16, 33), (40, 8, 37), (129, 8, 129), (26, 3, 71), (129, 4, 33),
-                                   (33, 4, 200)])
+                                   (33, 4, 200), (257, 4, 129)])
 def test_fused_passes_match_per_step_kernels(P, shape, direct):
     """The fused streaming passes run the same red-black schedule and point arithmetic as the
     one-kernel-per-step path (with contraction pinned in the shared point operations), so the
@@ -538,7 +538,12 @@ def test_warm_first_check_not_from_a_cold_solve(P):
 
 
 # ------------------------------------------- exact solve of a coarse level
+@pytest.mark.parametrize("direct", [1, 2])
 @pytest.mark.parametrize("prob,tol", [(W.SMALL, 1e-14), (W.BATCHED, 1e-14), (W.HIGH_SHIFT, 1e-14),
+                                      # direct = 1 takes a level above 64 nodes each way
+                                      # (two-kernel form): 127 x 127, 99 x 127, 107 x 46
+                                      # and 15 x 99 interior nodes
+                                      (W.SMALL.with_sizes(257, 4, 257), 1e-14),
                                       (W.SMALL.with_sizes(400, 8, 512), 1e-14),
                                       (W.SMALL.with_sizes(217, 6, 94), 1e-14),
                                       (W.SMALL.with_sizes(65, 5, 401), 1e-14),
@@ -546,15 +551,16 @@ def test_warm_first_check_not_from_a_cold_solve(P):
                                       # floor is 5e-14 with or without the exact solve
                                       (W.SMALL.with_sizes(401, 4, 65), 1e-13)],
                          ids=lambda x: f"{x.nr}x{x.ntheta}x{x.nz}" if hasattr(x, "nr") else str(x))
-def test_direct_coarse_solve_matches_oracle(P, prob, tol):
+def test_direct_coarse_solve_matches_oracle(P, prob, tol, direct):
     """The V-cycle stopping at a level solved exactly (axial eigenvectors, radial
     tridiagonal solves) meets the oracle, converges at least as fast per cycle as
     the V-cycle through every level (its coarse correction is exact rather than
-    one V-cycle's), and contracts like a two- or three-grid method."""
+    one V-cycle's), and contracts like a two- or three-grid method; in both
+    forms (direct = 1: up to 128 interior nodes each way, direct = 2: up to 64)."""
     rho = W.blob_charge(prob, seed=prob.nz)
     ref = solvers.solve_separable(fv.Grid.of(prob), rho, prob.bc)
-    say("direct", prob.nr, prob.ntheta, prob.nz)
-    a = P.Plan.for_problem(prob, direct=1)
+    say("direct", direct, prob.nr, prob.ntheta, prob.nz)
+    a = P.Plan.for_problem(prob, direct=direct)
     b = P.Plan.for_problem(prob, direct=0)
     pa, sa = a.solve(dev(rho), tol=tol)
     pa = host(pa).copy()
@@ -579,13 +585,23 @@ def test_direct_coarse_solve_matches_oracle(P, prob, tol):
 
 
 def test_direct_level_choice(P):
-    """The exact solve takes the first level from 1 on with at most 64 interior
-    nodes each way (one workgroup's LDS holds the plane and its transforms);
-    with option direct = 0 the V-cycle goes down to the bottom kernel."""
+    """Option direct = 1 (the default) takes the first level from 1 on with at
+    most 128 interior nodes each way, direct = 2 the first with at most 64 (one
+    workgroup's LDS holds the plane and its transforms); with direct = 0 the
+    V-cycle goes down to the bottom kernel."""
     info = P.Plan.for_problem(W.PAPER_SCALE).info()
-    assert info["direct_level"] == 3, info  # (400, 512) -> (201, 257) -> (101, 129) -> (51, 65)
+    assert info["direct_level"] == 2, info  # (400, 512) -> (201, 257) -> (101, 129)
     shapes = info["level_shapes"]
+    assert shapes[2][1] - 2 <= 128 < shapes[1][1] - 2 and shapes[2][0] - 2 <= 128
+    info = P.Plan.for_problem(W.PAPER_SCALE, direct=2).info()
+    assert info["direct_level"] == 3, info  # -> (51, 65)
     assert shapes[3][1] - 2 <= 64 < shapes[2][1] - 2 and shapes[3][0] - 2 <= 64
+    assert P.Plan.for_problem(W.PAPER_SCALE, direct=0).info()["direct_level"] == -1
+    # the option can change on a built plan
+    plan = P.Plan.for_problem(W.SMALL.with_sizes(257, 4, 257))
+    assert plan.info()["direct_level"] == 1
+    plan.set_option("direct", 2)
+    assert plan.info()["direct_level"] == 2
     info = P.Plan.for_problem(W.BATCHED).info()
     assert info["direct_level"] == 1, info
     plan = P.Plan.for_problem(W.BATCHED, direct=0)
