@@ -341,13 +341,25 @@ __global__ __launch_bounds__(kBigFwdThreads) void k_direct_fwd(BigArgs a) {
         // g[j][r] = sum_k V[k][j0 + j] f[k][r] for this wave's 16 columns, 4 tiles of 16 eigenvectors
 #pragma unroll
         for (int jt = 0; jt < 4; ++jt) acc[jt] = dbl4{0.0, 0.0, 0.0, 0.0};
+        // the next step's V operands are read from LDS before this step's products issue
+        const double* vcol = VG + (l >> 4) * kBigHalf + (l & 15);
+        double an[4];
+#pragma unroll
+        for (int jt = 0; jt < 4; ++jt) an[jt] = vcol[16 * jt];
 #pragma unroll
         for (int s = 0; s < kBigSteps; ++s) {
             if (s < ks) {
-                const double* vrow = VG + (4 * s + (l >> 4)) * kBigHalf + (l & 15);
+                double ac[4];
+#pragma unroll
+                for (int jt = 0; jt < 4; ++jt) ac[jt] = an[jt];
+                if (s + 1 < kBigSteps) {
+                    const double* vrow = vcol + 4 * (s + 1) * kBigHalf;
+#pragma unroll
+                    for (int jt = 0; jt < 4; ++jt) an[jt] = vrow[16 * jt];
+                }
 #pragma unroll
                 for (int jt = 0; jt < 4; ++jt)
-                    acc[jt] = __builtin_amdgcn_mfma_f64_16x16x4f64(vrow[16 * jt], fb[s], acc[jt], 0, 0, 0);
+                    acc[jt] = __builtin_amdgcn_mfma_f64_16x16x4f64(ac[jt], fb[s], acc[jt], 0, 0, 0);
             }
         }
     }
@@ -382,12 +394,16 @@ __global__ __launch_bounds__(kBigFwdThreads) void k_direct_fwd(BigArgs a) {
         double w = 0.0;
         for (int top = nri - 1; top >= 0; top -= kBigChain) {
             double gv[kBigChain], cv[kBigChain];
+            double rv[kBigChain], mv[kBigChain];
 #pragma unroll
             for (int u = 0; u < kBigChain; ++u) {
                 const int i = max(top - u, 0);
                 gv[u] = g[i];
-                cv[u] = re[i] * M[i * kBigHalf + l];
+                rv[u] = re[i];
+                mv[u] = M[i * kBigHalf + l];
             }
+#pragma unroll
+            for (int u = 0; u < kBigChain; ++u) cv[u] = rv[u] * mv[u];
 #pragma unroll
             for (int u = 0; u < kBigChain; ++u) {
                 w = fma(cv[u], w, gv[u]);
@@ -447,13 +463,24 @@ __global__ __launch_bounds__(kBigInvThreads) void k_direct_inv(BigArgs a) {
     dbl4 acc[4];
 #pragma unroll
     for (int kt = 0; kt < 4; ++kt) acc[kt] = dbl4{0.0, 0.0, 0.0, 0.0};
+    const double* vcol = smem + (l >> 4) * kBigHalf + (l & 15);
+    double an[4];
+#pragma unroll
+    for (int kt = 0; kt < 4; ++kt) an[kt] = vcol[16 * kt];
 #pragma unroll
     for (int s = 0; s < kBigSteps; ++s) {
         if (s < ks) {
-            const double* vrow = smem + (4 * s + (l >> 4)) * kBigHalf + (l & 15);
+            double ac[4];
+#pragma unroll
+            for (int kt = 0; kt < 4; ++kt) ac[kt] = an[kt];
+            if (s + 1 < kBigSteps) {
+                const double* vrow = vcol + 4 * (s + 1) * kBigHalf;
+#pragma unroll
+                for (int kt = 0; kt < 4; ++kt) an[kt] = vrow[16 * kt];
+            }
 #pragma unroll
             for (int kt = 0; kt < 4; ++kt)
-                acc[kt] = __builtin_amdgcn_mfma_f64_16x16x4f64(vrow[16 * kt], wb[s], acc[kt], 0, 0, 0);
+                acc[kt] = __builtin_amdgcn_mfma_f64_16x16x4f64(ac[kt], wb[s], acc[kt], 0, 0, 0);
         }
     }
     double* u = a.u + (size_t)plane * v.pstride + v.pitch + 1;
