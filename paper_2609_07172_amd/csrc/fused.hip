@@ -33,19 +33,25 @@ hipError_t fused_down(cylpoisson_plan* p, int l, bool zero_u, bool zero_interior
 }
 
 // The first finest down pass after a full-multigrid start with the start's
-// finest interpolation folded in (k_pass_fine_pro): FP64, two pre-sweeps and
-// one row of prefetch (the tuned finest pass), fused finest level.
+// finest interpolation folded in (k_pass_fine_pro): FP64, two pre-sweeps with
+// one row of prefetch (the tuned finest pass) or three with two, fused finest
+// level.
 bool fused_down_pro_ok(const cylpoisson_plan* p) {
-    if (!fused_supported(p, 0) || nu_pre(p, 0) != 2 || pass_prefetch<double>(2, p->opt.prefetch) != 1)
-        return false;
-    return pass_shape<double>(p, 0, 2, true, true).lds <= 64 * 1024;
+    const int nu = nu_pre(p, 0);
+    if (!fused_supported(p, 0) || (nu != 2 && nu != 3)) return false;
+    if (nu == 2 && pass_prefetch<double>(2, p->opt.prefetch) != 1) return false;
+    const Shape sh = pass_shape<double>(p, 0, nu, true, true);
+    // three sweeps: one wave per SIMD (at most 256 threads, the registers of
+    // two) and up to 80 KB of LDS (two workgroups per compute unit)
+    return nu == 2 ? sh.lds <= 64 * 1024 : (sh.threads <= 256 && sh.lds <= 80 * 1024);
 }
 
 hipError_t fused_down_pro(cylpoisson_plan* p, hipStream_t s, int p0, int np) {
     if (np < 0) np = p->nt;
     DeviceLevel& L = p->dl[0];
     DeviceLevel& C = p->dl[1];
-    const Shape sh = pass_shape<double>(p, 0, 2, true, true);
+    const int nu = nu_pre(p, 0);
+    const Shape sh = pass_shape<double>(p, 0, nu, true, true);
     PassArgs<double> a = make_args<double>(p, 0, sh, p0, np);
     a.u_in = L.u;  // its ring; the interior is zero plus the prolongated C.u
     a.f = L.f;
@@ -53,36 +59,55 @@ hipError_t fused_down_pro(cylpoisson_plan* p, hipStream_t s, int p0, int np) {
     a.fc = C.f;
     a.ec = C.u;
     a.zero_interior = 1;
-    k_pass_fine_pro<double, 2, 1><<<sh.nchunks * np, sh.threads, sh.lds, s>>>(a);
+    if (nu == 2) {
+        k_pass_fine_pro<double, 2, 1><<<sh.nchunks * np, sh.threads, sh.lds, s>>>(a);
+        return hipGetLastError();
+    }
+    constexpr int PD3 = pass_prefetch<double>(3, 1);
+    if (sh.lds > 64 * 1024) {
+        // beyond the default 64 KiB of dynamic LDS: allowed on the current device
+        // at every launch (a host call of a few microseconds)
+        const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_pass_fine_pro<double, 3, PD3>),
+                                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh.lds);
+        if (e != hipSuccess) return e;
+    }
+    k_pass_fine_pro<double, 3, PD3><<<sh.nchunks * np, sh.threads, sh.lds, s>>>(a);
     return hipGetLastError();
 }
 
-// The merged finest pass (k_pass_merge): FP64, two sweeps before and after
-// the finest coarse-grid correction (four in a row), one or two rows of
-// prefetch, at most 256 threads, fused passes on the finest level.
+// The merged finest pass (k_pass_merge): FP64, nu2 sweeps after one finest
+// coarse-grid correction and nu1 before the next (4 to 6 in a row), one or
+// two rows of prefetch, at most 256 threads, fused passes on the finest level.
 bool fused_merge_ok(const cylpoisson_plan* p) {
-    if (!p->opt.merge || !fused_supported(p, 0) || nu_pre(p, 0) != 2 || nu_post(p, 0) != 2) return false;
-    const Shape sh = pass_shape<double>(p, 0, 4, true, true, true);
+    const int nu = nu_pre(p, 0) + nu_post(p, 0);
+    if (!p->opt.merge || !fused_supported(p, 0) || nu < 4 || nu > 6) return false;
+    const Shape sh = pass_shape<double>(p, 0, nu, true, true, true);
     return sh.threads <= 256 && sh.lds <= 160 * 1024 && sh.nchunks <= kMaxPartial;
 }
 
-template <int PD>
+template <int NU, int PD>
 hipError_t launch_merge(const PassArgs<double>& a, int blocks, int threads, size_t lds, hipStream_t s) {
     // more than the default 64 KiB of dynamic LDS: allowed on the current
     // device at every launch (a host call of a few microseconds)
     if (lds > 64 * 1024) {
-        const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_pass_merge<double, 4, PD>),
+        const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_pass_merge<double, NU, PD>),
                                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
     }
-    k_pass_merge<double, 4, PD><<<blocks, threads, lds, s>>>(a);
+    k_pass_merge<double, NU, PD><<<blocks, threads, lds, s>>>(a);
     return hipGetLastError();
+}
+
+template <int NU>
+hipError_t launch_merge_pd(int pd, const PassArgs<double>& a, int blocks, int threads, size_t lds, hipStream_t s) {
+    return pd == 2 ? launch_merge<NU, 2>(a, blocks, threads, lds, s) : launch_merge<NU, 1>(a, blocks, threads, lds, s);
 }
 
 hipError_t fused_merge(cylpoisson_plan* p, hipStream_t s) {
     DeviceLevel& L = p->dl[0];
     DeviceLevel& C = p->dl[1];
-    const Shape sh = pass_shape<double>(p, 0, 4, true, true, true);
+    const int nu = nu_pre(p, 0) + nu_post(p, 0);
+    const Shape sh = pass_shape<double>(p, 0, nu, true, true, true);
     PassArgs<double> a = make_args<double>(p, 0, sh, 0, p->nt);
     a.u_in = L.u2;  // the last down pass's iterate, plus the prolongated C.u
     a.f = L.f;
@@ -90,9 +115,13 @@ hipError_t fused_merge(cylpoisson_plan* p, hipStream_t s) {
     a.fc = C.f;
     a.ec = C.u;
     a.zero_interior = 0;
-    const int blocks = sh.nchunks * p->nt;
-    return p->opt.merge_prefetch == 2 ? launch_merge<2>(a, blocks, sh.threads, sh.lds, s)
-                                      : launch_merge<1>(a, blocks, sh.threads, sh.lds, s);
+    const int blocks = sh.nchunks * p->nt, pd = p->opt.merge_prefetch;
+    switch (nu) {
+        case 4: return launch_merge_pd<4>(pd, a, blocks, sh.threads, sh.lds, s);
+        case 5: return launch_merge_pd<5>(pd, a, blocks, sh.threads, sh.lds, s);
+        case 6: return launch_merge_pd<6>(pd, a, blocks, sh.threads, sh.lds, s);
+        default: return hipErrorInvalidValue;
+    }
 }
 
 int fused_chunks(const cylpoisson_plan* p, int l, int nu) {

@@ -83,6 +83,8 @@ struct Pass {
     // colour of each column in every half-sweep is known at compile time.
     static constexpr int Q0 = 2 * NU + 3 + PD;
     static constexpr int Q = (Q0 & 1) ? Q0 + 1 : Q0;
+    // the step and half-sweep expansions below cover 2 NU <= 12 and Q <= 18
+    static_assert(2 * NU <= 12 && Q <= 18, "sweep count beyond the pass's unrolled steps");
     static constexpr int QS = Q + 1;  // LDS values per column history (odd stride)
     // up: coarse-correction rows in LDS, row K in slot K % kCRing.  The rows live
     // at one step are K(x) .. K(x + PD + 1) + 1 for the consumed row x: at most
@@ -413,6 +415,7 @@ struct Pass {
         nb[(h)] = c1col ? Bl[sy] : Ar[sy];                                            \
     }
         CP_NB(0) CP_NB(1) CP_NB(2) CP_NB(3) CP_NB(4) CP_NB(5) CP_NB(6) CP_NB(7)
+        CP_NB(8) CP_NB(9) CP_NB(10) CP_NB(11)
 #undef CP_NB
         constexpr int sr = (J - 2 * NU - 1 + 4 * Q) % Q;
         const T rnw = Bl[sr], rne = Ar[sr];
@@ -431,6 +434,7 @@ struct Pass {
         if (!CHK || (y >= ylo && y <= yhi)) half_sweep<sy, sm, sp, c1col, CHK>(y, nb[(h)]); \
     }
         CP_HS(0) CP_HS(1) CP_HS(2) CP_HS(3) CP_HS(4) CP_HS(5) CP_HS(6) CP_HS(7)
+        CP_HS(8) CP_HS(9) CP_HS(10) CP_HS(11)
 #undef CP_HS
         // row x - 2 nu is final now
         {
@@ -486,6 +490,7 @@ struct Pass {
     }
         CP_STEP(0) CP_STEP(1) CP_STEP(2) CP_STEP(3) CP_STEP(4) CP_STEP(5) CP_STEP(6) CP_STEP(7)
         CP_STEP(8) CP_STEP(9) CP_STEP(10) CP_STEP(11) CP_STEP(12) CP_STEP(13) CP_STEP(14) CP_STEP(15)
+        CP_STEP(16) CP_STEP(17)
 #undef CP_STEP
     }
 
@@ -563,7 +568,7 @@ __global__ void __launch_bounds__(512) k_pass_fine(PassArgs<T> a) {
 // The finest down pass of the first cycle after a full-multigrid start: the
 // interior of the input is zero plus the prolongated level-1 answer.
 template <typename T, int NU, int PD>
-__global__ void __launch_bounds__(512) k_pass_fine_pro(PassArgs<T> a) {
+__global__ void __launch_bounds__(NU == 2 ? 512 : 256) k_pass_fine_pro(PassArgs<T> a) {
     extern __shared__ double smem[];
     Pass<T, NU, PD, true, false, true> pass(a, (char*)smem);
     pass.run();

@@ -459,8 +459,12 @@ def test_coarse_sweep_counts_reach_the_oracle(P, nus, fused):
 
 # ------------------------------------------- merged finest pass (option merge)
 @pytest.mark.parametrize("shape,options", [((400, 16, 512), {}), ((129, 8, 129), {}), ((201, 5, 97), {}),
-                                           ((257, 8, 257), {"fmg": 1}), ((129, 8, 129), {"merge_prefetch": 2})],
-                         ids=["400x16x512", "129x8x129", "201x5x97", "fmg-257", "prefetch2"])
+                                           ((257, 8, 257), {"fmg": 1}), ((129, 8, 129), {"merge_prefetch": 2}),
+                                           # 5 and 6 sweeps in one merged pass
+                                           ((400, 16, 512), {"nu1": 3, "fmg": 1}), ((201, 5, 97), {"nu2": 3}),
+                                           ((129, 8, 129), {"nu1": 3, "nu2": 3, "merge_prefetch": 2})],
+                         ids=["400x16x512", "129x8x129", "201x5x97", "fmg-257", "prefetch2", "v32-fmg", "v23",
+                              "v33-prefetch2"])
 def test_merged_finest_passes_equal_the_separate_passes(P, shape, options):
     """A cycle without a check ends in one finest pass doing its up pass and the
     next cycle's down pass, with the node arithmetic of the two: iterates and
