@@ -145,6 +145,17 @@ constexpr int kDirectMaxNr = 64;
 // products; two workgroups per plane, each with half the eigenvectors).
 constexpr int kDirectBigMax = 128;
 
+// The cycles from one convergence check to the next, captured into a HIP
+// graph: cycles c0 .. ce, the start flags of cycle c0, the finest iterate
+// buffer at capture (the merged passes swap the two), and the norm partial
+// chunks each cycle recorded.
+struct GraphSeg {
+    int c0, ce, flags;
+    const double* u;
+    hipGraphExec_t exec;
+    std::vector<int> chunks;
+};
+
 // One level chosen for the exact separable solve, with its axial eigenvector
 // tables on the device.
 struct DirectLevel {
@@ -232,8 +243,7 @@ struct cylpoisson_plan {
 
     // captured V-cycles: key (cycle index, first-cycle flag) -> executable graph
     hipStream_t cap_stream = nullptr;
-    std::vector<std::pair<int, hipGraphExec_t>> graphs;
-    std::vector<int> graph_chunks;  // norm partial chunks recorded per captured cycle
+    std::vector<cp::GraphSeg> graphs;  // captured cycle segments (option "graph")
 
     // learned preconditioner: the network (not owned), FGMRES vectors V_0..V_m
     // and Z_0..Z_m-1 (node arrays, zero rings), dot partials, network scratch
@@ -379,6 +389,8 @@ bool direct_active(const cylpoisson_plan* p);
 hipError_t launch_direct(cylpoisson_plan* p, hipStream_t s, int p0 = 0, int np = -1);
 
 // ---- fused passes (fused.hip) ----
+// the LDS limits of the fused kernels (once per device, when a plan is built)
+hipError_t fused_prepare();
 bool fused_supported(const cylpoisson_plan* p, int l);
 // The LDS bottom kernel serves the small levels (options bottom, fused, point smoother).
 bool bottom_active(const cylpoisson_plan* p);

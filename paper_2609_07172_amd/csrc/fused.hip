@@ -63,15 +63,7 @@ hipError_t fused_down_pro(cylpoisson_plan* p, hipStream_t s, int p0, int np) {
         k_pass_fine_pro<double, 2, 1><<<sh.nchunks * np, sh.threads, sh.lds, s>>>(a);
         return hipGetLastError();
     }
-    constexpr int PD3 = pass_prefetch<double>(3, 1);
-    if (sh.lds > 64 * 1024) {
-        // beyond the default 64 KiB of dynamic LDS: allowed on the current device
-        // at every launch (a host call of a few microseconds)
-        const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_pass_fine_pro<double, 3, PD3>),
-                                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh.lds);
-        if (e != hipSuccess) return e;
-    }
-    k_pass_fine_pro<double, 3, PD3><<<sh.nchunks * np, sh.threads, sh.lds, s>>>(a);
+    k_pass_fine_pro<double, 3, pass_prefetch<double>(3, 1)><<<sh.nchunks * np, sh.threads, sh.lds, s>>>(a);
     return hipGetLastError();
 }
 
@@ -87,15 +79,27 @@ bool fused_merge_ok(const cylpoisson_plan* p) {
 
 template <int NU, int PD>
 hipError_t launch_merge(const PassArgs<double>& a, int blocks, int threads, size_t lds, hipStream_t s) {
-    // more than the default 64 KiB of dynamic LDS: allowed on the current
-    // device at every launch (a host call of a few microseconds)
-    if (lds > 64 * 1024) {
-        const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_pass_merge<double, NU, PD>),
-                                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        if (e != hipSuccess) return e;
-    }
     k_pass_merge<double, NU, PD><<<blocks, threads, lds, s>>>(a);
     return hipGetLastError();
+}
+
+// Dynamic LDS beyond the default 64 KiB for the kernels that take it (the
+// merged passes up to 160 KB, the three-sweep first down pass up to 80 KB),
+// allowed once on the current device when a plan is built, so that no launch
+// needs a host call (a launch under graph capture included).
+hipError_t fused_prepare() {
+    const void* k[] = {reinterpret_cast<const void*>(&k_pass_merge<double, 4, 1>),
+                       reinterpret_cast<const void*>(&k_pass_merge<double, 4, 2>),
+                       reinterpret_cast<const void*>(&k_pass_merge<double, 5, 1>),
+                       reinterpret_cast<const void*>(&k_pass_merge<double, 5, 2>),
+                       reinterpret_cast<const void*>(&k_pass_merge<double, 6, 1>),
+                       reinterpret_cast<const void*>(&k_pass_merge<double, 6, 2>),
+                       reinterpret_cast<const void*>(&k_pass_fine_pro<double, 3, pass_prefetch<double>(3, 1)>)};
+    for (const void* f : k) {
+        const hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 template <int NU>

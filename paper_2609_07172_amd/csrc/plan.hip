@@ -216,9 +216,8 @@ hipError_t upload(cylpoisson_plan* p, T** out, const std::vector<T>& host) {
 }  // namespace
 
 void drop_graphs(cylpoisson_plan* p) {
-    for (auto& g : p->graphs) (void)hipGraphExecDestroy(g.second);
+    for (auto& g : p->graphs) (void)hipGraphExecDestroy(g.exec);
     p->graphs.clear();
-    p->graph_chunks.clear();
 }
 
 namespace {
@@ -607,6 +606,7 @@ cylpoisson_plan* build_plan(cylpoisson_plan* p) {
                 D.rowc = rc;
             }
         }
+        CP_TRY(fused_prepare());
         // the bottom kernel: the first level from 1 on whose levels all fit in LDS
         for (int lb = 1; lb < nl; ++lb) {
             if (bottom_lds_bytes(p, lb) > kBottomLdsBytes) continue;

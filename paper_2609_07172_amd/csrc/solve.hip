@@ -375,42 +375,75 @@ void reset_stats(cylpoisson_plan* p) {
     p->events_used = 0;
 }
 
-// ---- captured V-cycles ----
-// With the option "graph", each V-cycle (the launches from the finest level
-// down and back) is captured once per cycle index into a HIP graph on a
-// stream of the plan, then replayed on the caller's stream; the kernel
-// arguments depend only on the plan, its options and the cycle index (norm
-// slot), so a replay equals the eager launches.  Options that change launch
-// parameters drop the cache.
-// Any V-cycle path can be captured: it launches kernels only (no memset or
-// copy); the per-step path's norms are formed outside the graph.
+// ---- captured cycle segments ----
+// With the option "graph", the cycles from one convergence check to the next
+// are captured into one HIP graph on a stream of the plan and replayed on the
+// caller's stream: every launch of those cycles, the merged finest passes and
+// the per-step path's residual norms included (kernels only: no memset or
+// copy).  The kernel arguments depend only on the plan, its options, the
+// cycle indices (norm slots), the first cycle's start and which of the two
+// finest buffers holds the iterate, so a replay equals the eager launches.
+// Options that change launch parameters drop the cache.
 bool graphs_active(const cylpoisson_plan* p, int G) { return p->opt.graph && G == 1 && !p->opt.timing; }
 
-hipError_t graph_cycle(cylpoisson_plan* p, hipStream_t s, int c, bool zero_top, NormSlot* ns) {
-    const int key = 2 * c + (zero_top ? 1 : 0);
-    for (size_t i = 0; i < p->graphs.size(); ++i)
-        if (p->graphs[i].first == key) {
-            ns->partial_chunks = p->graph_chunks[i];
-            return hipGraphLaunch(p->graphs[i].second, s);
+// Cycles c0 .. ce as the eager loop runs them, the last one ending in the up
+// pass whose norms the check reads; the cycles before it end in the merged
+// finest pass when `merging`.
+hipError_t run_segment(cylpoisson_plan* p, hipStream_t s, int c0, int ce, bool zero_top, bool pro, bool merging,
+                       std::vector<NormSlot>& slots) {
+    bool pending = false;
+    hipError_t e = hipSuccess;
+    for (int c = c0; c <= ce && e == hipSuccess; ++c) {
+        const bool zt = c == c0 && zero_top, pr = c == c0 && pro;
+        if (merging) {
+            if (!pending) e = cycle_down(p, s, zt, pr);
+            if (e != hipSuccess) break;
+            if (c == ce) {
+                e = cycle_up(p, s, c, &slots[c]);
+                pending = false;
+            } else {
+                e = cycle_merge(p, s);
+                slots[c].partial_chunks = kNoNorms;
+                pending = true;
+            }
+        } else {
+            e = vcycle(p, 0, s, zt, c, &slots[c], 0, -1, pr);
+        }
+        if (e == hipSuccess && slots[c].partial_chunks == -1) {
+            e = residual_norms(p, c, s);
+            slots[c].partial_chunks = 0;
+        }
+    }
+    return e;
+}
+
+hipError_t graph_segment(cylpoisson_plan* p, hipStream_t s, int c0, int ce, bool zero_top, bool pro, bool merging,
+                         std::vector<NormSlot>& slots) {
+    const int flags = (zero_top ? 1 : 0) | (pro ? 2 : 0) | (merging ? 4 : 0);
+    const int merges = merging ? ce - c0 : 0;
+    for (const GraphSeg& g : p->graphs)
+        if (g.c0 == c0 && g.ce == ce && g.flags == flags && g.u == p->dl[0].u) {
+            for (int c = c0; c <= ce; ++c) slots[c].partial_chunks = g.chunks[c - c0];
+            // the host's view of the finest buffers follows the replayed merges
+            for (int i = 0; i < merges; ++i) std::swap(p->dl[0].u, p->dl[0].u2);
+            return hipGraphLaunch(g.exec, s);
         }
     hipError_t e = hipSuccess;
     if (!p->cap_stream) e = hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking);
     if (e != hipSuccess) return e;
+    GraphSeg g{c0, ce, flags, p->dl[0].u, nullptr, {}};
     e = hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal);
     if (e != hipSuccess) return e;
-    NormSlot cap;
-    hipError_t ev = vcycle(p, 0, p->cap_stream, zero_top, c, &cap);
+    hipError_t ev = run_segment(p, p->cap_stream, c0, ce, zero_top, pro, merging, slots);
     hipGraph_t graph = nullptr;
     e = hipStreamEndCapture(p->cap_stream, &graph);
     if (ev != hipSuccess) e = ev;
-    hipGraphExec_t exec = nullptr;
-    if (e == hipSuccess) e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    if (e == hipSuccess) e = hipGraphInstantiate(&g.exec, graph, nullptr, nullptr, 0);
     if (graph) (void)hipGraphDestroy(graph);
     if (e != hipSuccess) return e;
-    p->graphs.emplace_back(key, exec);
-    p->graph_chunks.push_back(cap.partial_chunks);
-    ns->partial_chunks = cap.partial_chunks;
-    return hipGraphLaunch(exec, s);
+    for (int c = c0; c <= ce; ++c) g.chunks.push_back(slots[c].partial_chunks);
+    p->graphs.push_back(g);
+    return hipGraphLaunch(g.exec, s);
 }
 
 // ---- per-plane convergence masks ----
@@ -724,12 +757,16 @@ int run_cycles(cylpoisson_plan* p, double tol, hipStream_t s, bool ring_only, bo
     // A cycle after which the host does not check ends in the merged finest
     // pass, which also runs the next cycle's finest down pass (and everything
     // below it): `pending` then says the next cycle only needs its up pass.
-    const bool merging = !graphs && G == 1 && fused_supported(p, 0) && fused_merge_ok(p);
+    const bool merge_ok = G == 1 && fused_supported(p, 0) && fused_merge_ok(p);
+    const bool merging = !graphs && merge_ok;
     bool pending = false;
     for (int c = 1; c <= maxc; ++c) {
         const int next_check = k.next_check;
         if (graphs) {
-            CP_HIP(graph_cycle(p, s, c, c == 1 && ring_only, &slots[c]));
+            // every cycle up to the next check in one replay
+            const int ce = std::min(std::max(next_check, c), maxc);
+            CP_HIP(graph_segment(p, s, c, ce, c == 1 && ring_only, c == 1 && fmg_pro, merge_ok, slots));
+            c = ce;
         } else if (merging) {
             if (!pending) CP_HIP(cycle_down(p, s, c == 1 && ring_only, c == 1 && fmg_pro));
             if (c == next_check || c == maxc) {
@@ -1148,11 +1185,10 @@ int solve_impl(cylpoisson_plan* p, const double* rho, double* phi, double tol, v
     // the full-multigrid start also serves the mixed-precision solve, whose
     // FP64 refinement then starts from it as from a given iterate
     const bool fmg = !warm && !learned && fmg_active(p);
-    // the first down pass folds in the start's finest interpolation, except
-    // with graphs (the captured first cycle is the plain one) and in mixed
-    // precision (the first pass is the FP64 refinement); masks freeze no plane
-    // before the first cycle
-    const bool fmg_pro = fmg && !mixed && fused_down_pro_ok(p) && !graphs_active(p, groups_active(p));
+    // the first down pass folds in the start's finest interpolation, except in
+    // mixed precision (the first pass is the FP64 refinement); masks freeze no
+    // plane before the first cycle
+    const bool fmg_pro = fmg && !mixed && fused_down_pro_ok(p);
     const bool ring_only = !warm && !learned && !fmg && (mixed || fused_supported(p, 0));
     {
         Timed tm(p, kOther, s);
