@@ -206,7 +206,6 @@ struct cylpoisson_plan {
     double* d_lam = nullptr;
     double* d_F = nullptr;       // forward DFT matrix [N][N]
     double* d_G = nullptr;       // inverse DFT matrix [N][N]
-    double* d_tw = nullptr;      // (cos, sin)(2 pi k / N), k < N, for the register FFTs
     double* d_s = nullptr;       // s_q = r_i dr_i dz_k / eps0 per level-0 node [nz][nr] (0 on the ring)
     double* d_inv_s = nullptr;   // 1 / s_q (0 on the ring)
     double* d_cinv = nullptr;    // coarsest-level inverse per plane [N][n][n]
@@ -327,9 +326,11 @@ hipError_t launch_refine(const DeviceLevel& L, int nt, const double* lam, const 
                          double* partial, double* norms_out, hipStream_t s);
 
 // ---- register FFTs (fft.hip) ----
-bool fft_supported(int n);
+// Ntheta = n a power of two from 16 to 128, and ncols (z, r) columns per plane
+// within the kernels' 32-bit lane offsets
+bool fft_supported(int n, long long ncols);
 hipError_t launch_fft(bool inverse, int n, const double* in, double* out, long long ncols,
-                      const double* cs, const double* tw, hipStream_t s);
+                      const double* cs, hipStream_t s);
 
 // ---- bottom of the V-cycle (bottom.hip) ----
 size_t bottom_lds_bytes(const cylpoisson_plan* p, int lb);  // FP64 values

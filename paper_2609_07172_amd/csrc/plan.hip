@@ -694,15 +694,6 @@ cylpoisson_plan* build_plan(cylpoisson_plan* p) {
         dft_matrices(Ntheta, F, G);
         CP_TRY(upload(p, &p->d_F, F));
         CP_TRY(upload(p, &p->d_G, G));
-        {
-            std::vector<double> tw(2 * (size_t)Ntheta);
-            for (int k = 0; k < Ntheta; ++k) {
-                const long double a = 2.0L * 3.14159265358979323846264338327950288L * k / Ntheta;
-                tw[2 * k] = (double)cosl(a);
-                tw[2 * k + 1] = (double)sinl(a);
-            }
-            CP_TRY(upload(p, &p->d_tw, tw));
-        }
         CP_TRY(upload(p, &p->d_lam, p->lam));
         {
             // s_q = r_i dr_i dz_k / eps0 (Eq. mode_rhs) = rb_i zc_k / eps0 on level 0

@@ -364,8 +364,8 @@ hipError_t join_groups(cylpoisson_plan* p, int G, hipStream_t s) {
 hipError_t transform(cylpoisson_plan* p, bool inverse, const double* in, double* out,
                      const double* colscale, hipStream_t s) {
     const long long ncols = (long long)p->nz * p->nr;
-    if (p->opt.fft && fft_supported(p->nt))
-        return launch_fft(inverse, p->nt, in, out, ncols, colscale, p->d_tw, s);
+    if (p->opt.fft && fft_supported(p->nt, ncols))
+        return launch_fft(inverse, p->nt, in, out, ncols, colscale, s);
     return launch_dft(inverse ? p->d_G : p->d_F, in, out, p->nt, ncols, colscale, s);
 }
 

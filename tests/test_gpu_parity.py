@@ -46,7 +46,8 @@ def check_boundary(phi, p):
 
 
 # ------------------------------------------------------------------ DFT
-@pytest.mark.parametrize("shape", [(5, 16, 7), (9, 7, 4), (6, 1, 5), (4, 2, 6), (33, 128, 9)])
+@pytest.mark.parametrize("shape", [(5, 16, 7), (9, 7, 4), (6, 1, 5), (4, 2, 6), (33, 128, 9), (7, 32, 5),
+                                   (11, 64, 13), (40, 128, 33)])
 def test_dft_matches_oracle(P, shape):
     nr, nt, nz = shape
     say("dft", shape)
