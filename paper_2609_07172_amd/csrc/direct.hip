@@ -202,8 +202,8 @@ __global__ __launch_bounds__(kDirThreads) void k_direct(DirectArgs a) {
 // kernel and axial rows 64h .. 64h + 63 in the second, so 128 planes fill 256
 // compute units; wave w owns radial columns 16w .. 16w + 15, whose values it
 // keeps in registers for every k-step, while the eigenvector half sits in LDS.
-//   k_direct_fwd: g = V^T f for its eigenvectors, then one more wave
-//     eliminates and back-substitutes each eigenvector's system with the
+//   k_direct_fwd: g = V^T f for its eigenvectors, then the waves
+//     eliminate and back-substitute each eigenvector's system with the
 //     elimination factors m_i formed when the plan is built (per plane and
 //     eigenvector: the factor chain is a division per step, and on the FP64
 //     pipe the matrix products share it would run after them, not beside
@@ -223,9 +223,10 @@ constexpr int kBigInvThreads = kBigWaves * 64;
 constexpr int kBigLdg = kDirectBigMax + 1;                    // LDS pitch of g's rows (odd)
 constexpr int kBigV = kDirectBigMax * kBigHalf;               // one half of V (or V^T) in LDS
 constexpr int kBigVG = kBigV > kBigHalf * kBigLdg ? kBigV : kBigHalf * kBigLdg;
-constexpr int kBigFwdLds = kBigVG + kDirectBigMax * kBigHalf + 2 * kDirectBigMax;
+constexpr int kBigFwdLds = kBigVG + kDirectBigMax * kBigHalf + 2 * kDirectBigMax + 3 * (kBigWaves + 1) * kBigHalf;
 constexpr int kBigInvLds = kBigV;
-constexpr int kBigChain = 8;                                  // chain steps per block of LDS loads
+constexpr int kBigSeg = 16;                                   // rows per wave's elimination segment (>= 128 / 9)
+static_assert(kBigSeg * (kBigWaves + 1) >= kDirectBigMax, "the segments cover every row");
 
 struct BigArgs {
     LevelView v;
@@ -283,12 +284,10 @@ __device__ __forceinline__ bool big_block(int halves, int np, int* h, int* p) {
 __host__ inline int big_blocks(int halves, int np) { return halves == 1 ? np : 16 * ((np + 7) / 8); }
 
 // Transform and eliminations.  Waves 0 .. ceil(nri / 16) - 1 form g = V^T f
-// for their radial columns; then wave kBigWaves runs the eliminations,
+// for their radial columns; then all nine waves run the eliminations,
 //   d_i = m_i g_i + (rw_i m_i) d_{i-1},  w_i = d_i + (re_i m_i) w_{i+1}
-// (one fused multiply-add per step on each chain), loading its operands from
-// LDS kBigChain steps at a time (each step otherwise waits for its loads).
-// Factor rows past nri are zero, so the steps past the last node give zeros
-// that are never read.
+// (one fused multiply-add per step on each chain), each on one segment of
+// the rows (see below).
 __global__ __launch_bounds__(kBigFwdThreads) void k_direct_fwd(BigArgs a) {
     extern __shared__ double smem[];
     const LevelView v = a.v;
@@ -308,7 +307,7 @@ __global__ __launch_bounds__(kBigFwdThreads) void k_direct_fwd(BigArgs a) {
     // V's half whole (the products read rows up to 4 ceil(nzi / 4) - 1); the
     // factors' rows the eliminations' blocks reach (rows past nri are zero)
     HalfStage<kBigFwdThreads, 2> stage;
-    const int lim[2] = {kBigV, min(kDirectBigMax, (nri + kBigChain - 1) / kBigChain * kBigChain) * kBigHalf};
+    const int lim[2] = {kBigV, nri * kBigHalf};
     {
         const double* const src[2] = {a.V, a.M + (size_t)plane * kDirectBigMax * kDirectBigMax};
         stage.load(src, lim, j0, t);
@@ -372,46 +371,108 @@ __global__ __launch_bounds__(kBigFwdThreads) void k_direct_fwd(BigArgs a) {
                 VG[(16 * jt + (l >> 4) + 4 * q) * kBigLdg + 16 * wave + (l & 15)] = acc[jt][q];
     }
     __syncthreads();
-    if (wave == kBigWaves && l < nj) {
+    // The eliminations as segmented recurrences: wave w takes rows
+    // [w L, (w + 1) L) of every eigenvector (lane j), so each chain is L steps
+    // long instead of nri.  Forward, d_i = q_i d_{i-1} + e_i with q_i = rw_i m_i,
+    // e_i = m_i g_i: each segment runs from zero and keeps the product of its
+    // q_i; one wave then carries the true d into every segment; each segment
+    // adds carry times its running product.  Back substitution, w_i = c_i
+    // w_{i+1} + d_i with c_i = re_i m_i, the same from the top.  Steps past a
+    // segment's end are identities (factor 1, term 0), so no branch sits on a
+    // chain.
+    {
+        constexpr int S = kBigWaves + 1;
+        const int L = (nri + S - 1) / S;
+        const int i0 = wave * L, len = max(0, min(L, nri - i0));
         double* g = VG + l * kBigLdg;
-        double d = 0.0;
-        for (int i0 = 0; i0 < nri; i0 += kBigChain) {
-            double gv[kBigChain], qv[kBigChain];
+        double* Pe = M + kDirectBigMax * kBigHalf + 2 * kDirectBigMax;  // [S][64] segment products
+        double* De = Pe + S * kBigHalf;                                   // [S][64] segment ends
+        double* Ci = De + S * kBigHalf;                                   // [S][64] carries in
+        const bool lane_on = l < nj;
+        double fac[kBigSeg], val[kBigSeg];
+        // forward: local recurrences
+        {
 #pragma unroll
-            for (int u = 0; u < kBigChain; ++u) {
-                const double m = M[(i0 + u) * kBigHalf + l];
-                gv[u] = g[i0 + u] * m;
-                qv[u] = rw[i0 + u] * m;
+            for (int u = 0; u < kBigSeg; ++u) {
+                const int i = min(i0 + u, kDirectBigMax - 1);
+                const double m = M[i * kBigHalf + l];
+                const bool in = u < len;
+                fac[u] = in ? rw[i] * m : 1.0;
+                val[u] = in ? g[i] * m : 0.0;
+            }
+            double d = 0.0, P = 1.0;
+#pragma unroll
+            for (int u = 0; u < kBigSeg; ++u) {
+                d = fma(fac[u], d, val[u]);
+                P *= fac[u];
+                val[u] = d;
             }
 #pragma unroll
-            for (int u = 0; u < kBigChain; ++u) {
-                d = fma(qv[u], d, gv[u]);
-                gv[u] = d;
-            }
-#pragma unroll
-            for (int u = 0; u < kBigChain; ++u) g[i0 + u] = gv[u];
+            for (int u = 0; u < kBigSeg; ++u)
+                if (u < len && lane_on) g[i0 + u] = val[u];
+            Pe[wave * kBigHalf + l] = P;
+            De[wave * kBigHalf + l] = d;
         }
-        double w = 0.0;
-        for (int top = nri - 1; top >= 0; top -= kBigChain) {
-            double gv[kBigChain], cv[kBigChain];
-            double rv[kBigChain], mv[kBigChain];
+        __syncthreads();
+        if (wave == 0) {
+            double d = 0.0;
+            for (int w = 0; w < S; ++w) {
+                Ci[w * kBigHalf + l] = d;
+                d = fma(Pe[w * kBigHalf + l], d, De[w * kBigHalf + l]);
+            }
+        }
+        __syncthreads();
+        {
+            const double c = Ci[wave * kBigHalf + l];
+            double P = 1.0;
 #pragma unroll
-            for (int u = 0; u < kBigChain; ++u) {
-                const int i = max(top - u, 0);
-                gv[u] = g[i];
-                rv[u] = re[i];
-                mv[u] = M[i * kBigHalf + l];
+            for (int u = 0; u < kBigSeg; ++u) {
+                P *= fac[u];
+                if (u < len && lane_on) g[i0 + u] = fma(P, c, g[i0 + u]);
+            }
+        }
+        __syncthreads();
+        // back substitution: local recurrences from the segment's top row down
+        {
+#pragma unroll
+            for (int u = 0; u < kBigSeg; ++u) {
+                const int i = min(max(i0 + len - 1 - u, 0), kDirectBigMax - 1);
+                const bool in = u < len;
+                const double m = M[i * kBigHalf + l];
+                fac[u] = in ? re[i] * m : 1.0;
+                val[u] = in ? g[i] : 0.0;
+            }
+            double w = 0.0, P = 1.0;
+#pragma unroll
+            for (int u = 0; u < kBigSeg; ++u) {
+                w = fma(fac[u], w, val[u]);
+                P *= fac[u];
+                val[u] = w;
             }
 #pragma unroll
-            for (int u = 0; u < kBigChain; ++u) cv[u] = rv[u] * mv[u];
-#pragma unroll
-            for (int u = 0; u < kBigChain; ++u) {
-                w = fma(cv[u], w, gv[u]);
-                gv[u] = w;
+            for (int u = 0; u < kBigSeg; ++u)
+                if (u < len && lane_on) g[i0 + len - 1 - u] = val[u];
+            Pe[wave * kBigHalf + l] = P;
+            De[wave * kBigHalf + l] = w;
+        }
+        __syncthreads();
+        if (wave == 0) {
+            double w = 0.0;
+            for (int sg = S - 1; sg >= 0; --sg) {
+                Ci[sg * kBigHalf + l] = w;
+                w = fma(Pe[sg * kBigHalf + l], w, De[sg * kBigHalf + l]);
             }
+        }
+        __syncthreads();
+        {
+            const double c = Ci[wave * kBigHalf + l];
+            double P = 1.0;
 #pragma unroll
-            for (int u = 0; u < kBigChain; ++u)
-                if (top - u >= 0) g[top - u] = gv[u];
+            for (int u = 0; u < kBigSeg; ++u) {
+                P *= fac[u];
+                const int i = i0 + len - 1 - u;
+                if (u < len && lane_on) g[i] = fma(P, c, g[i]);
+            }
         }
     }
     __syncthreads();
