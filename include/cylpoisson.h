@@ -238,18 +238,19 @@ void cylpoisson_plan_destroy(cylpoisson_plan* plan);
  *                    the iterate's error u* - u (u* the solve to tol 1e-14 first)
  *                    (default 0)
  *   "fmg"            1 = full-multigrid start: the right-hand side is restricted
- *                    to every level, the LDS bottom kernel solves the coarsest
- *                    ones from zero, its answer is interpolated up to level 1,
- *                    which takes one V-cycle from it, and the V-cycles on the
+ *                    down to the level where the V-cycle stops, which is solved
+ *                    there (exactly under "direct", else by the LDS bottom
+ *                    kernel from zero); that answer is interpolated up to level
+ *                    1, which takes one V-cycle from it, and the V-cycles on the
  *                    finest level start from the interpolated level-1 answer.
  *                    Its error is then smaller per unit of residual, so a
  *                    looser tol reaches a given error (at 400 x 128 x 512, tol
- *                    1e-13 gives rel-L2 5e-13 in 6 cycles, against 8 cycles
+ *                    1e-13 gives rel-L2 2e-13 in 6 cycles, against 8 cycles
  *                    to 1e-14 from zero).  With "precision" 32 the FP64
  *                    refinement starts from that iterate (its residual measured
  *                    against the right-hand side as for a warm start).  Needs
- *                    the fused passes and the LDS bottom kernel; ignored
- *                    otherwise, and with "warm_start" or "krylov" (default 0)
+ *                    the fused passes down to that level; ignored otherwise,
+ *                    and with "warm_start" or "krylov" (default 0)
  *   "merge"          1 = a cycle after which no convergence check follows ends in
  *                    one finest-level pass that does its up pass and the next
  *                    cycle's down pass (prolongation, nu2 + nu1 sweeps, residual,
@@ -257,8 +258,9 @@ void cylpoisson_plan_destroy(cylpoisson_plan* plan);
  *                    iterates and answers are bitwise those of separate passes;
  *                    such a cycle's residual norm is not formed (NaN in the
  *                    history).  Applies with the fused passes on the finest level,
- *                    nu1 = nu2 = 2, at most 512 radial nodes, one plane group and
- *                    no graphs (default 1)
+ *                    nu1 + nu2 from 4 to 6, at most 512 radial nodes and one
+ *                    plane group; captured graphs ("graph") merge the same
+ *                    passes (default 1)
  *   "merge_prefetch" rows the merged pass loads ahead of the one it consumes (1 .. 2; default 1)
  *   "direct"         exact solve of a coarse level (Sec. 3.3 solves the coarsest one
  *                    directly): the V-cycle stops at that level and solves it on every
@@ -275,9 +277,10 @@ void cylpoisson_plan_destroy(cylpoisson_plan* plan);
  *                    by every FP64 V-cycle, the full-multigrid start included; the
  *                    FP32 inner cycles of "precision" 32 keep the bottom kernel.
  *                    Ignored where no level qualifies (0 .. 2; default 1)
- *   "graph"          1 = each V-cycle is captured once into a HIP graph and replayed
- *                    (single plane group, "timing" 0; default 0).  Setting any
- *                    option releases the captured graphs
+ *   "graph"          1 = the cycles from one convergence check to the next are
+ *                    captured once into a HIP graph and replayed (single plane
+ *                    group, "timing" 0; default 0).  Setting any option releases
+ *                    the captured graphs
  * Returns CYLPOISSON_OK, CYLPOISSON_EINVAL or CYLPOISSON_ENOMEM. */
 int cylpoisson_plan_set_option(cylpoisson_plan* plan, const char* key, double value);
 
