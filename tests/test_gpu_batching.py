@@ -158,14 +158,16 @@ def test_graph_replays_on_the_per_step_path(P, options):
         np.testing.assert_array_equal(host(a), host(b))
 
 
-def test_graph_replays_equal_eager_launches(P):
-    """Each cycle's graph is captured on the first solve and replayed on later
-    ones; every replay (with eager work and synchronisations in between) must
-    give the eager result bit for bit."""
+@pytest.mark.parametrize("options", [{}, {"masks": 1}, {"fmg": 1, "masks": 1}], ids=["plain", "masks", "fmg-masks"])
+def test_graph_replays_equal_eager_launches(P, options):
+    """The cycles between two checks are captured on the first solve that runs
+    them and replayed on later ones; every replay (with eager work and
+    synchronisations in between) must give the eager result bit for bit, with
+    per-plane masks updated between the segments too."""
     p = W.BATCHED.with_sizes(129, 16, 97)
     rhos = [dev(W.blob_charge(p, seed=s)) for s in (1, 2, 3)]
-    eager = P.Plan.for_problem(p)
-    graph = P.Plan.for_problem(p, graph=1)
+    eager = P.Plan.for_problem(p, **options)
+    graph = P.Plan.for_problem(p, graph=1, **options)
     for rep in range(3):
         for r in rhos:
             a, sa = eager.solve(r, tol=1e-14)

@@ -546,8 +546,9 @@ def test_warm_first_check_not_from_a_cold_solve(P):
 @pytest.mark.parametrize("direct", [1, 2])
 @pytest.mark.parametrize("prob,tol", [(W.SMALL, 1e-14), (W.BATCHED, 1e-14), (W.HIGH_SHIFT, 1e-14),
                                       # direct = 1 takes a level above 64 nodes each way
-                                      # (two-kernel form): 127 x 127, 99 x 127, 107 x 46
-                                      # and 15 x 99 interior nodes
+                                      # (two-kernel form): 128 x 128 (the largest), 127 x 127,
+                                      # 99 x 127, 107 x 46 and 15 x 99 interior nodes
+                                      (W.SMALL.with_sizes(259, 4, 259), 1e-14),
                                       (W.SMALL.with_sizes(257, 4, 257), 1e-14),
                                       (W.SMALL.with_sizes(400, 8, 512), 1e-14),
                                       (W.SMALL.with_sizes(217, 6, 94), 1e-14),
