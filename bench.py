@@ -34,11 +34,25 @@ REL_L2_TARGET = 1e-12
 # each start (error per residual: about 9 after the full-multigrid start, 70
 # from zero)
 START_TOL = {"fmg": 1e-13, "zero": 1e-14}
-# algorithmic bytes of the full-multigrid start per finest unknown: read f (8),
-# write the level-1 right-hand side (2), one V-cycle from level 1 down
-# (69.3 / 4); the first finest down pass then forms the start from the level-1
-# answer (2) instead of reading an iterate (8), so it is never written
-FMG_BYTES = 8.0 + 2.0 + 69.3 / 4 + 2.0 - 8.0
+
+
+def cycle_bytes(direct_level):
+    """Algorithmic bytes per finest unknown of one V-cycle: 52 B per unknown of
+    each level on fused down and up passes (26 B each), levels weighted 4^-l,
+    down to the level solved exactly (32 B per unknown of it: read f, write and
+    read w, write u); 52 * 4 / 3 = 69.3 B with every level on passes."""
+    if direct_level is None or direct_level < 1:
+        return 52.0 * 4.0 / 3.0
+    return sum(52.0 * 4.0 ** -l for l in range(direct_level)) + 32.0 * 4.0 ** -direct_level
+
+
+def fmg_bytes(direct_level):
+    """Algorithmic bytes of the full-multigrid start per finest unknown: read f
+    (8), write the level-1 right-hand side (2), one V-cycle from level 1 down
+    (the cycle's bytes below the finest level); the first finest down pass then
+    forms the start from the level-1 answer (2) instead of reading an iterate
+    (8), so it is never written."""
+    return 8.0 + 2.0 + (cycle_bytes(direct_level) - 52.0) + 2.0 - 8.0
 SEQ_FIELDS = 8  # seeded drift directions the 200-step sequence cycles through
 FUSED_SOURCES = ("paper_2609_07172_amd/csrc/fused.hip", "paper_2609_07172_amd/csrc/fused_pass.h",
                  "paper_2609_07172_amd/csrc/stencil.h")
@@ -776,8 +790,9 @@ def main():
     # each merged pass moves 24 B per finest unknown less than the up and down
     # passes it replaces (u and f read once, u written once)
     merges = launches.get("fine_merged", 0) / args.steps
-    model_bytes = (16.0 * problem.nodes + 16.0 * unknowns + 69.3 * st["cycles"] * unknowns
-                   + (FMG_BYTES * unknowns if fmg else 0.0) - 24.0 * merges * unknowns)
+    dlev = info["direct_level"]
+    model_bytes = (16.0 * problem.nodes + 16.0 * unknowns + cycle_bytes(dlev) * st["cycles"] * unknowns
+                   + (fmg_bytes(dlev) * unknowns if fmg else 0.0) - 24.0 * merges * unknowns)
     out = {
         "metric": METRIC,
         "value": round(ms, 4),
@@ -807,8 +822,8 @@ def main():
         "ms_min": round(min(per) * 1e3, 4),
         "ms_p50": round(float(np.median(per)) * 1e3, 4),
         # the whole solve against the algorithmic byte model: 16 B per node and per
-        # unknown for the transforms, 69.3 B per unknown and V-cycle, less 24 B
-        # per unknown and merged pass, and for the full-multigrid start FMG_BYTES
+        # unknown for the transforms, cycle_bytes per unknown and V-cycle, less 24 B
+        # per unknown and merged pass, and for the full-multigrid start fmg_bytes
         # per unknown (restrict f, one V-cycle from level 1 down)
         "solve_roofline": {"model_bytes": model_bytes,
                            "t_roof_ms": round(model_bytes / (HBM_PEAK_GBS * 1e9) * 1e3, 4),

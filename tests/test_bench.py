@@ -71,7 +71,12 @@ def test_accuracy_measures_on_a_planted_error():
 
 
 def test_full_multigrid_byte_model():
-    """Start: read f, write the level-1 right-hand side, one V-cycle from level 1
-    (a quarter of 69.3 B); the first down pass reads the level-1 answer (2 B)
-    instead of the iterate (8 B)."""
-    assert abs(bench.FMG_BYTES - (8 + 2 + 69.3 / 4 + 2 - 8)) < 1e-12
+    """A V-cycle: 52 B per unknown of each level on passes (weighted 4^-l) down
+    to the exactly solved level (32 B per unknown of it), 69.3 B with every
+    level on passes.  Start: read f, write the level-1 right-hand side, one
+    V-cycle from level 1 (the cycle's bytes below the finest level); the first
+    down pass reads the level-1 answer (2 B) instead of the iterate (8 B)."""
+    assert abs(bench.cycle_bytes(-1) - 52 * 4 / 3) < 1e-12
+    assert abs(bench.cycle_bytes(2) - (52 + 13 + 2)) < 1e-12  # 400 x 128 x 512: level 2 exact
+    assert abs(bench.fmg_bytes(-1) - (8 + 2 + 69.3333333333333 / 4 + 2 - 8)) < 1e-9
+    assert abs(bench.fmg_bytes(2) - (8 + 2 + 15 + 2 - 8)) < 1e-12
