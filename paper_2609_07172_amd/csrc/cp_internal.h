@@ -402,8 +402,8 @@ hipError_t fused_up(cylpoisson_plan* p, int l, double* partial, int partial_ld, 
 int fused_chunks(const cylpoisson_plan* p, int l, int nu);
 // The finest down pass whose input interior is zero plus the prolongated
 // level-1 iterate (first cycle after a full-multigrid start); when it applies.
-bool fused_down_pro_ok(const cylpoisson_plan* p);
-hipError_t fused_down_pro(cylpoisson_plan* p, hipStream_t s, int p0 = 0, int np = -1);
+bool fused_down_pro_ok(const cylpoisson_plan* p, int l = 0);
+hipError_t fused_down_pro(cylpoisson_plan* p, hipStream_t s, int p0 = 0, int np = -1, int l = 0);
 // The merged finest pass: the up pass of one cycle (u2 + P C.u, nu2 sweeps)
 // and the down pass of the next (nu1 sweeps, residual, C.f = P^T r), writing
 // the iterate to u (the caller then swaps u and u2).

@@ -32,27 +32,28 @@ hipError_t fused_down(cylpoisson_plan* p, int l, bool zero_u, bool zero_interior
                              sh.threads, sh.lds, s);
 }
 
-// The first finest down pass after a full-multigrid start with the start's
-// finest interpolation folded in (k_pass_fine_pro): FP64, two pre-sweeps with
-// one row of prefetch (the tuned finest pass) or three with two, fused finest
-// level.
-bool fused_down_pro_ok(const cylpoisson_plan* p) {
-    const int nu = nu_pre(p, 0);
-    if (!fused_supported(p, 0) || (nu != 2 && nu != 3)) return false;
+// The first down pass on level l after a full-multigrid start, with the
+// start's interpolation from level l + 1 folded in (k_pass_fine_pro): FP64,
+// two pre-sweeps with one row of prefetch or three with two, fused passes on
+// level l.  The finest level's first cycle uses it, and so does the start's
+// own V-cycle on level 1.
+bool fused_down_pro_ok(const cylpoisson_plan* p, int l) {
+    const int nu = nu_pre(p, l);
+    if (!fused_supported(p, l) || (nu != 2 && nu != 3)) return false;
     if (nu == 2 && pass_prefetch<double>(2, p->opt.prefetch) != 1) return false;
-    const Shape sh = pass_shape<double>(p, 0, nu, true, true);
+    const Shape sh = pass_shape<double>(p, l, nu, true, true);
     // three sweeps: one wave per SIMD (at most 256 threads, the registers of
     // two) and up to 80 KB of LDS (two workgroups per compute unit)
     return nu == 2 ? sh.lds <= 64 * 1024 : (sh.threads <= 256 && sh.lds <= 80 * 1024);
 }
 
-hipError_t fused_down_pro(cylpoisson_plan* p, hipStream_t s, int p0, int np) {
+hipError_t fused_down_pro(cylpoisson_plan* p, hipStream_t s, int p0, int np, int l) {
     if (np < 0) np = p->nt;
-    DeviceLevel& L = p->dl[0];
-    DeviceLevel& C = p->dl[1];
-    const int nu = nu_pre(p, 0);
-    const Shape sh = pass_shape<double>(p, 0, nu, true, true);
-    PassArgs<double> a = make_args<double>(p, 0, sh, p0, np);
+    DeviceLevel& L = p->dl[l];
+    DeviceLevel& C = p->dl[l + 1];
+    const int nu = nu_pre(p, l);
+    const Shape sh = pass_shape<double>(p, l, nu, true, true);
+    PassArgs<double> a = make_args<double>(p, l, sh, p0, np);
     a.u_in = L.u;  // its ring; the interior is zero plus the prolongated C.u
     a.f = L.f;
     a.u_out = L.u2;

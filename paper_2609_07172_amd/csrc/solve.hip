@@ -1122,9 +1122,11 @@ hipError_t fmg_start(cylpoisson_plan* p, hipStream_t s, bool fused_top) {
     if (e == hipSuccess) e = direct_active(p) ? launch_direct(p, s) : launch_bottom(p, s);
     for (int l = lb - 1; l >= 1 && e == hipSuccess; --l) {
         DeviceLevel& L = p->dl[l];
-        e = launch_prolong(L, p->dl[l + 1], nt, p->dl[l + 1].u, L.u, s, false);
+        // level 1's down pass forms the interpolated answer as it streams
+        const bool pro1 = l == 1 && fused_down_pro_ok(p, 1);
+        if (!pro1) e = launch_prolong(L, p->dl[l + 1], nt, p->dl[l + 1].u, L.u, s, false);
         if (l > 1) continue;
-        if (e == hipSuccess) e = fused_down(p, l, false, false, s);
+        if (e == hipSuccess) e = pro1 ? fused_down_pro(p, s, 0, -1, 1) : fused_down(p, l, false, false, s);
         if (e == hipSuccess) e = vcycle(p, l + 1, s, true, -1, nullptr);
         if (e == hipSuccess) e = fused_up(p, l, nullptr, kMaxPartial, nullptr, s);
     }
