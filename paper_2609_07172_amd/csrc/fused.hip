@@ -61,7 +61,12 @@ hipError_t fused_down_pro(cylpoisson_plan* p, hipStream_t s, int p0, int np, int
     a.ec = C.u;
     a.zero_interior = 1;
     if (nu == 2) {
-        k_pass_fine_pro<double, 2, 1><<<sh.nchunks * np, sh.threads, sh.lds, s>>>(a);
+        if (a.rows_steady)
+            k_pass_fine_pro_rows<double, 2, 1><<<sh.nchunks * np, sh.threads, sh.lds, s>>>(a);
+        else if (l == 0)
+            k_pass_fine_pro<double, 2, 1><<<sh.nchunks * np, sh.threads, sh.lds, s>>>(a);
+        else
+            k_pass_pro<double, 2, 1><<<sh.nchunks * np, sh.threads, sh.lds, s>>>(a);
         return hipGetLastError();
     }
     k_pass_fine_pro<double, 3, pass_prefetch<double>(3, 1)><<<sh.nchunks * np, sh.threads, sh.lds, s>>>(a);
@@ -80,6 +85,13 @@ bool fused_merge_ok(const cylpoisson_plan* p) {
 
 template <int NU, int PD>
 hipError_t launch_merge(const PassArgs<double>& a, int blocks, int threads, size_t lds, hipStream_t s) {
+    // the default merged pass has an instantiation with per-row unchecked steps
+    if constexpr (NU == 4 && PD == 1) {
+        if (a.rows_steady) {
+            k_pass_merge_rows<double, NU, PD><<<blocks, threads, lds, s>>>(a);
+            return hipGetLastError();
+        }
+    }
     k_pass_merge<double, NU, PD><<<blocks, threads, lds, s>>>(a);
     return hipGetLastError();
 }
@@ -90,6 +102,7 @@ hipError_t launch_merge(const PassArgs<double>& a, int blocks, int threads, size
 // needs a host call (a launch under graph capture included).
 hipError_t fused_prepare() {
     const void* k[] = {reinterpret_cast<const void*>(&k_pass_merge<double, 4, 1>),
+                       reinterpret_cast<const void*>(&k_pass_merge_rows<double, 4, 1>),
                        reinterpret_cast<const void*>(&k_pass_merge<double, 4, 2>),
                        reinterpret_cast<const void*>(&k_pass_merge<double, 5, 1>),
                        reinterpret_cast<const void*>(&k_pass_merge<double, 5, 2>),

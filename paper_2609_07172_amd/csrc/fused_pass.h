@@ -60,6 +60,7 @@ struct PassArgs {
     const int* colc;     // fine column -> coarse interior column it coincides with, else -1
     const int* rowc;     // fine row -> coarse interior row it coincides with, else -1
     int reg_lo, reg_hi;  // rows reg_lo <= y < reg_hi share the axial coefficients (zc0, zs0, zn0)
+    int rows_steady;     // rows outside that band also take unchecked steps (per-row coefficients)
     double* partial;     // up: per (plane, chunk) sum of squared residuals, or nullptr
     int partial_ld;      // stride between planes in `partial`
     double omega, zc0, zs0, zn0;
@@ -73,7 +74,10 @@ struct PassArgs {
 // PRO (down passes only): the input's interior is taken as zero plus the
 // prolongated coarse answer ec, formed as rows are consumed (the start of the
 // first cycle after a full-multigrid guess, which then is never written).
-template <typename T, int NU, int PD, bool DOWN, bool ZERO_U, bool PRO = false>
+// ROWS: the pass also has unchecked steps that form each row's coefficients
+// from its tables (kSteadyRows), for levels with few rows in the regular band;
+// its own instantiation, so the other passes keep their registers.
+template <typename T, int NU, int PD, bool DOWN, bool ZERO_U, bool PRO = false, bool ROWS = false>
 struct Pass {
     static_assert(!PRO || DOWN, "PRO is a down-pass mode");
     // the pass prolongates a coarse correction into its input rows
@@ -90,6 +94,7 @@ struct Pass {
     // at one step are K(x) .. K(x + PD + 1) + 1 for the consumed row x: at most
     // 4 with one row of prefetch (a coarse interval spans one or two fine rows).
     static constexpr int kCRing = PD == 1 ? 4 : 8;
+    static constexpr int kSteady = 0, kSteadyRows = 1, kChecked = 2;
 
     const PassArgs<T>& a;
     char* smem;
@@ -350,37 +355,40 @@ struct Pass {
     __device__ __forceinline__ CoefT<T> irregular(double rw, double re, double rb, double rm, int y) {
         return coef_as<T>(make_coef(rw, re, rb, rm, rowzc()[y - s], rowzs()[y - s], rowzn()[y - s], lam));
     }
-    template <bool CHK>
+    // Step modes: kSteady (every row in the regular band, no bounds checks),
+    // kSteadyRows (no bounds checks, every row's coefficients from its tables:
+    // the band's own rows give the band's values exactly) and kChecked.
+    template <int MODE>
     __device__ __forceinline__ CoefT<T> coef1(int y) {
-        if (!CHK || regular(y)) return cu1;
+        if (MODE == kSteady || (MODE == kChecked && regular(y))) return cu1;
         return irregular(rw1, re1, rb1, rm1, y);
     }
-    template <bool CHK>
+    template <int MODE>
     __device__ __forceinline__ CoefT<T> coef2(int y) {
-        if (!CHK || regular(y)) return cu2;
+        if (MODE == kSteady || (MODE == kChecked && regular(y))) return cu2;
         return irregular(rw2, re2, rb2, rm2, y);
     }
 
     // Half-sweep on row y (slot SY; SM = y-1, SP = y+1).  C1: the colour being
     // relaxed sits on column c1 of this row.  NB: the horizontal neighbour from
     // another thread (west of c1 or east of c2), published one step earlier.
-    template <int SY, int SM, int SP, bool C1, bool CHK>
+    template <int SY, int SM, int SP, bool C1, int MODE>
     __device__ __forceinline__ void half_sweep(int y, T nb) {
         if (C1) {
-            const T v = relax(uu[SY][0], ff[SY][0], nb, uu[SY][1], uu[SM][0], uu[SP][0], coef1<CHK>(y), om);
+            const T v = relax(uu[SY][0], ff[SY][0], nb, uu[SY][1], uu[SM][0], uu[SP][0], coef1<MODE>(y), om);
             uu[SY][0] = act1 ? v : uu[SY][0];
             At[SY] = uu[SY][0];
         } else {
-            const T v = relax(uu[SY][1], ff[SY][1], uu[SY][0], nb, uu[SM][1], uu[SP][1], coef2<CHK>(y), om);
+            const T v = relax(uu[SY][1], ff[SY][1], uu[SY][0], nb, uu[SM][1], uu[SP][1], coef2<MODE>(y), om);
             uu[SY][1] = act2 ? v : uu[SY][1];
             Bt[SY] = uu[SY][1];
         }
     }
 
-    template <int SY, int SM, int SP, bool CHK>
+    template <int SY, int SM, int SP, int MODE>
     __device__ __forceinline__ void residual_row(int y, T nw, T ne, T& r1, T& r2) {
-        const T x1 = residual(uu[SY][0], ff[SY][0], nw, uu[SY][1], uu[SM][0], uu[SP][0], coef1<CHK>(y));
-        const T x2 = residual(uu[SY][1], ff[SY][1], uu[SY][0], ne, uu[SM][1], uu[SP][1], coef2<CHK>(y));
+        const T x1 = residual(uu[SY][0], ff[SY][0], nw, uu[SY][1], uu[SM][0], uu[SP][0], coef1<MODE>(y));
+        const T x2 = residual(uu[SY][1], ff[SY][1], uu[SY][0], ne, uu[SM][1], uu[SP][1], coef2<MODE>(y));
         r1 = act1 ? x1 : T(0);
         r2 = act2 ? x2 : T(0);
     }
@@ -400,10 +408,12 @@ struct Pass {
     }
 
     // One step: consume row x and run every half-sweep, the residual and the
-    // transfers on the rows behind it.  CHK = false in the steady middle of the
-    // chunk, where every row involved is interior, regular and inside the chunk.
-    template <int J, bool CHK>
+    // transfers on the rows behind it.  Steady modes in the middle of the chunk,
+    // where every row involved is interior and inside the chunk (and, for
+    // kSteady, regular).
+    template <int J, int MODE>
     __device__ __forceinline__ void step(int x) {
+        constexpr bool CHK = MODE == kChecked;
         lds_barrier();
         // every LDS value read here was published at an earlier step, and this
         // step only writes locations nobody reads during it
@@ -431,7 +441,7 @@ struct Pass {
         constexpr int sp = (J - (h) + 4 * Q) % Q;                                            \
         constexpr bool c1col = ((((J - 1 - (h)) & 1) + 1) & 1) == ((h) & 1);                 \
         const int y = x - 1 - (h);                                                           \
-        if (!CHK || (y >= ylo && y <= yhi)) half_sweep<sy, sm, sp, c1col, CHK>(y, nb[(h)]); \
+        if (!CHK || (y >= ylo && y <= yhi)) half_sweep<sy, sm, sp, c1col, MODE>(y, nb[(h)]); \
     }
         CP_HS(0) CP_HS(1) CP_HS(2) CP_HS(3) CP_HS(4) CP_HS(5) CP_HS(6) CP_HS(7)
         CP_HS(8) CP_HS(9) CP_HS(10) CP_HS(11)
@@ -453,7 +463,7 @@ struct Pass {
         if (DOWN) {
             T r1 = T(0), r2 = T(0);
             if (!CHK || (y >= max(1, za - 1) && y <= min(a.v.nz - 2, zb)))
-                residual_row<jy, jm, jq, CHK>(y, rnw, rne, r1, r2);
+                residual_row<jy, jm, jq, MODE>(y, rnw, rne, r1, r2);
             r_m2[0] = r_m1[0];
             r_m2[1] = r_m1[1];
             r_m1[0] = r_0[0];
@@ -474,24 +484,35 @@ struct Pass {
         } else if (a.partial) {
             if (!CHK || (y >= za && y < zb && y <= a.v.nz - 2)) {
                 T r1, r2;
-                residual_row<jy, jm, jq, CHK>(y, rnw, rne, r1, r2);
+                residual_row<jy, jm, jq, MODE>(y, rnw, rne, r1, r2);
                 acc = fma((double)r1, (double)r1, acc);
                 acc = fma((double)r2, (double)r2, acc);
             }
         }
     }
 
-    template <bool CHK>
+    template <int MODE>
     __device__ __forceinline__ void group(int x0, int xend) {
+        constexpr bool CHK = MODE == kChecked;
         // Q consecutive steps with compile-time register and LDS slots
-#define CP_STEP(J)                                            \
-    if constexpr ((J) < Q) {                                  \
-        if (!CHK || x0 + (J) <= xend) step<(J), CHK>(x0 + (J)); \
+#define CP_STEP(J)                                             \
+    if constexpr ((J) < Q) {                                   \
+        if (!CHK || x0 + (J) <= xend) step<(J), MODE>(x0 + (J)); \
     }
         CP_STEP(0) CP_STEP(1) CP_STEP(2) CP_STEP(3) CP_STEP(4) CP_STEP(5) CP_STEP(6) CP_STEP(7)
         CP_STEP(8) CP_STEP(9) CP_STEP(10) CP_STEP(11) CP_STEP(12) CP_STEP(13) CP_STEP(14) CP_STEP(15)
         CP_STEP(16) CP_STEP(17)
 #undef CP_STEP
+    }
+
+    // The groups of Q steps from s that lie wholly in steps lo .. hi: [ga, gb).
+    __device__ __forceinline__ void whole_groups(int lo, int hi, int& ga, int& gb) const {
+        ga = gb = s;
+        if (hi >= lo) {
+            ga = s + ((lo - s + Q - 1) / Q) * Q;
+            gb = ga + ((hi + 1 - ga) / Q) * Q;
+            if (gb <= ga) ga = gb = s;
+        }
     }
 
     __device__ __forceinline__ int plane_of_block() const {
@@ -508,24 +529,29 @@ struct Pass {
         // to finish the pending restriction
         const int ylast = DOWN ? min(a.v.nz - 1, zb) : zb - 1;
         const int xlast = ylast + 2 * NU + 1 + (DOWN ? 1 : 0);
-        // steady steps: every row they touch (x - 2 NU - 1 .. x) is interior,
-        // regular and in the chunk
-        const int lo = max(za + 2 * NU + 2, a.reg_lo + 2 * NU + 1);
-        const int hi = min(min(zb + 2 * NU - 1, a.v.nz - 2), min(lend, a.reg_hi));
-        int ga = s, gb = s;  // [ga, gb): whole groups of steady steps
-        if (hi >= lo) {
-            ga = s + ((lo - s + Q - 1) / Q) * Q;
-            gb = ga + ((hi + 1 - ga) / Q) * Q;
-            if (gb <= ga) ga = gb = s;
-        }
+        // steady steps: every row they touch (x - 2 NU - 1 .. x) is interior
+        // and in the chunk, and for kSteady also regular
+        const int lo1 = za + 2 * NU + 2;
+        const int hi1 = min(min(zb + 2 * NU - 1, a.v.nz - 2), lend);
+        const int lo = max(lo1, a.reg_lo + 2 * NU + 1);
+        const int hi = min(hi1, a.reg_hi);
+        int ga, gb, ga1, gb1;  // [ga, gb), [ga1, gb1): whole groups of steady steps
+        whole_groups(lo, hi, ga, gb);
+        whole_groups(lo1, hi1, ga1, gb1);
 #pragma unroll
         for (int d = 0; d < PD; ++d) issue(s + d, d);
         // one instance of each step group: checked at both ends, steady between
         for (int x0 = s; x0 <= xlast; x0 += Q) {
-            if (x0 >= ga && x0 < gb)
-                group<false>(x0, x0 + Q - 1);
-            else
-                group<true>(x0, xlast);
+            if (x0 >= ga && x0 < gb) {
+                group<kSteady>(x0, x0 + Q - 1);
+            } else if constexpr (ROWS) {
+                if (x0 >= ga1 && x0 < gb1)
+                    group<kSteadyRows>(x0, x0 + Q - 1);
+                else
+                    group<kChecked>(x0, xlast);
+            } else {
+                group<kChecked>(x0, xlast);
+            }
         }
         if (DOWN && pendK >= 0) {
             lds_barrier();
@@ -555,6 +581,15 @@ __global__ void __launch_bounds__(512) k_pass(PassArgs<T> a) {
     pass.run();
 }
 
+// The same pass on a level with few rows in the regular band (a stretched
+// mesh): unchecked steps with per-row coefficients between the checked ends.
+template <typename T, int NU, int PD, bool DOWN, bool ZERO_U>
+__global__ void __launch_bounds__(512) k_pass_rows(PassArgs<T> a) {
+    extern __shared__ double smem[];
+    Pass<T, NU, PD, DOWN, ZERO_U, false, true> pass(a, (char*)smem);
+    pass.run();
+}
+
 // The same pass under its own symbol, launched for the finest level with the
 // default sweep count and prefetch depth, so that kernel traces and counters
 // report the finest level apart from the coarser ones.
@@ -564,6 +599,12 @@ __global__ void __launch_bounds__(512) k_pass_fine(PassArgs<T> a) {
     Pass<T, NU, PD, DOWN, ZERO_U> pass(a, (char*)smem);
     pass.run();
 }
+template <typename T, int NU, int PD, bool DOWN, bool ZERO_U>
+__global__ void __launch_bounds__(512) k_pass_fine_rows(PassArgs<T> a) {
+    extern __shared__ double smem[];
+    Pass<T, NU, PD, DOWN, ZERO_U, false, true> pass(a, (char*)smem);
+    pass.run();
+}
 
 // The finest down pass of the first cycle after a full-multigrid start: the
 // interior of the input is zero plus the prolongated level-1 answer.
@@ -571,6 +612,20 @@ template <typename T, int NU, int PD>
 __global__ void __launch_bounds__(NU == 2 ? 512 : 256) k_pass_fine_pro(PassArgs<T> a) {
     extern __shared__ double smem[];
     Pass<T, NU, PD, true, false, true> pass(a, (char*)smem);
+    pass.run();
+}
+// The same first down pass on a coarser level (level 1 in the start's own
+// V-cycle), under its own symbol.
+template <typename T, int NU, int PD>
+__global__ void __launch_bounds__(NU == 2 ? 512 : 256) k_pass_pro(PassArgs<T> a) {
+    extern __shared__ double smem[];
+    Pass<T, NU, PD, true, false, true> pass(a, (char*)smem);
+    pass.run();
+}
+template <typename T, int NU, int PD>
+__global__ void __launch_bounds__(NU == 2 ? 512 : 256) k_pass_fine_pro_rows(PassArgs<T> a) {
+    extern __shared__ double smem[];
+    Pass<T, NU, PD, true, false, true, true> pass(a, (char*)smem);
     pass.run();
 }
 
@@ -588,12 +643,29 @@ __global__ void __launch_bounds__(256) k_pass_merge(PassArgs<T> a) {
     Pass<T, NU, PD, true, false, true> pass(a, (char*)smem);
     pass.run();
 }
+template <typename T, int NU, int PD>
+__global__ void __launch_bounds__(256) k_pass_merge_rows(PassArgs<T> a) {
+    extern __shared__ double smem[];
+    Pass<T, NU, PD, true, false, true, true> pass(a, (char*)smem);
+    pass.run();
+}
 
 // ---- host side: launch dispatch, launch shape and arguments ----
 
 template <typename T, int NU, int PD, bool DOWN, bool ZERO_U>
 hipError_t launch_t(bool fine, const PassArgs<T>& a, int blocks, int threads, size_t lds, hipStream_t s) {
     if constexpr (NU == 2 && PD == 1) {
+        // the default sweeps on the FP64 path: levels with few regular rows
+        // take the instantiation with per-row unchecked steps
+        if constexpr (std::is_same<T, double>::value) {
+            if (a.rows_steady) {
+                if (fine)
+                    k_pass_fine_rows<T, NU, PD, DOWN, ZERO_U><<<blocks, threads, lds, s>>>(a);
+                else
+                    k_pass_rows<T, NU, PD, DOWN, ZERO_U><<<blocks, threads, lds, s>>>(a);
+                return hipGetLastError();
+            }
+        }
         if (fine) {
             k_pass_fine<T, NU, PD, DOWN, ZERO_U><<<blocks, threads, lds, s>>>(a);
             return hipGetLastError();
@@ -708,6 +780,8 @@ PassArgs<T> make_args(const cylpoisson_plan* p, int l, const Shape& sh, int p0, 
     a.rowc = L.rowc;
     a.reg_lo = L.reg_lo;
     a.reg_hi = L.reg_hi;
+    // a level whose regular band holds under half its rows (a stretched mesh)
+    a.rows_steady = 2 * (L.reg_hi - L.reg_lo) < L.v.nz - 2 ? 1 : 0;
     a.omega = p->opt.omega;
     a.zc0 = L.zc0;
     a.zs0 = L.zs0;

@@ -109,6 +109,24 @@ def test_stretched_cells_every_solver_path(P, options):
     assert rel_l2(host(phi), ref) <= 1e-12, rel_l2(host(phi), ref)
 
 
+@pytest.mark.parametrize("name", ["cell_stretched", "vertex_stretched", "cell_uniform"])
+@pytest.mark.parametrize("chunk", [0, 7])
+def test_fused_passes_on_meshes_equal_the_per_step_kernels(P, name, chunk):
+    """On a stretched mesh almost no two rows share their axial coefficients, so the
+    fused passes take unchecked steps that form every row's coefficients from its
+    tables; the iterates stay bitwise those of the one-kernel-per-step path (the
+    merged finest pass included: no check falls between the first cycles)."""
+    g, rho, _ = reference(name)
+    say("fused-vs-step mesh", name, "chunk", chunk)
+    a = plan_for(P, CASES[name], fused=1, max_cycles=5, chunk_rows=chunk, chunk_rows_coarse=chunk,
+                 chunk_rows_merge=chunk)
+    b = plan_for(P, CASES[name], fused=0, max_cycles=5)
+    pa, sa = a.solve(dev(rho), tol=1e-30, allow=(P.OK, P.NOT_CONVERGED))
+    pb, sb = b.solve(dev(rho), tol=1e-30, allow=(P.OK, P.NOT_CONVERGED))
+    assert sa["cycles"] == sb["cycles"] == 5
+    np.testing.assert_array_equal(host(pa), host(pb))
+
+
 def test_warm_start_on_a_mesh(P):
     g, rho, ref = reference("vertex_stretched")
     say("mesh warm start")
