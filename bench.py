@@ -447,8 +447,9 @@ def time_meshes(problem, args):
     """The paper-scale node counts on explicit cell-centred meshes (App. A):
     uniform cells, and cells stretched geometrically 4:1 towards the inner wall
     and towards z = 0 (boundary-layer refinement), each solved by plain
-    V-cycles, by V-cycle-preconditioned FGMRES and by V-cycles with the
-    alternating zebra line smoother."""
+    V-cycles, by plain V-cycles after the autotuner chose omega, by
+    V-cycle-preconditioned FGMRES and by V-cycles with the alternating zebra
+    line smoother."""
     import torch
 
     import paper_2609_07172_amd as P
@@ -466,9 +467,12 @@ def time_meshes(problem, args):
         rho = torch.from_numpy(W.mesh_blob_charge(W.cell_centres(rf), W.cell_centres(zf), nt, seed=11)).to("cuda:0")
         phi = torch.empty_like(rho)
         rec = {}
-        for label, opts in (("vcycles", {}), ("mg_fgmres", {"krylov": 1, "krylov_precond": 3}),
+        for label, opts in (("vcycles", {}), ("vcycles_tuned_omega", {"tune_omega": 1}),
+                            ("mg_fgmres", {"krylov": 1, "krylov_precond": 3}),
                             ("alternating_lines", {"smoother": 2})):
             plan = P.Plan.from_mesh(rf, zf, nt, P.CELL, problem.bc, **opts)
+            if opts.get("tune_omega"):
+                plan.autotune()
             for _ in range(2):
                 plan.solve(rho, tol=args.tol, phi=phi)
             torch.cuda.synchronize()
@@ -479,7 +483,8 @@ def time_meshes(problem, args):
             torch.cuda.synchronize()
             ms = (time.perf_counter() - t0) / steps * 1e3
             rec[label] = {"ms": round(ms, 4), "cycles": st["cycles"], "krylov_steps": st["krylov_iterations"],
-                          "rel_residual": st["rel_residual"], "fused_levels": plan.info()["fused_levels"]}
+                          "rel_residual": st["rel_residual"], "fused_levels": plan.info()["fused_levels"],
+                          "omega": plan.get_option("omega")}
             log(f"mesh {name} {label}: {ms:.3f} ms/solve, {st['cycles']} V-cycles, "
                 f"rel residual {st['rel_residual']:.3e}")
             plan.close()

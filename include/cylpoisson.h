@@ -281,6 +281,9 @@ void cylpoisson_plan_destroy(cylpoisson_plan* plan);
  *                    captured once into a HIP graph and replayed (single plane
  *                    group, "timing" 0; default 0).  Setting any option releases
  *                    the captured graphs
+ *   "tune_omega"     1 = cylpoisson_autotune also chooses "omega" (point smoother,
+ *                    no "krylov"): stretched meshes want more over-relaxation than
+ *                    the uniform grids the default is set for (0 .. 1; default 0)
  * Returns CYLPOISSON_OK, CYLPOISSON_EINVAL or CYLPOISSON_ENOMEM. */
 int cylpoisson_plan_set_option(cylpoisson_plan* plan, const char* key, double value);
 
@@ -295,8 +298,12 @@ int cylpoisson_plan_get_option(const cylpoisson_plan* plan, const char* key, dou
  * only when it is at least 3% faster.  Leaves those four options at the chosen
  * values (read them with cylpoisson_plan_get_option) and every other option as
  * it was.  Results of later solves do not depend on the choice beyond rounding
- * order (tile shapes do not change the arithmetic of a node).  Blocks; returns
- * OK, ENOMEM or an error of the trial solves. */
+ * order (tile shapes do not change the arithmetic of a node).  With option
+ * "tune_omega" 1 it then measures, for "omega" in 1.0 .. 1.5, the contraction
+ * per V-cycle from cycle 2 to cycle 6 of a solve from zero on the same charge,
+ * and sets the omega with the smallest contraction if that is under 0.9 times
+ * the current omega's (this one changes the iterates).  Blocks; returns OK,
+ * ENOMEM or an error of the trial solves. */
 int cylpoisson_autotune(cylpoisson_plan* plan, void* stream);
 
 /* Solve `count` independent problems (distinct plans, each with its own grid)

@@ -105,12 +105,52 @@ int cylpoisson_autotune(cylpoisson_plan* p, void* stream) {
         (void)cylpoisson_plan_set_option(p, c.key, keep);
         if (status != CYLPOISSON_OK) break;
     }
+    // The relaxation factor (option tune_omega, point smoother V-cycles only):
+    // the contraction per cycle from cycle 2 to cycle 6 of a solve from zero
+    // on the same charge (the check after a solve's last cycle is always
+    // formed), for each candidate; omega changes only for a clear gain.
+    double omega = saved.omega;
+    if (status == CYLPOISSON_OK && saved.tune_omega && saved.smoother == 0 && saved.krylov == 0) {
+        p->opt.fmg = 0;
+        auto contraction = [&](double w, double* rate) -> int {
+            p->opt.omega = w;
+            double rel[2] = {0.0, 0.0};
+            int cyc[2] = {0, 0};
+            const int maxc[2] = {2, 6};
+            for (int i = 0; i < 2; ++i) {
+                p->opt.max_cycles = maxc[i];
+                drop_graphs(p);
+                const int st = cylpoisson_solve(p, rho, phi, 1e-300, stream);
+                if (st != CYLPOISSON_OK && st != CYLPOISSON_NOT_CONVERGED) return st;
+                rel[i] = p->stats.rel_residual;
+                cyc[i] = p->stats.cycles;
+            }
+            *rate = (cyc[1] > cyc[0] && rel[0] > 0.0 && rel[1] > 0.0)
+                        ? std::pow(rel[1] / rel[0], 1.0 / (cyc[1] - cyc[0]))
+                        : 1.0;
+            return CYLPOISSON_OK;
+        };
+        double keep_rate = 1.0;
+        status = contraction(saved.omega, &keep_rate);
+        double best_rate = keep_rate;
+        for (double w : {1.0, 1.1, 1.15, 1.2, 1.25, 1.3, 1.35, 1.4, 1.5}) {
+            if (status != CYLPOISSON_OK || w == saved.omega) continue;
+            double r = 1.0;
+            status = contraction(w, &r);
+            if (status == CYLPOISSON_OK && r < best_rate) {
+                best_rate = r;
+                omega = w;
+            }
+        }
+        if (!(best_rate < 0.9 * keep_rate)) omega = saved.omega;
+    }
     const Options tuned = p->opt;
     p->opt = saved;
     p->opt.chunk_rows = tuned.chunk_rows;
     p->opt.chunk_rows_coarse = tuned.chunk_rows_coarse;
     p->opt.prefetch = tuned.prefetch;
     p->opt.groups = tuned.groups;
+    if (status == CYLPOISSON_OK) p->opt.omega = omega;
     drop_graphs(p);
     (void)hipFree(rho);
     (void)hipFree(phi);

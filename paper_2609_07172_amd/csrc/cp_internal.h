@@ -130,6 +130,7 @@ struct Options {
     int merge = 1;         // 1: merged finest pass between cycles without a convergence check
     int merge_prefetch = 1;  // rows the merged finest pass loads ahead (1 or 2)
     int chunk_rows_merge = 0;  // axial rows per workgroup of the merged pass (0 = automatic)
+    int tune_omega = 0;    // 1: cylpoisson_autotune also picks omega by the measured contraction
     int nn_target = 0;     // training targets: 0 = SOR correction of the residual, 1 = V-cycle iterate error
     int direct = 1;        // exact separable solve of a coarse level, where the V-cycles stop:
                            // 0 off; 1 the first level with <= 128 interior nodes each way;

@@ -950,6 +950,7 @@ int cylpoisson_plan_set_option(cylpoisson_plan* plan, const char* key, double va
     if (!std::strcmp(key, "merge")) return int_in(0, 1, &plan->opt.merge);
     if (!std::strcmp(key, "merge_prefetch")) return int_in(1, 2, &plan->opt.merge_prefetch);
     if (!std::strcmp(key, "chunk_rows_merge")) return int_in(0, 1 << 20, &plan->opt.chunk_rows_merge);
+    if (!std::strcmp(key, "tune_omega")) return int_in(0, 1, &plan->opt.tune_omega);
     if (!std::strcmp(key, "fft")) return int_in(0, 1, &plan->opt.fft);
     if (!std::strcmp(key, "inner_cycles")) return int_in(1, 8, &plan->opt.inner_cycles);
     if (!std::strcmp(key, "groups")) return int_in(1, 8, &plan->opt.groups);
@@ -1010,6 +1011,7 @@ int cylpoisson_plan_get_option(const cylpoisson_plan* plan, const char* key, dou
                  {"krylov_max", (double)o.krylov_max}, {"fallback", (double)o.fallback},
                  {"merge", (double)o.merge}, {"merge_prefetch", (double)o.merge_prefetch},
                  {"chunk_rows_merge", (double)o.chunk_rows_merge}, {"nn_target", (double)o.nn_target},
+                 {"tune_omega", (double)o.tune_omega},
                  {"direct", (double)o.direct}};
     for (const auto& t : table)
         if (!std::strcmp(key, t.name)) {

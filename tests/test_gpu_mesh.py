@@ -127,6 +127,24 @@ def test_fused_passes_on_meshes_equal_the_per_step_kernels(P, name, chunk):
     np.testing.assert_array_equal(host(pa), host(pb))
 
 
+def test_autotuner_picks_omega_on_a_stretched_mesh(P):
+    """With option tune_omega the autotuner sets the over-relaxation factor from the
+    measured contraction per cycle; on stretched cells the tuned plan needs no more
+    cycles than the default for the same answer, and omega is one of its candidates."""
+    g, rho, ref = reference("cell_stretched")
+    say("tune omega", g.shape)
+    _, st0 = plan_for(P, CASES["cell_stretched"]).solve(dev(rho), tol=1e-13)
+    plan = plan_for(P, CASES["cell_stretched"], tune_omega=1)
+    plan.autotune()
+    w = plan.get_option("omega")
+    say("omega", w, "default cycles", st0["cycles"])
+    assert w in (1.0, 1.1, 1.15, 1.2, 1.25, 1.3, 1.35, 1.4, 1.5)
+    phi, st = plan.solve(dev(rho), tol=1e-13)
+    assert st["status"] == P.OK, st
+    assert st["cycles"] <= st0["cycles"], (w, st["cycles"], st0["cycles"])
+    assert rel_l2(host(phi), ref) <= 1e-12
+
+
 def test_warm_start_on_a_mesh(P):
     g, rho, ref = reference("vertex_stretched")
     say("mesh warm start")
