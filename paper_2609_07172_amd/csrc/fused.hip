@@ -12,7 +12,10 @@ bool fused_supported(const cylpoisson_plan* p, int l) {
     // the up pass has thread t carry coarse interior column t + 1: the coarse
     // level must be coarsened in r (a level coarsened in z only is not fused)
     const bool coarse_cols = p->dl[l + 1].v.nr - 2 <= su.threads;
-    return su.threads >= 1 && su.threads <= 512 && std::max(sd.lds, su.lds) <= 64 * 1024 &&
+    // the ROWS passes hold their rows' inverse diagonals too: up to 80 KB
+    // (two workgroups per compute unit), allowed in fused_prepare
+    const size_t cap = (sd.rows || su.rows ? 80 : 64) * 1024;
+    return su.threads >= 1 && su.threads <= 512 && std::max(sd.lds, su.lds) <= cap &&
            std::max(sd.nchunks, su.nchunks) <= kMaxPartial && coarse_cols;
 }
 
@@ -44,7 +47,7 @@ bool fused_down_pro_ok(const cylpoisson_plan* p, int l) {
     const Shape sh = pass_shape<double>(p, l, nu, true, true);
     // three sweeps: one wave per SIMD (at most 256 threads, the registers of
     // two) and up to 80 KB of LDS (two workgroups per compute unit)
-    return nu == 2 ? sh.lds <= 64 * 1024 : (sh.threads <= 256 && sh.lds <= 80 * 1024);
+    return nu == 2 ? sh.lds <= (sh.rows ? 80 : 64) * 1024 : (sh.threads <= 256 && sh.lds <= 80 * 1024);
 }
 
 hipError_t fused_down_pro(cylpoisson_plan* p, hipStream_t s, int p0, int np, int l) {
@@ -97,7 +100,8 @@ hipError_t launch_merge(const PassArgs<double>& a, int blocks, int threads, size
 }
 
 // Dynamic LDS beyond the default 64 KiB for the kernels that take it (the
-// merged passes up to 160 KB, the three-sweep first down pass up to 80 KB),
+// merged passes up to 160 KB, the three-sweep first down pass and the ROWS
+// passes up to 80 KB),
 // allowed once on the current device when a plan is built, so that no launch
 // needs a host call (a launch under graph capture included).
 hipError_t fused_prepare() {
@@ -108,7 +112,14 @@ hipError_t fused_prepare() {
                        reinterpret_cast<const void*>(&k_pass_merge<double, 5, 2>),
                        reinterpret_cast<const void*>(&k_pass_merge<double, 6, 1>),
                        reinterpret_cast<const void*>(&k_pass_merge<double, 6, 2>),
-                       reinterpret_cast<const void*>(&k_pass_fine_pro<double, 3, pass_prefetch<double>(3, 1)>)};
+                       reinterpret_cast<const void*>(&k_pass_fine_pro<double, 3, pass_prefetch<double>(3, 1)>),
+                       reinterpret_cast<const void*>(&k_pass_fine_pro_rows<double, 2, 1>),
+                       reinterpret_cast<const void*>(&k_pass_rows<double, 2, 1, true, true>),
+                       reinterpret_cast<const void*>(&k_pass_rows<double, 2, 1, true, false>),
+                       reinterpret_cast<const void*>(&k_pass_rows<double, 2, 1, false, false>),
+                       reinterpret_cast<const void*>(&k_pass_fine_rows<double, 2, 1, true, true>),
+                       reinterpret_cast<const void*>(&k_pass_fine_rows<double, 2, 1, true, false>),
+                       reinterpret_cast<const void*>(&k_pass_fine_rows<double, 2, 1, false, false>)};
     for (const void* f : k) {
         const hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
         if (e != hipSuccess) return e;

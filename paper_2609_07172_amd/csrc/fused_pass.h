@@ -60,7 +60,7 @@ struct PassArgs {
     const int* colc;     // fine column -> coarse interior column it coincides with, else -1
     const int* rowc;     // fine row -> coarse interior row it coincides with, else -1
     int reg_lo, reg_hi;  // rows reg_lo <= y < reg_hi share the axial coefficients (zc0, zs0, zn0)
-    int rows_steady;     // rows outside that band also take unchecked steps (per-row coefficients)
+    int rows_steady;     // the launch is a ROWS instantiation (see Pass)
     double* partial;     // up: per (plane, chunk) sum of squared residuals, or nullptr
     int partial_ld;      // stride between planes in `partial`
     double omega, zc0, zs0, zn0;
@@ -95,6 +95,10 @@ struct Pass {
     // 4 with one row of prefetch (a coarse interval spans one or two fine rows).
     static constexpr int kCRing = PD == 1 ? 4 : 8;
     static constexpr int kSteady = 0, kSteadyRows = 1, kChecked = 2;
+    // ROWS passes that relax each column of a row at least twice keep the
+    // row's inverse diagonals in LDS (the merged pass and the plain down
+    // pass; in the up and first down passes the extra registers spill)
+    static constexpr bool CACHE = ROWS && (NU >= 4 || (DOWN && !PRO));
 
     const PassArgs<T>& a;
     char* smem;
@@ -107,6 +111,7 @@ struct Pass {
     T* vrows;
     double* tab;
     T* cringp;
+    double* icp;  // CACHE: inverse diagonals of the two columns of each row in flight, per slot
     T* At;  // own column c1
     T* Bt;  // own column c2
     T* Bl;  // column 2t (west of c1)
@@ -144,6 +149,9 @@ struct Pass {
         tab = (double*)(smem + off);
         off += (size_t)(PRO ? 10 : 7) * rows * sizeof(double);
         cringp = (T*)(smem + off);
+        if (XP) off += (size_t)kCRing * a.vc.nr * sizeof(T);
+        off = (off + 7) & ~(size_t)7;
+        icp = (double*)(smem + off);
     }
 
     __device__ __forceinline__ T* Vrow(int buf, int half) { return vrows + (2 * buf + half) * (a.tn + 1); }
@@ -160,6 +168,7 @@ struct Pass {
     __device__ __forceinline__ double* pw0() { return PRO ? tables() + 8 * rows : roww0(); }
     __device__ __forceinline__ double* pw1() { return PRO ? tables() + 9 * rows : roww1(); }
     __device__ __forceinline__ T* cring() { return cringp; }
+    __device__ __forceinline__ double* icache(int slot) { return icp + ((size_t)slot * (a.tn + 1) + t) * 2; }
     __device__ __forceinline__ T* crow(int K) { return cring() + (K & (kCRing - 1)) * a.vc.nr; }
 
     __device__ __forceinline__ bool interior_row(int x) const { return x >= 1 && x <= a.v.nz - 2; }
@@ -346,6 +355,13 @@ struct Pass {
         At[J] = uu[J][0];
         Bt[J] = uu[J][1];
         if (t == 0) Bl[J] = (T)col0()[x - s];
+        if constexpr (CACHE) {
+            // every relaxation of this row reads its inverse diagonals from here
+            // (one division per column and row instead of one per half-sweep)
+            const double zc = rowzc()[x - s], zs = rowzs()[x - s], zn = rowzn()[x - s];
+            icache(J)[0] = make_coef(rw1, re1, rb1, rm1, zc, zs, zn, lam).invd;
+            icache(J)[1] = make_coef(rw2, re2, rb2, rm2, zc, zs, zn, lam).invd;
+        }
     }
 
     // ---- arithmetic ----
@@ -355,17 +371,26 @@ struct Pass {
     __device__ __forceinline__ CoefT<T> irregular(double rw, double re, double rb, double rm, int y) {
         return coef_as<T>(make_coef(rw, re, rb, rm, rowzc()[y - s], rowzs()[y - s], rowzn()[y - s], lam));
     }
+    // The same with the inverse diagonal the row's consume step formed (CACHE).
+    template <int SY, int COL>
+    __device__ __forceinline__ CoefT<T> irregular_cached(double rw, double re, double rb, double rm, int y) {
+        Coef c = make_coef_products(rw, re, rb, rm, rowzc()[y - s], rowzs()[y - s], rowzn()[y - s], lam);
+        c.invd = icache(SY)[COL];
+        return coef_as<T>(c);
+    }
     // Step modes: kSteady (every row in the regular band, no bounds checks),
     // kSteadyRows (no bounds checks, every row's coefficients from its tables:
     // the band's own rows give the band's values exactly) and kChecked.
-    template <int MODE>
+    template <int MODE, int SY>
     __device__ __forceinline__ CoefT<T> coef1(int y) {
         if (MODE == kSteady || (MODE == kChecked && regular(y))) return cu1;
+        if constexpr (CACHE) return irregular_cached<SY, 0>(rw1, re1, rb1, rm1, y);
         return irregular(rw1, re1, rb1, rm1, y);
     }
-    template <int MODE>
+    template <int MODE, int SY>
     __device__ __forceinline__ CoefT<T> coef2(int y) {
         if (MODE == kSteady || (MODE == kChecked && regular(y))) return cu2;
+        if constexpr (CACHE) return irregular_cached<SY, 1>(rw2, re2, rb2, rm2, y);
         return irregular(rw2, re2, rb2, rm2, y);
     }
 
@@ -375,11 +400,11 @@ struct Pass {
     template <int SY, int SM, int SP, bool C1, int MODE>
     __device__ __forceinline__ void half_sweep(int y, T nb) {
         if (C1) {
-            const T v = relax(uu[SY][0], ff[SY][0], nb, uu[SY][1], uu[SM][0], uu[SP][0], coef1<MODE>(y), om);
+            const T v = relax(uu[SY][0], ff[SY][0], nb, uu[SY][1], uu[SM][0], uu[SP][0], coef1<MODE, SY>(y), om);
             uu[SY][0] = act1 ? v : uu[SY][0];
             At[SY] = uu[SY][0];
         } else {
-            const T v = relax(uu[SY][1], ff[SY][1], uu[SY][0], nb, uu[SM][1], uu[SP][1], coef2<MODE>(y), om);
+            const T v = relax(uu[SY][1], ff[SY][1], uu[SY][0], nb, uu[SM][1], uu[SP][1], coef2<MODE, SY>(y), om);
             uu[SY][1] = act2 ? v : uu[SY][1];
             Bt[SY] = uu[SY][1];
         }
@@ -387,8 +412,8 @@ struct Pass {
 
     template <int SY, int SM, int SP, int MODE>
     __device__ __forceinline__ void residual_row(int y, T nw, T ne, T& r1, T& r2) {
-        const T x1 = residual(uu[SY][0], ff[SY][0], nw, uu[SY][1], uu[SM][0], uu[SP][0], coef1<MODE>(y));
-        const T x2 = residual(uu[SY][1], ff[SY][1], uu[SY][0], ne, uu[SM][1], uu[SP][1], coef2<MODE>(y));
+        const T x1 = residual(uu[SY][0], ff[SY][0], nw, uu[SY][1], uu[SM][0], uu[SP][0], coef1<MODE, SY>(y));
+        const T x2 = residual(uu[SY][1], ff[SY][1], uu[SY][0], ne, uu[SM][1], uu[SP][1], coef2<MODE, SY>(y));
         r1 = act1 ? x1 : T(0);
         r2 = act2 ? x2 : T(0);
     }
@@ -719,6 +744,7 @@ hipError_t launch_nu(bool fine, int nu, int pd, bool down, bool zero_u, const Pa
 struct Shape {
     int tn, threads, chunk, nchunks, blocks;
     size_t lds;
+    bool rows;  // the launch takes the ROWS instantiation (per-row unchecked steps)
 };
 
 // Launch shape of a pass.  `merge`: the merged finest pass (nu = nu2 + nu1
@@ -754,6 +780,11 @@ Shape pass_shape(const cylpoisson_plan* p, int l, int nu, bool down, bool pro = 
     sh.nchunks = (rows + chunk - 1) / chunk;
     sh.blocks = sh.nchunks * p->nt;
     const int pd = merge ? p->opt.merge_prefetch : pass_prefetch<T>(nu, p->opt.prefetch);
+    // a level whose regular band holds under half its rows (a stretched mesh)
+    // runs the ROWS instantiation where one exists: FP64, one row of prefetch,
+    // two sweeps (four in the merged pass)
+    sh.rows = std::is_same<T, double>::value && 2 * (L.reg_hi - L.reg_lo) < L.v.nz - 2 && pd == 1 &&
+              nu == (merge ? 4 : 2);
     const int q0 = 2 * nu + 3 + pd;
     const size_t qs = (size_t)((q0 & 1) ? q0 + 1 : q0) + 1;
     const size_t trows = (size_t)(chunk + 4 * nu + 6);
@@ -761,6 +792,11 @@ Shape pass_shape(const cylpoisson_plan* p, int l, int nu, bool down, bool pro = 
     off = (off + 7) & ~(size_t)7;
     off += (size_t)(pro ? 10 : 7) * trows * sizeof(double);
     if (!down || pro) off += (size_t)(pd == 1 ? 4 : 8) * p->dl[l + 1].v.nr * sizeof(T);
+    if (sh.rows && (nu >= 4 || (down && !pro))) {
+        // inverse diagonals of the two columns of each slot's row (Pass::CACHE)
+        off = (off + 7) & ~(size_t)7;
+        off += (qs - 1) * 2 * (size_t)(sh.tn + 1) * sizeof(double);
+    }
     sh.lds = std::max(off, (size_t)sh.threads * sizeof(double));  // final block reduction
     return sh;
 }
@@ -780,8 +816,7 @@ PassArgs<T> make_args(const cylpoisson_plan* p, int l, const Shape& sh, int p0, 
     a.rowc = L.rowc;
     a.reg_lo = L.reg_lo;
     a.reg_hi = L.reg_hi;
-    // a level whose regular band holds under half its rows (a stretched mesh)
-    a.rows_steady = 2 * (L.reg_hi - L.reg_lo) < L.v.nz - 2 ? 1 : 0;
+    a.rows_steady = sh.rows ? 1 : 0;
     a.omega = p->opt.omega;
     a.zc0 = L.zc0;
     a.zs0 = L.zs0;

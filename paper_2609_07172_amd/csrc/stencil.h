@@ -33,8 +33,10 @@ __device__ __forceinline__ CoefT<T> coef_as(const Coef& c) {
 // Coefficients of one node from its radial and axial table entries and the
 // plane's shift lambda: the face conductances of App. A and the diagonal
 // D0 + lambda mu (Eqs. interior_base_diagonal, mode_mass_coefficient).
-__device__ __forceinline__ Coef make_coef(double rw, double re, double rb, double rm, double zc,
-                                          double zs, double zn, double lambda) {
+// make_coef without its division: every field but invd (left zero), for a
+// caller that already holds 1 / diag of the same node.
+__device__ __forceinline__ Coef make_coef_products(double rw, double re, double rb, double rm, double zc,
+                                                   double zs, double zn, double lambda) {
 #pragma clang fp contract(off)
     Coef c;
     c.gw = rw * zc;
@@ -42,6 +44,13 @@ __device__ __forceinline__ Coef make_coef(double rw, double re, double rb, doubl
     c.gs = rb * zs;
     c.gn = rb * zn;
     c.diag = fma(lambda, rm * zc, (c.gw + c.ge) + (c.gs + c.gn));
+    c.invd = 0.0;
+    return c;
+}
+
+__device__ __forceinline__ Coef make_coef(double rw, double re, double rb, double rm, double zc,
+                                          double zs, double zn, double lambda) {
+    Coef c = make_coef_products(rw, re, rb, rm, zc, zs, zn, lambda);
     c.invd = 1.0 / c.diag;
     return c;
 }
