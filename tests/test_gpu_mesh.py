@@ -240,7 +240,8 @@ def test_paper_scale_stretched_cells_sampled_planes(P):
     z = 0: three Fourier planes of the GPU solution (the GPU's own forward DFT
     of phi) against the oracle's direct solves of those modes.  Per-plane
     errors are bounded by the field's (Parseval), so each must be within
-    1e-12 of the interior field norm."""
+    1e-12 of the interior field norm.  All 128 planes: the residual of every
+    mode equation for the oracle's DFT of the answer."""
     nr, nt, nz = 400, 128, 512
     rf = W.stretched_points(0.02, 0.05, nr - 2, 4.0 ** (1.0 / (nr - 3)))
     zf = W.stretched_points(0.0, 0.1, nz - 2, 0.25 ** (1.0 / (nz - 3)))
@@ -265,6 +266,19 @@ def test_paper_scale_stretched_cells_sampled_planes(P):
         err = np.linalg.norm(got[p, 1:-1, 1:-1] - ref) * np.sqrt(nt)
         say("plane", p, err / norm)
         assert err <= 1e-12 * norm, (p, err / norm)
+    # every plane at full size: the oracle's own DFT of the answer satisfies each
+    # mode equation (A_0 + lambda_p M) u_p = b_p to the solve's tolerance (the
+    # library weighs the planes as Parseval does, within a factor of 2 of this sum)
+    up = spectral.forward(phi[:, 1:-1, 1:-1])
+    A0 = solvers.plane_matrix(g)
+    r2 = b2 = 0.0
+    for p in range(nt):
+        r = bp[p].ravel() - solvers.mode_operator(A0, g.mu, float(lam[p])) @ up[p].ravel()
+        r2 += float(r @ r)
+        b2 += float(bp[p].ravel() @ bp[p].ravel())
+    rel = np.sqrt(r2 / b2)
+    say("all-plane relative residual", rel, "library", st["rel_residual"])
+    assert rel <= 3e-13, rel
 
 
 @pytest.mark.parametrize("smoother", [1, 2])
