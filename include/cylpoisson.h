@@ -88,8 +88,8 @@ typedef struct {
      * 3-D right-hand side s rho + b^D. */
     double rel_residual_history[CYLPOISSON_MAX_HISTORY];
     /* Device time per kernel class in the last solve, from HIP events recorded
-     * around each launch on the solve's stream when the option "timing" is 1
-     * (all zero otherwise).  Classes: 0 forward DFT, 1 inverse DFT, 2 finest-level
+     * around each launch on the solve's stream when the option "timing" is 1,
+     * for classes 2, 3 and 6 only when it is 2 (all zero otherwise).  Classes: 0 forward DFT, 1 inverse DFT, 2 finest-level
      * down pass (smoothing, residual, restriction), 3 finest-level up pass
      * (prolongation, smoothing, residual norm), 4 all coarser levels (one
      * interval per cycle), 5 other work (initialisation, norm reductions, the
@@ -180,7 +180,9 @@ void cylpoisson_plan_destroy(cylpoisson_plan* plan);
  *                    sweep everywhere (default 1)
  *   "chunk_rows"     axial rows per workgroup of the fused passes (0 = automatic)
  *   "prefetch"       rows the fused passes load ahead of the one they consume (1 .. 3; default 1)
- *   "timing"         1 = record per-kernel-class device times (cylpoisson_stats)
+ *   "timing"         1 = record per-kernel-class device times (cylpoisson_stats);
+ *                    2 = the finest-level pass classes only (fewer event records
+ *                    between the other launches); 0 = off (0 .. 2; default 0)
  *   "bottom"         1 = run the small levels of each plane in one LDS-resident
  *                    kernel (with "fused" = 1; default 1)
  *   "smoother"       0 = point red-black SOR (default); 1 = zebra line relaxation

@@ -939,7 +939,7 @@ int cylpoisson_plan_set_option(cylpoisson_plan* plan, const char* key, double va
     if (!std::strcmp(key, "fused")) return int_in(0, 1, &plan->opt.fused);
     if (!std::strcmp(key, "chunk_rows")) return int_in(0, 1 << 20, &plan->opt.chunk_rows);
     if (!std::strcmp(key, "chunk_rows_coarse")) return int_in(0, 1 << 20, &plan->opt.chunk_rows_coarse);
-    if (!std::strcmp(key, "timing")) return int_in(0, 1, &plan->opt.timing);
+    if (!std::strcmp(key, "timing")) return int_in(0, 2, &plan->opt.timing);
     // a fourth row in flight needs more registers than the FP64 up pass has (it spills)
     if (!std::strcmp(key, "prefetch")) return int_in(1, 3, &plan->opt.prefetch);
     if (!std::strcmp(key, "bottom")) return int_in(0, 1, &plan->opt.bottom);

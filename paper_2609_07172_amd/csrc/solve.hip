@@ -91,12 +91,16 @@ double weighted(const cylpoisson_plan* p, const double* norms) {
     return s;
 }
 
+enum { kDftFwd = 0, kDftInv = 1, kFineDown = 2, kFineUp = 3, kCoarse = 4, kOther = 5, kFineMerged = 6 };
+
 // HIP events around a launch (or a group of launches) of one kernel class,
-// recorded on the solve's stream when the option "timing" is set.
+// recorded on the solve's stream when the option "timing" is set (2: the
+// finest-level pass classes only, so the other launches run unbracketed).
 class Timed {
   public:
     Timed(cylpoisson_plan* p, int cls, hipStream_t s) : p_(p), s_(s) {
         if (!p->opt.timing || cls < 0) return;
+        if (p->opt.timing == 2 && cls != kFineDown && cls != kFineUp && cls != kFineMerged) return;
         const int need = 2 * (p->events_used + 1);
         while ((int)p->events.size() < need) {
             hipEvent_t e;
@@ -123,8 +127,6 @@ class Timed {
     hipStream_t s_;
     int idx_ = -1;
 };
-
-enum { kDftFwd = 0, kDftInv = 1, kFineDown = 2, kFineUp = 3, kCoarse = 4, kOther = 5, kFineMerged = 6 };
 
 // After the stream has drained: fold the recorded event pairs into the stats.
 void collect_timing(cylpoisson_plan* p) {

@@ -488,6 +488,22 @@ def test_merged_finest_passes_equal_the_separate_passes(P, shape, options):
     assert histories_agree(sa["history"], sb["history"])
 
 
+def test_timing_two_records_the_finest_passes_only(P):
+    """Option timing = 2 brackets only the finest-level passes with events (the
+    classes the roofline figures use); timing = 1 brackets every launch."""
+    p = W.SMALL.with_sizes(65, 8, 65)
+    rho = dev(W.blob_charge(p, seed=12))
+    say("timing modes")
+    plan = P.Plan.for_problem(p, timing=2)
+    _, st = plan.solve(rho, tol=1e-13)
+    kl = st["kernel_launches"]
+    assert kl["fine_up"] >= 1 and kl["fine_down"] >= 1 and st["kernel_ms"]["fine_up"] > 0, kl
+    assert kl["coarse_levels"] == kl["other"] == kl["dft_forward"] == kl["dft_inverse"] == 0, kl
+    plan.set_option("timing", 1)
+    _, st = plan.solve(rho, tol=1e-13)
+    assert st["kernel_launches"]["coarse_levels"] >= 1 and st["kernel_launches"]["dft_forward"] == 1
+
+
 def test_first_check_follows_the_last_converged_solve(P):
     """A repeated solve to the same tol checks first at the cycle count the last
     one needed: fewer host round trips, the same answer."""
