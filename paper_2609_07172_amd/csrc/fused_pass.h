@@ -94,7 +94,10 @@ struct Pass {
     // at one step are K(x) .. K(x + PD + 1) + 1 for the consumed row x: at most
     // 4 with one row of prefetch (a coarse interval spans one or two fine rows).
     static constexpr int kCRing = PD == 1 ? 4 : 8;
-    static constexpr int kSteady = 0, kSteadyRows = 1, kChecked = 2;
+    static constexpr int kSteady = 0, kSteadyRows = 1, kChecked = 2, kCheckedBand = 3;
+    // kCheckedBand steps exist in the FP64 passes with one row of prefetch
+    // (the defaults); elsewhere their registers would cost occupancy or spill
+    static constexpr bool BAND = std::is_same<T, double>::value && PD == 1;
     // ROWS passes that relax each column of a row at least twice keep the
     // row's inverse diagonals in LDS (the merged pass and the plain down
     // pass; in the up and first down passes the extra registers spill)
@@ -380,16 +383,19 @@ struct Pass {
     }
     // Step modes: kSteady (every row in the regular band, no bounds checks),
     // kSteadyRows (no bounds checks, every row's coefficients from its tables:
-    // the band's own rows give the band's values exactly) and kChecked.
+    // the band's own rows give the band's values exactly), kChecked, and
+    // kCheckedBand (bounds checked, every row in the band: the half-sweeps of
+    // rows out of range run and keep their old values, so a step's half-sweeps
+    // have no branches between them).
     template <int MODE, int SY>
     __device__ __forceinline__ CoefT<T> coef1(int y) {
-        if (MODE == kSteady || (MODE == kChecked && regular(y))) return cu1;
+        if (MODE == kSteady || MODE == kCheckedBand || (MODE == kChecked && regular(y))) return cu1;
         if constexpr (CACHE) return irregular_cached<SY, 0>(rw1, re1, rb1, rm1, y);
         return irregular(rw1, re1, rb1, rm1, y);
     }
     template <int MODE, int SY>
     __device__ __forceinline__ CoefT<T> coef2(int y) {
-        if (MODE == kSteady || (MODE == kChecked && regular(y))) return cu2;
+        if (MODE == kSteady || MODE == kCheckedBand || (MODE == kChecked && regular(y))) return cu2;
         if constexpr (CACHE) return irregular_cached<SY, 1>(rw2, re2, rb2, rm2, y);
         return irregular(rw2, re2, rb2, rm2, y);
     }
@@ -397,15 +403,16 @@ struct Pass {
     // Half-sweep on row y (slot SY; SM = y-1, SP = y+1).  C1: the colour being
     // relaxed sits on column c1 of this row.  NB: the horizontal neighbour from
     // another thread (west of c1 or east of c2), published one step earlier.
+    // ON false: the row is out of range and keeps its value (kCheckedBand).
     template <int SY, int SM, int SP, bool C1, int MODE>
-    __device__ __forceinline__ void half_sweep(int y, T nb) {
+    __device__ __forceinline__ void half_sweep(int y, T nb, bool on = true) {
         if (C1) {
             const T v = relax(uu[SY][0], ff[SY][0], nb, uu[SY][1], uu[SM][0], uu[SP][0], coef1<MODE, SY>(y), om);
-            uu[SY][0] = act1 ? v : uu[SY][0];
+            uu[SY][0] = act1 && on ? v : uu[SY][0];
             At[SY] = uu[SY][0];
         } else {
             const T v = relax(uu[SY][1], ff[SY][1], uu[SY][0], nb, uu[SM][1], uu[SP][1], coef2<MODE, SY>(y), om);
-            uu[SY][1] = act2 ? v : uu[SY][1];
+            uu[SY][1] = act2 && on ? v : uu[SY][1];
             Bt[SY] = uu[SY][1];
         }
     }
@@ -438,7 +445,7 @@ struct Pass {
     // kSteady, regular).
     template <int J, int MODE>
     __device__ __forceinline__ void step(int x) {
-        constexpr bool CHK = MODE == kChecked;
+        constexpr bool CHK = MODE == kChecked || MODE == kCheckedBand;
         lds_barrier();
         // every LDS value read here was published at an earlier step, and this
         // step only writes locations nobody reads during it
@@ -466,7 +473,10 @@ struct Pass {
         constexpr int sp = (J - (h) + 4 * Q) % Q;                                            \
         constexpr bool c1col = ((((J - 1 - (h)) & 1) + 1) & 1) == ((h) & 1);                 \
         const int y = x - 1 - (h);                                                           \
-        if (!CHK || (y >= ylo && y <= yhi)) half_sweep<sy, sm, sp, c1col, MODE>(y, nb[(h)]); \
+        if constexpr (MODE == kCheckedBand)                                                  \
+            half_sweep<sy, sm, sp, c1col, MODE>(y, nb[(h)], y >= ylo && y <= yhi);             \
+        else if (!CHK || (y >= ylo && y <= yhi))                                             \
+            half_sweep<sy, sm, sp, c1col, MODE>(y, nb[(h)]);                                 \
     }
         CP_HS(0) CP_HS(1) CP_HS(2) CP_HS(3) CP_HS(4) CP_HS(5) CP_HS(6) CP_HS(7)
         CP_HS(8) CP_HS(9) CP_HS(10) CP_HS(11)
@@ -518,7 +528,7 @@ struct Pass {
 
     template <int MODE>
     __device__ __forceinline__ void group(int x0, int xend) {
-        constexpr bool CHK = MODE == kChecked;
+        constexpr bool CHK = MODE == kChecked || MODE == kCheckedBand;
         // Q consecutive steps with compile-time register and LDS slots
 #define CP_STEP(J)                                             \
     if constexpr ((J) < Q) {                                   \
@@ -572,6 +582,12 @@ struct Pass {
             } else if constexpr (ROWS) {
                 if (x0 >= ga1 && x0 < gb1)
                     group<kSteadyRows>(x0, x0 + Q - 1);
+                else
+                    group<kChecked>(x0, xlast);
+            } else if constexpr (BAND) {
+                // every row whose coefficients the group's steps use is in the band
+                if (x0 - 2 * NU - 1 >= a.reg_lo && x0 + Q - 2 < a.reg_hi)
+                    group<kCheckedBand>(x0, xlast);
                 else
                     group<kChecked>(x0, xlast);
             } else {
