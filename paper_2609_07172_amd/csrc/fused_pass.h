@@ -95,9 +95,9 @@ struct Pass {
     // 4 with one row of prefetch (a coarse interval spans one or two fine rows).
     static constexpr int kCRing = PD == 1 ? 4 : 8;
     static constexpr int kSteady = 0, kSteadyRows = 1, kChecked = 2, kCheckedBand = 3;
-    // kCheckedBand steps exist in the FP64 passes with one row of prefetch
-    // (the defaults); elsewhere their registers would cost occupancy or spill
-    static constexpr bool BAND = std::is_same<T, double>::value && PD == 1;
+    // kCheckedBand steps exist in the passes with one row of prefetch (the
+    // defaults); with more rows in flight their registers spill
+    static constexpr bool BAND = PD == 1;
     // ROWS passes that relax each column of a row at least twice keep the
     // row's inverse diagonals in LDS (the merged pass and the plain down
     // pass; in the up and first down passes the extra registers spill)
