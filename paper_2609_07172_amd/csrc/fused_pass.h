@@ -94,7 +94,7 @@ struct Pass {
     // at one step are K(x) .. K(x + PD + 1) + 1 for the consumed row x: at most
     // 4 with one row of prefetch (a coarse interval spans one or two fine rows).
     static constexpr int kCRing = PD == 1 ? 4 : 8;
-    static constexpr int kSteady = 0, kSteadyRows = 1, kChecked = 2, kCheckedBand = 3;
+    static constexpr int kSteady = 0, kSteadyRows = 1, kChecked = 2, kCheckedBand = 3, kCheckedRows = 4;
     // kCheckedBand steps exist in the passes with one row of prefetch (the
     // defaults); with more rows in flight their registers spill
     static constexpr bool BAND = PD == 1;
@@ -386,10 +386,12 @@ struct Pass {
     // the band's own rows give the band's values exactly), kChecked, and
     // kCheckedBand (bounds checked, every row in the band: the half-sweeps of
     // rows out of range run and keep their old values, so a step's half-sweeps
-    // have no branches between them).
+    // have no branches between them), and kCheckedRows (the same with every
+    // row's coefficients from its tables, in the ROWS passes).
     template <int MODE, int SY>
     __device__ __forceinline__ CoefT<T> coef1(int y) {
         if (MODE == kSteady || MODE == kCheckedBand || (MODE == kChecked && regular(y))) return cu1;
+        static_assert(MODE != kCheckedRows || ROWS, "kCheckedRows steps belong to the ROWS passes");
         if constexpr (CACHE) return irregular_cached<SY, 0>(rw1, re1, rb1, rm1, y);
         return irregular(rw1, re1, rb1, rm1, y);
     }
@@ -445,7 +447,7 @@ struct Pass {
     // kSteady, regular).
     template <int J, int MODE>
     __device__ __forceinline__ void step(int x) {
-        constexpr bool CHK = MODE == kChecked || MODE == kCheckedBand;
+        constexpr bool CHK = MODE == kChecked || MODE == kCheckedBand || MODE == kCheckedRows;
         lds_barrier();
         // every LDS value read here was published at an earlier step, and this
         // step only writes locations nobody reads during it
@@ -473,7 +475,7 @@ struct Pass {
         constexpr int sp = (J - (h) + 4 * Q) % Q;                                            \
         constexpr bool c1col = ((((J - 1 - (h)) & 1) + 1) & 1) == ((h) & 1);                 \
         const int y = x - 1 - (h);                                                           \
-        if constexpr (MODE == kCheckedBand)                                                  \
+        if constexpr (MODE == kCheckedBand || MODE == kCheckedRows)                          \
             half_sweep<sy, sm, sp, c1col, MODE>(y, nb[(h)], y >= ylo && y <= yhi);             \
         else if (!CHK || (y >= ylo && y <= yhi))                                             \
             half_sweep<sy, sm, sp, c1col, MODE>(y, nb[(h)]);                                 \
@@ -528,7 +530,7 @@ struct Pass {
 
     template <int MODE>
     __device__ __forceinline__ void group(int x0, int xend) {
-        constexpr bool CHK = MODE == kChecked || MODE == kCheckedBand;
+        constexpr bool CHK = MODE == kChecked || MODE == kCheckedBand || MODE == kCheckedRows;
         // Q consecutive steps with compile-time register and LDS slots
 #define CP_STEP(J)                                             \
     if constexpr ((J) < Q) {                                   \
@@ -583,7 +585,7 @@ struct Pass {
                 if (x0 >= ga1 && x0 < gb1)
                     group<kSteadyRows>(x0, x0 + Q - 1);
                 else
-                    group<kChecked>(x0, xlast);
+                    group<kCheckedRows>(x0, xlast);
             } else if constexpr (BAND) {
                 // every row whose coefficients the group's steps use is in the band
                 if (x0 - 2 * NU - 1 >= a.reg_lo && x0 + Q - 2 < a.reg_hi)
