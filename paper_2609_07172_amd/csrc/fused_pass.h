@@ -74,9 +74,10 @@ struct PassArgs {
 // PRO (down passes only): the input's interior is taken as zero plus the
 // prolongated coarse answer ec, formed as rows are consumed (the start of the
 // first cycle after a full-multigrid guess, which then is never written).
-// ROWS: the pass also has unchecked steps that form each row's coefficients
-// from its tables (kSteadyRows), for levels with few rows in the regular band;
-// its own instantiation, so the other passes keep their registers.
+// ROWS: the pass forms each row's coefficients from its tables in all its
+// steps (kSteadyRows in the middle of the chunk, kCheckedRows at its ends),
+// for levels with few rows in the regular band; its own instantiation, so
+// the other passes keep their registers.
 template <typename T, int NU, int PD, bool DOWN, bool ZERO_U, bool PRO = false, bool ROWS = false>
 struct Pass {
     static_assert(!PRO || DOWN, "PRO is a down-pass mode");
@@ -381,13 +382,13 @@ struct Pass {
         c.invd = icache(SY)[COL];
         return coef_as<T>(c);
     }
-    // Step modes: kSteady (every row in the regular band, no bounds checks),
+    // Step modes: kSteady (every row in the regular band, no bounds checks);
     // kSteadyRows (no bounds checks, every row's coefficients from its tables:
-    // the band's own rows give the band's values exactly), kChecked, and
+    // the band's own rows give the band's values exactly); kChecked;
     // kCheckedBand (bounds checked, every row in the band: the half-sweeps of
     // rows out of range run and keep their old values, so a step's half-sweeps
-    // have no branches between them), and kCheckedRows (the same with every
-    // row's coefficients from its tables, in the ROWS passes).
+    // have no branches between them); kCheckedRows (the same with every row's
+    // coefficients from its tables, in the ROWS passes).
     template <int MODE, int SY>
     __device__ __forceinline__ CoefT<T> coef1(int y) {
         if (MODE == kSteady || MODE == kCheckedBand || (MODE == kChecked && regular(y))) return cu1;
@@ -405,7 +406,8 @@ struct Pass {
     // Half-sweep on row y (slot SY; SM = y-1, SP = y+1).  C1: the colour being
     // relaxed sits on column c1 of this row.  NB: the horizontal neighbour from
     // another thread (west of c1 or east of c2), published one step earlier.
-    // ON false: the row is out of range and keeps its value (kCheckedBand).
+    // ON false: the row is out of range and keeps its value (kCheckedBand,
+    // kCheckedRows).
     template <int SY, int SM, int SP, bool C1, int MODE>
     __device__ __forceinline__ void half_sweep(int y, T nb, bool on = true) {
         if (C1) {
